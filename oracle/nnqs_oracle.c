@@ -1,0 +1,384 @@
+/*
+ * Plain FP64 CPU oracle for the local energy of a second-quantised molecular
+ * Hamiltonian.  TEST INFRASTRUCTURE: only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load this library; the product
+ * path never does.  It shares no source with the HIP library.
+ *
+ * What it computes (paper: Section 2.1 Eq. 4 local energy; Eq. 6 sample mean
+ * with the unique-sample weights of Section 3.1; Eq. 9 Hamiltonian; Section
+ * 3.4 items 4-5 sample-aware evaluation over a sorted table of packed keys):
+ *
+ *   E_loc(x) = sum_{x'} H_{x x'} psi(x') / psi(x)
+ *            = sum_{x'} H_{x x'} exp((l' - l) + i (phi' - phi))
+ *
+ * with psi = exp(l + i phi) and, in the sample-aware form, x' restricted to
+ * the table of unique samples.
+ *
+ * Conventions (readings of the paper, stated once):
+ *  - spin orbital p = 2*i + s, s = 0 up, 1 down; key bit p = occupation of p;
+ *    word 0 holds bits 0..63, word 1 bits 64..127;
+ *  - Jordan-Wigner string over lower indices:
+ *      a_p |x> = x_p (-1)^{#occupied q < p} |x - e_p>,
+ *      a+_p|x> = (1 - x_p) (-1)^{#occupied q < p} |x + e_p>;
+ *  - H = E_core + sum_pq h_pq a+_p a_q + 1/2 sum_pqrs <pq|rs> a+_p a+_q a_s a_r
+ *    with <pq|rs> = (i_p i_r | i_q i_s) delta(s_p,s_r) delta(s_q,s_s) and
+ *    (ij|kl) the spatial chemists'-notation integrals g[((i*K+j)*K+k)*K+l].
+ *
+ * Every matrix element is found by the textbook Slater-Condon rules from the
+ * pair (x, x') and its sign by literally applying the operator string to x.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------ bit helpers */
+static int bit_of(const uint64_t *x, int p) { return (int)((x[p >> 6] >> (p & 63)) & 1u); }
+static void flip_bit(uint64_t *x, int p) { x[p >> 6] ^= (uint64_t)1 << (p & 63); }
+
+/* number of occupied spin orbitals with index below p (the JW string) */
+static int occupied_below(const uint64_t *x, int p) {
+    int c = 0;
+    for (int q = 0; q < p; q++) c += bit_of(x, q);
+    return c;
+}
+
+/* apply a_p in place; returns the sign, or 0 if the result vanishes */
+static int apply_annihilate(uint64_t *x, int p) {
+    if (!bit_of(x, p)) return 0;
+    int s = (occupied_below(x, p) & 1) ? -1 : 1;
+    flip_bit(x, p);
+    return s;
+}
+
+/* apply a+_p in place; returns the sign, or 0 if the result vanishes */
+static int apply_create(uint64_t *x, int p) {
+    if (bit_of(x, p)) return 0;
+    int s = (occupied_below(x, p) & 1) ? -1 : 1;
+    flip_bit(x, p);
+    return s;
+}
+
+static int popcount128(const uint64_t *x) {
+    int c = 0;
+    for (int p = 0; p < 128; p++) c += bit_of(x, p);
+    return c;
+}
+
+/* ------------------------------------------------------------- integrals */
+typedef struct {
+    int K;
+    const double *h;
+    const double *g;
+    double ecore;
+} ora_ham;
+
+static double one_body(const ora_ham *H, int p, int q) {
+    if ((p & 1) != (q & 1)) return 0.0;
+    return H->h[(p >> 1) * H->K + (q >> 1)];
+}
+
+/* physicists' <pq|rs> over spin orbitals */
+static double phys(const ora_ham *H, int p, int q, int r, int s) {
+    if ((p & 1) != (r & 1) || (q & 1) != (s & 1)) return 0.0;
+    int K = H->K;
+    int i = p >> 1, j = r >> 1, k = q >> 1, l = s >> 1; /* (p r | q s) */
+    return H->g[(((size_t)i * K + j) * K + k) * K + l];
+}
+
+/* ----------------------------------------------------- Slater-Condon rules */
+/* <x'|H|x> (= <x|H|x'>, H is real symmetric).  *sign_out receives the sign of
+ * the excitation operator applied to x (1 for the diagonal, 0 if unconnected). */
+static double slater_condon(const ora_ham *H, const uint64_t *x, const uint64_t *xp, int *sign_out) {
+    int N = 2 * H->K;
+    int removed[4], added[4], nr = 0, na = 0;
+    for (int p = 0; p < N; p++) {
+        int a = bit_of(x, p), b = bit_of(xp, p);
+        if (a && !b) {
+            if (nr == 4) { *sign_out = 0; return 0.0; }
+            removed[nr++] = p;
+        } else if (!a && b) {
+            if (na == 4) { *sign_out = 0; return 0.0; }
+            added[na++] = p;
+        }
+    }
+    if (nr != na || nr > 2) { *sign_out = 0; return 0.0; }
+    if (nr == 0) { /* diagonal */
+        double e = H->ecore;
+        for (int p = 0; p < N; p++) {
+            if (!bit_of(x, p)) continue;
+            e += one_body(H, p, p);
+            for (int q = 0; q < N; q++) {
+                if (!bit_of(x, q)) continue;
+                e += 0.5 * (phys(H, p, q, p, q) - phys(H, p, q, q, p));
+            }
+        }
+        *sign_out = 1;
+        return e;
+    }
+    if (nr == 1) { /* single: x' = a+_p a_q x */
+        int q = removed[0], p = added[0];
+        uint64_t y[2] = {x[0], x[1]};
+        int s = apply_annihilate(y, q);
+        s *= apply_create(y, p);
+        double v = one_body(H, p, q);
+        for (int k = 0; k < N; k++) {
+            if (!bit_of(x, k)) continue;
+            v += phys(H, p, k, q, k) - phys(H, p, k, k, q);
+        }
+        *sign_out = s;
+        return s * v;
+    }
+    /* double: x' = a+_a a+_b a_j a_i x with i<j, a<b */
+    int i = removed[0], j = removed[1], a = added[0], b = added[1];
+    uint64_t y[2] = {x[0], x[1]};
+    int s = apply_annihilate(y, i);
+    s *= apply_annihilate(y, j);
+    s *= apply_create(y, b);
+    s *= apply_create(y, a);
+    *sign_out = s;
+    return s * (phys(H, a, b, i, j) - phys(H, a, b, j, i));
+}
+
+/* ------------------------------------------------------ connection lists */
+typedef struct {
+    int n_occ[2], n_vir[2];
+    int occ[2][64], vir[2][64];
+} orbital_lists;
+
+static void build_lists(int K, const uint64_t *x, orbital_lists *L) {
+    for (int s = 0; s < 2; s++) {
+        L->n_occ[s] = L->n_vir[s] = 0;
+        for (int i = 0; i < K; i++) {
+            int p = 2 * i + s;
+            if (bit_of(x, p)) L->occ[s][L->n_occ[s]++] = p;
+            else L->vir[s][L->n_vir[s]++] = p;
+        }
+    }
+}
+
+int64_t ora_n_connections(int K, int n_up, int n_dn) {
+    int64_t vu = K - n_up, vd = K - n_dn;
+    int64_t pu = (int64_t)n_up * (n_up - 1) / 2, pd = (int64_t)n_dn * (n_dn - 1) / 2;
+    return 1 + n_up * vu + n_dn * vd + pu * (vu * (vu - 1) / 2) + pd * (vd * (vd - 1) / 2) +
+           n_up * vu * n_dn * vd;
+}
+
+/* Enumerates the connected configurations of x in the canonical order
+ *   diagonal; singles up, singles down (occupied rank, virtual rank);
+ *   same-spin doubles up, down (occupied pair, virtual pair, each
+ *   lexicographic in rank); opposite-spin doubles (i_up, a_up, j_dn, b_dn).
+ * exc receives (i, j, a, b) as sorted spin-orbital indices, 255 where absent.
+ * Returns the number written. */
+static int64_t enumerate(int K, const uint64_t *x, uint64_t *xp, uint8_t *exc) {
+    orbital_lists L;
+    build_lists(K, x, &L);
+    int64_t c = 0;
+#define EMIT(I, J, A, B)                                                                     \
+    do {                                                                                     \
+        uint64_t y[2] = {x[0], x[1]};                                                        \
+        int e_[4] = {(I), (J), (A), (B)};                                                    \
+        for (int t_ = 0; t_ < 4; t_++)                                                       \
+            if (e_[t_] >= 0) flip_bit(y, e_[t_]);                                            \
+        xp[2 * c] = y[0];                                                                    \
+        xp[2 * c + 1] = y[1];                                                                \
+        if (exc) {                                                                           \
+            int lo = (I), hi = (J), al = (A), ah = (B);                                      \
+            if (hi >= 0 && hi < lo) { int t2 = lo; lo = hi; hi = t2; }                       \
+            if (ah >= 0 && ah < al) { int t2 = al; al = ah; ah = t2; }                       \
+            exc[4 * c + 0] = (uint8_t)(lo < 0 ? 255 : lo);                                   \
+            exc[4 * c + 1] = (uint8_t)(hi < 0 ? 255 : hi);                                   \
+            exc[4 * c + 2] = (uint8_t)(al < 0 ? 255 : al);                                   \
+            exc[4 * c + 3] = (uint8_t)(ah < 0 ? 255 : ah);                                   \
+        }                                                                                    \
+        c++;                                                                                 \
+    } while (0)
+    EMIT(-1, -1, -1, -1);
+    for (int s = 0; s < 2; s++)
+        for (int o = 0; o < L.n_occ[s]; o++)
+            for (int v = 0; v < L.n_vir[s]; v++) EMIT(L.occ[s][o], -1, L.vir[s][v], -1);
+    for (int s = 0; s < 2; s++)
+        for (int o1 = 0; o1 < L.n_occ[s]; o1++)
+            for (int o2 = o1 + 1; o2 < L.n_occ[s]; o2++)
+                for (int v1 = 0; v1 < L.n_vir[s]; v1++)
+                    for (int v2 = v1 + 1; v2 < L.n_vir[s]; v2++)
+                        EMIT(L.occ[s][o1], L.occ[s][o2], L.vir[s][v1], L.vir[s][v2]);
+    for (int ou = 0; ou < L.n_occ[0]; ou++)
+        for (int vu = 0; vu < L.n_vir[0]; vu++)
+            for (int od = 0; od < L.n_occ[1]; od++)
+                for (int vd = 0; vd < L.n_vir[1]; vd++)
+                    EMIT(L.occ[0][ou], L.occ[1][od], L.vir[0][vu], L.vir[1][vd]);
+#undef EMIT
+    return c;
+}
+
+/* Public: general matrix element <x'|H|x>; sign_out may be NULL. */
+double ora_hxx(int K, const double *h, const double *g, double ecore, const uint64_t *x,
+               const uint64_t *xp, int *sign_out) {
+    ora_ham H = {K, h, g, ecore};
+    int s;
+    double v = slater_condon(&H, x, xp, &s);
+    if (sign_out) *sign_out = s;
+    return v;
+}
+
+/* Public: all connections of one configuration, canonical order.  Returns the
+ * count, or -1 if x violates the particle numbers. */
+int64_t ora_connections(int K, int n_up, int n_dn, const double *h, const double *g, double ecore,
+                        const uint64_t *x, uint64_t *xp, int8_t *sign, uint8_t *exc, double *hxx) {
+    int nu = 0, nd = 0;
+    for (int i = 0; i < K; i++) {
+        nu += bit_of(x, 2 * i);
+        nd += bit_of(x, 2 * i + 1);
+    }
+    if (nu != n_up || nd != n_dn || popcount128(x) != nu + nd) return -1;
+    ora_ham H = {K, h, g, ecore};
+    int64_t C = enumerate(K, x, xp, exc);
+    for (int64_t c = 0; c < C; c++) {
+        int s;
+        double v = slater_condon(&H, x, xp + 2 * c, &s);
+        if (sign) sign[c] = (int8_t)s;
+        if (hxx) hxx[c] = v;
+    }
+    return C;
+}
+
+/* ------------------------------------------------ compensated summation */
+/* Neumaier's improved Kahan-Babuska summation. */
+typedef struct { double s, c; } neumaier;
+static void nsum_add(neumaier *a, double v) {
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+static double nsum_value(const neumaier *a) { return a->s + a->c; }
+
+/* ------------------------------------------------ sorted sample table */
+typedef struct {
+    uint64_t w0, w1;
+    double logabs, phase;
+} table_entry;
+
+/* unsigned 128-bit order, word 1 major */
+static int cmp_entry(const void *pa, const void *pb) {
+    const table_entry *a = (const table_entry *)pa, *b = (const table_entry *)pb;
+    if (a->w1 != b->w1) return a->w1 < b->w1 ? -1 : 1;
+    if (a->w0 != b->w0) return a->w0 < b->w0 ? -1 : 1;
+    return 0;
+}
+
+static table_entry *make_table(const uint64_t *tkeys, const double *tl, const double *tp, int64_t nt) {
+    table_entry *T = (table_entry *)malloc(sizeof(table_entry) * (size_t)(nt > 0 ? nt : 1));
+    for (int64_t i = 0; i < nt; i++) {
+        T[i].w0 = tkeys[2 * i];
+        T[i].w1 = tkeys[2 * i + 1];
+        T[i].logabs = tl[i];
+        T[i].phase = tp[i];
+    }
+    qsort(T, (size_t)nt, sizeof(table_entry), cmp_entry);
+    return T;
+}
+
+/* Public: sort a table (keys + payload) with the C library's qsort; used to
+ * check the device table build.  Returns 1 if the keys are unique, 0 if not. */
+int ora_sort_table(const uint64_t *tkeys, const double *tl, const double *tp, int64_t nt,
+                   uint64_t *keys_out, double *l_out, double *p_out) {
+    table_entry *T = make_table(tkeys, tl, tp, nt);
+    int unique = 1;
+    for (int64_t i = 0; i < nt; i++) {
+        keys_out[2 * i] = T[i].w0;
+        keys_out[2 * i + 1] = T[i].w1;
+        l_out[i] = T[i].logabs;
+        p_out[i] = T[i].phase;
+        if (i > 0 && cmp_entry(&T[i - 1], &T[i]) == 0) unique = 0;
+    }
+    free(T);
+    return unique;
+}
+
+/* Public: sample-aware local energies (x' restricted to the table).
+ * eloc[2*k] = Re, eloc[2*k+1] = Im; absum[k] (optional) receives
+ * sum |H_xx'| |psi(x')/psi(x)| over the hits, the scale used for tolerances.
+ * Returns 0, or -1 if a sample violates the particle numbers. */
+int ora_eloc_table(int K, int n_up, int n_dn, const double *h, const double *g, double ecore,
+                   const uint64_t *tkeys, const double *tlogabs, const double *tphase, int64_t nt,
+                   const uint64_t *keys, const double *logabs, const double *phase, int64_t n,
+                   double *eloc, double *absum, int nthreads) {
+    ora_ham H = {K, h, g, ecore};
+    table_entry *T = make_table(tkeys, tlogabs, tphase, nt);
+    int64_t C = ora_n_connections(K, n_up, n_dn);
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        uint64_t *xp = (uint64_t *)malloc(sizeof(uint64_t) * 2 * (size_t)C);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t k = 0; k < n; k++) {
+            const uint64_t *x = keys + 2 * k;
+            int nu = 0, nd = 0;
+            for (int i = 0; i < K; i++) {
+                nu += bit_of(x, 2 * i);
+                nd += bit_of(x, 2 * i + 1);
+            }
+            if (nu != n_up || nd != n_dn || popcount128(x) != nu + nd) {
+#pragma omp atomic write
+                bad = 1;
+                eloc[2 * k] = eloc[2 * k + 1] = NAN;
+                continue;
+            }
+            int64_t cnt = enumerate(K, x, xp, NULL);
+            neumaier re = {0, 0}, im = {0, 0}, ab = {0, 0};
+            for (int64_t c = 0; c < cnt; c++) {
+                table_entry probe = {xp[2 * c], xp[2 * c + 1], 0, 0};
+                const table_entry *hit =
+                    (const table_entry *)bsearch(&probe, T, (size_t)nt, sizeof(table_entry), cmp_entry);
+                if (!hit) continue;
+                int s;
+                double hv = slater_condon(&H, x, xp + 2 * c, &s);
+                double mag = exp(hit->logabs - logabs[k]);
+                double ang = hit->phase - phase[k];
+                nsum_add(&re, hv * mag * cos(ang));
+                nsum_add(&im, hv * mag * sin(ang));
+                nsum_add(&ab, fabs(hv) * mag);
+            }
+            eloc[2 * k] = nsum_value(&re);
+            eloc[2 * k + 1] = nsum_value(&im);
+            if (absum) absum[k] = nsum_value(&ab);
+        }
+        free(xp);
+    }
+    free(T);
+    return bad ? -1 : 0;
+}
+
+/* Public: weighted energy of Eq. 6 over unique samples with occurrence
+ * counts: out = {sum c Re / sum c, sum c Im / sum c, sum c,
+ *                sum c (Re - E)^2 / sum c}. */
+void ora_energy(const uint32_t *counts, const double *eloc, int64_t n, double *out) {
+    neumaier w = {0, 0}, re = {0, 0}, im = {0, 0};
+    for (int64_t k = 0; k < n; k++) {
+        double c = (double)counts[k];
+        nsum_add(&w, c);
+        nsum_add(&re, c * eloc[2 * k]);
+        nsum_add(&im, c * eloc[2 * k + 1]);
+    }
+    double W = nsum_value(&w);
+    double E = nsum_value(&re) / W;
+    neumaier var = {0, 0};
+    for (int64_t k = 0; k < n; k++) {
+        double d = eloc[2 * k] - E;
+        nsum_add(&var, (double)counts[k] * d * d);
+    }
+    out[0] = E;
+    out[1] = nsum_value(&im) / W;
+    out[2] = W;
+    out[3] = nsum_value(&var) / W;
+}

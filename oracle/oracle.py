@@ -1,0 +1,149 @@
+"""ctypes binding of the plain-C FP64 oracle (test infrastructure only).
+
+The C source ``nnqs_oracle.c`` follows the paper's definitions: Eq. 4 (local
+energy), Eq. 6 (sample mean over unique samples weighted by their counts,
+Section 3.1), Eq. 9 (second-quantised Hamiltonian) and Section 3.4 items 4-5
+(sample-aware evaluation over a sorted table of packed integer keys).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = [os.path.join(_HERE, "nnqs_oracle.c")]
+_LIB = os.path.join(_HERE, "libnnqs_oracle.so")
+_lib = None
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_i8p = ctypes.POINTER(ctypes.c_int8)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_f32p = ctypes.POINTER(ctypes.c_float)
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build() -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wno-unknown-pragmas",
+           "-o", _LIB + ".tmp", *_SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or any(os.path.getmtime(s) > os.path.getmtime(_LIB) for s in _SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    lib.ora_n_connections.restype = ctypes.c_int64
+    lib.ora_n_connections.argtypes = [ctypes.c_int] * 3
+    lib.ora_hxx.restype = ctypes.c_double
+    lib.ora_hxx.argtypes = [ctypes.c_int, _f64p, _f64p, ctypes.c_double, _u64p, _u64p,
+                            ctypes.POINTER(ctypes.c_int)]
+    lib.ora_connections.restype = ctypes.c_int64
+    lib.ora_connections.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _f64p, _f64p, ctypes.c_double,
+                                    _u64p, _u64p, _i8p, _u8p, _f64p]
+    lib.ora_sort_table.restype = ctypes.c_int
+    lib.ora_sort_table.argtypes = [_u64p, _f64p, _f64p, ctypes.c_int64, _u64p, _f64p, _f64p]
+    lib.ora_eloc_table.restype = ctypes.c_int
+    lib.ora_eloc_table.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _f64p, _f64p, ctypes.c_double,
+                                   _u64p, _f64p, _f64p, ctypes.c_int64,
+                                   _u64p, _f64p, _f64p, ctypes.c_int64, _f64p, _f64p, ctypes.c_int]
+    lib.ora_energy.restype = None
+    lib.ora_energy.argtypes = [_u32p, _f64p, ctypes.c_int64, _f64p]
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def n_connections(K: int, n_up: int, n_dn: int) -> int:
+    return int(_load().ora_n_connections(K, n_up, n_dn))
+
+
+def hxx(K, h, g, e_core, x, xp):
+    """``<x'|H|x>`` and the sign of the excitation operator on ``x``."""
+    h, g = _c(h, np.float64), _c(g, np.float64)
+    x, xp = _c(x, np.uint64), _c(xp, np.uint64)
+    s = ctypes.c_int(0)
+    v = _load().ora_hxx(K, _p(h, _f64p), _p(g, _f64p), float(e_core), _p(x, _u64p), _p(xp, _u64p),
+                        ctypes.byref(s))
+    return v, s.value
+
+
+def connections(K, n_up, n_dn, h, g, e_core, x):
+    """Canonical-order connections of one configuration: ``(xp[C,2], sign[C],
+    exc[C,4], hxx[C])``."""
+    lib = _load()
+    C = n_connections(K, n_up, n_dn)
+    h, g, x = _c(h, np.float64), _c(g, np.float64), _c(x, np.uint64)
+    xp = np.zeros((C, 2), np.uint64)
+    sign = np.zeros(C, np.int8)
+    exc = np.zeros((C, 4), np.uint8)
+    hv = np.zeros(C, np.float64)
+    r = lib.ora_connections(K, n_up, n_dn, _p(h, _f64p), _p(g, _f64p), float(e_core), _p(x, _u64p),
+                            _p(xp, _u64p), _p(sign, _i8p), _p(exc, _u8p), _p(hv, _f64p))
+    if r < 0:
+        raise ValueError("configuration violates the particle numbers")
+    assert r == C
+    return xp, sign, exc, hv
+
+
+def sort_table(keys, logabs, phase):
+    """Sorted copy of a table (qsort, unsigned 128-bit order, word 1 major)
+    and whether its keys are unique."""
+    keys, logabs, phase = _c(keys, np.uint64), _c(logabs, np.float64), _c(phase, np.float64)
+    n = logabs.shape[0]
+    ko = np.zeros((n, 2), np.uint64)
+    lo = np.zeros(n, np.float64)
+    po = np.zeros(n, np.float64)
+    u = _load().ora_sort_table(_p(keys, _u64p), _p(logabs, _f64p), _p(phase, _f64p), n,
+                               _p(ko, _u64p), _p(lo, _f64p), _p(po, _f64p))
+    return ko, lo, po, bool(u)
+
+
+def eloc_table(K, n_up, n_dn, h, g, e_core, tkeys, tlogabs, tphase, keys, logabs, phase,
+               nthreads: int = 0, with_absum: bool = False):
+    """Sample-aware local energies ``complex128[n]`` (and optionally the
+    per-sample scale ``sum |H| |psi'/psi|``)."""
+    lib = _load()
+    h, g = _c(h, np.float64), _c(g, np.float64)
+    tkeys, tlogabs, tphase = _c(tkeys, np.uint64), _c(tlogabs, np.float64), _c(tphase, np.float64)
+    keys, logabs, phase = _c(keys, np.uint64), _c(logabs, np.float64), _c(phase, np.float64)
+    n = logabs.shape[0]
+    out = np.zeros((n, 2), np.float64)
+    ab = np.zeros(n, np.float64)
+    r = lib.ora_eloc_table(K, n_up, n_dn, _p(h, _f64p), _p(g, _f64p), float(e_core),
+                           _p(tkeys, _u64p), _p(tlogabs, _f64p), _p(tphase, _f64p), tlogabs.shape[0],
+                           _p(keys, _u64p), _p(logabs, _f64p), _p(phase, _f64p), n,
+                           _p(out, _f64p), _p(ab, _f64p), int(nthreads))
+    if r < 0:
+        raise ValueError("a sample violates the particle numbers")
+    e = out[:, 0] + 1j * out[:, 1]
+    return (e, ab) if with_absum else e
+
+
+def energy(counts, eloc):
+    """``[E_re, E_im, sum_w, var]`` of Eq. 6 with occurrence counts."""
+    counts = _c(counts, np.uint32)
+    e = np.ascontiguousarray(np.stack([np.real(eloc), np.imag(eloc)], axis=1), dtype=np.float64)
+    out = np.zeros(4, np.float64)
+    _load().ora_energy(_p(counts, _u32p), _p(e, _f64p), counts.shape[0], _p(out, _f64p))
+    return out
