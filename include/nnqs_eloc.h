@@ -1,0 +1,194 @@
+/*
+ * nnqs_eloc.h -- C ABI of the MI355X (gfx950) local-energy library.
+ *
+ * The library evaluates the local energy of a neural-network quantum state
+ * for a second-quantised molecular Hamiltonian (paper: Section 2.1, Eq. 4):
+ *
+ *     E_loc(x) = sum_{x'} H_{x x'} psi(x') / psi(x),
+ *
+ * over a batch of unique sampled occupation bit strings x, and the sample
+ * mean of Eq. 6 weighted by each unique sample's occurrence count (Section
+ * 3.1, batch autoregressive sampling keeps unique samples with weights).
+ * The Hamiltonian is Eq. 9 (Section 2.3), given by its one- and two-electron
+ * integrals; connected configurations x' are single and double excitations
+ * that conserve the up and down electron numbers (Eq. 12 constraint).
+ *
+ * Conventions used by every entry point:
+ *  - K spatial orbitals, N = 2K spin orbitals (4 <= N <= 128, N even);
+ *    spin orbital p = 2*i + s, s = 0 up, s = 1 down (Section 3.3: spatial
+ *    orbital i maps to an adjacent up/down qubit pair).
+ *  - A configuration is a 128-bit key of two uint64 words, key[0] holding
+ *    bits 0..63 and key[1] bits 64..127; bit p = occupation of spin orbital p
+ *    (Section 3.4 item 5: samples packed into one or two integers).  Keys of
+ *    N <= 64 systems have key[1] == 0.  Tables are ordered as unsigned
+ *    128-bit integers, key[1] major.
+ *  - Jordan-Wigner strings run over lower indices:
+ *      a_p |x> = x_p (-1)^{#occupied q<p} |x - e_p>.
+ *  - Integrals are spatial, chemists' notation, row-major doubles:
+ *      h[i*K + j],  g[((i*K + j)*K + k)*K + l] = (ij|kl)  (8-fold symmetric),
+ *    so that H = E_core + sum h_pq a+_p a_q
+ *              + 1/2 sum <pq|rs> a+_p a+_q a_s a_r,
+ *    <pq|rs> = (i_p i_r|i_q i_s) when spins of (p,r) and of (q,s) agree.
+ *  - Amplitudes travel in log-polar form: psi(x) = exp(logabs + i*phase).
+ *    Complex outputs are interleaved (re, im) doubles.
+ *  - Device pointers are HIP device (or managed) memory on the current
+ *    device; host pointers are marked "host".  The caller owns every pointer
+ *    it passes.  Objects created by *_create own their device memory until
+ *    the matching *_destroy.  No entry point allocates caller-visible output.
+ *  - `stream` is a hipStream_t cast to void* (NULL = the null stream).  All
+ *    device work is enqueued asynchronously on it; entry points return after
+ *    enqueueing unless they say they synchronise.
+ *  - Errors are reported by return code (nnqs_status) and a thread-local
+ *    message (nnqs_last_error).  Host-side checks run before anything is
+ *    enqueued; on such an error no output is touched.
+ */
+#ifndef NNQS_ELOC_H
+#define NNQS_ELOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nnqs_status;
+
+enum {
+    NNQS_OK = 0,
+    NNQS_EINVAL = -1,       /* bad argument: null pointer, size, N odd or > 128, n_s > K */
+    NNQS_EDUP = -2,         /* a table holds the same key twice */
+    NNQS_ECONSERVE = -3,    /* a key has the wrong number of up or down electrons */
+    NNQS_ERANGE = -4,       /* a log-amplitude is not finite, or a size exceeds a capacity */
+    NNQS_ENOMEM = -5,       /* device allocation failed */
+    NNQS_EHIP = -6,         /* a HIP runtime call failed */
+    NNQS_EUNSUPPORTED = -7  /* no gfx950 GPU, or a kernel build that spills to private memory */
+};
+
+/* Flags for calls that read device-resident inputs. */
+enum {
+    /* Validate the device inputs before computing: the call synchronises
+     * `stream`, returns NNQS_ECONSERVE / NNQS_ERANGE / NNQS_EDUP if the check
+     * fails and then leaves every output untouched.  Without this flag the
+     * call never synchronises (it can be captured in a HIP graph); invalid
+     * samples then get NaN outputs and set the sticky device status that
+     * nnqs_table_status reports. */
+    NNQS_VALIDATE = 1u
+};
+
+/* Message of the last failing call on this thread ("" if none).  Valid
+ * until the next call on the same thread. */
+const char *nnqs_last_error(void);
+
+/* Library version string. */
+const char *nnqs_version(void);
+
+/* ------------------------------------------------------------------ system */
+/* Molecular Hamiltonian of Eq. 9 resident on the current device. */
+typedef struct nnqs_system nnqs_system;
+
+/* Copies the integrals (host arrays, layouts above) to the device and
+ * precomputes the diagonal Coulomb/exchange tables.
+ *   n_spin_orb: N, even, 4..128;  n_up, n_dn: electrons per spin, 0..K.
+ * Synchronous.  Errors: EINVAL, ENOMEM, EHIP, EUNSUPPORTED. */
+nnqs_status nnqs_system_create(nnqs_system **out, int32_t n_spin_orb, int32_t n_up, int32_t n_dn,
+                               const double *h, const double *g, double e_core);
+
+/* Releases the device copies.  NULL is accepted. */
+nnqs_status nnqs_system_destroy(nnqs_system *sys);
+
+/* Number C of connected configurations per sample, the diagonal included:
+ * C = 1 + n_u v_u + n_d v_d + C(n_u,2) C(v_u,2) + C(n_d,2) C(v_d,2)
+ *       + n_u v_u n_d v_d,  v_s = K - n_s.  Returns -1 for NULL. */
+int64_t nnqs_connection_count(const nnqs_system *sys);
+
+/* -------------------------------------------------------------------- table */
+/* Sorted table of unique samples with their amplitudes (Section 3.4 item 5:
+ * the id and wave-function lookup tables), plus the device-side search
+ * structures of the sample-aware lookup. */
+typedef struct nnqs_table nnqs_table;
+
+/* Allocates a table for up to `capacity` samples of `sys` (which must
+ * outlive it).  Synchronous.  Errors: EINVAL, ENOMEM, EHIP. */
+nnqs_status nnqs_table_create(nnqs_table **out, const nnqs_system *sys, int64_t capacity);
+
+/* Releases the table.  NULL is accepted. */
+nnqs_status nnqs_table_destroy(nnqs_table *tab);
+
+/* Builds the table from n samples (device arrays): keys [n][2], logabs [n],
+ * phase [n].  Sorts the keys (payload permuted alongside), and builds the
+ * search structures.  Duplicate keys set the sticky status NNQS_EDUP.
+ * flags: NNQS_VALIDATE (see above).  Errors: EINVAL, ERANGE (n > capacity),
+ * EDUP / ECONSERVE / ERANGE with NNQS_VALIDATE, EHIP. */
+nnqs_status nnqs_table_build(nnqs_table *tab, const uint64_t *keys, const double *logabs,
+                             const double *phase, int64_t n, uint32_t flags, void *stream);
+
+/* Copies the sorted table into device arrays keys_out [n][2], logabs_out [n],
+ * phase_out [n] (n = current size, written to *n_out on the host).
+ * Synchronises `stream`.  For tests. */
+nnqs_status nnqs_table_export(const nnqs_table *tab, uint64_t *keys_out, double *logabs_out,
+                              double *phase_out, int64_t *n_out, void *stream);
+
+/* Synchronises `stream`, then returns and clears the sticky device status
+ * set by earlier builds / evaluations on this table (NNQS_OK if none). */
+nnqs_status nnqs_table_status(nnqs_table *tab, void *stream);
+
+/* ------------------------------------------------------------ enumeration */
+/* Connected configurations of n samples in canonical order (for parity
+ * checks): diagonal; singles up then down, (occupied rank, virtual rank);
+ * same-spin doubles up then down, (occupied pair, virtual pair), pairs in
+ * lexicographic rank order; opposite-spin doubles (i_up, a_up, j_dn, b_dn).
+ * Outputs are device arrays of n*C entries (C = nnqs_connection_count):
+ *   xprime [n][C][2] keys of x';
+ *   sign   [n][C]    sign of the excitation operator a+_a a+_b a_j a_i
+ *                    (i<j, a<b) or a+_p a_q acting on x, +1 on the diagonal;
+ *   exc    [n][C][4] spin-orbital indices (i, j, a, b) sorted, 255 absent;
+ *   hxx    [n][C]    H_{x x'} (sign included).
+ * Any output pointer may be NULL to skip it.  Samples with wrong particle
+ * numbers get sign 0 and NaN hxx.  Errors: EINVAL, ECONSERVE (VALIDATE). */
+nnqs_status nnqs_connections(const nnqs_system *sys, const uint64_t *keys, int64_t n,
+                             uint64_t *xprime, int8_t *sign, uint8_t *exc, double *hxx,
+                             uint32_t flags, void *stream);
+
+/* -------------------------------------------------- sample-aware E_loc */
+/* Local energies of n samples with psi(x') taken from the table and x'
+ * outside the table skipped (Section 3.4 item 4, sample-aware evaluation;
+ * Algorithm 2 fuses the lookup with the accumulation).  Inputs (device):
+ * keys [n][2], counts [n] occurrence weights, logabs [n], phase [n] of the
+ * samples themselves.  Outputs (device): eloc [n][2] complex E_loc(x);
+ * energy [4] = { sum c Re E_loc / sum c, sum c Im E_loc / sum c, sum c,
+ * sum c (Re E_loc - E)^2 / sum c } (Eq. 6 over unique samples); energy may
+ * be NULL.  Matrix elements, ratios and sums are FP64; per-sample sums are
+ * compensated (Neumaier) and the reduction order is fixed, so repeated
+ * calls give bit-identical results.  Calls sharing one table must be ordered
+ * on one stream (the energy reduction uses the table's scratch).
+ * Errors: EINVAL, ECONSERVE / ERANGE (VALIDATE), EHIP. */
+nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint64_t *keys,
+                            const uint32_t *counts, const double *logabs, const double *phase,
+                            int64_t n, double *eloc, double *energy, uint32_t flags, void *stream);
+
+/* Weighted energy of Eq. 6 alone from precomputed local energies (device
+ * arrays counts [n], eloc [n][2]) into energy [4] (layout as above), using
+ * the table's scratch.  Errors: EINVAL, EHIP. */
+nnqs_status nnqs_energy(nnqs_table *tab, const uint32_t *counts, const double *eloc, int64_t n,
+                        double *energy, void *stream);
+
+/* ------------------------------------------------------------- tuning */
+/* Launch parameters of the sample-aware kernel (0 = library default). */
+typedef struct {
+    int32_t waves_per_block;   /* 1..16 (the sample-aware kernel uses at most 12) */
+    int32_t blocks_per_cu;     /* grid = blocks_per_cu * CU count */
+    int32_t filter_log2_bits;  /* LDS membership filter size, 10..20 (2^k bits) */
+    int32_t splitter_levels;   /* binary-search levels staged in LDS, 0..13 */
+} nnqs_tune;
+
+/* Sets the launch parameters used by later nnqs_eloc_table calls on `tab`.
+ * NULL restores the defaults.  Errors: EINVAL (out of range). */
+nnqs_status nnqs_table_set_tune(nnqs_table *tab, const nnqs_tune *tune);
+
+/* Reads back the parameters in use. */
+nnqs_status nnqs_table_get_tune(const nnqs_table *tab, nnqs_tune *tune);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNQS_ELOC_H */

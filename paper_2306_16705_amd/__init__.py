@@ -1,0 +1,17 @@
+"""MI355X-native local-energy library for neural-network quantum states.
+
+Python face of ``libnnqs_eloc.so``: thin wrappers with the names of the C ABI
+(``include/nnqs_eloc.h``) that marshal torch device tensors and streams.
+All computation happens in the HIP kernels of the library; there is no
+fallback path.
+"""
+from .api import (  # noqa: F401
+    NNQSError,
+    NNQS_VALIDATE,
+    System,
+    Table,
+    connections,
+    eloc_table,
+    energy,
+    version,
+)

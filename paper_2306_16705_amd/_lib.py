@@ -1,0 +1,79 @@
+"""ctypes binding of ``libnnqs_eloc.so`` (argument marshalling only).
+
+Every entry point of ``include/nnqs_eloc.h`` is declared here with the same
+name.  Device buffers are torch tensors on the current HIP device; streams
+are torch streams.  Nothing here computes any part of the method.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnnqs_eloc.so")
+
+_c_void_p = ctypes.c_void_p
+_i32, _i64, _u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+_f64 = ctypes.c_double
+
+# (restype, argtypes) of every exported symbol.
+SIGNATURES = {
+    "nnqs_last_error": (ctypes.c_char_p, []),
+    "nnqs_version": (ctypes.c_char_p, []),
+    "nnqs_system_create": (_i32, [ctypes.POINTER(_c_void_p), _i32, _i32, _i32, _c_void_p, _c_void_p, _f64]),
+    "nnqs_system_destroy": (_i32, [_c_void_p]),
+    "nnqs_connection_count": (_i64, [_c_void_p]),
+    "nnqs_table_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p, _i64]),
+    "nnqs_table_destroy": (_i32, [_c_void_p]),
+    "nnqs_table_build": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _u32, _c_void_p]),
+    "nnqs_table_export": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, ctypes.POINTER(_i64), _c_void_p]),
+    "nnqs_table_status": (_i32, [_c_void_p, _c_void_p]),
+    "nnqs_connections": (_i32, [_c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _u32,
+                                _c_void_p]),
+    "nnqs_eloc_table": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p,
+                               _c_void_p, _u32, _c_void_p]),
+    "nnqs_energy": (_i32, [_c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p]),
+    "nnqs_table_set_tune": (_i32, [_c_void_p, _c_void_p]),
+    "nnqs_table_get_tune": (_i32, [_c_void_p, _c_void_p]),
+}
+
+STATUS_NAMES = {0: "NNQS_OK", -1: "NNQS_EINVAL", -2: "NNQS_EDUP", -3: "NNQS_ECONSERVE", -4: "NNQS_ERANGE",
+                -5: "NNQS_ENOMEM", -6: "NNQS_EHIP", -7: "NNQS_EUNSUPPORTED"}
+NNQS_VALIDATE = 1
+
+
+class NNQSError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        self.code = code
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("waves_per_block", _i32), ("blocks_per_cu", _i32), ("filter_log2_bits", _i32),
+                ("splitter_levels", _i32)]
+
+
+_lib = None
+
+
+def load():
+    """Load the built library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2306_16705_amd.build.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(code: int) -> None:
+    if code != 0:
+        msg = load().nnqs_last_error().decode(errors="replace")
+        raise NNQSError(code, msg)

@@ -1,0 +1,179 @@
+"""Object wrappers over the C ABI (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import NNQS_VALIDATE, NNQSError, Tune  # noqa: F401
+
+_KEY_DTYPES = (torch.int64, torch.uint64)
+
+
+def version() -> str:
+    return L.load().nnqs_version().decode()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, name, dtypes, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+class System:
+    """Hamiltonian of Eq. 9 on the current device (``nnqs_system_*``)."""
+
+    def __init__(self, n_spin_orb: int, n_up: int, n_dn: int, h, g, e_core: float = 0.0):
+        K = n_spin_orb // 2
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        if h.shape != (K, K) or g.shape != (K, K, K, K):
+            raise ValueError("h must be [K, K] and g [K, K, K, K]")
+        self._lib = L.load()
+        out = ctypes.c_void_p()
+        L.check(self._lib.nnqs_system_create(ctypes.byref(out), n_spin_orb, n_up, n_dn,
+                                             h.ctypes.data_as(ctypes.c_void_p), g.ctypes.data_as(ctypes.c_void_p),
+                                             float(e_core)))
+        self.handle = out
+        self.n_spin_orb, self.n_up, self.n_dn, self.K = n_spin_orb, n_up, n_dn, K
+
+    @property
+    def connection_count(self) -> int:
+        return int(self._lib.nnqs_connection_count(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.nnqs_system_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Table:
+    """Sorted unique-sample table (``nnqs_table_*``)."""
+
+    def __init__(self, system: System, capacity: int):
+        self._lib = L.load()
+        self.system = system
+        out = ctypes.c_void_p()
+        L.check(self._lib.nnqs_table_create(ctypes.byref(out), system.handle, int(capacity)))
+        self.handle = out
+        self.capacity = int(capacity)
+
+    def build(self, keys, logabs, phase, validate: bool = False, stream=None):
+        n = keys.shape[0]
+        _need(keys, "keys", _KEY_DTYPES, (n, 2))
+        _need(logabs, "logabs", (torch.float64,), (n,))
+        _need(phase, "phase", (torch.float64,), (n,))
+        L.check(self._lib.nnqs_table_build(self.handle, _ptr(keys), _ptr(logabs), _ptr(phase), n,
+                                           NNQS_VALIDATE if validate else 0, _stream(stream)))
+        return self
+
+    def export(self, stream=None):
+        dev = torch.device("cuda", torch.cuda.current_device())
+        keys = torch.empty((self.capacity, 2), dtype=torch.int64, device=dev)
+        la = torch.empty(self.capacity, dtype=torch.float64, device=dev)
+        ph = torch.empty(self.capacity, dtype=torch.float64, device=dev)
+        n = ctypes.c_int64(0)
+        L.check(self._lib.nnqs_table_export(self.handle, _ptr(keys), _ptr(la), _ptr(ph), ctypes.byref(n),
+                                            _stream(stream)))
+        m = n.value
+        return keys[:m], la[:m], ph[:m]
+
+    def status(self, stream=None) -> int:
+        return int(self._lib.nnqs_table_status(self.handle, _stream(stream)))
+
+    def set_tune(self, waves_per_block=0, blocks_per_cu=0, filter_log2_bits=0, splitter_levels=0):
+        t = Tune(waves_per_block, blocks_per_cu, filter_log2_bits, splitter_levels)
+        L.check(self._lib.nnqs_table_set_tune(self.handle, ctypes.byref(t)))
+
+    def get_tune(self) -> dict:
+        t = Tune()
+        L.check(self._lib.nnqs_table_get_tune(self.handle, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in Tune._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.nnqs_table_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def connections(system: System, keys, validate: bool = False, stream=None):
+    """Canonical-order connections of every sample: dict of device tensors
+    ``xprime [n, C, 2] int64``, ``sign [n, C] int8``, ``exc [n, C, 4] uint8``,
+    ``hxx [n, C] float64`` (``nnqs_connections``)."""
+    n = keys.shape[0]
+    _need(keys, "keys", _KEY_DTYPES, (n, 2))
+    C = system.connection_count
+    dev = keys.device
+    out = dict(xprime=torch.empty((n, C, 2), dtype=torch.int64, device=dev),
+               sign=torch.empty((n, C), dtype=torch.int8, device=dev),
+               exc=torch.empty((n, C, 4), dtype=torch.uint8, device=dev),
+               hxx=torch.empty((n, C), dtype=torch.float64, device=dev))
+    L.check(L.load().nnqs_connections(system.handle, _ptr(keys), n, _ptr(out["xprime"]), _ptr(out["sign"]),
+                                      _ptr(out["exc"]), _ptr(out["hxx"]), NNQS_VALIDATE if validate else 0,
+                                      _stream(stream)))
+    return out
+
+
+def eloc_table(system: System, table: Table, keys, counts, logabs, phase, eloc=None, energy=None,
+               with_energy: bool = True, validate: bool = False, stream=None):
+    """Sample-aware local energies (``nnqs_eloc_table``).  Returns
+    ``(eloc [n, 2] float64, energy [4] float64 or None)``."""
+    n = keys.shape[0]
+    _need(keys, "keys", _KEY_DTYPES, (n, 2))
+    _need(logabs, "logabs", (torch.float64,), (n,))
+    _need(phase, "phase", (torch.float64,), (n,))
+    if counts is not None:
+        _need(counts, "counts", (torch.int32, torch.uint32), (n,))
+    if eloc is None:
+        eloc = torch.empty((n, 2), dtype=torch.float64, device=keys.device)
+    _need(eloc, "eloc", (torch.float64,), (n, 2))
+    if with_energy and energy is None:
+        energy = torch.empty(4, dtype=torch.float64, device=keys.device)
+    if energy is not None:
+        _need(energy, "energy", (torch.float64,), (4,))
+    L.check(L.load().nnqs_eloc_table(system.handle, table.handle, _ptr(keys), _ptr(counts), _ptr(logabs),
+                                     _ptr(phase), n, _ptr(eloc), _ptr(energy) if with_energy else None,
+                                     NNQS_VALIDATE if validate else 0, _stream(stream)))
+    return eloc, (energy if with_energy else None)
+
+
+def energy(table: Table, counts, eloc, out=None, stream=None):
+    """Weighted energy of Eq. 6 from precomputed local energies (``nnqs_energy``)."""
+    n = eloc.shape[0]
+    _need(counts, "counts", (torch.int32, torch.uint32), (n,))
+    _need(eloc, "eloc", (torch.float64,), (n, 2))
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=eloc.device)
+    L.check(L.load().nnqs_energy(table.handle, _ptr(counts), _ptr(eloc), n, _ptr(out), _stream(stream)))
+    return out

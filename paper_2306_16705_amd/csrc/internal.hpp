@@ -1,0 +1,267 @@
+// Internal definitions shared by the translation units of libnnqs_eloc.
+// Device helpers for 128-bit occupation keys, Jordan-Wigner signs and
+// Slater-Condon matrix elements of the Hamiltonian of Eq. 9.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "nnqs_eloc.h"
+
+namespace nnqs {
+
+// ------------------------------------------------------------------ errors
+nnqs_status fail(nnqs_status code, const char *fmt, ...);
+void clear_error();
+
+#define NNQS_HIP_CHECK(call)                                                              \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::nnqs::fail(NNQS_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------ device-side views
+// Everything a kernel needs about the Hamiltonian, passed by value.
+struct SysView {
+    int K, N, n_up, n_dn;
+    int64_t C;               // connections per sample, diagonal included
+    const double *h;         // [K*K]
+    const double *g;         // [K^4] chemists' (ij|kl)
+    const double *Jm;        // [K*K] (ii|jj)
+    const double *Km;        // [K*K] (ij|ji)
+    const uint64_t *hashT;   // [128] per-spin-orbital hash words (GF(2)-linear hash)
+    double ecore;
+    uint64_t valid0, valid1; // masks of the N valid key bits
+};
+
+// Sorted sample table as seen by kernels.
+struct TableView {
+    const uint64_t *keys;    // [n][2] sorted ascending (word 1 major)
+    const double *logabs;    // [n]
+    const double *phase;     // [n]
+    const uint32_t *filter;  // membership filter, 2^filter_log2 bits
+    const uint64_t *split;   // [2^split_levels - 1][2] staged search keys
+    int64_t n;
+    int log2n;               // ceil(log2(n)), 0 for n == 1
+    int filter_log2;         // bits of the filter = 2^filter_log2
+    int split_levels;        // levels of the search tree staged in LDS
+};
+
+constexpr uint64_t EVEN_BITS = 0x5555555555555555ull;
+constexpr uint64_t ODD_BITS = 0xAAAAAAAAAAAAAAAAull;
+
+// Sticky device status: first error wins.
+__device__ inline void set_status(int *status, int code) {
+    if (status) atomicCAS(status, 0, code);
+}
+
+// ---------------------------------------------------------- 128-bit keys
+struct Key {
+    uint64_t lo, hi;
+};
+
+__device__ __forceinline__ bool key_less(const Key &a, const Key &b) {
+    return (a.hi < b.hi) || (a.hi == b.hi && a.lo < b.lo);
+}
+__device__ __forceinline__ bool key_eq(const Key &a, const Key &b) { return a.lo == b.lo && a.hi == b.hi; }
+
+__device__ __forceinline__ void key_flip(Key &k, int p) {
+    uint64_t m = 1ull << (p & 63);
+    if (p < 64) k.lo ^= m;
+    else k.hi ^= m;
+}
+
+__device__ __forceinline__ int key_bit(const Key &k, int p) {
+    return (int)(((p < 64 ? k.lo : k.hi) >> (p & 63)) & 1ull);
+}
+
+// popcount of the bits of k strictly below position p (0 <= p <= 128)
+__device__ __forceinline__ int popc_below(const Key &k, int p) {
+    if (p <= 0) return 0;
+    if (p < 64) return __popcll(k.lo & ((1ull << p) - 1ull));
+    if (p == 64) return __popcll(k.lo);
+    int q = p - 64;
+    uint64_t mh = (q >= 64) ? ~0ull : ((1ull << q) - 1ull);
+    return __popcll(k.lo) + __popcll(k.hi & mh);
+}
+
+// -------------------------------------------------- Hamiltonian elements
+__device__ __forceinline__ double g_at(const SysView &S, int i, int j, int k, int l) {
+    const int K = S.K;
+    return S.g[(((size_t)i * K + j) * K + k) * K + l];
+}
+
+// <pq|rs> over spin orbitals = (i_p i_r | i_q i_s) if spins of (p,r), (q,s) agree
+__device__ __forceinline__ double phys_el(const SysView &S, int p, int q, int r, int s) {
+    if (((p ^ r) & 1) | ((q ^ s) & 1)) return 0.0;
+    return g_at(S, p >> 1, r >> 1, q >> 1, s >> 1);
+}
+
+// Diagonal element <x|H|x>, evaluated by one lane (loops over occupied orbitals).
+__device__ inline double diag_element(const SysView &S, const Key &x) {
+    double e = S.ecore;
+    const int K = S.K;
+    for (int p = 0; p < S.N; p++) {
+        if (!key_bit(x, p)) continue;
+        const int ip = p >> 1;
+        double acc = S.h[ip * K + ip];
+        for (int q = 0; q < S.N; q++) {
+            if (!key_bit(x, q)) continue;
+            const int iq = q >> 1;
+            double v = S.Jm[ip * K + iq];
+            if (((p ^ q) & 1) == 0) v -= S.Km[ip * K + iq];
+            acc += 0.5 * v;
+        }
+        e += acc;
+    }
+    return e;
+}
+
+// Sign parity of a+_p a_q acting on x (q occupied, p empty, p != q): the
+// number of occupied orbitals strictly between them.
+__device__ __forceinline__ int single_parity(const Key &x, int q, int p) {
+    int lo = q < p ? q : p, hi = q < p ? p : q;
+    return (popc_below(x, hi) - popc_below(x, lo + 1)) & 1;
+}
+
+// Sign parity of a+_a a+_b a_j a_i acting on x, with i<j occupied and a<b empty.
+__device__ __forceinline__ int double_parity(const Key &x, int i, int j, int a, int b) {
+    Key y = x;
+    int par = popc_below(y, i);
+    key_flip(y, i);
+    par += popc_below(y, j);
+    key_flip(y, j);
+    par += popc_below(y, b);
+    key_flip(y, b);
+    par += popc_below(y, a);
+    return par & 1;
+}
+
+// Single-excitation element (without the sign): h_pq + sum_{k in x}
+// [(pq|kk) - delta(s_k, s_p) (pk|kq)], spatial indices of p, q.
+__device__ inline double single_element(const SysView &S, const Key &x, int q, int p) {
+    const int K = S.K;
+    const int ip = p >> 1, iq = q >> 1, sp = p & 1;
+    double v = S.h[ip * K + iq];
+    for (int w = 0; w < 2; w++) {
+        uint64_t m = w ? x.hi : x.lo;
+        while (m) {
+            int b = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            int k = w * 64 + b;
+            int ik = k >> 1;
+            double t = g_at(S, ip, iq, ik, ik);
+            if ((k & 1) == sp) t -= g_at(S, ip, ik, ik, iq);
+            v += t;
+        }
+    }
+    return v;
+}
+
+// Full element <x'|H|x> for an excitation given by raw indices: i == 255 is
+// the diagonal (value `diag`), j == 255 a single q=i -> p=a, otherwise a
+// double removing {i, j} and adding {a, b} (any order).  *sign_out gets +-1.
+__device__ inline double excitation_element(const SysView &S, const Key &x, double diag, int i, int j, int a,
+                                            int b, int *sign_out) {
+    if (i == 255) {
+        *sign_out = 1;
+        return diag;
+    }
+    if (j == 255) {
+        int s = single_parity(x, i, a) ? -1 : 1;
+        *sign_out = s;
+        return s * single_element(S, x, i, a);
+    }
+    int i0 = i < j ? i : j, j0 = i < j ? j : i;
+    int a0 = a < b ? a : b, b0 = a < b ? b : a;
+    int s = double_parity(x, i0, j0, a0, b0) ? -1 : 1;
+    *sign_out = s;
+    return s * (phys_el(S, a0, b0, i0, j0) - phys_el(S, a0, b0, j0, i0));
+}
+
+// -------------------------------------------------- compensated summation
+struct NSum {  // Neumaier
+    double s, c;
+    __device__ __forceinline__ void add(double v) {
+        double t = s + v;
+        if (fabs(s) >= fabs(v)) c += (s - t) + v;
+        else c += (v - t) + s;
+        s = t;
+    }
+};
+
+// Combine two compensated partial sums exactly up to the final rounding
+// (Knuth's TwoSum on the leading parts).
+__device__ __forceinline__ void nsum_merge(double &s, double &c, double s2, double c2) {
+    double t = s + s2;
+    double bp = t - s;
+    double ap = t - bp;
+    double err = (s - ap) + (s2 - bp);
+    s = t;
+    c = (c + c2) + err;
+}
+
+// Wave-wide sum of compensated pairs (butterfly, fixed order: every lane
+// ends with the same bits).
+__device__ __forceinline__ void wave_nsum(double &s, double &c) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double s2 = __shfl_xor(s, off, 64);
+        double c2 = __shfl_xor(c, off, 64);
+        nsum_merge(s, c, s2, c2);
+    }
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------- host-side objects
+}  // namespace nnqs
+
+struct nnqs_system {
+    nnqs::SysView view;
+    double *d_h = nullptr, *d_g = nullptr, *d_J = nullptr, *d_K = nullptr;
+    uint64_t *d_hash = nullptr;
+    int *d_status = nullptr;  // scratch status word for validation of connection exports
+    int device = 0;
+    int cu_count = 0;
+    int max_lds = 0;  // bytes of LDS a block may use
+};
+
+struct nnqs_table {
+    const nnqs_system *sys = nullptr;
+    int64_t capacity = 0;
+    int64_t n = 0;
+    int64_t padded = 0;            // power of two >= capacity (sort buffers)
+    uint64_t *keys = nullptr;      // [capacity][2] sorted
+    double *logabs = nullptr, *phase = nullptr;
+    uint64_t *sort_keys = nullptr; // [padded][2]
+    uint32_t *sort_idx = nullptr;  // [padded]
+    uint32_t *filter = nullptr;    // 2^20 bits maximum
+    uint64_t *split = nullptr;     // [2^13 - 1][2] maximum
+    int *status = nullptr;         // sticky device status
+    double *partials = nullptr;    // energy reduction scratch
+    int filter_log2 = 0;           // as built
+    int split_levels = 0;          // as built
+    nnqs_tune tune{};
+};
+
+namespace nnqs {
+nnqs::TableView table_view(const nnqs_table *t);
+// Enqueue the two-stage deterministic energy reduction.
+nnqs_status enqueue_energy(nnqs_table *tab, const uint32_t *counts, const double *eloc, int64_t n,
+                           double *energy, hipStream_t st);
+// Synchronise and read/clear the sticky status.
+nnqs_status read_status(nnqs_table *tab, hipStream_t st, bool clear);
+constexpr int kMaxFilterLog2 = 20;
+constexpr int kMaxSplitLevels = 13;
+constexpr int kPartialBlocks = 1024;
+}  // namespace nnqs
