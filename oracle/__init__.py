@@ -12,4 +12,9 @@ from .oracle import (  # noqa: F401
     sort_table,
     eloc_table,
     energy,
+    net_order,
+    pack_net,
+    net_conditionals,
+    net_logpsi,
+    eloc_model,
 )

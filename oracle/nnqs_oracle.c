@@ -382,3 +382,257 @@ void ora_energy(const uint32_t *counts, const double *eloc, int64_t n, double *o
     out[2] = W;
     out[3] = nsum_value(&var) / W;
 }
+
+/* ======================================================================
+ * Amplitude and phase networks (paper: Section 3.1, Eq. 11 and Fig. 2:
+ * a decoder-only transformer gives |psi|^2 autoregressively, an MLP gives the
+ * phase; Section 4.1: phase MLP of three dense layers N x 512 x 512 x 1;
+ * Section 3.3, Eq. 12: tokens are spatial-orbital pairs sampled in reverse
+ * qubit order with the electron-number mask).  Readings where the paper is
+ * silent: pre-LN blocks (eps 1e-5), causal multi-head attention scaled by
+ * 1/sqrt(head dim), FFN with exact-erf GELU, input = embedding of the
+ * previous token (a begin token 4 at the first position) + learned position
+ * embedding, output head -> 4 logits + a fixed per-orbital bias, the mask also
+ * forbids leaving more electrons than remaining positions, and
+ * log|psi| = 1/2 sum_s log pi(t_s | t_<s).
+ *
+ * Weights arrive as one float64 array in this order (matrices [in][out]):
+ *   tok_emb[5][d] pos_emb[K][d]
+ *   per layer: ln1_g[d] ln1_b[d] wq[d][d] bq[d] wk[d][d] bk[d] wv[d][d] bv[d]
+ *              wo[d][d] bo[d] ln2_g[d] ln2_b[d] w1[d][F] b1[F] w2[F][d] b2[d]
+ *   lnf_g[d] lnf_b[d] head_w[d][4] head_b[4] logit_bias[K][4]
+ *   ph_w1[2K][P] ph_b1[P] ph_w2[P][P] ph_b2[P] ph_w3[P][1] ph_b3[1]
+ * ====================================================================== */
+typedef struct {
+    int K, d, L, H, F, P, n_up, n_dn;
+} ora_net;
+
+static double gelu(double v) { return 0.5 * v * (1.0 + erf(v / sqrt(2.0))); }
+
+static void layer_norm(const double *x, const double *g, const double *b, int d, double *y) {
+    double m = 0.0, v = 0.0;
+    for (int c = 0; c < d; c++) m += x[c];
+    m /= d;
+    for (int c = 0; c < d; c++) v += (x[c] - m) * (x[c] - m);
+    v /= d;
+    double r = 1.0 / sqrt(v + 1e-5);
+    for (int c = 0; c < d; c++) y[c] = (x[c] - m) * r * g[c] + b[c];
+}
+
+/* y[n] = x[m] W[m][n] + b[n] */
+static void dense(const double *x, const double *W, const double *b, int m, int n, double *y) {
+    for (int j = 0; j < n; j++) {
+        double s = b ? b[j] : 0.0;
+        for (int i = 0; i < m; i++) s += x[i] * W[(size_t)i * n + j];
+        y[j] = s;
+    }
+}
+
+int64_t ora_net_size(int K, int d, int L, int H, int F, int P) {
+    (void)H;
+    int64_t per = 2 * d + 4 * ((int64_t)d * d + d) + 2 * d + (int64_t)d * F + F + (int64_t)F * d + d;
+    return 5 * (int64_t)d + (int64_t)K * d + L * per + 2 * d + 4 * (int64_t)d + 4 + 4 * (int64_t)K +
+           (int64_t)2 * K * P + P + (int64_t)P * P + P + P + 1;
+}
+
+/* Token of the configuration at autoregressive position s (orbital K-1-s):
+ * t = n_up + 2 n_dn of that spatial orbital. */
+static int token_at(const uint64_t *x, int K, int s) {
+    int i = K - 1 - s;
+    return bit_of(x, 2 * i) + 2 * bit_of(x, 2 * i + 1);
+}
+
+/* Conditional log-probabilities logp[K][4] (masked entries -inf) of one
+ * configuration under the amplitude transformer. */
+static void transformer_conditionals(const ora_net *net, const double *w, const uint64_t *x, double *logp) {
+    const int K = net->K, d = net->d, L = net->L, H = net->H, F = net->F;
+    const int dh = d / H;
+    const double *tok_emb = w, *pos_emb = w + 5 * d;
+    const double *p = pos_emb + (size_t)K * d;
+    double *h = (double *)malloc(sizeof(double) * K * d);
+    double *a = (double *)malloc(sizeof(double) * K * d);
+    double *q = (double *)malloc(sizeof(double) * K * d);
+    double *k = (double *)malloc(sizeof(double) * K * d);
+    double *v = (double *)malloc(sizeof(double) * K * d);
+    double *o = (double *)malloc(sizeof(double) * K * d);
+    double *f = (double *)malloc(sizeof(double) * F);
+    double *t = (double *)malloc(sizeof(double) * d);
+    double *sc = (double *)malloc(sizeof(double) * K);
+    for (int s = 0; s < K; s++) {
+        int prev = s == 0 ? 4 : token_at(x, K, s - 1);
+        for (int c = 0; c < d; c++) h[s * d + c] = tok_emb[prev * d + c] + pos_emb[s * d + c];
+    }
+    for (int l = 0; l < L; l++) {
+        const double *ln1_g = p, *ln1_b = p + d, *wq = p + 2 * d, *bq = wq + d * d, *wk = bq + d, *bk = wk + d * d,
+                     *wv = bk + d, *bv = wv + d * d, *wo = bv + d, *bo = wo + d * d, *ln2_g = bo + d,
+                     *ln2_b = ln2_g + d, *w1 = ln2_b + d, *b1 = w1 + (size_t)d * F, *w2 = b1 + F,
+                     *b2 = w2 + (size_t)F * d;
+        p = b2 + d;
+        for (int s = 0; s < K; s++) {
+            layer_norm(h + s * d, ln1_g, ln1_b, d, a + s * d);
+            dense(a + s * d, wq, bq, d, d, q + s * d);
+            dense(a + s * d, wk, bk, d, d, k + s * d);
+            dense(a + s * d, wv, bv, d, d, v + s * d);
+        }
+        for (int s = 0; s < K; s++) {
+            for (int hh = 0; hh < H; hh++) {
+                double mx = -INFINITY;
+                for (int r = 0; r <= s; r++) {
+                    double z = 0.0;
+                    for (int c = 0; c < dh; c++) z += q[s * d + hh * dh + c] * k[r * d + hh * dh + c];
+                    sc[r] = z / sqrt((double)dh);
+                    if (sc[r] > mx) mx = sc[r];
+                }
+                double den = 0.0;
+                for (int r = 0; r <= s; r++) {
+                    sc[r] = exp(sc[r] - mx);
+                    den += sc[r];
+                }
+                for (int c = 0; c < dh; c++) {
+                    double z = 0.0;
+                    for (int r = 0; r <= s; r++) z += sc[r] * v[r * d + hh * dh + c];
+                    o[s * d + hh * dh + c] = z / den;
+                }
+            }
+        }
+        for (int s = 0; s < K; s++) {
+            dense(o + s * d, wo, bo, d, d, t);
+            for (int c = 0; c < d; c++) h[s * d + c] += t[c];
+            layer_norm(h + s * d, ln2_g, ln2_b, d, t);
+            dense(t, w1, b1, d, F, f);
+            for (int c = 0; c < F; c++) f[c] = gelu(f[c]);
+            double *u = a + s * d; /* reuse as scratch row */
+            dense(f, w2, b2, F, d, u);
+            for (int c = 0; c < d; c++) h[s * d + c] += u[c];
+        }
+    }
+    const double *lnf_g = p, *lnf_b = p + d, *head_w = p + 2 * d, *head_b = head_w + 4 * d,
+                 *bias = head_b + 4;
+    int up = 0, dn = 0;
+    for (int s = 0; s < K; s++) {
+        double z[4];
+        layer_norm(h + s * d, lnf_g, lnf_b, d, t);
+        dense(t, head_w, head_b, d, 4, z);
+        int i = K - 1 - s, rem = K - 1 - s;
+        double mx = -INFINITY;
+        int allowed[4];
+        for (int c = 0; c < 4; c++) {
+            z[c] += bias[i * 4 + c];
+            int bu = c & 1, bd = c >> 1;
+            allowed[c] = (up + bu <= net->n_up) && (dn + bd <= net->n_dn) && (net->n_up - up - bu <= rem) &&
+                         (net->n_dn - dn - bd <= rem);
+            if (allowed[c] && z[c] > mx) mx = z[c];
+        }
+        double den = 0.0;
+        for (int c = 0; c < 4; c++)
+            if (allowed[c]) den += exp(z[c] - mx);
+        for (int c = 0; c < 4; c++) logp[s * 4 + c] = allowed[c] ? (z[c] - mx) - log(den) : -INFINITY;
+        int tk = token_at(x, K, s);
+        up += tk & 1;
+        dn += tk >> 1;
+    }
+    free(h); free(a); free(q); free(k); free(v); free(o); free(f); free(t); free(sc);
+}
+
+static const double *phase_weights(const ora_net *net, const double *w) {
+    const int K = net->K, d = net->d, L = net->L, F = net->F;
+    int64_t per = 2 * d + 4 * ((int64_t)d * d + d) + 2 * d + (int64_t)d * F + F + (int64_t)F * d + d;
+    return w + 5 * (int64_t)d + (int64_t)K * d + L * per + 2 * d + 4 * (int64_t)d + 4 + 4 * (int64_t)K;
+}
+
+/* log|psi(x)| and phi(x) of one configuration. */
+static void net_logpsi(const ora_net *net, const double *w, const uint64_t *x, double *logabs, double *phase) {
+    const int K = net->K, N = 2 * K, P = net->P;
+    double *lp = (double *)malloc(sizeof(double) * K * 4);
+    transformer_conditionals(net, w, x, lp);
+    double s = 0.0;
+    for (int t = 0; t < K; t++) s += lp[t * 4 + token_at(x, K, t)];
+    *logabs = 0.5 * s;
+    free(lp);
+    const double *w1 = phase_weights(net, w), *b1 = w1 + (size_t)N * P, *w2 = b1 + P, *b2 = w2 + (size_t)P * P,
+                 *w3 = b2 + P, *b3 = w3 + P;
+    double *in = (double *)malloc(sizeof(double) * N);
+    double *z1 = (double *)malloc(sizeof(double) * P);
+    double *z2 = (double *)malloc(sizeof(double) * P);
+    for (int q = 0; q < N; q++) in[q] = bit_of(x, q);
+    dense(in, w1, b1, N, P, z1);
+    for (int c = 0; c < P; c++) z1[c] = gelu(z1[c]);
+    dense(z1, w2, b2, P, P, z2);
+    for (int c = 0; c < P; c++) z2[c] = gelu(z2[c]);
+    double ph;
+    dense(z2, w3, b3, P, 1, &ph);
+    *phase = ph;
+    free(in); free(z1); free(z2);
+}
+
+/* Public: conditionals of one configuration (for causality checks). */
+void ora_net_conditionals(int K, int d, int L, int H, int F, int P, int n_up, int n_dn, const double *w,
+                          const uint64_t *x, double *logp) {
+    ora_net net = {K, d, L, H, F, P, n_up, n_dn};
+    transformer_conditionals(&net, w, x, logp);
+}
+
+/* Public: log|psi| and phase of n configurations. */
+void ora_net_logpsi(int K, int d, int L, int H, int F, int P, int n_up, int n_dn, const double *w,
+                    const uint64_t *keys, int64_t n, double *logabs, double *phase, int nthreads) {
+    ora_net net = {K, d, L, H, F, P, n_up, n_dn};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < n; k++) net_logpsi(&net, w, keys + 2 * k, logabs + k, phase + k);
+}
+
+/* Public: full local energies, every connected x' evaluated by the networks
+ * (Eq. 4 over all x' with H_xx' != 0).  The sample's own amplitude is the
+ * network's as well.  absum as in ora_eloc_table. */
+int ora_eloc_model(int K, int n_up, int n_dn, const double *h, const double *g, double ecore, int d, int L,
+                   int H, int F, int P, const double *w, const uint64_t *keys, int64_t n, double *eloc,
+                   double *absum, int nthreads) {
+    ora_ham Ham = {K, h, g, ecore};
+    ora_net net = {K, d, L, H, F, P, n_up, n_dn};
+    int64_t C = ora_n_connections(K, n_up, n_dn);
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    for (int64_t k = 0; k < n; k++) {
+        const uint64_t *x = keys + 2 * k;
+        int nu = 0, nd = 0;
+        for (int i = 0; i < K; i++) {
+            nu += bit_of(x, 2 * i);
+            nd += bit_of(x, 2 * i + 1);
+        }
+        if (nu != n_up || nd != n_dn || popcount128(x) != nu + nd) {
+            bad = 1;
+            eloc[2 * k] = eloc[2 * k + 1] = NAN;
+            continue;
+        }
+        double l0, p0;
+        net_logpsi(&net, w, x, &l0, &p0);
+        uint64_t *xp = (uint64_t *)malloc(sizeof(uint64_t) * 2 * (size_t)C);
+        double *lv = (double *)malloc(sizeof(double) * (size_t)C);
+        double *pv = (double *)malloc(sizeof(double) * (size_t)C);
+        int64_t cnt = enumerate(K, x, xp, NULL);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t c = 0; c < cnt; c++) net_logpsi(&net, w, xp + 2 * c, lv + c, pv + c);
+        neumaier re = {0, 0}, im = {0, 0}, ab = {0, 0};
+        for (int64_t c = 0; c < cnt; c++) {
+            int s;
+            double hv = slater_condon(&Ham, x, xp + 2 * c, &s);
+            double mag = exp(lv[c] - l0);
+            nsum_add(&re, hv * mag * cos(pv[c] - p0));
+            nsum_add(&im, hv * mag * sin(pv[c] - p0));
+            nsum_add(&ab, fabs(hv) * mag);
+        }
+        eloc[2 * k] = nsum_value(&re);
+        eloc[2 * k + 1] = nsum_value(&im);
+        if (absum) absum[k] = nsum_value(&ab);
+        free(xp); free(lv); free(pv);
+    }
+    return bad ? -1 : 0;
+}

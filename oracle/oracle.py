@@ -62,6 +62,16 @@ def _load():
                                    _u64p, _f64p, _f64p, ctypes.c_int64, _f64p, _f64p, ctypes.c_int]
     lib.ora_energy.restype = None
     lib.ora_energy.argtypes = [_u32p, _f64p, ctypes.c_int64, _f64p]
+    _i = ctypes.c_int
+    lib.ora_net_size.restype = ctypes.c_int64
+    lib.ora_net_size.argtypes = [_i] * 6
+    lib.ora_net_conditionals.restype = None
+    lib.ora_net_conditionals.argtypes = [_i] * 8 + [_f64p, _u64p, _f64p]
+    lib.ora_net_logpsi.restype = None
+    lib.ora_net_logpsi.argtypes = [_i] * 8 + [_f64p, _u64p, ctypes.c_int64, _f64p, _f64p, _i]
+    lib.ora_eloc_model.restype = ctypes.c_int
+    lib.ora_eloc_model.argtypes = [_i, _i, _i, _f64p, _f64p, ctypes.c_double, _i, _i, _i, _i, _i, _f64p,
+                                   _u64p, ctypes.c_int64, _f64p, _f64p, _i]
     _lib = lib
     return lib
 
@@ -147,3 +157,65 @@ def energy(counts, eloc):
     out = np.zeros(4, np.float64)
     _load().ora_energy(_p(counts, _u32p), _p(e, _f64p), counts.shape[0], _p(out, _f64p))
     return out
+
+
+# ------------------------------------------------------------------ networks
+def net_order(L: int):
+    """Names of the network weights in the order the C oracle reads them."""
+    names = ["tok_emb", "pos_emb"]
+    for l in range(L):
+        names += [f"l{l}.{k}" for k in ("ln1_g", "ln1_b", "wq", "bq", "wk", "bk", "wv", "bv", "wo", "bo",
+                                        "ln2_g", "ln2_b", "w1", "b1", "w2", "b2")]
+    names += ["lnf_g", "lnf_b", "head_w", "head_b", "logit_bias", "ph_w1", "ph_b1", "ph_w2", "ph_b2",
+              "ph_w3", "ph_b3"]
+    return names
+
+
+def pack_net(weights: dict, shape) -> np.ndarray:
+    """Flatten the weight dict into the oracle's float64 layout."""
+    flat = np.concatenate([np.asarray(weights[k], dtype=np.float64).ravel() for k in net_order(shape.n_layers)])
+    n = _load().ora_net_size(shape.K, shape.d_model, shape.n_layers, shape.n_heads, shape.d_ff, shape.phase_hidden)
+    assert flat.size == n, (flat.size, n)
+    return np.ascontiguousarray(flat)
+
+
+def _dims(shape):
+    return (shape.K, shape.d_model, shape.n_layers, shape.n_heads, shape.d_ff, shape.phase_hidden)
+
+
+def net_conditionals(weights, shape, n_up, n_dn, x):
+    """Masked conditional log-probabilities ``[K, 4]`` of one configuration."""
+    w = pack_net(weights, shape)
+    x = _c(x, np.uint64)
+    out = np.zeros((shape.K, 4), np.float64)
+    _load().ora_net_conditionals(*_dims(shape), n_up, n_dn, _p(w, _f64p), _p(x, _u64p), _p(out, _f64p))
+    return out
+
+
+def net_logpsi(weights, shape, n_up, n_dn, keys, nthreads: int = 0):
+    """``(log|psi|, phase)`` of every configuration in ``keys [n, 2]``."""
+    w = pack_net(weights, shape)
+    keys = _c(keys, np.uint64).reshape(-1, 2)
+    n = keys.shape[0]
+    la = np.zeros(n, np.float64)
+    ph = np.zeros(n, np.float64)
+    _load().ora_net_logpsi(*_dims(shape), n_up, n_dn, _p(w, _f64p), _p(keys, _u64p), n, _p(la, _f64p),
+                           _p(ph, _f64p), int(nthreads))
+    return la, ph
+
+
+def eloc_model(K, n_up, n_dn, h, g, e_core, weights, shape, keys, nthreads: int = 0, with_absum: bool = False):
+    """Full local energies with every x' amplitude from the networks."""
+    w = pack_net(weights, shape)
+    h, g = _c(h, np.float64), _c(g, np.float64)
+    keys = _c(keys, np.uint64).reshape(-1, 2)
+    n = keys.shape[0]
+    out = np.zeros((n, 2), np.float64)
+    ab = np.zeros(n, np.float64)
+    d = _dims(shape)
+    r = _load().ora_eloc_model(K, n_up, n_dn, _p(h, _f64p), _p(g, _f64p), float(e_core), d[1], d[2], d[3], d[4],
+                               d[5], _p(w, _f64p), _p(keys, _u64p), n, _p(out, _f64p), _p(ab, _f64p), int(nthreads))
+    if r < 0:
+        raise ValueError("a sample violates the particle numbers")
+    e = out[:, 0] + 1j * out[:, 1]
+    return (e, ab) if with_absum else e
