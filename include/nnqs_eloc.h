@@ -172,6 +172,82 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
 nnqs_status nnqs_energy(nnqs_table *tab, const uint32_t *counts, const double *eloc, int64_t n,
                         double *energy, void *stream);
 
+/* ------------------------------------------------------------------ model */
+/* Wave-function ansatz of Section 3.1 (Eq. 11, Fig. 2): a decoder-only
+ * transformer gives |psi|^2 autoregressively (Eq. 8) over tokens that are
+ * spatial-orbital pairs taken in reverse orbital order with the electron
+ * number mask of Eq. 12 (Section 3.3); an MLP of three dense layers
+ * N x P x P x 1 gives the phase (Section 4.1).  Readings where the paper is
+ * silent: pre-LN blocks (eps 1e-5), causal multi-head attention scaled by
+ * 1/sqrt(d_model/n_heads), FFN with exact-erf GELU, input of position s = the
+ * embedding of the token at s-1 (a begin token 4 at s = 0) + a learned
+ * position embedding, final LN and a d_model -> 4 head plus a fixed bias
+ * table[orbital][token], a mask that also forbids leaving more electrons than
+ * remaining positions, log|psi| = 1/2 sum_s log pi(t_s | t_<s), and GELU
+ * between the phase layers.  Token of orbital i: t = n_up(i) + 2 n_dn(i);
+ * position s holds orbital K-1-s. */
+typedef struct nnqs_model nnqs_model;
+
+typedef struct {
+    int32_t n_orb;        /* K spatial orbitals = sequence length, 2..64 */
+    int32_t d_model;      /* multiple of n_heads, <= 128 */
+    int32_t n_layers;     /* >= 1 */
+    int32_t n_heads;
+    int32_t d_ff;         /* <= 1024 */
+    int32_t phase_hidden; /* P, <= 1024 */
+    int32_t n_up, n_dn;   /* electron numbers used by the mask */
+} nnqs_model_desc;
+
+/* Precision of the network evaluation. */
+enum {
+    NNQS_FP64 = 0, /* every operation in FP64 (parity path) */
+    NNQS_BF16 = 1  /* BF16 MFMA with FP32 accumulation and FP32 normalisation
+                      and softmax; log|psi| and phase returned as FP64.
+                      Needs d_model 64, n_heads 4, d_ff 256, P 512. */
+};
+
+/* Number of FP32 weights the layout below holds for `desc`; -1 if invalid. */
+int64_t nnqs_model_weight_count(const nnqs_model_desc *desc);
+
+/* Copies host FP32 weights (row-major matrices [in][out], y = x W + b) in
+ * this order:
+ *   tok_emb[5][d] pos_emb[K][d]
+ *   per layer: ln1_g[d] ln1_b[d] wq[d][d] bq[d] wk[d][d] bk[d] wv[d][d] bv[d]
+ *              wo[d][d] bo[d] ln2_g[d] ln2_b[d] w1[d][F] b1[F] w2[F][d] b2[d]
+ *   lnf_g[d] lnf_b[d] head_w[d][4] head_b[4] logit_bias[K][4]
+ *   ph_w1[2K][P] ph_b1[P] ph_w2[P][P] ph_b2[P] ph_w3[P][1] ph_b3[1]
+ * to the device in FP64 and BF16 forms.  Synchronous.
+ * Errors: EINVAL, ENOMEM, EHIP, EUNSUPPORTED. */
+nnqs_status nnqs_model_create(nnqs_model **out, const nnqs_model_desc *desc, const float *weights);
+
+/* Releases the model.  NULL is accepted. */
+nnqs_status nnqs_model_destroy(nnqs_model *model);
+
+/* log|psi| and phase of n configurations (device keys [n][2]) into device
+ * arrays logabs [n], phase [n].  Keys outside the model's electron sector get
+ * logabs = -inf.  Errors: EINVAL, EUNSUPPORTED (precision), EHIP. */
+nnqs_status nnqs_model_logpsi(const nnqs_model *model, const uint64_t *keys, int64_t n, int32_t precision,
+                              double *logabs, double *phase, void *stream);
+
+/* Counters of a full evaluation (host struct). */
+typedef struct {
+    int64_t connections; /* connected configurations enumerated, diagonal included */
+    int64_t evaluated;   /* of these, evaluated by the network (all, without a screen) */
+} nnqs_stats;
+
+/* Full local energies (Eq. 4 over every connected x', psi from the model,
+ * the samples' own psi from the model too) of n samples (device keys [n][2],
+ * counts [n]) into device eloc [n][2] and energy [4] (layout as in
+ * nnqs_eloc_table; energy may be NULL).  The network runs in `precision`;
+ * matrix elements, amplitude ratios and all sums are FP64 with compensated
+ * summation.  `stats` (host, may be NULL) receives the counters; filling it
+ * synchronises `stream`.  Uses library-owned scratch sized at first use
+ * (one call at a time per model).  Errors: EINVAL, ECONSERVE (VALIDATE),
+ * ENOMEM, EUNSUPPORTED, EHIP. */
+nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model, int32_t precision, const uint64_t *keys,
+                            const uint32_t *counts, int64_t n, double *eloc, double *energy, nnqs_stats *stats,
+                            uint32_t flags, void *stream);
+
 /* ------------------------------------------------------------- tuning */
 /* Launch parameters of the sample-aware kernel (0 = library default). */
 typedef struct {

@@ -7,11 +7,16 @@ fallback path.
 """
 from .api import (  # noqa: F401
     NNQSError,
+    NNQS_BF16,
+    NNQS_FP64,
     NNQS_VALIDATE,
+    Model,
     System,
     Table,
     connections,
+    eloc_model,
     eloc_table,
     energy,
+    model_logpsi,
     version,
 )

@@ -35,6 +35,12 @@ SIGNATURES = {
     "nnqs_energy": (_i32, [_c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p]),
     "nnqs_table_set_tune": (_i32, [_c_void_p, _c_void_p]),
     "nnqs_table_get_tune": (_i32, [_c_void_p, _c_void_p]),
+    "nnqs_model_weight_count": (_i64, [_c_void_p]),
+    "nnqs_model_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p, _c_void_p]),
+    "nnqs_model_destroy": (_i32, [_c_void_p]),
+    "nnqs_model_logpsi": (_i32, [_c_void_p, _c_void_p, _i64, _i32, _c_void_p, _c_void_p, _c_void_p]),
+    "nnqs_eloc_model": (_i32, [_c_void_p, _c_void_p, _i32, _c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p,
+                               _c_void_p, _u32, _c_void_p]),
 }
 
 STATUS_NAMES = {0: "NNQS_OK", -1: "NNQS_EINVAL", -2: "NNQS_EDUP", -3: "NNQS_ECONSERVE", -4: "NNQS_ERANGE",
@@ -52,6 +58,18 @@ class Tune(ctypes.Structure):
     _fields_ = [("waves_per_block", _i32), ("blocks_per_cu", _i32), ("filter_log2_bits", _i32),
                 ("splitter_levels", _i32)]
 
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("n_orb", _i32), ("d_model", _i32), ("n_layers", _i32), ("n_heads", _i32), ("d_ff", _i32),
+                ("phase_hidden", _i32), ("n_up", _i32), ("n_dn", _i32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("connections", _i64), ("evaluated", _i64)]
+
+
+NNQS_FP64 = 0
+NNQS_BF16 = 1
 
 _lib = None
 

@@ -7,7 +7,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from ._lib import NNQS_VALIDATE, NNQSError, Tune  # noqa: F401
+from ._lib import NNQS_BF16, NNQS_FP64, NNQS_VALIDATE, ModelDesc, NNQSError, Stats, Tune  # noqa: F401
 
 _KEY_DTYPES = (torch.int64, torch.uint64)
 
@@ -177,3 +177,79 @@ def energy(table: Table, counts, eloc, out=None, stream=None):
         out = torch.empty(4, dtype=torch.float64, device=eloc.device)
     L.check(L.load().nnqs_energy(table.handle, _ptr(counts), _ptr(eloc), n, _ptr(out), _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------------- model
+_LAYER_KEYS = ("ln1_g", "ln1_b", "wq", "bq", "wk", "bk", "wv", "bv", "wo", "bo", "ln2_g", "ln2_b", "w1", "b1",
+               "w2", "b2")
+
+
+def pack_model_weights(weights: dict, n_layers: int) -> np.ndarray:
+    """FP32 weights in the order ``nnqs_model_create`` documents."""
+    order = ["tok_emb", "pos_emb"] + [f"l{l}.{k}" for l in range(n_layers) for k in _LAYER_KEYS]
+    order += ["lnf_g", "lnf_b", "head_w", "head_b", "logit_bias", "ph_w1", "ph_b1", "ph_w2", "ph_b2", "ph_w3",
+              "ph_b3"]
+    return np.ascontiguousarray(np.concatenate([np.asarray(weights[k], np.float32).ravel() for k in order]))
+
+
+class Model:
+    """Amplitude transformer + phase MLP on the device (``nnqs_model_*``)."""
+
+    def __init__(self, shape, n_up: int, n_dn: int, weights: dict):
+        self._lib = L.load()
+        self.desc = ModelDesc(shape.K, shape.d_model, shape.n_layers, shape.n_heads, shape.d_ff,
+                              shape.phase_hidden, n_up, n_dn)
+        flat = pack_model_weights(weights, shape.n_layers)
+        count = self._lib.nnqs_model_weight_count(ctypes.byref(self.desc))
+        if count != flat.size:
+            raise ValueError(f"weight count {flat.size} does not match the model description ({count})")
+        out = ctypes.c_void_p()
+        L.check(self._lib.nnqs_model_create(ctypes.byref(out), ctypes.byref(self.desc),
+                                            flat.ctypes.data_as(ctypes.c_void_p)))
+        self.handle = out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.nnqs_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def model_logpsi(model: Model, keys, precision: int = NNQS_FP64, logabs=None, phase=None, stream=None):
+    """``(log|psi|, phase)`` device tensors for ``keys [n, 2]`` (``nnqs_model_logpsi``)."""
+    n = keys.shape[0]
+    _need(keys, "keys", _KEY_DTYPES, (n, 2))
+    if logabs is None:
+        logabs = torch.empty(n, dtype=torch.float64, device=keys.device)
+    if phase is None:
+        phase = torch.empty(n, dtype=torch.float64, device=keys.device)
+    L.check(L.load().nnqs_model_logpsi(model.handle, _ptr(keys), n, int(precision), _ptr(logabs), _ptr(phase),
+                                       _stream(stream)))
+    return logabs, phase
+
+
+def eloc_model(system: System, model: Model, keys, counts=None, precision: int = NNQS_FP64, eloc=None,
+               energy=None, with_energy: bool = True, with_stats: bool = False, validate: bool = False,
+               stream=None):
+    """Full local energies with every x' from the network (``nnqs_eloc_model``).
+    Returns ``(eloc [n, 2], energy [4] or None, stats dict or None)``."""
+    n = keys.shape[0]
+    _need(keys, "keys", _KEY_DTYPES, (n, 2))
+    if with_energy:
+        _need(counts, "counts", (torch.int32, torch.uint32), (n,))
+        if energy is None:
+            energy = torch.empty(4, dtype=torch.float64, device=keys.device)
+    if eloc is None:
+        eloc = torch.empty((n, 2), dtype=torch.float64, device=keys.device)
+    st = Stats()
+    L.check(L.load().nnqs_eloc_model(system.handle, model.handle, int(precision), _ptr(keys), _ptr(counts), n,
+                                     _ptr(eloc), _ptr(energy) if with_energy else None,
+                                     ctypes.byref(st) if with_stats else None, NNQS_VALIDATE if validate else 0,
+                                     _stream(stream)))
+    stats = {"connections": st.connections, "evaluated": st.evaluated} if with_stats else None
+    return eloc, (energy if with_energy else None), stats

@@ -259,6 +259,8 @@ nnqs::TableView table_view(const nnqs_table *t);
 // Enqueue the two-stage deterministic energy reduction.
 nnqs_status enqueue_energy(nnqs_table *tab, const uint32_t *counts, const double *eloc, int64_t n,
                            double *energy, hipStream_t st);
+nnqs_status enqueue_energy_partials(double *partials, const uint32_t *counts, const double *eloc, int64_t n,
+                                    double *energy, hipStream_t st);
 // Synchronise and read/clear the sticky status.
 nnqs_status read_status(nnqs_table *tab, hipStream_t st, bool clear);
 constexpr int kMaxFilterLog2 = 20;

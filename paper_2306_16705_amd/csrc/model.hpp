@@ -1,0 +1,52 @@
+// Internal definitions of the wave-function model (see model.hip).
+#pragma once
+
+#include "internal.hpp"
+
+namespace nnqs {
+
+struct ModelOffsets {  // element offsets into the flat weight array
+    int64_t tok_emb, pos_emb, layer0, layer_stride, lnf_g, lnf_b, head_w, head_b, bias;
+    int64_t ph_w1, ph_b1, ph_w2, ph_b2, ph_w3, ph_b3, total;
+};
+
+struct LayerOffsets {  // element offsets inside one layer block
+    int64_t ln1_g, ln1_b, wq, bq, wk, bk, wv, bv, wo, bo, ln2_g, ln2_b, w1, b1, w2, b2;
+};
+
+struct ModelView {
+    int K, d, L, H, F, P, n_up, n_dn;
+    const double *w64;
+    ModelOffsets off;
+};
+
+ModelOffsets model_offsets(const nnqs_model_desc &m);
+
+}  // namespace nnqs
+
+struct nnqs_model {
+    nnqs_model_desc desc{};
+    nnqs::ModelOffsets off{};
+    double *d_w64 = nullptr;
+    int max_lds = 0;
+    // BF16 path: transposed BF16 matrices and FP32 vectors (model_bf16.hip)
+    void *d_bf16 = nullptr;
+    float *d_f32 = nullptr;
+    bool bf16_ok = false;
+    // full-E_loc scratch (eloc_model.hip), grown on demand
+    uint64_t *d_xkeys = nullptr;
+    double *d_xla = nullptr, *d_xph = nullptr, *d_sla = nullptr, *d_sph = nullptr;
+    int64_t xcap = 0, scap = 0;
+    double *d_partials = nullptr;
+};
+
+namespace nnqs {
+ModelView model_view(const nnqs_model *m);
+nnqs_status enqueue_logpsi(const nnqs_model *m, const uint64_t *keys, int64_t n, int32_t precision, double *logabs,
+                           double *phase, hipStream_t st);
+nnqs_status bf16_model_init(nnqs_model *m, const float *weights);
+void bf16_model_free(nnqs_model *m);
+nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs,
+                                double *phase, hipStream_t st);
+void eloc_model_free(nnqs_model *m);
+}  // namespace nnqs

@@ -274,15 +274,20 @@ __global__ void __launch_bounds__(256) k_energy_final(const double *__restrict__
     }
 }
 
-nnqs_status enqueue_energy(nnqs_table *tab, const uint32_t *counts, const double *eloc, int64_t n, double *energy,
-                           hipStream_t st) {
+nnqs_status enqueue_energy_partials(double *partials, const uint32_t *counts, const double *eloc, int64_t n,
+                                    double *energy, hipStream_t st) {
     int64_t blocks = (n + 1023) / 1024;
     if (blocks < 1) blocks = 1;
     if (blocks > kPartialBlocks) blocks = kPartialBlocks;
-    hipLaunchKernelGGL(k_energy_partial, dim3((unsigned)blocks), dim3(256), 0, st, counts, eloc, n, tab->partials);
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, tab->partials, (int)blocks, energy);
+    hipLaunchKernelGGL(k_energy_partial, dim3((unsigned)blocks), dim3(256), 0, st, counts, eloc, n, partials);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, partials, (int)blocks, energy);
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
+}
+
+nnqs_status enqueue_energy(nnqs_table *tab, const uint32_t *counts, const double *eloc, int64_t n, double *energy,
+                           hipStream_t st) {
+    return enqueue_energy_partials(tab->partials, counts, eloc, n, energy, st);
 }
 
 nnqs_status read_status(nnqs_table *tab, hipStream_t st, bool clear) {

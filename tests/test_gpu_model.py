@@ -1,0 +1,90 @@
+"""GPU parity of the network forward and of the full local energy against
+the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import assert_eloc_close, dev, eloc_complex
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_16705_amd as nn
+    return nn
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} {kw}", flush=True)
+
+
+def _random_connected(d, n_samples, per_sample, seed):
+    """Random connected configurations x' of the first samples (oracle enumeration)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_samples):
+        xp, _, _, _ = oracle.connections(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"], d["keys"][k])
+        out.append(xp[rng.choice(len(xp), size=min(per_sample, len(xp)), replace=False)])
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("kw", [dict(cfg=1, model=True), dict(cfg=2, K=12, n_up=4, n_dn=3, n_unique=200, model=True),
+                                dict(cfg=3, n_unique=8)])
+def test_logpsi_fp64_matches_oracle(nn, kw):
+    kw = dict(kw)
+    cfg = kw.pop("cfg")
+    d = synth.config_inputs(cfg, **kw)
+    _print_case("logpsi_fp64", K=d["K"])
+    shape, w = d["model_shape"], d["weights"]
+    M = nn.Model(shape, d["n_up"], d["n_dn"], w)
+    keys = d["keys"] if d["K"] < 60 else np.concatenate([d["keys"], _random_connected(d, 2, 300, 5)])
+    la, ph = nn.model_logpsi(M, dev(keys), nn.NNQS_FP64)
+    torch.cuda.synchronize()
+    ola, oph = oracle.net_logpsi(w, shape, d["n_up"], d["n_dn"], keys, nthreads=0)
+    la, ph = la.cpu().numpy(), ph.cpu().numpy()
+    assert np.max(np.abs(la - ola) / np.maximum(1.0, np.abs(ola))) < 1e-12
+    assert np.max(np.abs(ph - oph)) < 1e-12
+
+
+@pytest.mark.parametrize("kw,take", [(dict(K=5, n_up=2, n_dn=2), None), (dict(K=6, n_up=2, n_dn=3), None),
+                                     (dict(K=16, n_up=4, n_dn=4, n_unique=64), 4)])
+def test_eloc_model_fp64_matches_oracle(nn, kw, take):
+    cfg = 1 if "n_unique" not in kw else 2
+    d = synth.config_inputs(cfg, model=True, **kw)
+    _print_case("eloc_model_fp64", **kw)
+    shape, w = d["model_shape"], d["weights"]
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(shape, d["n_up"], d["n_dn"], w)
+    keys = d["keys"] if take is None else d["keys"][:take]
+    counts = d["counts"][: len(keys)]
+    e, en, st = nn.eloc_model(S, M, dev(keys), dev(counts, torch.int32), nn.NNQS_FP64, with_stats=True)
+    g = eloc_complex(e)
+    ora, absum = oracle.eloc_model(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"], w, shape, keys,
+                                   with_absum=True)
+    assert_eloc_close(g, ora, absum, label=str(kw))
+    assert st["connections"] == len(keys) * S.connection_count
+    ref = oracle.energy(counts, g)
+    assert abs(en[0].item() - ref[0]) <= 1e-12 * abs(ref[0])
+
+
+def test_eloc_model_whole_sector_equals_table_path(nn):
+    """Over a whole sector, the full path equals the sample-aware path fed with
+    the network's own amplitudes (both on the GPU)."""
+    d = synth.config_inputs(1, K=6, n_up=3, n_dn=2, model=True)
+    _print_case("eloc_model_vs_table")
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    keys = dev(d["keys"])
+    cnt = dev(d["counts"], torch.int32)
+    la, ph = nn.model_logpsi(M, keys, nn.NNQS_FP64)
+    T = nn.Table(S, capacity=keys.shape[0]).build(keys, la, ph, validate=True)
+    e1, _ = nn.eloc_table(S, T, keys, cnt, la, ph)
+    e2, _, _ = nn.eloc_model(S, M, keys, cnt, nn.NNQS_FP64)
+    torch.cuda.synchronize()
+    a, b = eloc_complex(e1), eloc_complex(e2)
+    assert np.max(np.abs(a - b)) <= 1e-11 * max(1.0, np.abs(a).max())
