@@ -88,3 +88,25 @@ def test_eloc_model_whole_sector_equals_table_path(nn):
     torch.cuda.synchronize()
     a, b = eloc_complex(e1), eloc_complex(e2)
     assert np.max(np.abs(a - b)) <= 1e-11 * max(1.0, np.abs(a).max())
+
+
+@pytest.mark.parametrize("kw", [dict(cfg=1, model=True), dict(cfg=3, n_unique=16)])
+def test_logpsi_bf16_error_vs_oracle(nn, kw):
+    """BF16 MFMA forward: the error against the FP64 oracle is measured and
+    bounded (|d log|psi|| <= 0.02 + 1e-3 |log|psi||, |d phase| <= 0.02)."""
+    kw = dict(kw)
+    cfg = kw.pop("cfg")
+    d = synth.config_inputs(cfg, **kw)
+    _print_case("logpsi_bf16", K=d["K"])
+    shape, w = d["model_shape"], d["weights"]
+    M = nn.Model(shape, d["n_up"], d["n_dn"], w)
+    keys = d["keys"] if d["K"] < 60 else np.concatenate([d["keys"], _random_connected(d, 2, 500, 9)])
+    la, ph = nn.model_logpsi(M, dev(keys), nn.NNQS_BF16)
+    torch.cuda.synchronize()
+    ola, oph = oracle.net_logpsi(w, shape, d["n_up"], d["n_dn"], keys)
+    la, ph = la.cpu().numpy(), ph.cpu().numpy()
+    dla, dph = np.abs(la - ola), np.abs(ph - oph)
+    print(f"BF16 vs FP64 oracle K={d['K']}: max |dlogabs| {dla.max():.3e} (rel {np.max(dla / np.abs(ola)):.3e}), "
+          f"max |dphase| {dph.max():.3e}, n={len(keys)}")
+    assert np.all(dla <= 0.02 + 1e-3 * np.abs(ola))
+    assert np.all(dph <= 0.02)
