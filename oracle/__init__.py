@@ -17,4 +17,8 @@ from .oracle import (  # noqa: F401
     net_conditionals,
     net_logpsi,
     eloc_model,
+    screen_size,
+    screen_forward,
+    screen_loss_grad,
+    adam_step,
 )

@@ -636,3 +636,105 @@ int ora_eloc_model(int K, int n_up, int n_dn, const double *h, const double *g, 
     }
     return bad ? -1 : 0;
 }
+
+/* ======================================================================
+ * Learned screen (not in the paper: its only filter is the sample-aware
+ * restriction of Section 3.4 item 4).  An MLP predicts log|psi(x')| from the
+ * occupation bits of x' and one-hot codes of the excitation indices
+ * (i, j, a, b) (sorted, absent indices give all-zero codes):
+ *   u = [bits(x') | onehot(i) | onehot(j) | onehot(a) | onehot(b)]  (5N)
+ *   z1 = GELU(u W1 + b1), z2 = GELU(z1 W2 + b2), y = z2 . w3 + b3.
+ * Weights (float64): W1[5N][H] b1[H] W2[H][H] b2[H] w3[H] b3[1].
+ * Training: mean squared error, Adam with bias correction.
+ * ====================================================================== */
+int64_t ora_screen_size(int N, int H) { return (int64_t)5 * N * H + H + (int64_t)H * H + H + H + 1; }
+
+static void screen_input(int N, const uint64_t *x, const uint8_t *e, double *u) {
+    for (int p = 0; p < 5 * N; p++) u[p] = 0.0;
+    for (int p = 0; p < N; p++) u[p] = bit_of(x, p);
+    for (int t = 0; t < 4; t++)
+        if (e[t] != 255) u[(t + 1) * N + e[t]] = 1.0;
+}
+
+static double gelu_grad(double v) {
+    const double pdf = exp(-0.5 * v * v) * 0.39894228040143267794; /* 1/sqrt(2 pi) */
+    return 0.5 * (1.0 + erf(v / sqrt(2.0))) + v * pdf;
+}
+
+/* forward of one example; keeps pre-activations for the backward pass */
+static double screen_one(int N, int H, const double *w, const double *u, double *a1, double *a2) {
+    const double *W1 = w, *b1 = W1 + (size_t)5 * N * H, *W2 = b1 + H, *b2 = W2 + (size_t)H * H, *w3 = b2 + H,
+                 *b3 = w3 + H;
+    dense(u, W1, b1, 5 * N, H, a1);
+    double *z1 = (double *)calloc((size_t)H, sizeof(double));
+    for (int c = 0; c < H; c++) z1[c] = gelu(a1[c]);
+    dense(z1, W2, b2, H, H, a2);
+    double y = b3[0];
+    for (int c = 0; c < H; c++) y += gelu(a2[c]) * w3[c];
+    free(z1);
+    return y;
+}
+
+void ora_screen_forward(int N, int H, const double *w, const uint64_t *keys, const uint8_t *exc, int64_t n,
+                        double *pred) {
+    double *u = (double *)malloc(sizeof(double) * 5 * N);
+    double *a1 = (double *)malloc(sizeof(double) * H), *a2 = (double *)malloc(sizeof(double) * H);
+    for (int64_t k = 0; k < n; k++) {
+        screen_input(N, keys + 2 * k, exc + 4 * k, u);
+        pred[k] = screen_one(N, H, w, u, a1, a2);
+    }
+    free(u); free(a1); free(a2);
+}
+
+/* loss = mean_k (pred_k - target_k)^2 and its gradient w.r.t. every weight */
+double ora_screen_loss_grad(int N, int H, const double *w, const uint64_t *keys, const uint8_t *exc,
+                            const double *target, int64_t n, double *grad) {
+    const int64_t size = ora_screen_size(N, H);
+    const double *W2 = w + (size_t)5 * N * H + H, *w3 = W2 + (size_t)H * H + H;
+    double *gW1 = grad, *gb1 = gW1 + (size_t)5 * N * H, *gW2 = gb1 + H, *gb2 = gW2 + (size_t)H * H,
+           *gw3 = gb2 + H, *gb3 = gw3 + H;
+    for (int64_t q = 0; q < size; q++) grad[q] = 0.0;
+    double *u = (double *)malloc(sizeof(double) * 5 * N);
+    double *a1 = (double *)malloc(sizeof(double) * H), *a2 = (double *)malloc(sizeof(double) * H);
+    double *d2 = (double *)malloc(sizeof(double) * H), *d1 = (double *)malloc(sizeof(double) * H);
+    double loss = 0.0;
+    for (int64_t k = 0; k < n; k++) {
+        screen_input(N, keys + 2 * k, exc + 4 * k, u);
+        const double y = screen_one(N, H, w, u, a1, a2);
+        const double r = y - target[k];
+        loss += r * r;
+        const double gy = 2.0 * r / (double)n;
+        gb3[0] += gy;
+        for (int c = 0; c < H; c++) {
+            gw3[c] += gy * gelu(a2[c]);
+            d2[c] = gy * w3[c] * gelu_grad(a2[c]);
+        }
+        for (int c = 0; c < H; c++) {
+            gb2[c] += d2[c];
+            const double z = gelu(a1[c]);
+            for (int j = 0; j < H; j++) gW2[(size_t)c * H + j] += z * d2[j];
+        }
+        for (int c = 0; c < H; c++) {
+            double s = 0.0;
+            for (int j = 0; j < H; j++) s += W2[(size_t)c * H + j] * d2[j];
+            d1[c] = s * gelu_grad(a1[c]);
+            gb1[c] += d1[c];
+        }
+        for (int p = 0; p < 5 * N; p++)
+            if (u[p] != 0.0)
+                for (int c = 0; c < H; c++) gW1[(size_t)p * H + c] += u[p] * d1[c];
+    }
+    free(u); free(a1); free(a2); free(d1); free(d2);
+    return loss / (double)n;
+}
+
+/* Adam (Kingma & Ba 2015) with bias correction, step number t >= 1 */
+void ora_adam_step(double *w, const double *grad, double *m, double *v, int64_t size, double lr, double beta1,
+                   double beta2, double eps, int t) {
+    const double c1 = 1.0 - pow(beta1, t), c2 = 1.0 - pow(beta2, t);
+    for (int64_t q = 0; q < size; q++) {
+        m[q] = beta1 * m[q] + (1.0 - beta1) * grad[q];
+        v[q] = beta2 * v[q] + (1.0 - beta2) * grad[q] * grad[q];
+        w[q] -= lr * (m[q] / c1) / (sqrt(v[q] / c2) + eps);
+    }
+}

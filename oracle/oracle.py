@@ -72,6 +72,15 @@ def _load():
     lib.ora_eloc_model.restype = ctypes.c_int
     lib.ora_eloc_model.argtypes = [_i, _i, _i, _f64p, _f64p, ctypes.c_double, _i, _i, _i, _i, _i, _f64p,
                                    _u64p, ctypes.c_int64, _f64p, _f64p, _i]
+    lib.ora_screen_size.restype = ctypes.c_int64
+    lib.ora_screen_size.argtypes = [_i, _i]
+    lib.ora_screen_forward.restype = None
+    lib.ora_screen_forward.argtypes = [_i, _i, _f64p, _u64p, _u8p, ctypes.c_int64, _f64p]
+    lib.ora_screen_loss_grad.restype = ctypes.c_double
+    lib.ora_screen_loss_grad.argtypes = [_i, _i, _f64p, _u64p, _u8p, _f64p, ctypes.c_int64, _f64p]
+    lib.ora_adam_step.restype = None
+    lib.ora_adam_step.argtypes = [_f64p, _f64p, _f64p, _f64p, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, _i]
     _lib = lib
     return lib
 
@@ -219,3 +228,36 @@ def eloc_model(K, n_up, n_dn, h, g, e_core, weights, shape, keys, nthreads: int 
         raise ValueError("a sample violates the particle numbers")
     e = out[:, 0] + 1j * out[:, 1]
     return (e, ab) if with_absum else e
+
+
+# ------------------------------------------------------------------- screen
+def screen_size(N: int, H: int) -> int:
+    return int(_load().ora_screen_size(N, H))
+
+
+def screen_forward(N, H, w, keys, exc):
+    w = _c(w, np.float64)
+    keys = _c(keys, np.uint64).reshape(-1, 2)
+    exc = _c(exc, np.uint8).reshape(-1, 4)
+    out = np.zeros(keys.shape[0], np.float64)
+    _load().ora_screen_forward(N, H, _p(w, _f64p), _p(keys, _u64p), _p(exc, _u8p), keys.shape[0], _p(out, _f64p))
+    return out
+
+
+def screen_loss_grad(N, H, w, keys, exc, target):
+    w = _c(w, np.float64)
+    keys = _c(keys, np.uint64).reshape(-1, 2)
+    exc = _c(exc, np.uint8).reshape(-1, 4)
+    target = _c(target, np.float64)
+    g = np.zeros(screen_size(N, H), np.float64)
+    loss = _load().ora_screen_loss_grad(N, H, _p(w, _f64p), _p(keys, _u64p), _p(exc, _u8p), _p(target, _f64p),
+                                        keys.shape[0], _p(g, _f64p))
+    return float(loss), g
+
+
+def adam_step(w, grad, m, v, lr, beta1, beta2, eps, t):
+    """In-place Adam update of float64 arrays w, m, v."""
+    for a in (w, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _load().ora_adam_step(_p(w, _f64p), _p(grad, _f64p), _p(m, _f64p), _p(v, _f64p), w.size, lr, beta1, beta2,
+                          eps, int(t))
