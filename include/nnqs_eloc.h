@@ -201,9 +201,10 @@ typedef struct {
 /* Precision of the network evaluation. */
 enum {
     NNQS_FP64 = 0, /* every operation in FP64 (parity path) */
-    NNQS_BF16 = 1  /* BF16 MFMA with FP32 accumulation and FP32 normalisation
+    NNQS_BF16 = 1, /* BF16 MFMA with FP32 accumulation and FP32 normalisation
                       and softmax; log|psi| and phase returned as FP64.
                       Needs d_model 64, n_heads 4, d_ff 256, P 512. */
+    NNQS_FP32 = 2  /* FP32 arithmetic (screen training) */
 };
 
 /* Number of FP32 weights the layout below holds for `desc`; -1 if invalid. */
@@ -229,24 +230,74 @@ nnqs_status nnqs_model_destroy(nnqs_model *model);
 nnqs_status nnqs_model_logpsi(const nnqs_model *model, const uint64_t *keys, int64_t n, int32_t precision,
                               double *logabs, double *phase, void *stream);
 
+/* ----------------------------------------------------------------- screen */
+/* Learned screen (an addition to the paper, whose only filter is the
+ * sample-aware restriction of Section 3.4 item 4): an MLP that predicts
+ * log|psi(x')| of a connected configuration from
+ *   u = [bits of x' (N) | one-hot(i) | one-hot(j) | one-hot(a) | one-hot(b)]
+ * (5N inputs; (i, j, a, b) sorted spin-orbital indices, 255 = absent, as in
+ * nnqs_connections), z1 = GELU(u W1 + b1), z2 = GELU(z1 W2 + b2),
+ * y = z2 . w3 + b3.  It is trained on the network's own amplitudes (mean
+ * squared error, Adam) by these kernels; nnqs_eloc_model can then skip the
+ * transformer for connections whose prediction lies more than `skip_nats`
+ * below the sample's own log|psi|. */
+typedef struct nnqs_screen nnqs_screen;
+
+/* Weights in order W1[5N][H] b1[H] W2[H][H] b2[H] w3[H] b3[1]; -1 if invalid
+ * (N even 4..128, 1 <= H <= 1024). */
+int64_t nnqs_screen_weight_count(int32_t n_spin_orb, int32_t hidden);
+
+/* Creates a screen from host FP64 weights (layout above); Adam moments start
+ * at zero.  Synchronous.  Errors: EINVAL, ENOMEM, EHIP. */
+nnqs_status nnqs_screen_create(nnqs_screen **out, int32_t n_spin_orb, int32_t hidden, const double *weights);
+
+/* Releases the screen.  NULL is accepted. */
+nnqs_status nnqs_screen_destroy(nnqs_screen *screen);
+
+/* Copies the current FP64 weights to the host.  Synchronises `stream`. */
+nnqs_status nnqs_screen_get_weights(const nnqs_screen *screen, double *host_out, void *stream);
+
+/* Predictions for n connections (device xkeys [n][2], exc [n][4]) into device
+ * pred [n].  precision: NNQS_FP64, NNQS_FP32, or NNQS_BF16 (the inference
+ * kernel of nnqs_eloc_model; needs H = 256).  Errors: EINVAL, EUNSUPPORTED,
+ * ENOMEM, EHIP. */
+nnqs_status nnqs_screen_forward(nnqs_screen *screen, const uint64_t *xkeys, const uint8_t *exc, int64_t n,
+                                int32_t precision, double *pred, void *stream);
+
+/* Gradient of loss = mean_k (pred_k - target_k)^2 over the weights (device
+ * grad [count], layout as the weights) and the loss (device loss [1], may be
+ * NULL).  precision NNQS_FP64 or NNQS_FP32; reductions in a fixed order.
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EHIP. */
+nnqs_status nnqs_screen_gradient(nnqs_screen *screen, const uint64_t *xkeys, const uint8_t *exc,
+                                 const double *target, int64_t n, int32_t precision, double *grad, double *loss,
+                                 void *stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected) of the FP64 weights with a
+ * device gradient.  Errors: EINVAL, EHIP. */
+nnqs_status nnqs_screen_adam_step(nnqs_screen *screen, const double *grad, double lr, double beta1, double beta2,
+                                  double eps, void *stream);
+
 /* Counters of a full evaluation (host struct). */
 typedef struct {
     int64_t connections; /* connected configurations enumerated, diagonal included */
-    int64_t evaluated;   /* of these, evaluated by the network (all, without a screen) */
+    int64_t evaluated;   /* of these, evaluated by the network (all without a screen) */
 } nnqs_stats;
 
 /* Full local energies (Eq. 4 over every connected x', psi from the model,
  * the samples' own psi from the model too) of n samples (device keys [n][2],
  * counts [n]) into device eloc [n][2] and energy [4] (layout as in
- * nnqs_eloc_table; energy may be NULL).  The network runs in `precision`;
- * matrix elements, amplitude ratios and all sums are FP64 with compensated
- * summation.  `stats` (host, may be NULL) receives the counters; filling it
- * synchronises `stream`.  Uses library-owned scratch sized at first use
- * (one call at a time per model).  Errors: EINVAL, ECONSERVE (VALIDATE),
- * ENOMEM, EUNSUPPORTED, EHIP. */
-nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model, int32_t precision, const uint64_t *keys,
-                            const uint32_t *counts, int64_t n, double *eloc, double *energy, nnqs_stats *stats,
-                            uint32_t flags, void *stream);
+ * nnqs_eloc_table; energy may be NULL).  With a screen (may be NULL), only
+ * connections whose predicted log|psi(x')| is at least log|psi(x)| -
+ * skip_nats (and the diagonal) are evaluated by the network; the rest
+ * contribute zero.  The network runs in `precision`; matrix elements,
+ * amplitude ratios and all sums are FP64 with compensated summation.
+ * `stats` (host, may be NULL) receives the counters; with a screen or with
+ * stats the call synchronises `stream`.  Uses library-owned scratch sized at
+ * first use (one call at a time per model).  Errors: EINVAL, ECONSERVE
+ * (VALIDATE), ENOMEM, EUNSUPPORTED, EHIP. */
+nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model, nnqs_screen *screen, double skip_nats,
+                            int32_t precision, const uint64_t *keys, const uint32_t *counts, int64_t n,
+                            double *eloc, double *energy, nnqs_stats *stats, uint32_t flags, void *stream);
 
 /* ------------------------------------------------------------- tuning */
 /* Launch parameters of the sample-aware kernel (0 = library default). */

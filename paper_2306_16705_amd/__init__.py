@@ -8,9 +8,11 @@ fallback path.
 from .api import (  # noqa: F401
     NNQSError,
     NNQS_BF16,
+    NNQS_FP32,
     NNQS_FP64,
     NNQS_VALIDATE,
     Model,
+    Screen,
     System,
     Table,
     connections,

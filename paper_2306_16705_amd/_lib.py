@@ -39,8 +39,16 @@ SIGNATURES = {
     "nnqs_model_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p, _c_void_p]),
     "nnqs_model_destroy": (_i32, [_c_void_p]),
     "nnqs_model_logpsi": (_i32, [_c_void_p, _c_void_p, _i64, _i32, _c_void_p, _c_void_p, _c_void_p]),
-    "nnqs_eloc_model": (_i32, [_c_void_p, _c_void_p, _i32, _c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p,
-                               _c_void_p, _u32, _c_void_p]),
+    "nnqs_eloc_model": (_i32, [_c_void_p, _c_void_p, _c_void_p, _f64, _i32, _c_void_p, _c_void_p, _i64, _c_void_p,
+                               _c_void_p, _c_void_p, _u32, _c_void_p]),
+    "nnqs_screen_weight_count": (_i64, [_i32, _i32]),
+    "nnqs_screen_create": (_i32, [ctypes.POINTER(_c_void_p), _i32, _i32, _c_void_p]),
+    "nnqs_screen_destroy": (_i32, [_c_void_p]),
+    "nnqs_screen_get_weights": (_i32, [_c_void_p, _c_void_p, _c_void_p]),
+    "nnqs_screen_forward": (_i32, [_c_void_p, _c_void_p, _c_void_p, _i64, _i32, _c_void_p, _c_void_p]),
+    "nnqs_screen_gradient": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _i32, _c_void_p, _c_void_p,
+                                    _c_void_p]),
+    "nnqs_screen_adam_step": (_i32, [_c_void_p, _c_void_p, _f64, _f64, _f64, _f64, _c_void_p]),
 }
 
 STATUS_NAMES = {0: "NNQS_OK", -1: "NNQS_EINVAL", -2: "NNQS_EDUP", -3: "NNQS_ECONSERVE", -4: "NNQS_ERANGE",
@@ -70,6 +78,7 @@ class Stats(ctypes.Structure):
 
 NNQS_FP64 = 0
 NNQS_BF16 = 1
+NNQS_FP32 = 2
 
 _lib = None
 

@@ -7,7 +7,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from ._lib import NNQS_BF16, NNQS_FP64, NNQS_VALIDATE, ModelDesc, NNQSError, Stats, Tune  # noqa: F401
+from ._lib import NNQS_BF16, NNQS_FP32, NNQS_FP64, NNQS_VALIDATE, ModelDesc, NNQSError, Stats, Tune  # noqa: F401
 
 _KEY_DTYPES = (torch.int64, torch.uint64)
 
@@ -235,8 +235,10 @@ def model_logpsi(model: Model, keys, precision: int = NNQS_FP64, logabs=None, ph
 
 def eloc_model(system: System, model: Model, keys, counts=None, precision: int = NNQS_FP64, eloc=None,
                energy=None, with_energy: bool = True, with_stats: bool = False, validate: bool = False,
-               stream=None):
-    """Full local energies with every x' from the network (``nnqs_eloc_model``).
+               screen=None, skip_nats: float = 12.0, stream=None):
+    """Full local energies with every x' from the network, or with a learned
+    screen only those predicted within ``skip_nats`` of the sample's own
+    amplitude (``nnqs_eloc_model``).
     Returns ``(eloc [n, 2], energy [4] or None, stats dict or None)``."""
     n = keys.shape[0]
     _need(keys, "keys", _KEY_DTYPES, (n, 2))
@@ -247,9 +249,70 @@ def eloc_model(system: System, model: Model, keys, counts=None, precision: int =
     if eloc is None:
         eloc = torch.empty((n, 2), dtype=torch.float64, device=keys.device)
     st = Stats()
-    L.check(L.load().nnqs_eloc_model(system.handle, model.handle, int(precision), _ptr(keys), _ptr(counts), n,
+    L.check(L.load().nnqs_eloc_model(system.handle, model.handle, screen.handle if screen is not None else None,
+                                     float(skip_nats), int(precision), _ptr(keys), _ptr(counts), n,
                                      _ptr(eloc), _ptr(energy) if with_energy else None,
                                      ctypes.byref(st) if with_stats else None, NNQS_VALIDATE if validate else 0,
                                      _stream(stream)))
     stats = {"connections": st.connections, "evaluated": st.evaluated} if with_stats else None
     return eloc, (energy if with_energy else None), stats
+
+
+# ------------------------------------------------------------------ screen
+class Screen:
+    """Learned screen MLP (``nnqs_screen_*``): FP64 master weights on the device."""
+
+    def __init__(self, n_spin_orb: int, hidden: int, weights):
+        self._lib = L.load()
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        cnt = self._lib.nnqs_screen_weight_count(n_spin_orb, hidden)
+        if cnt != w.size:
+            raise ValueError(f"screen needs {cnt} weights, got {w.size}")
+        out = ctypes.c_void_p()
+        L.check(self._lib.nnqs_screen_create(ctypes.byref(out), n_spin_orb, hidden, w.ctypes.data_as(ctypes.c_void_p)))
+        self.handle = out
+        self.n_spin_orb, self.hidden, self.count = n_spin_orb, hidden, int(cnt)
+
+    def weights(self, stream=None) -> np.ndarray:
+        out = np.empty(self.count, np.float64)
+        L.check(self._lib.nnqs_screen_get_weights(self.handle, out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return out
+
+    def forward(self, xkeys, exc, precision: int = NNQS_FP64, out=None, stream=None):
+        n = xkeys.shape[0]
+        _need(xkeys, "xkeys", _KEY_DTYPES, (n, 2))
+        _need(exc, "exc", (torch.uint8,), (n, 4))
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=xkeys.device)
+        L.check(self._lib.nnqs_screen_forward(self.handle, _ptr(xkeys), _ptr(exc), n, int(precision), _ptr(out),
+                                              _stream(stream)))
+        return out
+
+    def gradient(self, xkeys, exc, target, precision: int = NNQS_FP64, grad=None, loss=None, stream=None):
+        n = xkeys.shape[0]
+        _need(xkeys, "xkeys", _KEY_DTYPES, (n, 2))
+        _need(exc, "exc", (torch.uint8,), (n, 4))
+        _need(target, "target", (torch.float64,), (n,))
+        if grad is None:
+            grad = torch.empty(self.count, dtype=torch.float64, device=xkeys.device)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device=xkeys.device)
+        L.check(self._lib.nnqs_screen_gradient(self.handle, _ptr(xkeys), _ptr(exc), _ptr(target), n, int(precision),
+                                               _ptr(grad), _ptr(loss), _stream(stream)))
+        return grad, loss
+
+    def adam_step(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _need(grad, "grad", (torch.float64,), (self.count,))
+        L.check(self._lib.nnqs_screen_adam_step(self.handle, _ptr(grad), float(lr), float(beta1), float(beta2),
+                                                float(eps), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.nnqs_screen_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

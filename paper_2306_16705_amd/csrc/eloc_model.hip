@@ -21,7 +21,8 @@ constexpr int kConnPerBlock = 4096;            // connections handled by one blo
 constexpr int64_t kMaxChunkConnections = 1 << 24;
 
 __global__ void __launch_bounds__(256) k_enum_keys(SysView S, const uint64_t *__restrict__ keys, int64_t m,
-                                                   int64_t blocks_per_sample, uint64_t *__restrict__ out) {
+                                                   int64_t blocks_per_sample, uint64_t *__restrict__ out,
+                                                   uint8_t *__restrict__ exc_out) {
     __shared__ WaveLds wl_all[4];
     const int lane = lane_id();
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -42,7 +43,94 @@ __global__ void __launch_bounds__(256) k_enum_keys(SysView S, const uint64_t *__
         const Key xp = apply_excitation(x, i, j, a, b);
         out[2 * (smp * C + c)] = xp.lo;
         out[2 * (smp * C + c) + 1] = xp.hi;
+        if (exc_out) {  // sorted spin-orbital indices, 255 absent (screen input)
+            uint8_t *e = exc_out + 4 * (smp * C + c);
+            if (j == 255) {
+                e[0] = (uint8_t)i;
+                e[1] = 255;
+                e[2] = (uint8_t)a;
+                e[3] = 255;
+            } else {
+                e[0] = (uint8_t)(i < j ? i : j);
+                e[1] = (uint8_t)(i < j ? j : i);
+                e[2] = (uint8_t)(a < b ? a : b);
+                e[3] = (uint8_t)(a < b ? b : a);
+            }
+        }
     }
+}
+
+// Screen selection: keep the diagonal and every connection whose predicted
+// log|psi(x')| is within skip_nats of the sample's own.  Two-pass
+// deterministic compaction in canonical order.
+constexpr int kSelBlock = 1024;
+
+__global__ void __launch_bounds__(256) k_sel_count(const float *__restrict__ pred, const double *__restrict__ sla,
+                                                   int64_t C, int64_t total, double skip, int32_t *__restrict__ cnt) {
+    __shared__ int sh[256];
+    const int64_t b0 = (int64_t)blockIdx.x * kSelBlock;
+    int c = 0;
+    for (int64_t e = b0 + threadIdx.x; e < b0 + kSelBlock && e < total; e += 256) {
+        const int64_t smp = e / C, cc = e - smp * C;
+        c += (cc == 0 || (double)pred[e] >= sla[smp] - skip) ? 1 : 0;
+    }
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sel_scan(int32_t *__restrict__ cnt, int nblocks, int64_t *__restrict__ total_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t run = 0;
+    for (int b = 0; b < nblocks; b++) {
+        const int v = cnt[b];
+        cnt[b] = (int32_t)run;
+        run += v;
+    }
+    *total_out = run;
+}
+
+__global__ void __launch_bounds__(256) k_sel_write(const float *__restrict__ pred, const double *__restrict__ sla,
+                                                   int64_t C, int64_t total, double skip,
+                                                   const int32_t *__restrict__ off, int32_t *__restrict__ sel,
+                                                   const uint64_t *__restrict__ xkeys, uint64_t *__restrict__ ckeys,
+                                                   double *__restrict__ xla, double *__restrict__ xph) {
+    // one wave walks its block's range in order; ballots keep canonical order
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * kSelBlock;
+    int64_t pos = off[blockIdx.x];
+    for (int64_t e0 = b0; e0 < b0 + kSelBlock && e0 < total; e0 += 64) {
+        const int64_t e = e0 + lane;
+        bool keep = false;
+        if (e < total && e < b0 + kSelBlock) {
+            const int64_t smp = e / C, cc = e - smp * C;
+            keep = cc == 0 || (double)pred[e] >= sla[smp] - skip;
+            xla[e] = -INFINITY;  // skipped connections contribute zero
+            xph[e] = 0.0;
+        }
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int64_t p = pos + __popcll(m & ((1ull << lane) - 1ull));
+            sel[p] = (int32_t)e;
+            ckeys[2 * p] = xkeys[2 * e];
+            ckeys[2 * p + 1] = xkeys[2 * e + 1];
+        }
+        pos += __popcll(m);
+    }
+}
+
+__global__ void k_scatter_sel(const int32_t *__restrict__ sel, const int64_t *__restrict__ nsel,
+                              const double *__restrict__ cla, const double *__restrict__ cph, double *__restrict__ xla,
+                              double *__restrict__ xph) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= *nsel) return;
+    xla[sel[k]] = cla[k];
+    xph[sel[k]] = cph[k];
 }
 
 __global__ void __launch_bounds__(256) k_eloc_partial(SysView S, const uint64_t *__restrict__ keys,
@@ -141,6 +229,20 @@ void eloc_model_free(nnqs_model *m) {
     hipFree(m->d_sla);
     hipFree(m->d_sph);
     hipFree(m->d_partials);
+    hipFree(m->d_xexc);
+    hipFree(m->d_pred);
+    hipFree(m->d_sel);
+    hipFree(m->d_blockcnt);
+    hipFree(m->d_ckeys);
+    hipFree(m->d_cla);
+    hipFree(m->d_cph);
+    hipFree(m->d_nsel);
+    m->d_xexc = nullptr;
+    m->d_pred = nullptr;
+    m->d_sel = m->d_blockcnt = nullptr;
+    m->d_ckeys = nullptr;
+    m->d_cla = m->d_cph = nullptr;
+    m->d_nsel = nullptr;
     m->d_xkeys = nullptr;
     m->d_xla = m->d_xph = m->d_sla = m->d_sph = m->d_partials = nullptr;
     m->xcap = m->scap = 0;
@@ -150,9 +252,10 @@ void eloc_model_free(nnqs_model *m) {
 
 using namespace nnqs;
 
-extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model, int32_t precision,
-                                       const uint64_t *keys, const uint32_t *counts, int64_t n, double *eloc,
-                                       double *energy, nnqs_stats *stats, uint32_t flags, void *stream) {
+extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model, nnqs_screen *screen,
+                                       double skip_nats, int32_t precision, const uint64_t *keys,
+                                       const uint32_t *counts, int64_t n, double *eloc, double *energy,
+                                       nnqs_stats *stats, uint32_t flags, void *stream) {
     clear_error();
     if (!sys || !model || !keys || !eloc) return fail(NNQS_EINVAL, "null pointer argument");
     if (energy && !counts) return fail(NNQS_EINVAL, "energy requested without counts");
@@ -161,6 +264,7 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         return fail(NNQS_EINVAL, "model and system disagree on orbitals or electron numbers");
     if (precision != NNQS_FP64 && precision != NNQS_BF16) return fail(NNQS_EUNSUPPORTED, "unknown precision");
     if (precision == NNQS_BF16 && !model->bf16_ok) return fail(NNQS_EUNSUPPORTED, "model shape has no BF16 path");
+    if (screen && !(skip_nats > 0.0)) return fail(NNQS_EINVAL, "skip_nats must be positive");
     hipStream_t st = as_stream(stream);
     if (flags & NNQS_VALIDATE) {
         hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(1), 0, st, sys->d_status);
@@ -183,6 +287,15 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_xph), (size_t)chunk * C * 8);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_partials),
                                      std::max<size_t>((size_t)chunk * bps * 4, kPartialBlocks * 8) * 8);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_xexc), (size_t)chunk * C * 4);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_pred), (size_t)chunk * C * 4);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_sel), (size_t)chunk * C * 4);
+        if (s1 == NNQS_OK)
+            s1 = grow(reinterpret_cast<void **>(&model->d_blockcnt), ((size_t)chunk * C / kSelBlock + 2) * 4);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_ckeys), (size_t)chunk * C * 16);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cla), (size_t)chunk * C * 8);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cph), (size_t)chunk * C * 8);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_nsel), 8);
         if (s1 != NNQS_OK) {
             eloc_model_free(model);
             return s1;
@@ -201,13 +314,40 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
     }
     nnqs_status s1 = enqueue_logpsi(model, keys, n, precision, model->d_sla, model->d_sph, st);
     if (s1 != NNQS_OK) return s1;
+    int64_t evaluated = 0;
     for (int64_t s0 = 0; s0 < n; s0 += chunk) {
         const int64_t m = n - s0 < chunk ? n - s0 : chunk;
         const unsigned grid = (unsigned)(m * bps);
         hipLaunchKernelGGL(k_enum_keys, dim3(grid), dim3(256), 0, st, sys->view, keys + 2 * s0, m, bps,
-                           model->d_xkeys);
-        s1 = enqueue_logpsi(model, model->d_xkeys, m * C, precision, model->d_xla, model->d_xph, st);
-        if (s1 != NNQS_OK) return s1;
+                           model->d_xkeys, screen ? model->d_xexc : (uint8_t *)nullptr);
+        if (!screen) {
+            s1 = enqueue_logpsi(model, model->d_xkeys, m * C, precision, model->d_xla, model->d_xph, st);
+            if (s1 != NNQS_OK) return s1;
+            evaluated += m * C;
+        } else {
+            const int64_t total = m * C;
+            const int nb = (int)((total + kSelBlock - 1) / kSelBlock);
+            s1 = screen_infer(screen, model->d_xkeys, model->d_xexc, total, model->d_pred, st);
+            if (s1 != NNQS_OK) return s1;
+            hipLaunchKernelGGL(k_sel_count, dim3(nb), dim3(256), 0, st, model->d_pred, model->d_sla + s0, C, total,
+                               skip_nats, model->d_blockcnt);
+            hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(1), 0, st, model->d_blockcnt, nb, model->d_nsel);
+            hipLaunchKernelGGL(k_sel_write, dim3(nb), dim3(64), 0, st, model->d_pred, model->d_sla + s0, C, total,
+                               skip_nats, model->d_blockcnt, model->d_sel, model->d_xkeys, model->d_ckeys,
+                               model->d_xla, model->d_xph);
+            NNQS_HIP_CHECK(hipGetLastError());
+            int64_t nsel = 0;
+            NNQS_HIP_CHECK(hipMemcpyAsync(&nsel, model->d_nsel, 8, hipMemcpyDeviceToHost, st));
+            NNQS_HIP_CHECK(hipStreamSynchronize(st));
+            if (nsel > 0) {
+                s1 = enqueue_logpsi(model, model->d_ckeys, nsel, precision, model->d_cla, model->d_cph, st);
+                if (s1 != NNQS_OK) return s1;
+                hipLaunchKernelGGL(k_scatter_sel, dim3((unsigned)((nsel + 255) / 256)), dim3(256), 0, st,
+                                   model->d_sel, model->d_nsel, model->d_cla, model->d_cph, model->d_xla,
+                                   model->d_xph);
+            }
+            evaluated += nsel;
+        }
         hipLaunchKernelGGL(k_eloc_partial, dim3(grid), dim3(256), 0, st, sys->view, keys + 2 * s0,
                            model->d_sla + s0, model->d_sph + s0, m, bps, model->d_xla, model->d_xph,
                            model->d_partials);
@@ -222,7 +362,7 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
     if (stats) {
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
         stats->connections = n * C;
-        stats->evaluated = n * C;
+        stats->evaluated = evaluated;
     }
     return NNQS_OK;
 }

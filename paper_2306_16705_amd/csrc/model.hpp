@@ -38,6 +38,14 @@ struct nnqs_model {
     double *d_xla = nullptr, *d_xph = nullptr, *d_sla = nullptr, *d_sph = nullptr;
     int64_t xcap = 0, scap = 0;
     double *d_partials = nullptr;
+    // screen scratch (eloc_model.hip)
+    uint8_t *d_xexc = nullptr;
+    float *d_pred = nullptr;
+    int32_t *d_sel = nullptr;       // survivor indices (chunk-local)
+    int32_t *d_blockcnt = nullptr;  // per-block survivor counts / offsets
+    uint64_t *d_ckeys = nullptr;    // compacted survivor keys
+    double *d_cla = nullptr, *d_cph = nullptr;
+    int64_t *d_nsel = nullptr;
 };
 
 namespace nnqs {
@@ -49,4 +57,6 @@ void bf16_model_free(nnqs_model *m);
 nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs,
                                 double *phase, hipStream_t st);
 void eloc_model_free(nnqs_model *m);
+nnqs_status screen_infer(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, int64_t n, float *pred,
+                         hipStream_t st);
 }  // namespace nnqs

@@ -1,0 +1,564 @@
+// Learned screen: an MLP that predicts log|psi(x')| of a connected
+// configuration from the occupation bits of x' and one-hot codes of its
+// excitation indices, trained on amplitudes the network itself produces, so
+// that connections predicted far below the sample's own amplitude can skip
+// the transformer.  (The paper's only filter is the sample-aware restriction
+// of Section 3.4 item 4; this is an addition.)
+//
+//   u  = [bits(x') | onehot(i) | onehot(j) | onehot(a) | onehot(b)]   (5N)
+//   z1 = GELU(u W1 + b1), z2 = GELU(z1 W2 + b2), y = z2 . w3 + b3
+//
+// Master weights and Adam moments are FP64 on the device.  Forward and
+// gradient run in FP64 (parity path) or FP32; every reduction has a fixed
+// order, so results are reproducible.  The inference kernel used inside the
+// full local energy computes the first layer in FP32 from the sparse input
+// and the hidden layer with BF16 MFMA, FP32 accumulation.
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct nnqs_screen {
+    int N = 0, H = 0;
+    int64_t count = 0;
+    double *w = nullptr, *m = nullptr, *v = nullptr;  // FP64 master weights and Adam moments
+    int64_t t = 0;                                     // Adam step count
+    float *w32 = nullptr;                              // FP32 copy (W1 b1 b2 w3 b3 read by inference)
+    __bf16 *w2t = nullptr;                             // BF16 W2 transposed [H][H] (n-major)
+    bool infer_dirty = true;
+    // scratch (grown on demand): activations for gradients
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+namespace nnqs {
+
+struct ScreenOff {
+    int64_t W1, b1, W2, b2, w3, b3, total;
+};
+
+__host__ __device__ inline ScreenOff screen_off(int N, int H) {
+    ScreenOff o{};
+    o.W1 = 0;
+    o.b1 = (int64_t)5 * N * H;
+    o.W2 = o.b1 + H;
+    o.b2 = o.W2 + (int64_t)H * H;
+    o.w3 = o.b2 + H;
+    o.b3 = o.w3 + H;
+    o.total = o.b3 + 1;
+    return o;
+}
+
+template <typename T> __device__ __forceinline__ T gelu_t(T v);
+template <> __device__ __forceinline__ double gelu_t<double>(double v) {
+    return 0.5 * v * (1.0 + erf(v * 0.70710678118654752440));
+}
+template <> __device__ __forceinline__ float gelu_t<float>(float v) {
+    return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f));
+}
+template <typename T> __device__ __forceinline__ T gelu_grad_t(T v) {
+    const T cdf = T(0.5) * (T(1) + (sizeof(T) == 8 ? (T)erf((double)v * 0.70710678118654752440)
+                                                    : (T)erff((float)v * 0.70710678118654752f)));
+    const T pdf = (sizeof(T) == 8 ? (T)exp(-0.5 * (double)v * (double)v) : (T)__expf(-0.5f * (float)v * (float)v)) *
+                  T(0.39894228040143267794);
+    return cdf + v * pdf;
+}
+
+// Active inputs of example k: the set bits of x' and up to four one-hot codes.
+struct ScreenInput {
+    Key x;
+    uint8_t e[4];
+};
+
+__device__ __forceinline__ ScreenInput load_input(const uint64_t *keys, const uint8_t *exc, int64_t k) {
+    ScreenInput in;
+    in.x.lo = keys[2 * k];
+    in.x.hi = keys[2 * k + 1];
+    for (int t = 0; t < 4; t++) in.e[t] = exc[4 * k + t];
+    return in;
+}
+
+// a1[k][c] = b1[c] + sum over active inputs p of W1[p][c]  (one thread per (k, c))
+template <typename T>
+__global__ void k_screen_layer1(int N, int H, const double *__restrict__ w, const uint64_t *__restrict__ keys,
+                                const uint8_t *__restrict__ exc, int64_t n, T *__restrict__ a1) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * H) return;
+    const int64_t k = e / H;
+    const int c = (int)(e - k * H);
+    const ScreenOff o = screen_off(N, H);
+    const ScreenInput in = load_input(keys, exc, k);
+    T acc = (T)w[o.b1 + c];
+    for (int wd = 0; wd < 2; wd++) {
+        uint64_t m = wd ? in.x.hi : in.x.lo;
+        while (m) {
+            const int b = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int p = wd * 64 + b;
+            if (p < N) acc += (T)w[o.W1 + (int64_t)p * H + c];
+        }
+    }
+    for (int t = 0; t < 4; t++)
+        if (in.e[t] != 255) acc += (T)w[o.W1 + (int64_t)((t + 1) * N + in.e[t]) * H + c];
+    a1[e] = acc;
+}
+
+// C[M][Nc] = op(A) op(B) (+ optional row bias, GELU on input, etc. done
+// separately).  Plain 16x16 LDS-tiled product for the training path.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gemm(const T *__restrict__ A, int lda, bool ta, const T *__restrict__ B,
+                                              int ldb, bool tb, T *__restrict__ C, int ldc, int64_t M, int Nc,
+                                              int64_t Kd) {
+    __shared__ T As[16][17], Bs[16][17];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t row = (int64_t)blockIdx.y * 16 + ty;
+    const int col = blockIdx.x * 16 + tx;
+    T acc = 0;
+    for (int64_t k0 = 0; k0 < Kd; k0 += 16) {
+        const int64_t ka = k0 + tx, kb = k0 + ty;
+        const int64_t ar = (int64_t)blockIdx.y * 16 + ty;
+        As[ty][tx] = (ar < M && ka < Kd) ? (ta ? A[ka * lda + ar] : A[ar * lda + ka]) : T(0);
+        Bs[ty][tx] = (kb < Kd && col < Nc) ? (tb ? B[(int64_t)col * ldb + kb] : B[kb * ldb + col]) : T(0);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++) acc += As[ty][kk] * Bs[kk][tx];
+        __syncthreads();
+    }
+    if (row < M && col < Nc) C[row * ldc + col] = acc;
+}
+
+template <typename T> __global__ void k_gelu_copy(const T *__restrict__ a, T *__restrict__ z, int64_t cnt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < cnt) z[e] = gelu_t<T>(a[e]);
+}
+
+template <typename T>
+__global__ void k_add_bias(T *__restrict__ a, const double *__restrict__ b, int64_t n, int H) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n * H) a[e] += (T)b[e % H];
+}
+
+// y[k] = b3 + sum_c GELU(a2[k][c]) w3[c]
+template <typename T>
+__global__ void k_screen_out(const T *__restrict__ a2, const double *__restrict__ w, int N, int H, int64_t n,
+                             T *__restrict__ y) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const ScreenOff o = screen_off(N, H);
+    T acc = (T)w[o.b3];
+    for (int c = 0; c < H; c++) acc += gelu_t<T>(a2[k * H + c]) * (T)w[o.w3 + c];
+    y[k] = acc;
+}
+
+template <typename T>
+__global__ void k_to_double(const T *__restrict__ s, double *__restrict__ d, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) d[k] = (double)s[k];
+}
+
+// gy[k] = 2 (y_k - t_k) / n ; loss partial per block written to lossp
+template <typename T>
+__global__ void k_mse_grad(const T *__restrict__ y, const double *__restrict__ target, int64_t n,
+                           T *__restrict__ gy) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    gy[k] = (T)(2.0 * ((double)y[k] - target[k]) / (double)n);
+}
+
+__global__ void k_mse_loss(const double *__restrict__ target, const void *__restrict__ yv, bool is_double,
+                           int64_t n, double *__restrict__ loss) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+        const double y = is_double ? static_cast<const double *>(yv)[k] : (double)static_cast<const float *>(yv)[k];
+        const double r = y - target[k];
+        s += r * r;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = sh[0] / (double)n;
+}
+
+// d2[k][c] = gy[k] w3[c] GELU'(a2[k][c]); also z2 = GELU(a2) for gw3
+template <typename T>
+__global__ void k_back_out(const T *__restrict__ a2, const T *__restrict__ gy, const double *__restrict__ w, int N,
+                           int H, int64_t n, T *__restrict__ d2, T *__restrict__ z2) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * H) return;
+    const int c = (int)(e % H);
+    const ScreenOff o = screen_off(N, H);
+    const T a = a2[e];
+    d2[e] = gy[e / H] * (T)w[o.w3 + c] * gelu_grad_t<T>(a);
+    z2[e] = gelu_t<T>(a);
+}
+
+// column sums (fixed order): out[c] = sum_k M[k][c] (* vec[k] if vec)
+template <typename T>
+__global__ void k_colsum(const T *__restrict__ Mx, const T *__restrict__ vec, int64_t n, int H,
+                         double *__restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= H) return;
+    double s = 0.0;
+    for (int64_t k = 0; k < n; k++) s += (double)(vec ? Mx[k * H + c] * vec[k] : Mx[k * H + c]);
+    out[c] = s;
+}
+
+template <typename T> __global__ void k_sum(const T *__restrict__ v, int64_t n, double *__restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int64_t k = 0; k < n; k++) s += (double)v[k];
+    *out = s;
+}
+
+// d1 = dz1 * GELU'(a1) in place in dz1
+template <typename T> __global__ void k_mul_gelu_grad(T *__restrict__ dz, const T *__restrict__ a, int64_t cnt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < cnt) dz[e] *= gelu_grad_t<T>(a[e]);
+}
+
+// gW1[p][c] = sum over examples with input p active of d1[k][c] (one thread per (p, c))
+template <typename T>
+__global__ void k_grad_w1(int N, int H, const uint64_t *__restrict__ keys, const uint8_t *__restrict__ exc, int64_t n,
+                          const T *__restrict__ d1, double *__restrict__ g) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)5 * N * H) return;
+    const int p = (int)(e / H), c = (int)(e % H);
+    const int field = p / N, q = p - field * N;
+    double s = 0.0;
+    for (int64_t k = 0; k < n; k++) {
+        bool on;
+        if (field == 0) on = ((q < 64 ? keys[2 * k] : keys[2 * k + 1]) >> (q & 63)) & 1ull;
+        else on = exc[4 * k + field - 1] == q;
+        if (on) s += (double)d1[k * H + c];
+    }
+    g[e] = s;
+}
+
+template <typename T> __global__ void k_store_grad(const T *__restrict__ s, double *__restrict__ d, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) d[k] = (double)s[k];
+}
+
+__global__ void k_adam(double *__restrict__ w, const double *__restrict__ g, double *__restrict__ m,
+                       double *__restrict__ v, int64_t n, double lr, double b1, double b2, double eps, double c1,
+                       double c2) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    m[q] = b1 * m[q] + (1.0 - b1) * g[q];
+    v[q] = b2 * v[q] + (1.0 - b2) * g[q] * g[q];
+    w[q] -= lr * (m[q] / c1) / (sqrt(v[q] / c2) + eps);
+}
+
+__global__ void k_refresh_infer(const double *__restrict__ w, int N, int H, float *__restrict__ w32,
+                                __bf16 *__restrict__ w2t) {
+    const ScreenOff o = screen_off(N, H);
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < o.total) w32[e] = (float)w[e];
+    if (e < (int64_t)H * H) {
+        const int nn = (int)(e / H), k = (int)(e % H);
+        w2t[e] = (__bf16)(float)w[o.W2 + (int64_t)k * H + nn];  // w2t[n][k] = W2[k][n]
+    }
+}
+
+// --------------------------------------------------------------- inference
+// 16 connections per wave: first layer from the sparse input in FP32, into
+// LDS as BF16; hidden layer with v_mfma_f32_16x16x32_bf16 (B tiles from the
+// transposed BF16 W2 in L2); output dot product by DPP row sums.
+constexpr int kScreenH = 256;
+
+__device__ __forceinline__ float dpp_sum16(float v) {
+    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x141, 0xF, 0xF, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x140, 0xF, 0xF, true));
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_screen_infer(int N, const float *__restrict__ w32,
+                                                      const __bf16 *__restrict__ w2t,
+                                                      const uint64_t *__restrict__ keys,
+                                                      const uint8_t *__restrict__ exc, int64_t n,
+                                                      float *__restrict__ pred) {
+    constexpr int H = kScreenH, ZLD = H + 8;
+    __shared__ __align__(16) __bf16 zs[4][16 * ZLD];
+    const int l = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c16 = l & 15, r0 = 4 * (l >> 4), kq = 8 * (l >> 4);
+    __bf16 *Z = zs[w];
+    const ScreenOff o = screen_off(N, H);
+    for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * 16; base < n; base += (int64_t)gridDim.x * 64) {
+        // layer 1: lane (row = c16, quarter = l >> 4) computes 64 of the 256 units of its row
+        const int64_t k = base + c16;
+        const bool ok = k < n;
+        Key x;
+        x.lo = ok ? keys[2 * k] : 0ull;
+        x.hi = ok ? keys[2 * k + 1] : 0ull;
+        uint8_t e4[4] = {255, 255, 255, 255};
+        if (ok)
+            for (int t = 0; t < 4; t++) e4[t] = exc[4 * k + t];
+        const int c0 = (l >> 4) * 64;
+        float acc[64];
+#pragma unroll
+        for (int c = 0; c < 64; c++) acc[c] = w32[o.b1 + c0 + c];
+        for (int wd = 0; wd < 2; wd++) {
+            uint64_t m = wd ? x.hi : x.lo;
+            while (m) {
+                const int b = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                const int p = wd * 64 + b;
+                const float *row = w32 + o.W1 + (int64_t)p * H + c0;
+#pragma unroll
+                for (int c = 0; c < 64; c++) acc[c] += row[c];
+            }
+        }
+        for (int t = 0; t < 4; t++) {
+            if (e4[t] == 255) continue;
+            const float *row = w32 + o.W1 + (int64_t)((t + 1) * N + e4[t]) * H + c0;
+#pragma unroll
+            for (int c = 0; c < 64; c++) acc[c] += row[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 64; c++) Z[c16 * ZLD + c0 + c] = (__bf16)gelu_t<float>(acc[c]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // layer 2 + output
+        float part[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < H / 16; nb++) {
+            f32x4 a2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < H; ks += 32) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(Z + c16 * ZLD + ks + kq);
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(w2t + (int64_t)(nb * 16 + c16) * H + ks + kq);
+                a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, a2, 0, 0, 0);
+            }
+            const float bb = w32[o.b2 + nb * 16 + c16], ww = w32[o.w3 + nb * 16 + c16];
+#pragma unroll
+            for (int i = 0; i < 4; i++) part[i] += gelu_t<float>(a2[i] + bb) * ww;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) part[i] = dpp_sum16(part[i]);
+        if (c16 == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int64_t kk = base + r0 + i;
+                if (kk < n) pred[kk] = part[i] + w32[o.b3];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+static unsigned gridfor(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+static nnqs_status ensure_scratch(nnqs_screen *s, size_t bytes, hipStream_t st) {
+    if (s->scratch_bytes >= bytes) return NNQS_OK;
+    NNQS_HIP_CHECK(hipStreamSynchronize(st));
+    hipFree(s->scratch);
+    s->scratch = nullptr;
+    s->scratch_bytes = 0;
+    if (hipMalloc(&s->scratch, bytes) != hipSuccess) return fail(NNQS_ENOMEM, "screen scratch of %zu bytes", bytes);
+    s->scratch_bytes = bytes;
+    return NNQS_OK;
+}
+
+nnqs_status screen_refresh(nnqs_screen *s, hipStream_t st) {
+    if (!s->infer_dirty) return NNQS_OK;
+    const ScreenOff o = screen_off(s->N, s->H);
+    hipLaunchKernelGGL(k_refresh_infer, dim3(gridfor(o.total)), dim3(256), 0, st, s->w, s->N, s->H, s->w32, s->w2t);
+    NNQS_HIP_CHECK(hipGetLastError());
+    s->infer_dirty = false;
+    return NNQS_OK;
+}
+
+// BF16 inference into FP32 predictions (used by the full local energy).
+nnqs_status screen_infer(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, int64_t n, float *pred,
+                         hipStream_t st) {
+    if (s->H != kScreenH) return fail(NNQS_EUNSUPPORTED, "BF16 screen inference needs hidden = 256");
+    nnqs_status r = screen_refresh(s, st);
+    if (r != NNQS_OK) return r;
+    int64_t blocks = (n + 63) / 64;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_screen_infer, dim3((unsigned)blocks), dim3(256), 0, st, s->N, s->w32, s->w2t, keys, exc, n,
+                       pred);
+    NNQS_HIP_CHECK(hipGetLastError());
+    return NNQS_OK;
+}
+
+__global__ void k_convert_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) d[k] = (float)s[k];
+}
+
+// Forward (and optionally the MSE gradient) in precision T.  Scratch holds
+// a1, z1, a2, d2, z2, dz1 ([n][H] each), y, gy ([n] each), the W2 gradient
+// ([H][H]) and, for FP32, a converted copy of W2 ([H][H]).
+template <typename T>
+static nnqs_status screen_fwd_bwd(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, const double *target,
+                                  int64_t n, double *pred, double *grad, double *loss, hipStream_t st) {
+    const int N = s->N, H = s->H;
+    const ScreenOff o = screen_off(N, H);
+    const size_t nh = (size_t)n * H, hh = (size_t)H * H;
+    nnqs_status r = ensure_scratch(s, (6 * nh + 2 * (size_t)n + 2 * hh) * sizeof(T) + 256, st);
+    if (r != NNQS_OK) return r;
+    T *a1 = static_cast<T *>(s->scratch), *z1 = a1 + nh, *a2 = z1 + nh, *d2 = a2 + nh, *z2 = d2 + nh, *dz1 = z2 + nh,
+      *y = dz1 + nh, *gy = y + n, *w2c = gy + n, *gw2 = w2c + hh;
+    const T *W2;
+    if (sizeof(T) == 8) {
+        W2 = reinterpret_cast<const T *>(s->w + o.W2);
+    } else {
+        hipLaunchKernelGGL(k_convert_f32, dim3(gridfor((int64_t)hh)), dim3(256), 0, st, s->w + o.W2,
+                           reinterpret_cast<float *>(w2c), (int64_t)hh);
+        W2 = w2c;
+    }
+    hipLaunchKernelGGL(k_screen_layer1<T>, dim3(gridfor(nh)), dim3(256), 0, st, N, H, s->w, keys, exc, n, a1);
+    hipLaunchKernelGGL(k_gelu_copy<T>, dim3(gridfor(nh)), dim3(256), 0, st, a1, z1, (int64_t)nh);
+    hipLaunchKernelGGL(k_gemm<T>, dim3(gridfor(H, 16), (unsigned)((n + 15) / 16)), dim3(256), 0, st, z1, H, false, W2,
+                       H, false, a2, H, n, H, (int64_t)H);
+    hipLaunchKernelGGL(k_add_bias<T>, dim3(gridfor(nh)), dim3(256), 0, st, a2, s->w + o.b2, n, H);
+    hipLaunchKernelGGL(k_screen_out<T>, dim3(gridfor(n)), dim3(256), 0, st, a2, s->w, N, H, n, y);
+    if (pred) hipLaunchKernelGGL(k_to_double<T>, dim3(gridfor(n)), dim3(256), 0, st, y, pred, n);
+    if (grad) {
+        if (loss)
+            hipLaunchKernelGGL(k_mse_loss, dim3(1), dim3(256), 0, st, target, (const void *)y, sizeof(T) == 8, n,
+                               loss);
+        hipLaunchKernelGGL(k_mse_grad<T>, dim3(gridfor(n)), dim3(256), 0, st, y, target, n, gy);
+        hipLaunchKernelGGL(k_back_out<T>, dim3(gridfor(nh)), dim3(256), 0, st, a2, gy, s->w, N, H, n, d2, z2);
+        hipLaunchKernelGGL(k_sum<T>, dim3(1), dim3(1), 0, st, gy, n, grad + o.b3);
+        hipLaunchKernelGGL(k_colsum<T>, dim3(gridfor(H)), dim3(256), 0, st, z2, gy, n, H, grad + o.w3);
+        hipLaunchKernelGGL(k_colsum<T>, dim3(gridfor(H)), dim3(256), 0, st, d2, (const T *)nullptr, n, H,
+                           grad + o.b2);
+        // gW2 = z1^T d2 ([H][H])
+        hipLaunchKernelGGL(k_gemm<T>, dim3(gridfor(H, 16), gridfor(H, 16)), dim3(256), 0, st, z1, H, true, d2, H,
+                           false, gw2, H, (int64_t)H, H, n);
+        hipLaunchKernelGGL(k_store_grad<T>, dim3(gridfor((int64_t)hh)), dim3(256), 0, st, gw2, grad + o.W2,
+                           (int64_t)hh);
+        // dz1 = d2 W2^T, then times GELU'(a1)
+        hipLaunchKernelGGL(k_gemm<T>, dim3(gridfor(H, 16), (unsigned)((n + 15) / 16)), dim3(256), 0, st, d2, H,
+                           false, W2, H, true, dz1, H, n, H, (int64_t)H);
+        hipLaunchKernelGGL(k_mul_gelu_grad<T>, dim3(gridfor(nh)), dim3(256), 0, st, dz1, a1, (int64_t)nh);
+        hipLaunchKernelGGL(k_colsum<T>, dim3(gridfor(H)), dim3(256), 0, st, dz1, (const T *)nullptr, n, H,
+                           grad + o.b1);
+        hipLaunchKernelGGL(k_grad_w1<T>, dim3(gridfor((int64_t)5 * N * H)), dim3(256), 0, st, N, H, keys, exc, n,
+                           dz1, grad + o.W1);
+    }
+    NNQS_HIP_CHECK(hipGetLastError());
+    return NNQS_OK;
+}
+
+}  // namespace nnqs
+
+using namespace nnqs;
+
+extern "C" {
+
+int64_t nnqs_screen_weight_count(int32_t n_spin_orb, int32_t hidden) {
+    if (n_spin_orb < 4 || n_spin_orb > 128 || (n_spin_orb & 1) || hidden < 1 || hidden > 1024) return -1;
+    return screen_off(n_spin_orb, hidden).total;
+}
+
+nnqs_status nnqs_screen_create(nnqs_screen **out, int32_t n_spin_orb, int32_t hidden, const double *weights) {
+    clear_error();
+    if (!out || !weights) return fail(NNQS_EINVAL, "null pointer argument");
+    *out = nullptr;
+    const int64_t cnt = nnqs_screen_weight_count(n_spin_orb, hidden);
+    if (cnt < 0) return fail(NNQS_EINVAL, "invalid screen shape (N=%d, hidden=%d)", n_spin_orb, hidden);
+    nnqs_screen *s = new nnqs_screen();
+    s->N = n_spin_orb;
+    s->H = hidden;
+    s->count = cnt;
+    if (hipMalloc(&s->w, cnt * 8) != hipSuccess || hipMalloc(&s->m, cnt * 8) != hipSuccess ||
+        hipMalloc(&s->v, cnt * 8) != hipSuccess || hipMalloc(&s->w32, cnt * 4) != hipSuccess ||
+        hipMalloc(&s->w2t, (size_t)hidden * hidden * 2) != hipSuccess) {
+        nnqs_screen_destroy(s);
+        return fail(NNQS_ENOMEM, "screen allocation failed");
+    }
+    if (hipMemcpy(s->w, weights, cnt * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(s->m, 0, cnt * 8) != hipSuccess || hipMemset(s->v, 0, cnt * 8) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        nnqs_screen_destroy(s);
+        return fail(NNQS_EHIP, "screen initialisation failed");
+    }
+    *out = s;
+    return NNQS_OK;
+}
+
+nnqs_status nnqs_screen_destroy(nnqs_screen *s) {
+    if (!s) return NNQS_OK;
+    hipFree(s->w);
+    hipFree(s->m);
+    hipFree(s->v);
+    hipFree(s->w32);
+    hipFree(s->w2t);
+    hipFree(s->scratch);
+    delete s;
+    return NNQS_OK;
+}
+
+nnqs_status nnqs_screen_get_weights(const nnqs_screen *s, double *host_out, void *stream) {
+    clear_error();
+    if (!s || !host_out) return fail(NNQS_EINVAL, "null pointer argument");
+    hipStream_t st = as_stream(stream);
+    NNQS_HIP_CHECK(hipMemcpyAsync(host_out, s->w, s->count * 8, hipMemcpyDeviceToHost, st));
+    NNQS_HIP_CHECK(hipStreamSynchronize(st));
+    return NNQS_OK;
+}
+
+nnqs_status nnqs_screen_forward(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, int64_t n,
+                                int32_t precision, double *pred, void *stream) {
+    clear_error();
+    if (!s || !keys || !exc || !pred) return fail(NNQS_EINVAL, "null pointer argument");
+    if (n <= 0) return fail(NNQS_EINVAL, "n must be positive");
+    hipStream_t st = as_stream(stream);
+    if (precision == NNQS_FP64) return screen_fwd_bwd<double>(s, keys, exc, nullptr, n, pred, nullptr, nullptr, st);
+    if (precision == NNQS_FP32) return screen_fwd_bwd<float>(s, keys, exc, nullptr, n, pred, nullptr, nullptr, st);
+    if (precision == NNQS_BF16) {
+        nnqs_status r = ensure_scratch(s, (size_t)n * 4 + 256, st);
+        if (r != NNQS_OK) return r;
+        float *p32 = static_cast<float *>(s->scratch);
+        r = screen_infer(s, keys, exc, n, p32, st);
+        if (r != NNQS_OK) return r;
+        hipLaunchKernelGGL(k_to_double<float>, dim3(gridfor(n)), dim3(256), 0, st, p32, pred, n);
+        NNQS_HIP_CHECK(hipGetLastError());
+        return NNQS_OK;
+    }
+    return fail(NNQS_EUNSUPPORTED, "unknown precision %d", precision);
+}
+
+nnqs_status nnqs_screen_gradient(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, const double *target,
+                                 int64_t n, int32_t precision, double *grad, double *loss, void *stream) {
+    clear_error();
+    if (!s || !keys || !exc || !target || !grad) return fail(NNQS_EINVAL, "null pointer argument");
+    if (n <= 0) return fail(NNQS_EINVAL, "n must be positive");
+    hipStream_t st = as_stream(stream);
+    if (precision == NNQS_FP64) return screen_fwd_bwd<double>(s, keys, exc, target, n, nullptr, grad, loss, st);
+    if (precision == NNQS_FP32) return screen_fwd_bwd<float>(s, keys, exc, target, n, nullptr, grad, loss, st);
+    return fail(NNQS_EUNSUPPORTED, "gradients are available in FP64 and FP32");
+}
+
+nnqs_status nnqs_screen_adam_step(nnqs_screen *s, const double *grad, double lr, double beta1, double beta2,
+                                  double eps, void *stream) {
+    clear_error();
+    if (!s || !grad) return fail(NNQS_EINVAL, "null pointer argument");
+    if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+        return fail(NNQS_EINVAL, "invalid Adam hyper-parameters");
+    hipStream_t st = as_stream(stream);
+    s->t += 1;
+    const double c1 = 1.0 - std::pow(beta1, (double)s->t), c2 = 1.0 - std::pow(beta2, (double)s->t);
+    hipLaunchKernelGGL(k_adam, dim3(gridfor(s->count)), dim3(256), 0, st, s->w, grad, s->m, s->v, s->count, lr, beta1,
+                       beta2, eps, c1, c2);
+    NNQS_HIP_CHECK(hipGetLastError());
+    s->infer_dirty = true;
+    return NNQS_OK;
+}
+
+}  // extern "C"
