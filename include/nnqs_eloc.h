@@ -258,7 +258,8 @@ nnqs_status nnqs_screen_destroy(nnqs_screen *screen);
 nnqs_status nnqs_screen_get_weights(const nnqs_screen *screen, double *host_out, void *stream);
 
 /* Predictions for n connections (device xkeys [n][2], exc [n][4]) into device
- * pred [n].  precision: NNQS_FP64, NNQS_FP32, or NNQS_BF16 (the inference
+ * pred [n].  Key bits at or above N and excitation codes >= N (255 included)
+ * contribute no input.  precision: NNQS_FP64, NNQS_FP32, or NNQS_BF16 (the inference
  * kernel of nnqs_eloc_model; needs H = 256).  Errors: EINVAL, EUNSUPPORTED,
  * ENOMEM, EHIP. */
 nnqs_status nnqs_screen_forward(nnqs_screen *screen, const uint64_t *xkeys, const uint8_t *exc, int64_t n,

@@ -652,8 +652,8 @@ int64_t ora_screen_size(int N, int H) { return (int64_t)5 * N * H + H + (int64_t
 static void screen_input(int N, const uint64_t *x, const uint8_t *e, double *u) {
     for (int p = 0; p < 5 * N; p++) u[p] = 0.0;
     for (int p = 0; p < N; p++) u[p] = bit_of(x, p);
-    for (int t = 0; t < 4; t++)
-        if (e[t] != 255) u[(t + 1) * N + e[t]] = 1.0;
+    for (int t = 0; t < 4; t++) /* 255 marks an absent index; other codes >= N are ignored too */
+        if (e[t] < N) u[(t + 1) * N + e[t]] = 1.0;
 }
 
 static double gelu_grad(double v) {

@@ -24,12 +24,35 @@ namespace nnqs {
 // nothing spills to private memory.
 constexpr int kSaMaxThreads = 768;
 
-// Blocked membership filter: the word is picked by the low hash bits, two
-// bit positions inside it by the high word.
-__device__ __forceinline__ bool filter_hit(const uint32_t *f, uint32_t wmask, uint64_t hh) {
-    uint32_t w = f[(uint32_t)hh & wmask];
-    uint32_t hb = (uint32_t)(hh >> 32);
-    return (__builtin_amdgcn_ubfe(w, hb & 31u, 1u) & __builtin_amdgcn_ubfe(w, (hb >> 5) & 31u, 1u)) != 0u;
+// Dynamic LDS layout of the sample-aware kernel: the filter words, the staged
+// search keys, the low 32 bits of the 128 hash words, then one WaveLds per
+// wave (16-byte aligned).
+struct SaLayout {
+    size_t split, hash, waves, total;
+};
+
+__host__ __device__ inline SaLayout sa_layout(int filter_log2, int split_levels, int W, int waves) {
+    SaLayout L;
+    L.split = ((size_t)1 << (filter_log2 - 5)) * 4;
+    L.hash = L.split + (((size_t)1 << split_levels) - 1) * 8 * W;
+    L.waves = (L.hash + 128 * 4 + 15) & ~(size_t)15;
+    L.total = L.waves + sizeof(WaveLds) * waves;
+    return L;
+}
+
+// Two-bit probe of the blocked filter (geometry in internal.hpp).  The bit
+// extracts use the low five bits of their offset operand, which are hash
+// bits 0-4 and 5-9.
+__device__ __forceinline__ uint32_t filter_load(const uint32_t *f, uint32_t wmask, uint32_t h) {
+    // byte offset of word filter_word(h, wmask)
+    const uint32_t off = (h >> (kFilterWordShift - 2)) & (wmask << 2);
+    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(f) + off);
+}
+__device__ __forceinline__ uint32_t filter_test(uint32_t w, uint32_t h) {
+    return __builtin_amdgcn_ubfe(w, h, 1u) & __builtin_amdgcn_ubfe(w, h >> 5, 1u);
+}
+__device__ __forceinline__ uint32_t filter_probe(const uint32_t *f, uint32_t wmask, uint32_t h) {
+    return filter_test(filter_load(f, wmask, h), h);
 }
 
 template <int W>
@@ -40,8 +63,12 @@ __device__ __forceinline__ Key load_key(const uint64_t *k, int64_t i) {
     return r;
 }
 
-// Lower-bound search; the first `split_levels` levels read LDS copies of the
-// keys they probe (every key at positions (m+1)*2^(L-s) - 1).
+// Lower-bound search for t in the sorted table.  The first split_levels
+// levels read LDS copies of the keys they probe (every key at position
+// (m+1)*2^(L-s) - 1).  The remaining levels are taken up to three at a time
+// by 8-way rounds whose probes are independent loads; the last round loads
+// the eight keys from the current lower bound on, so the key the search
+// ends on is already in registers for the equality test.
 template <int W>
 __device__ __forceinline__ int64_t table_find(const TableView &T, const uint64_t *s_lds, const Key &t) {
     const int L = T.log2n, s = T.split_levels;
@@ -54,13 +81,41 @@ __device__ __forceinline__ int64_t table_find(const TableView &T, const uint64_t
         k.hi = (W == 2) ? s_lds[j * W + 1] : 0ull;
         if (key_less(k, t)) lo += step;
     }
-    for (int lvl = s; lvl < L; lvl++) {
-        const int64_t step = int64_t(1) << (L - 1 - lvl);
-        const int64_t idx = lo + step - 1;
-        if (idx < T.n && key_less(load_key<W>(T.keys, idx), t)) lo += step;
+    const int64_t last = T.n - 1;
+    int r = L - s;
+    if (r == 0) return (lo < T.n && key_eq(load_key<W>(T.keys, lo), t)) ? lo : -1;
+    int q = r % 3 == 0 ? 3 : r % 3;  // levels taken by the first round
+    while (r > q) {
+        const int64_t st = int64_t(1) << (r - q);
+        int c = 0;
+        for (int k = 1; k < (1 << q); k++) {
+            const int64_t idx = lo + k * st - 1;
+            const Key kk = load_key<W>(T.keys, idx < last ? idx : last);
+            c += (idx < T.n && key_less(kk, t)) ? 1 : 0;
+        }
+        lo += c * st;
+        r -= q;
+        q = 3;
     }
-    if (lo < T.n && key_eq(load_key<W>(T.keys, lo), t)) return lo;
-    return -1;
+    Key kk[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) kk[k] = load_key<W>(T.keys, lo + k < last ? lo + k : last);
+    const int probes = (1 << q) - 1;
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < 7; k++) c += (k < probes && lo + k < T.n && key_less(kk[k], t)) ? 1 : 0;
+    Key e = kk[0];
+#pragma unroll
+    for (int k = 1; k < 8; k++)
+        if (c == k) e = kk[k];
+    const int64_t pos = lo + c;
+    return (pos < T.n && key_eq(e, t)) ? pos : -1;
+}
+
+__device__ __forceinline__ uint32_t wave_xor32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v ^= __shfl_xor(v, off, 64);
+    return v;
 }
 
 template <int W>
@@ -73,10 +128,11 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView 
     const int nwords = 1 << (lds_filter_log2 - 5);
     const int big_words = 1 << (T.filter_log2 - 5);
     const int nsplit = (1 << T.split_levels) - 1;
+    const SaLayout lay = sa_layout(lds_filter_log2, T.split_levels, W, blockDim.x >> 6);
     uint32_t *f_lds = reinterpret_cast<uint32_t *>(smem);
-    uint64_t *s_lds = reinterpret_cast<uint64_t *>(smem + (size_t)nwords * 4);
-    uint64_t *h_lds = s_lds + (size_t)nsplit * W;
-    WaveLds *wl_all = reinterpret_cast<WaveLds *>(h_lds + 128);
+    uint64_t *s_lds = reinterpret_cast<uint64_t *>(smem + lay.split);
+    uint32_t *h_lds = reinterpret_cast<uint32_t *>(smem + lay.hash);
+    WaveLds *wl_all = reinterpret_cast<WaveLds *>(smem + lay.waves);
 
     // Stage the filter (folded to the LDS size: OR of aliasing words keeps
     // every member), the top search levels and the hash words.
@@ -89,7 +145,7 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView 
         s_lds[(size_t)i * W] = T.split[2 * i];
         if (W == 2) s_lds[(size_t)i * W + 1] = T.split[2 * i + 1];
     }
-    for (int i = threadIdx.x; i < 128; i += blockDim.x) h_lds[i] = S.hashT[i];
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) h_lds[i] = (uint32_t)S.hashT[i];
     __syncthreads();
 
     const int lane = lane_id();
@@ -113,24 +169,27 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView 
             continue;
         }
         build_lists(S, x, wl);
-        // hash of x and per-lane list values held in registers
-        uint64_t part = 0;
+        uint32_t part = 0;
         if (lane < K) {
             if (key_bit(x, 2 * lane)) part ^= h_lds[2 * lane];
             if (key_bit(x, 2 * lane + 1)) part ^= h_lds[2 * lane + 1];
         }
-        const uint64_t hx = wave_xor64(part);
+        const uint32_t hx = wave_xor32(part);
         const double diag = wave_diag(S, x, wl);
-        // per-lane copies of the lists (lane l holds entry l) for wave-uniform
-        // readlane access in the outer loops
-        const int occ_u = lane < nu ? wl.occ[0][lane] : 0;
-        const int occ_d = lane < nd ? wl.occ[1][lane] : 0;
-        const int vir_u = lane < vu ? wl.vir[0][lane] : 0;
-        const uint64_t hocc_u = h_lds[occ_u], hocc_d = h_lds[occ_d], hvir_u = h_lds[vir_u];
+        // Lane l holds entry l of the occupied-up, occupied-down and empty-up
+        // lists as (low hash bits | orbital << 25); the loops read them with
+        // wave-uniform readlane, which yields the orbital with a scalar shift.
+        auto pack = [&](int p) -> uint32_t { return (h_lds[p] & kFilterHashMask) | ((uint32_t)p << 25); };
+        const uint32_t po_u = lane < nu ? pack(wl.occ[0][lane]) : 0u;
+        const uint32_t po_d = lane < nd ? pack(wl.occ[1][lane]) : 0u;
+        const uint32_t pv_u = lane < vu ? pack(wl.vir[0][lane]) : 0u;
 
         NSum are{0.0, 0.0}, aim{0.0, 0.0};
-        int qh = 0, qt = 0;  // wave-uniform ring counters
+        int qh = 0, qt = 0;  // wave-uniform ring counters (ring of 256)
 
+        // Resolve one queued candidate: matrix element first (its integral
+        // loads overlap the search), then the lookup and, on a hit, the
+        // log-polar amplitude ratio into the lane's compensated sums.
         auto process = [&](uint32_t e) {
             const int i = e & 255, j = (e >> 8) & 255, a = (e >> 16) & 255, b = e >> 24;
             Key xp = x;
@@ -142,10 +201,10 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView 
                     key_flip(xp, b);
                 }
             }
+            int sg;
+            const double hv = excitation_element(S, x, diag, i, j, a, b, &sg);
             const int64_t idx = table_find<W>(T, s_lds, xp);
             if (idx >= 0) {
-                int sg;
-                const double hv = excitation_element(S, x, diag, i, j, a, b, &sg);
                 const double r = exp(T.logabs[idx] - la);
                 double sn, cs;
                 sincos(T.phase[idx] - ph, &sn, &cs);
@@ -153,23 +212,22 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView 
                 aim.add(hv * r * sn);
             }
         };
-        auto drain = [&](int cnt) {
-            wave_sync();
-            if (lane < cnt) process(wl.queue[(qh + lane) & 127]);
-            qh += cnt;
-            wave_sync();
-        };
-        auto push = [&](bool cand, uint32_t code) {
-            const uint64_t m = __ballot(cand);
-            if (m) {
-                if (cand) wl.queue[(qt + mbcnt(m)) & 127] = code;
-                qt += __popcll(m);
-                if (qt - qh >= 64) drain(64);
+        auto drain_full = [&]() {
+            while (qt - qh >= 64) {
+                wave_sync();
+                process(wl.queue[(qh + lane) & 255]);
+                qh += 64;
+                wave_sync();
             }
         };
+        // Append the candidates of ballot mask m (uniform) in lane order.
+        auto push = [&](uint64_t m, uint32_t code) {
+            if ((m >> lane) & 1ull) wl.queue[(qt + mbcnt(m)) & 255] = code;
+            qt += __popcll(m);
+        };
 
-        // diagonal: always resolved through the table like any x'
-        push(lane == 0, 0xFFFFFFFFu);
+        // diagonal: resolved through the table like any x'
+        push(1ull, 0xFFFFFFFFu);
 
         // singles
         const int nsu = nu * vu, nsin = nsu + nd * vd;
@@ -187,64 +245,99 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView 
                     v = (t - nsu) - o * vd;
                 }
             }
-            const int q = ok ? wl.occ[sp][o] : 0, p = ok ? wl.vir[sp][v] : 0;
-            const uint64_t hh = hx ^ h_lds[q] ^ h_lds[p];
-            push(ok && filter_hit(f_lds, wmask, hh), (uint32_t)q | 0xFF00u | ((uint32_t)p << 16) | 0xFF000000u);
+            const int q = wl.occ[sp][o], p = wl.vir[sp][v];
+            const uint32_t hh = hx ^ h_lds[q] ^ h_lds[p];
+            const uint64_t m = __ballot(ok && filter_probe(f_lds, wmask, hh) != 0u);
+            if (m) {
+                push(m, (uint32_t)q | 0xFF00u | ((uint32_t)p << 16) | 0xFF000000u);
+                drain_full();
+            }
         }
 
-        // same-spin doubles: lane = empty pair (a<b), loop = occupied pair (i<j)
+        // same-spin doubles: lane = empty pair (a<b), loops = occupied pair
+        // (i<j), the inner one two connections per step
         for (int sp = 0; sp < 2; sp++) {
             const int ns = sp ? nd : nu, nv = sp ? vd : vu;
             const int npv = nv * (nv - 1) / 2;
-            const int occ_s = sp ? occ_d : occ_u;
-            const uint64_t hocc_s = sp ? hocc_d : hocc_u;
+            const uint32_t po_s = sp ? po_d : po_u;
             if (ns < 2 || npv == 0) continue;
             for (int base = 0; base < npv; base += 64) {
                 const int vp = base + lane;
-                const bool ok = vp < npv;
-                int r1 = 0, rem = ok ? vp : 0;
+                const uint64_t okm = __ballot(vp < npv);
+                int r1 = 0, rem = vp < npv ? vp : 0;
                 while (rem >= nv - 1 - r1) {
                     rem -= nv - 1 - r1;
                     r1++;
                 }
                 const int a = wl.vir[sp][r1], b = wl.vir[sp][r1 + 1 + rem];
-                const uint64_t hab = hx ^ h_lds[a] ^ h_lds[b];
+                const uint32_t hab = hx ^ h_lds[a] ^ h_lds[b];
                 const uint32_t cab = ((uint32_t)a << 16) | ((uint32_t)b << 24);
                 for (int o1 = 0; o1 < ns - 1; o1++) {
-                    const int i = readlane32(occ_s, o1);
-                    const uint64_t hi_ = hab ^ readlane64(hocc_s, o1);
-                    for (int o2 = o1 + 1; o2 < ns; o2++) {
-                        const int j = readlane32(occ_s, o2);
-                        const uint64_t hh = hi_ ^ readlane64(hocc_s, o2);
-                        push(ok && filter_hit(f_lds, wmask, hh), cab | (uint32_t)i | ((uint32_t)j << 8));
+                    const uint32_t s1 = (uint32_t)readlane32((int)po_s, o1);
+                    const uint32_t h1 = hab ^ s1, ci = s1 >> 25;
+                    for (int o2 = o1 + 1; o2 < ns; o2 += 2) {
+                        const bool two = o2 + 1 < ns;
+                        const uint32_t sa = (uint32_t)readlane32((int)po_s, o2);
+                        const uint32_t sb = (uint32_t)readlane32((int)po_s, two ? o2 + 1 : o2);
+                        const uint32_t ha = h1 ^ sa, hb = h1 ^ sb;
+                        const uint32_t wa = filter_load(f_lds, wmask, ha);
+                        const uint32_t wb = filter_load(f_lds, wmask, hb);
+                        __builtin_amdgcn_sched_barrier(0);  // both filter reads in flight before the tests
+                        const uint32_t pa = filter_test(wa, ha), pb = filter_test(wb, hb);
+                        const uint64_t ma = __ballot(pa != 0u) & okm;
+                        const uint64_t mb = __ballot(pb != 0u) & (two ? okm : 0ull);
+                        if (ma | mb) {
+                            push(ma, cab | ci | ((sa >> 25) << 8));
+                            push(mb, cab | ci | ((sb >> 25) << 8));
+                            drain_full();
+                        }
                     }
                 }
             }
         }
 
-        // opposite-spin doubles: lane = down single (j -> b), loop = up single (i -> a)
+        // opposite-spin doubles: lane = down single (j -> b), loops = up
+        // single (i -> a), the inner one two connections per step
         const int nsd = nd * vd;
         if (nsu > 0 && nsd > 0) {
             for (int base = 0; base < nsd; base += 64) {
                 const int d = base + lane;
-                const bool ok = d < nsd;
-                const int od = ok ? d / vd : 0;
-                const int bd = ok ? d - od * vd : 0;
+                const uint64_t okm = __ballot(d < nsd);
+                const int od = d < nsd ? d / vd : 0;
+                const int bd = d < nsd ? d - od * vd : 0;
                 const int j = wl.occ[1][od], b = wl.vir[1][bd];
-                const uint64_t hd = hx ^ h_lds[j] ^ h_lds[b];
+                const uint32_t hd = hx ^ h_lds[j] ^ h_lds[b];
                 const uint32_t cjb = ((uint32_t)j << 8) | ((uint32_t)b << 24);
                 for (int o = 0; o < nu; o++) {
-                    const int i = readlane32(occ_u, o);
-                    const uint64_t hdi = hd ^ readlane64(hocc_u, o);
-                    for (int v = 0; v < vu; v++) {
-                        const int a = readlane32(vir_u, v);
-                        const uint64_t hh = hdi ^ readlane64(hvir_u, v);
-                        push(ok && filter_hit(f_lds, wmask, hh), cjb | (uint32_t)i | ((uint32_t)a << 16));
+                    const uint32_t s1 = (uint32_t)readlane32((int)po_u, o);
+                    const uint32_t h1 = hd ^ s1, ci = s1 >> 25;
+                    for (int v = 0; v < vu; v += 2) {
+                        const bool two = v + 1 < vu;
+                        const uint32_t sa = (uint32_t)readlane32((int)pv_u, v);
+                        const uint32_t sb = (uint32_t)readlane32((int)pv_u, two ? v + 1 : v);
+                        const uint32_t ha = h1 ^ sa, hb = h1 ^ sb;
+                        const uint32_t wa = filter_load(f_lds, wmask, ha);
+                        const uint32_t wb = filter_load(f_lds, wmask, hb);
+                        __builtin_amdgcn_sched_barrier(0);  // both filter reads in flight before the tests
+                        const uint32_t pa = filter_test(wa, ha), pb = filter_test(wb, hb);
+                        const uint64_t ma = __ballot(pa != 0u) & okm;
+                        const uint64_t mb = __ballot(pb != 0u) & (two ? okm : 0ull);
+                        if (ma | mb) {
+                            push(ma, cjb | ci | ((sa >> 25) << 16));
+                            push(mb, cjb | ci | ((sb >> 25) << 16));
+                            drain_full();
+                        }
                     }
                 }
             }
         }
-        if (qt > qh) drain(qt - qh);
+        while (qt > qh) {
+            const int cnt = qt - qh < 64 ? qt - qh : 64;
+            wave_sync();
+            if (lane < cnt) process(wl.queue[(qh + lane) & 255]);
+            qh += cnt;
+            wave_sync();
+        }
 
         double rs = are.s, rc = are.c, is = aim.s, ic = aim.c;
         wave_nsum(rs, rc);
@@ -344,8 +437,7 @@ __global__ void k_validate_samples(SysView S, const uint64_t *__restrict__ keys,
 __global__ void k_zero_int(int *p) { *p = 0; }
 
 static size_t sa_lds_bytes(int filter_log2, int split_levels, int W, int waves) {
-    return ((size_t)1 << (filter_log2 - 5)) * 4 + (((size_t)1 << split_levels) - 1) * 8 * W + 128 * 8 +
-           sizeof(WaveLds) * waves;
+    return sa_layout(filter_log2, split_levels, W, waves).total;
 }
 
 }  // namespace nnqs

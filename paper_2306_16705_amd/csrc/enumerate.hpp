@@ -9,7 +9,7 @@ namespace nnqs {
 struct WaveLds {
     uint8_t occ[2][64];  // occupied spin orbitals per spin, ascending
     uint8_t vir[2][64];  // empty spin orbitals per spin, ascending
-    uint32_t queue[128]; // candidate ring: i | j<<8 | a<<16 | b<<24 (255 = none)
+    uint32_t queue[256]; // candidate ring: i | j<<8 | a<<16 | b<<24 (255 = none)
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }

@@ -264,6 +264,17 @@ nnqs_status enqueue_energy_partials(double *partials, const uint32_t *counts, co
 // Synchronise and read/clear the sticky status.
 nnqs_status read_status(nnqs_table *tab, hipStream_t st, bool clear);
 constexpr int kMaxFilterLog2 = 20;
+
+// Membership-filter geometry, read from the low 32 bits of the linear key
+// hash: bits 0-4 and 5-9 select two bits of a 32-bit filter word, bits
+// 10..(filter_log2 + 4) select the word.  Bits 25-31 are never read, which
+// lets the enumeration kernel pack an orbital index into them.
+constexpr int kFilterWordShift = 10;
+constexpr uint32_t kFilterHashMask = 0x01FFFFFFu;
+static_assert(kMaxFilterLog2 - 5 + kFilterWordShift <= 25, "filter word index must stay below bit 25");
+
+__device__ __forceinline__ uint32_t filter_word(uint32_t h, uint32_t wmask) { return (h >> kFilterWordShift) & wmask; }
+__device__ __forceinline__ uint32_t filter_bits(uint32_t h) { return (1u << (h & 31u)) | (1u << ((h >> 5) & 31u)); }
 constexpr int kMaxSplitLevels = 13;
 constexpr int kPartialBlocks = 1024;
 }  // namespace nnqs

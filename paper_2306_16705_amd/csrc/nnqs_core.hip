@@ -179,12 +179,9 @@ __global__ void k_table_finalize(SysView S, const uint64_t *__restrict__ sk, con
     if (i > 0 && sk[2 * i - 2] == lo && sk[2 * i - 1] == hi) set_status(status, NNQS_EDUP);
     if (!isfinite(l) || !isfinite(ph_in[src])) set_status(status, NNQS_ERANGE);
     if (!key_conserves(S, lo, hi)) set_status(status, NNQS_ECONSERVE);
-    uint64_t h = key_hash(S, lo, hi);
-    uint32_t words_mask = (1u << (filter_log2 - 5)) - 1u;
-    uint32_t w = (uint32_t)h & words_mask;
-    uint32_t hb = (uint32_t)(h >> 32);
-    uint32_t bits = (1u << (hb & 31u)) | (1u << ((hb >> 5) & 31u));
-    atomicOr(&filter[w], bits);
+    const uint32_t h = (uint32_t)key_hash(S, lo, hi);
+    const uint32_t words_mask = (1u << (filter_log2 - 5)) - 1u;
+    atomicOr(&filter[filter_word(h, words_mask)], filter_bits(h));
 }
 
 __global__ void k_table_split(const uint64_t *__restrict__ keys, int64_t n, int log2n, int levels,

@@ -101,8 +101,8 @@ __global__ void k_screen_layer1(int N, int H, const double *__restrict__ w, cons
             if (p < N) acc += (T)w[o.W1 + (int64_t)p * H + c];
         }
     }
-    for (int t = 0; t < 4; t++)
-        if (in.e[t] != 255) acc += (T)w[o.W1 + (int64_t)((t + 1) * N + in.e[t]) * H + c];
+    for (int t = 0; t < 4; t++)  // 255 (absent) and any other code >= N add nothing
+        if (in.e[t] < N) acc += (T)w[o.W1 + (int64_t)((t + 1) * N + in.e[t]) * H + c];
     a1[e] = acc;
 }
 
@@ -313,13 +313,14 @@ __global__ void __launch_bounds__(256) k_screen_infer(int N, const float *__rest
                 const int b = __ffsll((unsigned long long)m) - 1;
                 m &= m - 1;
                 const int p = wd * 64 + b;
+                if (p >= N) break;  // bits above the spin orbitals carry no input
                 const float *row = w32 + o.W1 + (int64_t)p * H + c0;
 #pragma unroll
                 for (int c = 0; c < 64; c++) acc[c] += row[c];
             }
         }
         for (int t = 0; t < 4; t++) {
-            if (e4[t] == 255) continue;
+            if (e4[t] >= N) continue;  // absent
             const float *row = w32 + o.W1 + (int64_t)((t + 1) * N + e4[t]) * H + c0;
 #pragma unroll
             for (int c = 0; c < 64; c++) acc[c] += row[c];

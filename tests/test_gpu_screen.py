@@ -1,0 +1,163 @@
+"""GPU parity of the learned screen (forward, MSE gradient, Adam) against the
+FP64 oracle, and the gain of a trained screen inside the full local energy."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import dev, eloc_complex
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_16705_amd as nn
+    return nn
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} {kw}", flush=True)
+
+
+def _connection_inputs(K, n, seed):
+    """``n`` random (x', excitation) pairs from the oracle's enumeration of a
+    few samples of an N=2K system, with random regression targets."""
+    d = synth.config_inputs(2, K=K, n_up=K // 4, n_dn=K // 4, n_unique=16)
+    rng = np.random.default_rng(seed)
+    keys, excs = [], []
+    for k in rng.choice(len(d["keys"]), size=4, replace=False):
+        xp, _, exc, _ = oracle.connections(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], 0.0, d["keys"][k])
+        c = rng.choice(len(xp), size=(n + 3) // 4, replace=len(xp) < (n + 3) // 4)
+        keys.append(xp[c])
+        excs.append(exc[c])
+    keys = np.concatenate(keys)[:n]
+    excs = np.concatenate(excs)[:n]
+    return keys, excs, rng.normal(-6.0, 3.0, size=n)
+
+
+def _weights(N, H, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, 0.15, size=oracle.screen_size(N, H))
+
+
+@pytest.mark.parametrize("K,H,n", [(24, 256, 300), (24, 40, 37), (12, 16, 1), (60, 256, 129)])
+def test_forward_and_gradient_fp64_match_oracle(nn, K, H, n):
+    N = 2 * K
+    _print_case("screen_fp64", N=N, H=H, n=n)
+    keys, exc, target = _connection_inputs(K, n, seed=K + H)
+    w = _weights(N, H, seed=n)
+    S = nn.Screen(N, H, w)
+    pred = S.forward(dev(keys), dev(exc), nn.NNQS_FP64).cpu().numpy()
+    ref = oracle.screen_forward(N, H, w, keys, exc)
+    assert np.max(np.abs(pred - ref) / np.maximum(1.0, np.abs(ref))) < 1e-12
+    g, loss = S.gradient(dev(keys), dev(exc), dev(target), nn.NNQS_FP64)
+    oloss, og = oracle.screen_loss_grad(N, H, w, keys, exc, target)
+    assert abs(loss.item() - oloss) <= 1e-12 * max(1.0, abs(oloss))
+    g = g.cpu().numpy()
+    assert np.max(np.abs(g - og)) <= 1e-11 * np.abs(og).max()
+
+
+@pytest.mark.parametrize("K,H,n", [(24, 256, 300), (24, 40, 37)])
+def test_fp32_error_vs_oracle(nn, K, H, n):
+    """FP32 training precision: forward within 1e-4 (1 + |y|) and gradient
+    within 1e-4 of its largest component, against the FP64 oracle."""
+    N = 2 * K
+    _print_case("screen_fp32", N=N, H=H, n=n)
+    keys, exc, target = _connection_inputs(K, n, seed=3 * K + H)
+    w = _weights(N, H, seed=7)
+    S = nn.Screen(N, H, w)
+    pred = S.forward(dev(keys), dev(exc), nn.NNQS_FP32).cpu().numpy()
+    ref = oracle.screen_forward(N, H, w, keys, exc)
+    assert np.all(np.abs(pred - ref) <= 1e-4 * (1.0 + np.abs(ref)))
+    g, loss = S.gradient(dev(keys), dev(exc), dev(target), nn.NNQS_FP32)
+    oloss, og = oracle.screen_loss_grad(N, H, w, keys, exc, target)
+    rel = np.max(np.abs(g.cpu().numpy() - og)) / np.abs(og).max()
+    print(f"FP32 screen: max fwd err {np.max(np.abs(pred - ref)):.3e}, grad rel {rel:.3e}, "
+          f"loss {loss.item():.6g} vs {oloss:.6g}")
+    assert rel < 1e-4
+    assert abs(loss.item() - oloss) <= 1e-4 * max(1.0, abs(oloss))
+
+
+def test_adam_steps_match_oracle(nn):
+    """Three FP64 gradient + Adam steps on the device against the same three
+    steps of the oracle (each side computes its own gradients)."""
+    K, H, n = 24, 64, 200
+    N = 2 * K
+    _print_case("screen_adam", N=N, H=H, n=n)
+    keys, exc, target = _connection_inputs(K, n, seed=11)
+    w = _weights(N, H, seed=12)
+    S = nn.Screen(N, H, w)
+    dk, de, dt = dev(keys), dev(exc), dev(target)
+    ow, om, ov = w.copy(), np.zeros_like(w), np.zeros_like(w)
+    for t in range(1, 4):
+        g, _ = S.gradient(dk, de, dt, nn.NNQS_FP64)
+        S.adam_step(g, lr=1e-2)
+        _, og = oracle.screen_loss_grad(N, H, ow, keys, exc, target)
+        oracle.adam_step(ow, og, om, ov, 1e-2, 0.9, 0.999, 1e-8, t)
+    gw = S.weights()
+    assert np.max(np.abs(gw - ow)) <= 1e-10 * max(1.0, np.abs(ow).max())
+
+
+@pytest.mark.parametrize("n", [1, 64, 1000])
+def test_bf16_inference_error_vs_oracle(nn, n):
+    """BF16 inference (FP32 sparse first layer, BF16 MFMA second layer): the
+    error against the FP64 oracle is within 0.05 + 0.01 |y| nats, far inside
+    the 12-nat skip margin it serves."""
+    K, H = 60, 256
+    N = 2 * K
+    _print_case("screen_bf16", N=N, H=H, n=n)
+    keys, exc, _ = _connection_inputs(K, n, seed=n)
+    w = _weights(N, H, seed=n + 1)
+    S = nn.Screen(N, H, w)
+    pred = S.forward(dev(keys), dev(exc), nn.NNQS_BF16).cpu().numpy()
+    ref = oracle.screen_forward(N, H, w, keys, exc)
+    err = np.abs(pred - ref)
+    print(f"BF16 screen n={n}: max err {err.max():.3e} over y range [{ref.min():.3f}, {ref.max():.3f}]")
+    assert np.all(err <= 0.05 + 0.01 * np.abs(ref))
+
+
+def test_screen_shape_errors(nn):
+    w = _weights(24, 40, 0)
+    S = nn.Screen(24, 40, w)
+    keys, exc, _ = _connection_inputs(12, 8, 0)
+    with pytest.raises(nn.NNQSError):  # BF16 inference is built for hidden = 256
+        S.forward(dev(keys), dev(exc), nn.NNQS_BF16)
+    with pytest.raises(nn.NNQSError):
+        S.gradient(dev(keys), dev(exc), dev(np.zeros(8)), nn.NNQS_BF16)
+    with pytest.raises(ValueError):
+        nn.Screen(24, 40, w[:-1])
+
+
+def test_trained_screen_cuts_evaluations_within_1e4_ha(nn):
+    """A screen trained on connections of training samples (labels: the
+    network's own log|psi(x')|) skips most network evaluations of held-out
+    samples while the weighted energy moves by at most 1e-4 Ha."""
+    from paper_2306_16705_amd import screen_train
+    d = synth.config_inputs(2, n_unique=96, model=True)
+    _print_case("screen_gain", K=d["K"])
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    keys = dev(d["keys"])
+    train_keys, test_keys = keys[:64], keys[64:]
+    test_cnt = dev(d["counts"][64:], torch.int32)
+    xk, ex, lab = screen_train.connection_dataset(S, M, train_keys, per_sample=2048, seed=1)
+    scr = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=2))
+    losses = screen_train.train(scr, xk, ex, lab, steps=800, batch=4096, lr=2e-3, seed=3)
+    print(f"screen training loss {losses[0]:.4g} -> {np.mean(losses[-20:]):.4g} on {xk.shape[0]} pairs")
+    assert np.mean(losses[-20:]) < 0.1 * losses[0]
+    e0, en0, st0 = nn.eloc_model(S, M, test_keys, test_cnt, nn.NNQS_BF16, with_stats=True)
+    e1, en1, st1 = nn.eloc_model(S, M, test_keys, test_cnt, nn.NNQS_BF16, with_stats=True, screen=scr,
+                                 skip_nats=12.0)
+    torch.cuda.synchronize()
+    de = abs(en1[0].item() - en0[0].item())
+    frac = st1["evaluated"] / st1["connections"]
+    per = np.max(np.abs(eloc_complex(e1) - eloc_complex(e0)))
+    print(f"screened: evaluated {st1['evaluated']} of {st1['connections']} ({frac:.3f}), "
+          f"|dE| {de:.3e} Ha, max per-sample |dE_loc| {per:.3e}")
+    assert st0["evaluated"] == st0["connections"]
+    assert frac < 0.5
+    assert de <= 1e-4
