@@ -30,6 +30,33 @@ ALU_OPS_PER_CONNECTION = 8
 ALU_PEAK_GOPS = 256 * 64 * 2.4
 
 
+# HBM traffic of one k_eloc_sa<1> launch on this workload: rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the same
+# counter reads for a plain device copy of known size.  The figures hold only
+# for the kernel sources they were taken with (hash below); otherwise the
+# bench reports no traffic.
+SA_COUNTERS = {"sources_sha256_16": None, "fetch_kib": None, "write_kib": None,
+               "fetch_scale": 2.0, "write_scale": 1.0}
+SA_SOURCES = ("paper_2306_16705_amd/csrc/eloc_sa.hip", "paper_2306_16705_amd/csrc/enumerate.hpp",
+              "paper_2306_16705_amd/csrc/internal.hpp")
+
+
+def sa_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SA_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def sa_traffic_bytes():
+    c = SA_COUNTERS
+    if c["fetch_kib"] is None or c["sources_sha256_16"] != sa_sources_hash():
+        return None
+    return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -41,6 +68,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-samples", type=int, default=8192,
                     help="samples the oracle evaluates for the CPU baseline (0 = skip)")
+    ap.add_argument("--full-samples", type=int, default=16,
+                    help="samples of the N=120 transformer workload timed in the full-E_loc leg (0 = skip)")
+    ap.add_argument("--fp64-samples", type=int, default=1,
+                    help="of these, samples also evaluated by the plain FP64 path (error reference)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
@@ -133,6 +164,8 @@ def main():
                "sample": f"first {m} of the {n} samples against the full table, FP64, {dt:.2f} s wall",
                "connections_per_s": m * C / dt}
 
+    full = full_path_leg(args, nn, synth, np, torch) if args.full_samples > 0 else None
+
     out = {
         "metric": "E_loc samples/s + connections/s at 1e-4 Ha error; learned/BF16 vs plain",
         "value": samples_s,
@@ -153,11 +186,75 @@ def main():
         "energy": float(en[0]),
         "max_abs_err_vs_oracle_ha": max_err,
         "roofline": {"bound": "alu", "kernel": "k_eloc_sa<1>", "achieved": achieved, "peak": ALU_PEAK_GOPS,
-                     "unit": "Gop/s", "frac": achieved / ALU_PEAK_GOPS, "traffic": None,
+                     "unit": "Gop/s", "frac": achieved / ALU_PEAK_GOPS, "traffic": sa_traffic_bytes(),
+                     "traffic_unit": "bytes per launch", "sources_sha256_16": sa_sources_hash(),
                      "kernel_ms": kernel_ms, "ops_per_connection": ALU_OPS_PER_CONNECTION},
         "cpu_baseline": cpu,
+        "full_path": full,
     }
     print(json.dumps(out), flush=True)
+
+
+def full_path_leg(args, nn, synth, np, torch):
+    """Full E_loc on the N=120 (20 up + 20 down) transformer workload: plain
+    FP64, plain BF16, and BF16 behind the learned screen with FP64
+    refinement of the large terms.  The screen is trained first (untimed) on
+    connections of 16 further samples."""
+    log("full path: N=120 transformer workload")
+    n = args.full_samples
+    d = synth.config_inputs(3, n_unique=n + 16)
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    C = S.connection_count
+    keys = torch.from_numpy(d["keys"].view(np.int64).copy()).cuda()
+    cnt = torch.from_numpy(d["counts"].astype(np.int32)).cuda()
+    from paper_2306_16705_amd import screen_train
+    t = time.perf_counter()
+    xk, ex, lab = screen_train.connection_dataset(S, M, keys[n:], per_sample=8192, seed=1)
+    scr = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=2))
+    losses = screen_train.train(scr, xk, ex, lab, steps=1500, batch=4096, lr=2e-3, seed=3)
+    t_train = time.perf_counter() - t
+    log(f"screen trained in {t_train:.1f} s, loss {losses[0]:.4g} -> {float(np.mean(losses[-20:])):.4g}")
+    tk, tc = keys[:n].contiguous(), cnt[:n].contiguous()
+    screened_kw = dict(screen=scr, skip_nats=18.0, skip_rule=nn.NNQS_SKIP_CONTRIBUTION, refine_nats=8.0)
+
+    def timed(prec, k, c, **kw):
+        nn.eloc_model(S, M, k[:1], c[:1], prec, **kw)  # warm scratch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, en, st = nn.eloc_model(S, M, k, c, prec, with_stats=True, **kw)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e.cpu().numpy(), en.cpu().numpy(), st
+
+    dt16, e16, en16, st16 = timed(nn.NNQS_BF16, tk, tc)
+    dts, es, ens, sts = timed(nn.NNQS_BF16, tk, tc, **screened_kw)
+    m = min(args.fp64_samples, n)
+    res = {"workload": f"full E_loc, N=120 (K=60), 20 up + 20 down, transformer d_model 64, 4 layers, 4 heads, "
+                       f"FFN 256 + phase MLP, {n} samples ({C} connections each)",
+           "samples": n, "connections_per_sample": C,
+           "plain_bf16": {"samples_per_s": n / dt16, "connections_per_s": n * C / dt16, "energy": float(en16[0])},
+           "screened_bf16_refined": {"samples_per_s": n / dts, "connections_per_s": n * C / dts,
+                                     "energy": float(ens[0]), "evaluated_fraction": sts["evaluated"] / sts["connections"],
+                                     "refined_fraction": sts["refined"] / sts["connections"],
+                                     "skip_rule": "contribution", "skip_nats": 18.0, "refine_nats": 8.0},
+           "screen_training_s": t_train,
+           "speedup_screened_vs_plain_bf16": dt16 / dts}
+    if m > 0:
+        dt64, e64, en64, _ = timed(nn.NNQS_FP64, tk[:m].contiguous(), tc[:m].contiguous())
+        w = d["counts"][:m].astype(np.float64)
+
+        def energy_of(e):
+            return float(np.sum(w * e[:m, 0]) / np.sum(w))
+        ref = energy_of(e64)
+        res["plain_fp64"] = {"samples_per_s": m / dt64, "connections_per_s": m * C / dt64, "samples": m,
+                             "energy": ref}
+        res["energy_err_vs_fp64_ha"] = {"plain_bf16": energy_of(e16) - ref,
+                                        "screened_bf16_refined": energy_of(es) - ref,
+                                        "over_samples": m}
+        res["speedup_screened_vs_plain_fp64"] = (n / dts) / (m / dt64)
+    log(f"full path: plain BF16 {n / dt16:.3g} samples/s, screened {n / dts:.3g} samples/s "
+        f"({res['speedup_screened_vs_plain_bf16']:.2f}x)")
+    return res
 
 
 if __name__ == "__main__":

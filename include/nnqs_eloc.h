@@ -281,24 +281,46 @@ nnqs_status nnqs_screen_adam_step(nnqs_screen *screen, const double *grad, doubl
 /* Counters of a full evaluation (host struct). */
 typedef struct {
     int64_t connections; /* connected configurations enumerated, diagonal included */
-    int64_t evaluated;   /* of these, evaluated by the network (all without a screen) */
+    int64_t evaluated;   /* of these, evaluated by the network in `precision` (all without a screen) */
+    int64_t refined;     /* of these, evaluated again by the FP64 network (refinement) */
 } nnqs_stats;
+
+/* Screen rules: a connection x' goes to the network when
+ *   NNQS_SKIP_RATIO:        pred(x') >= log|psi(x)| - skip_nats
+ *   NNQS_SKIP_CONTRIBUTION: log|H_xx'| + pred(x') >= log|psi(x)| - skip_nats
+ * (the second bounds the skipped term |H_xx' psi(x')/psi(x)| by
+ * exp(-skip_nats) Ha when the prediction is right). */
+enum { NNQS_SKIP_RATIO = 0, NNQS_SKIP_CONTRIBUTION = 1 };
+
+/* Options of nnqs_eloc_model (NULL = {12, NNQS_SKIP_RATIO, 0}).
+ * refine_nats > 0 turns on the precision ladder for a lower-precision
+ * network: the samples' own amplitudes come from the FP64 network, and every
+ * connection whose first-pass contribution |H_xx' psi(x')/psi(x)| is at
+ * least exp(-refine_nats) Ha (and the diagonal) is evaluated again by the
+ * FP64 network, so the lower precision only touches the terms below that
+ * size. */
+typedef struct {
+    double skip_nats;
+    int32_t skip_rule;
+    double refine_nats;
+} nnqs_eloc_opts;
 
 /* Full local energies (Eq. 4 over every connected x', psi from the model,
  * the samples' own psi from the model too) of n samples (device keys [n][2],
  * counts [n]) into device eloc [n][2] and energy [4] (layout as in
  * nnqs_eloc_table; energy may be NULL).  With a screen (may be NULL), only
- * connections whose predicted log|psi(x')| is at least log|psi(x)| -
- * skip_nats (and the diagonal) are evaluated by the network; the rest
- * contribute zero.  The network runs in `precision`; matrix elements,
- * amplitude ratios and all sums are FP64 with compensated summation.
- * `stats` (host, may be NULL) receives the counters; with a screen or with
- * stats the call synchronises `stream`.  Uses library-owned scratch sized at
- * first use (one call at a time per model).  Errors: EINVAL, ECONSERVE
- * (VALIDATE), ENOMEM, EUNSUPPORTED, EHIP. */
-nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model, nnqs_screen *screen, double skip_nats,
-                            int32_t precision, const uint64_t *keys, const uint32_t *counts, int64_t n,
-                            double *eloc, double *energy, nnqs_stats *stats, uint32_t flags, void *stream);
+ * the diagonal and the connections the screen rule of `opts` keeps are
+ * evaluated by the network; the rest contribute zero.  The network runs in
+ * `precision` (then, with refinement, FP64 for the large terms); matrix
+ * elements, amplitude ratios and all sums are FP64 with compensated
+ * summation.  `stats` (host, may be NULL) receives the counters; with a
+ * screen, refinement or stats the call synchronises `stream`.  Uses
+ * library-owned scratch sized at first use (one call at a time per model).
+ * Errors: EINVAL, ECONSERVE (VALIDATE), ENOMEM, EUNSUPPORTED, EHIP. */
+nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model, nnqs_screen *screen,
+                            const nnqs_eloc_opts *opts, int32_t precision, const uint64_t *keys,
+                            const uint32_t *counts, int64_t n, double *eloc, double *energy, nnqs_stats *stats,
+                            uint32_t flags, void *stream);
 
 /* ------------------------------------------------------------- tuning */
 /* Launch parameters of the sample-aware kernel (0 = library default). */

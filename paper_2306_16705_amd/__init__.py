@@ -10,6 +10,8 @@ from .api import (  # noqa: F401
     NNQS_BF16,
     NNQS_FP32,
     NNQS_FP64,
+    NNQS_SKIP_CONTRIBUTION,
+    NNQS_SKIP_RATIO,
     NNQS_VALIDATE,
     Model,
     Screen,

@@ -39,8 +39,8 @@ SIGNATURES = {
     "nnqs_model_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p, _c_void_p]),
     "nnqs_model_destroy": (_i32, [_c_void_p]),
     "nnqs_model_logpsi": (_i32, [_c_void_p, _c_void_p, _i64, _i32, _c_void_p, _c_void_p, _c_void_p]),
-    "nnqs_eloc_model": (_i32, [_c_void_p, _c_void_p, _c_void_p, _f64, _i32, _c_void_p, _c_void_p, _i64, _c_void_p,
-                               _c_void_p, _c_void_p, _u32, _c_void_p]),
+    "nnqs_eloc_model": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i32, _c_void_p, _c_void_p, _i64,
+                               _c_void_p, _c_void_p, _c_void_p, _u32, _c_void_p]),
     "nnqs_screen_weight_count": (_i64, [_i32, _i32]),
     "nnqs_screen_create": (_i32, [ctypes.POINTER(_c_void_p), _i32, _i32, _c_void_p]),
     "nnqs_screen_destroy": (_i32, [_c_void_p]),
@@ -73,7 +73,15 @@ class ModelDesc(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("connections", _i64), ("evaluated", _i64)]
+    _fields_ = [("connections", _i64), ("evaluated", _i64), ("refined", _i64)]
+
+
+class ElocOpts(ctypes.Structure):
+    _fields_ = [("skip_nats", _f64), ("skip_rule", _i32), ("refine_nats", _f64)]
+
+
+NNQS_SKIP_RATIO = 0
+NNQS_SKIP_CONTRIBUTION = 1
 
 
 NNQS_FP64 = 0

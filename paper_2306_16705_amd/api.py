@@ -7,7 +7,8 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from ._lib import NNQS_BF16, NNQS_FP32, NNQS_FP64, NNQS_VALIDATE, ModelDesc, NNQSError, Stats, Tune  # noqa: F401
+from ._lib import (NNQS_BF16, NNQS_FP32, NNQS_FP64, NNQS_SKIP_CONTRIBUTION, NNQS_SKIP_RATIO,  # noqa: F401
+                   NNQS_VALIDATE, ModelDesc, NNQSError, Stats, Tune)
 
 _KEY_DTYPES = (torch.int64, torch.uint64)
 
@@ -235,11 +236,15 @@ def model_logpsi(model: Model, keys, precision: int = NNQS_FP64, logabs=None, ph
 
 def eloc_model(system: System, model: Model, keys, counts=None, precision: int = NNQS_FP64, eloc=None,
                energy=None, with_energy: bool = True, with_stats: bool = False, validate: bool = False,
-               screen=None, skip_nats: float = 12.0, stream=None):
-    """Full local energies with every x' from the network, or with a learned
-    screen only those predicted within ``skip_nats`` of the sample's own
-    amplitude (``nnqs_eloc_model``).
-    Returns ``(eloc [n, 2], energy [4] or None, stats dict or None)``."""
+               screen=None, skip_nats: float = 12.0, skip_rule: int = L.NNQS_SKIP_RATIO, refine_nats: float = 0.0,
+               stream=None):
+    """Full local energies with every x' from the network (``nnqs_eloc_model``).
+
+    With a learned ``screen`` only connections kept by ``skip_rule`` at
+    ``skip_nats`` go to the network; ``refine_nats > 0`` re-evaluates in FP64
+    every connection whose first-pass contribution is at least
+    ``exp(-refine_nats)`` Ha.  Returns ``(eloc [n, 2], energy [4] or None,
+    stats dict or None)``."""
     n = keys.shape[0]
     _need(keys, "keys", _KEY_DTYPES, (n, 2))
     if with_energy:
@@ -249,12 +254,13 @@ def eloc_model(system: System, model: Model, keys, counts=None, precision: int =
     if eloc is None:
         eloc = torch.empty((n, 2), dtype=torch.float64, device=keys.device)
     st = Stats()
+    opts = L.ElocOpts(float(skip_nats), int(skip_rule), float(refine_nats))
     L.check(L.load().nnqs_eloc_model(system.handle, model.handle, screen.handle if screen is not None else None,
-                                     float(skip_nats), int(precision), _ptr(keys), _ptr(counts), n,
+                                     ctypes.byref(opts), int(precision), _ptr(keys), _ptr(counts), n,
                                      _ptr(eloc), _ptr(energy) if with_energy else None,
                                      ctypes.byref(st) if with_stats else None, NNQS_VALIDATE if validate else 0,
                                      _stream(stream)))
-    stats = {"connections": st.connections, "evaluated": st.evaluated} if with_stats else None
+    stats = {"connections": st.connections, "evaluated": st.evaluated, "refined": st.refined} if with_stats else None
     return eloc, (energy if with_energy else None), stats
 
 

@@ -22,7 +22,7 @@ constexpr int64_t kMaxChunkConnections = 1 << 24;
 
 __global__ void __launch_bounds__(256) k_enum_keys(SysView S, const uint64_t *__restrict__ keys, int64_t m,
                                                    int64_t blocks_per_sample, uint64_t *__restrict__ out,
-                                                   uint8_t *__restrict__ exc_out) {
+                                                   uint8_t *__restrict__ exc_out, float *__restrict__ loghx_out) {
     __shared__ WaveLds wl_all[4];
     const int lane = lane_id();
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -43,6 +43,11 @@ __global__ void __launch_bounds__(256) k_enum_keys(SysView S, const uint64_t *__
         const Key xp = apply_excitation(x, i, j, a, b);
         out[2 * (smp * C + c)] = xp.lo;
         out[2 * (smp * C + c) + 1] = xp.hi;
+        if (loghx_out) {  // log|H_xx'| for the selection rules; the diagonal is always kept
+            int sg;
+            const double hv = c == 0 ? 0.0 : excitation_element(S, x, 0.0, i, j, a, b, &sg);
+            loghx_out[smp * C + c] = c == 0 ? INFINITY : logf((float)fabs(hv));
+        }
         if (exc_out) {  // sorted spin-orbital indices, 255 absent (screen input)
             uint8_t *e = exc_out + 4 * (smp * C + c);
             if (j == 255) {
@@ -60,20 +65,35 @@ __global__ void __launch_bounds__(256) k_enum_keys(SysView S, const uint64_t *__
     }
 }
 
-// Screen selection: keep the diagonal and every connection whose predicted
-// log|psi(x')| is within skip_nats of the sample's own.  Two-pass
+// Selection of connections by a score against the sample's own log|psi|:
+// keep e when score(e) >= sla[sample] - thr, where score is a float or double
+// per-connection value (a screen prediction, or the first-pass log|psi(x')|)
+// plus, optionally, log|H_xx'|.  The diagonal is always kept.  Two-pass
 // deterministic compaction in canonical order.
 constexpr int kSelBlock = 1024;
 
-__global__ void __launch_bounds__(256) k_sel_count(const float *__restrict__ pred, const double *__restrict__ sla,
-                                                   int64_t C, int64_t total, double skip, int32_t *__restrict__ cnt) {
+struct SelRule {
+    const float *pf;   // per-connection score (float), or
+    const double *pd;  // per-connection score (double)
+    const float *lh;   // optional log|H_xx'| added to the score
+    const double *sla; // the samples' own log|psi| (chunk-local)
+    int64_t C;
+    double thr;
+};
+
+__device__ __forceinline__ bool sel_keep(const SelRule &R, int64_t e) {
+    const int64_t smp = e / R.C, cc = e - smp * R.C;
+    if (cc == 0) return true;
+    double v = R.pf ? (double)R.pf[e] : R.pd[e];
+    if (R.lh) v += (double)R.lh[e];
+    return v >= R.sla[smp] - R.thr;
+}
+
+__global__ void __launch_bounds__(256) k_sel_count(SelRule R, int64_t total, int32_t *__restrict__ cnt) {
     __shared__ int sh[256];
     const int64_t b0 = (int64_t)blockIdx.x * kSelBlock;
     int c = 0;
-    for (int64_t e = b0 + threadIdx.x; e < b0 + kSelBlock && e < total; e += 256) {
-        const int64_t smp = e / C, cc = e - smp * C;
-        c += (cc == 0 || (double)pred[e] >= sla[smp] - skip) ? 1 : 0;
-    }
+    for (int64_t e = b0 + threadIdx.x; e < b0 + kSelBlock && e < total; e += 256) c += sel_keep(R, e) ? 1 : 0;
     sh[threadIdx.x] = c;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
@@ -94,13 +114,13 @@ __global__ void k_sel_scan(int32_t *__restrict__ cnt, int nblocks, int64_t *__re
     *total_out = run;
 }
 
-__global__ void __launch_bounds__(256) k_sel_write(const float *__restrict__ pred, const double *__restrict__ sla,
-                                                   int64_t C, int64_t total, double skip,
-                                                   const int32_t *__restrict__ off, int32_t *__restrict__ sel,
-                                                   const uint64_t *__restrict__ xkeys, uint64_t *__restrict__ ckeys,
-                                                   double *__restrict__ xla, double *__restrict__ xph) {
-    // one wave walks its block's range in order; ballots keep canonical order
-    if (threadIdx.x >= 64) return;
+// One wave walks its block's range in order; ballots keep canonical order.
+// With `clear`, connections left out get log|psi| = -inf (they contribute
+// zero) in xla / xph.
+__global__ void __launch_bounds__(64) k_sel_write(SelRule R, int64_t total, const int32_t *__restrict__ off,
+                                                  int32_t *__restrict__ sel, const uint64_t *__restrict__ xkeys,
+                                                  uint64_t *__restrict__ ckeys, bool clear,
+                                                  double *__restrict__ xla, double *__restrict__ xph) {
     const int lane = threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.x * kSelBlock;
     int64_t pos = off[blockIdx.x];
@@ -108,10 +128,11 @@ __global__ void __launch_bounds__(256) k_sel_write(const float *__restrict__ pre
         const int64_t e = e0 + lane;
         bool keep = false;
         if (e < total && e < b0 + kSelBlock) {
-            const int64_t smp = e / C, cc = e - smp * C;
-            keep = cc == 0 || (double)pred[e] >= sla[smp] - skip;
-            xla[e] = -INFINITY;  // skipped connections contribute zero
-            xph[e] = 0.0;
+            keep = sel_keep(R, e);
+            if (clear) {
+                xla[e] = -INFINITY;
+                xph[e] = 0.0;
+            }
         }
         const uint64_t m = __ballot(keep);
         if (keep) {
@@ -231,6 +252,8 @@ void eloc_model_free(nnqs_model *m) {
     hipFree(m->d_partials);
     hipFree(m->d_xexc);
     hipFree(m->d_pred);
+    hipFree(m->d_loghx);
+    m->d_loghx = nullptr;
     hipFree(m->d_sel);
     hipFree(m->d_blockcnt);
     hipFree(m->d_ckeys);
@@ -248,12 +271,38 @@ void eloc_model_free(nnqs_model *m) {
     m->xcap = m->scap = 0;
 }
 
+// Compact the connections of one chunk that pass rule R, evaluate them with
+// the network in `precision` and scatter the results into xla / xph.  With
+// `clear`, connections that fail the rule get log|psi| = -inf.  Returns the
+// number evaluated (the call synchronises the stream to read it).
+static nnqs_status select_and_evaluate(nnqs_model *model, const SelRule &R, int64_t total, bool clear,
+                                       int32_t precision, hipStream_t st, int64_t *evaluated) {
+    const int nb = (int)((total + kSelBlock - 1) / kSelBlock);
+    hipLaunchKernelGGL(k_sel_count, dim3(nb), dim3(256), 0, st, R, total, model->d_blockcnt);
+    hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(1), 0, st, model->d_blockcnt, nb, model->d_nsel);
+    hipLaunchKernelGGL(k_sel_write, dim3(nb), dim3(64), 0, st, R, total, model->d_blockcnt, model->d_sel,
+                       model->d_xkeys, model->d_ckeys, clear, model->d_xla, model->d_xph);
+    NNQS_HIP_CHECK(hipGetLastError());
+    int64_t nsel = 0;
+    NNQS_HIP_CHECK(hipMemcpyAsync(&nsel, model->d_nsel, 8, hipMemcpyDeviceToHost, st));
+    NNQS_HIP_CHECK(hipStreamSynchronize(st));
+    if (nsel > 0) {
+        nnqs_status s1 = enqueue_logpsi(model, model->d_ckeys, nsel, precision, model->d_cla, model->d_cph, st);
+        if (s1 != NNQS_OK) return s1;
+        hipLaunchKernelGGL(k_scatter_sel, dim3((unsigned)((nsel + 255) / 256)), dim3(256), 0, st, model->d_sel,
+                           model->d_nsel, model->d_cla, model->d_cph, model->d_xla, model->d_xph);
+        NNQS_HIP_CHECK(hipGetLastError());
+    }
+    *evaluated = nsel;
+    return NNQS_OK;
+}
+
 }  // namespace nnqs
 
 using namespace nnqs;
 
 extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model, nnqs_screen *screen,
-                                       double skip_nats, int32_t precision, const uint64_t *keys,
+                                       const nnqs_eloc_opts *opts, int32_t precision, const uint64_t *keys,
                                        const uint32_t *counts, int64_t n, double *eloc, double *energy,
                                        nnqs_stats *stats, uint32_t flags, void *stream) {
     clear_error();
@@ -264,7 +313,14 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         return fail(NNQS_EINVAL, "model and system disagree on orbitals or electron numbers");
     if (precision != NNQS_FP64 && precision != NNQS_BF16) return fail(NNQS_EUNSUPPORTED, "unknown precision");
     if (precision == NNQS_BF16 && !model->bf16_ok) return fail(NNQS_EUNSUPPORTED, "model shape has no BF16 path");
-    if (screen && !(skip_nats > 0.0)) return fail(NNQS_EINVAL, "skip_nats must be positive");
+    nnqs_eloc_opts o{12.0, NNQS_SKIP_RATIO, 0.0};
+    if (opts) o = *opts;
+    if (screen && !(o.skip_nats > 0.0)) return fail(NNQS_EINVAL, "skip_nats must be positive");
+    if (o.skip_rule != NNQS_SKIP_RATIO && o.skip_rule != NNQS_SKIP_CONTRIBUTION)
+        return fail(NNQS_EINVAL, "unknown skip rule %d", o.skip_rule);
+    if (!(o.refine_nats >= 0.0)) return fail(NNQS_EINVAL, "refine_nats must be >= 0");
+    const bool refine = o.refine_nats > 0.0 && precision != NNQS_FP64;
+    const bool need_lh = refine || (screen && o.skip_rule == NNQS_SKIP_CONTRIBUTION);
     hipStream_t st = as_stream(stream);
     if (flags & NNQS_VALIDATE) {
         hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(1), 0, st, sys->d_status);
@@ -282,19 +338,21 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
     const int64_t bps = (C + kConnPerBlock - 1) / kConnPerBlock;
     if (model->xcap < chunk * C) {
         NNQS_HIP_CHECK(hipStreamSynchronize(st));  // scratch may be in use by earlier work on this stream
-        nnqs_status s1 = grow(reinterpret_cast<void **>(&model->d_xkeys), (size_t)chunk * C * 16);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_xla), (size_t)chunk * C * 8);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_xph), (size_t)chunk * C * 8);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_partials),
-                                     std::max<size_t>((size_t)chunk * bps * 4, kPartialBlocks * 8) * 8);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_xexc), (size_t)chunk * C * 4);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_pred), (size_t)chunk * C * 4);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_sel), (size_t)chunk * C * 4);
+        const size_t cc = (size_t)chunk * C;
+        nnqs_status s1 = grow(reinterpret_cast<void **>(&model->d_xkeys), cc * 16);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_xla), cc * 8);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_xph), cc * 8);
         if (s1 == NNQS_OK)
-            s1 = grow(reinterpret_cast<void **>(&model->d_blockcnt), ((size_t)chunk * C / kSelBlock + 2) * 4);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_ckeys), (size_t)chunk * C * 16);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cla), (size_t)chunk * C * 8);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cph), (size_t)chunk * C * 8);
+            s1 = grow(reinterpret_cast<void **>(&model->d_partials),
+                      std::max<size_t>((size_t)chunk * bps * 4, kPartialBlocks * 8) * 8);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_xexc), cc * 4);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_pred), cc * 4);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_loghx), cc * 4);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_sel), cc * 4);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_blockcnt), (cc / kSelBlock + 2) * 4);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_ckeys), cc * 16);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cla), cc * 8);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cph), cc * 8);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_nsel), 8);
         if (s1 != NNQS_OK) {
             eloc_model_free(model);
@@ -312,41 +370,38 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         }
         model->scap = n;
     }
-    nnqs_status s1 = enqueue_logpsi(model, keys, n, precision, model->d_sla, model->d_sph, st);
+    // the samples' own amplitudes: in the top precision of the evaluation
+    nnqs_status s1 =
+        enqueue_logpsi(model, keys, n, refine ? NNQS_FP64 : precision, model->d_sla, model->d_sph, st);
     if (s1 != NNQS_OK) return s1;
-    int64_t evaluated = 0;
+    int64_t evaluated = 0, refined = 0;
     for (int64_t s0 = 0; s0 < n; s0 += chunk) {
         const int64_t m = n - s0 < chunk ? n - s0 : chunk;
+        const int64_t total = m * C;
         const unsigned grid = (unsigned)(m * bps);
         hipLaunchKernelGGL(k_enum_keys, dim3(grid), dim3(256), 0, st, sys->view, keys + 2 * s0, m, bps,
-                           model->d_xkeys, screen ? model->d_xexc : (uint8_t *)nullptr);
+                           model->d_xkeys, screen ? model->d_xexc : (uint8_t *)nullptr,
+                           need_lh ? model->d_loghx : (float *)nullptr);
         if (!screen) {
-            s1 = enqueue_logpsi(model, model->d_xkeys, m * C, precision, model->d_xla, model->d_xph, st);
+            s1 = enqueue_logpsi(model, model->d_xkeys, total, precision, model->d_xla, model->d_xph, st);
             if (s1 != NNQS_OK) return s1;
-            evaluated += m * C;
+            evaluated += total;
         } else {
-            const int64_t total = m * C;
-            const int nb = (int)((total + kSelBlock - 1) / kSelBlock);
             s1 = screen_infer(screen, model->d_xkeys, model->d_xexc, total, model->d_pred, st);
             if (s1 != NNQS_OK) return s1;
-            hipLaunchKernelGGL(k_sel_count, dim3(nb), dim3(256), 0, st, model->d_pred, model->d_sla + s0, C, total,
-                               skip_nats, model->d_blockcnt);
-            hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(1), 0, st, model->d_blockcnt, nb, model->d_nsel);
-            hipLaunchKernelGGL(k_sel_write, dim3(nb), dim3(64), 0, st, model->d_pred, model->d_sla + s0, C, total,
-                               skip_nats, model->d_blockcnt, model->d_sel, model->d_xkeys, model->d_ckeys,
-                               model->d_xla, model->d_xph);
-            NNQS_HIP_CHECK(hipGetLastError());
-            int64_t nsel = 0;
-            NNQS_HIP_CHECK(hipMemcpyAsync(&nsel, model->d_nsel, 8, hipMemcpyDeviceToHost, st));
-            NNQS_HIP_CHECK(hipStreamSynchronize(st));
-            if (nsel > 0) {
-                s1 = enqueue_logpsi(model, model->d_ckeys, nsel, precision, model->d_cla, model->d_cph, st);
-                if (s1 != NNQS_OK) return s1;
-                hipLaunchKernelGGL(k_scatter_sel, dim3((unsigned)((nsel + 255) / 256)), dim3(256), 0, st,
-                                   model->d_sel, model->d_nsel, model->d_cla, model->d_cph, model->d_xla,
-                                   model->d_xph);
-            }
-            evaluated += nsel;
+            SelRule R{model->d_pred, nullptr, o.skip_rule == NNQS_SKIP_CONTRIBUTION ? model->d_loghx : nullptr,
+                      model->d_sla + s0, C, o.skip_nats};
+            int64_t k = 0;
+            s1 = select_and_evaluate(model, R, total, true, precision, st, &k);
+            if (s1 != NNQS_OK) return s1;
+            evaluated += k;
+        }
+        if (refine) {  // FP64 for every connection whose first-pass contribution is not negligible
+            SelRule R{nullptr, model->d_xla, model->d_loghx, model->d_sla + s0, C, o.refine_nats};
+            int64_t k = 0;
+            s1 = select_and_evaluate(model, R, total, false, NNQS_FP64, st, &k);
+            if (s1 != NNQS_OK) return s1;
+            refined += k;
         }
         hipLaunchKernelGGL(k_eloc_partial, dim3(grid), dim3(256), 0, st, sys->view, keys + 2 * s0,
                            model->d_sla + s0, model->d_sph + s0, m, bps, model->d_xla, model->d_xph,
@@ -363,6 +418,7 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
         stats->connections = n * C;
         stats->evaluated = evaluated;
+        stats->refined = refined;
     }
     return NNQS_OK;
 }

@@ -41,6 +41,7 @@ struct nnqs_model {
     // screen scratch (eloc_model.hip)
     uint8_t *d_xexc = nullptr;
     float *d_pred = nullptr;
+    float *d_loghx = nullptr;       // log|H_xx'| per connection (selection rules)
     int32_t *d_sel = nullptr;       // survivor indices (chunk-local)
     int32_t *d_blockcnt = nullptr;  // per-block survivor counts / offsets
     uint64_t *d_ckeys = nullptr;    // compacted survivor keys

@@ -124,14 +124,23 @@ def excitation_level(keys: np.ndarray, ref: np.ndarray) -> np.ndarray:
 
 
 def geometric_samples(K: int, n_up: int, n_dn: int, n_unique: int,
-                      rng: np.random.Generator, p_level: float = 0.4):
+                      rng: np.random.Generator, p_level: float = 0.4,
+                      fermi_decay: float | None = None):
     """Unique configurations drawn around the reference occupation.
 
     Each draw takes a level ``k`` with ``P(k) = p (1-p)^k`` (k = 0, 1, ...) and
     applies ``k`` random moves; a move picks a spin uniformly, then one occupied
-    and one empty orbital of that spin uniformly, and moves the electron.  Draws
+    and one empty orbital of that spin, and moves the electron.  Draws
     continue until ``n_unique`` distinct keys are seen; the first occurrence
     order is kept.  Returns ``(keys uint64[n, 2], level int64[n])``.
+
+    With ``fermi_decay = None`` the two orbitals are uniform.  With a value
+    ``lam`` an occupied orbital ``i`` below the Fermi level ``F`` (the
+    electron count of that spin) is picked with weight ``exp(-lam (F-1-i))``
+    and an empty orbital ``a`` above it with weight ``exp(-lam (a-F))``
+    (orbitals on the other side of ``F`` weigh 1), so that samples stay near
+    the Fermi level, where a model with an orbital-ordered logit bias puts
+    its weight.
     """
     n_sector = sector_size(K, n_up, n_dn)
     if n_unique > n_sector:
@@ -154,8 +163,19 @@ def geometric_samples(K: int, n_up: int, n_dn: int, n_unique: int,
             o = occ[rows, spin]
             r_occ = rng.random((B, K))
             r_emp = rng.random((B, K))
-            ri = np.where(o, r_occ, -1.0).argmax(axis=1)
-            ra = np.where(~o, r_emp, -1.0).argmax(axis=1)
+            if fermi_decay is None:
+                ri = np.where(o, r_occ, -1.0).argmax(axis=1)
+                ra = np.where(~o, r_emp, -1.0).argmax(axis=1)
+            else:
+                # weighted choice by the Gumbel-max rule: argmax(log w + G)
+                F = np.where(spin == 0, n_up, n_dn)[:, None]
+                orb = np.arange(K)[None, :]
+                lw_hole = -fermi_decay * np.maximum(0, F - 1 - orb)
+                lw_part = -fermi_decay * np.maximum(0, orb - F)
+                g_occ = -np.log(-np.log(np.maximum(r_occ, 1e-300)))
+                g_emp = -np.log(-np.log(np.maximum(r_emp, 1e-300)))
+                ri = np.where(o, lw_hole + g_occ, -np.inf).argmax(axis=1)
+                ra = np.where(~o, lw_part + g_emp, -np.inf).argmax(axis=1)
             ok = act & o.any(axis=1) & (~o).any(axis=1)
             occ[rows[ok], spin[ok], ri[ok]] = False
             occ[rows[ok], spin[ok], ra[ok]] = True
@@ -318,7 +338,9 @@ def config_inputs(cfg: int, sys: int = 0, *, K: int | None = None, n_up: int | N
         phase = rng.uniform(0.0, 2.0 * np.pi, size=keys.shape[0])
         counts = np.ones(keys.shape[0], dtype=np.uint32)
     else:
-        keys, level = geometric_samples(K, n_up, n_dn, n_unique, rng)
+        # model workloads draw moves near the Fermi level with the decay of
+        # the model's own logit bias (|psi|^2 falls by exp(-beta) per orbital)
+        keys, level = geometric_samples(K, n_up, n_dn, n_unique, rng, fermi_decay=beta if model else None)
         logabs, phase = sample_amplitudes(level, rng)
         counts = sample_counts(keys.shape[0], rng)
     out = dict(cfg=cfg, sys=sys, K=K, N=2 * K, n_up=n_up, n_dn=n_dn, h=h, g=g, e_core=e_core,

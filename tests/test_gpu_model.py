@@ -110,3 +110,47 @@ def test_logpsi_bf16_error_vs_oracle(nn, kw):
           f"max |dphase| {dph.max():.3e}, n={len(keys)}")
     assert np.all(dla <= 0.02 + 1e-3 * np.abs(ola))
     assert np.all(dph <= 0.02)
+
+
+def test_eloc_model_refined_bf16_equals_fp64_when_all_terms_refined(nn):
+    """Precision ladder: with a refinement threshold far below every term
+    (exp(-60) Ha), the BF16 pass only decides what to refine, every term and
+    the samples' own amplitudes come from the FP64 network, and the result is
+    the FP64 path's."""
+    d = synth.config_inputs(1, K=6, n_up=2, n_dn=3, model=True)
+    _print_case("eloc_model_refine_all")
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    keys, cnt = dev(d["keys"]), dev(d["counts"], torch.int32)
+    e64, en64, _ = nn.eloc_model(S, M, keys, cnt, nn.NNQS_FP64)
+    e, en, st = nn.eloc_model(S, M, keys, cnt, nn.NNQS_BF16, refine_nats=60.0, with_stats=True)
+    torch.cuda.synchronize()
+    a, b = eloc_complex(e64), eloc_complex(e)
+    assert st["evaluated"] == st["connections"]
+    assert 0 < st["refined"] <= st["connections"]
+    assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.abs(a).max())
+
+
+def test_eloc_model_refinement_shrinks_bf16_error(nn):
+    """Precision ladder on N=32 (4 + 4 electrons): the error of the BF16
+    path against the FP64 path is stated, and refining every term above
+    exp(-8) Ha in FP64 cuts it at least tenfold while re-evaluating only part
+    of the connections."""
+    d = synth.config_inputs(2, K=16, n_up=4, n_dn=4, n_unique=12, model=True)
+    _print_case("eloc_model_refine_error")
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    keys, cnt = dev(d["keys"]), dev(d["counts"], torch.int32)
+    e64, en64, _ = nn.eloc_model(S, M, keys, cnt, nn.NNQS_FP64)
+    e16, en16, _ = nn.eloc_model(S, M, keys, cnt, nn.NNQS_BF16)
+    er, enr, st = nn.eloc_model(S, M, keys, cnt, nn.NNQS_BF16, refine_nats=8.0, with_stats=True)
+    torch.cuda.synchronize()
+    ref = eloc_complex(e64)
+    d16 = np.abs(eloc_complex(e16) - ref)
+    dr = np.abs(eloc_complex(er) - ref)
+    frac = st["refined"] / st["connections"]
+    print(f"E_loc vs FP64: BF16 max {d16.max():.3e} Ha, BF16 + refine(8) max {dr.max():.3e} Ha "
+          f"(refined {frac:.3f} of connections); energy {en16[0].item() - en64[0].item():.3e} / "
+          f"{enr[0].item() - en64[0].item():.3e} Ha")
+    assert dr.max() <= 0.1 * d16.max()
+    assert frac < 1.0
