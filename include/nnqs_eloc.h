@@ -328,7 +328,10 @@ typedef struct {
     int32_t waves_per_block;   /* 1..16 (the sample-aware kernel uses at most 12) */
     int32_t blocks_per_cu;     /* grid = blocks_per_cu * CU count */
     int32_t filter_log2_bits;  /* LDS membership filter size, 10..20 (2^k bits) */
-    int32_t splitter_levels;   /* binary-search levels staged in LDS, 0..13 */
+    int32_t splitter_levels;   /* binary-search levels staged in LDS, 1..13 */
+    int32_t search;            /* table levels below the LDS ones: 1 = one load per level,
+                                  2 = three levels per round of independent loads */
+    int32_t tile_samples;      /* batched launch: samples per work tile, 1..65536 */
 } nnqs_tune;
 
 /* Sets the launch parameters used by later nnqs_eloc_table calls on `tab`.
@@ -337,6 +340,61 @@ nnqs_status nnqs_table_set_tune(nnqs_table *tab, const nnqs_tune *tune);
 
 /* Reads back the parameters in use. */
 nnqs_status nnqs_table_get_tune(const nnqs_table *tab, nnqs_tune *tune);
+
+/* ------------------------------------------------------------ batching */
+/* Many systems (uneven N, electron and sample counts) evaluated by one
+ * persistent sample-aware launch.  A step of a batch: for every item with a
+ * model, log|psi| and phase of its samples from the BF16 network (written to
+ * the item's logabs / phase); for every item, its table built from the
+ * samples; one persistent launch over all (system, sample-tile) work items,
+ * pulled by blocks from a device counter; for every item with `energy`, the
+ * weighted energy (Eq. 6).  A step neither synchronises the host nor
+ * allocates, so it can be captured into a hipGraph and replayed. */
+typedef struct nnqs_batch nnqs_batch;
+
+typedef struct {
+    const nnqs_system *system;
+    nnqs_table *table;        /* of `system`, capacity >= n; rebuilt every step */
+    nnqs_model *model;        /* NULL: logabs / phase are inputs; else outputs of the model (BF16) */
+    const uint64_t *keys;     /* device [n][2], unique samples */
+    const uint32_t *counts;   /* device [n], may be NULL when energy is NULL */
+    double *logabs, *phase;   /* device [n] */
+    int64_t n;
+    double *eloc;             /* device [n][2] output */
+    double *energy;           /* device [4] output, may be NULL */
+} nnqs_batch_item;
+
+/* Plans a batch over n_items items (device buffers stay owned by the caller
+ * and must outlive the batch; the tables take the batch's tune).  The tune
+ * starts from the first table's.  Synchronous.  Errors: EINVAL, ENOMEM,
+ * EUNSUPPORTED, EHIP. */
+nnqs_status nnqs_batch_create(nnqs_batch **out, const nnqs_batch_item *items, int32_t n_items);
+
+/* Releases the batch (and its graph).  NULL is accepted. */
+nnqs_status nnqs_batch_destroy(nnqs_batch *batch);
+
+/* Enqueues one step on `stream`.  Errors: EHIP and those of the table build. */
+nnqs_status nnqs_batch_run(nnqs_batch *batch, void *stream);
+
+/* Records one step on `stream` (a created stream, not the null stream) into
+ * a hipGraph owned by the batch, replacing any earlier one.  Nothing runs. */
+nnqs_status nnqs_batch_capture(nnqs_batch *batch, void *stream);
+
+/* Replays the captured step on `stream`.  Errors: EINVAL (nothing captured). */
+nnqs_status nnqs_batch_launch(nnqs_batch *batch, void *stream);
+
+/* Schedule of the batch (waves_per_block, blocks_per_cu, filter_log2_bits,
+ * splitter_levels, search, tile_samples; 0 keeps a field).  Changing it
+ * drops a captured graph.  Synchronous. */
+nnqs_status nnqs_batch_set_tune(nnqs_batch *batch, const nnqs_tune *tune);
+nnqs_status nnqs_batch_get_tune(const nnqs_batch *batch, nnqs_tune *tune);
+
+/* Autotuner: times every candidate schedule (waves per block {8, 12} x
+ * splitter levels {8, 10, 12} x search {1, 2} x tile samples {64, 256, 1024})
+ * on the batch itself, best of `reps` steps after one warm-up step each,
+ * keeps the fastest and returns it (best, best_ms may be NULL).  Runs many
+ * steps on `stream` and synchronises it; drops a captured graph. */
+nnqs_status nnqs_batch_autotune(nnqs_batch *batch, int32_t reps, nnqs_tune *best, double *best_ms, void *stream);
 
 #ifdef __cplusplus
 }

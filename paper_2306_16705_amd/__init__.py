@@ -6,6 +6,7 @@ All computation happens in the HIP kernels of the library; there is no
 fallback path.
 """
 from .api import (  # noqa: F401
+    Batch,
     NNQSError,
     NNQS_BF16,
     NNQS_FP32,

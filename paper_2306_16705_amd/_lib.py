@@ -49,6 +49,14 @@ SIGNATURES = {
     "nnqs_screen_gradient": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _i32, _c_void_p, _c_void_p,
                                     _c_void_p]),
     "nnqs_screen_adam_step": (_i32, [_c_void_p, _c_void_p, _f64, _f64, _f64, _f64, _c_void_p]),
+    "nnqs_batch_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p, _i32]),
+    "nnqs_batch_destroy": (_i32, [_c_void_p]),
+    "nnqs_batch_run": (_i32, [_c_void_p, _c_void_p]),
+    "nnqs_batch_capture": (_i32, [_c_void_p, _c_void_p]),
+    "nnqs_batch_launch": (_i32, [_c_void_p, _c_void_p]),
+    "nnqs_batch_set_tune": (_i32, [_c_void_p, _c_void_p]),
+    "nnqs_batch_get_tune": (_i32, [_c_void_p, _c_void_p]),
+    "nnqs_batch_autotune": (_i32, [_c_void_p, _i32, _c_void_p, _c_void_p, _c_void_p]),
 }
 
 STATUS_NAMES = {0: "NNQS_OK", -1: "NNQS_EINVAL", -2: "NNQS_EDUP", -3: "NNQS_ECONSERVE", -4: "NNQS_ERANGE",
@@ -64,7 +72,13 @@ class NNQSError(RuntimeError):
 
 class Tune(ctypes.Structure):
     _fields_ = [("waves_per_block", _i32), ("blocks_per_cu", _i32), ("filter_log2_bits", _i32),
-                ("splitter_levels", _i32)]
+                ("splitter_levels", _i32), ("search", _i32), ("tile_samples", _i32)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("system", _c_void_p), ("table", _c_void_p), ("model", _c_void_p), ("keys", _c_void_p),
+                ("counts", _c_void_p), ("logabs", _c_void_p), ("phase", _c_void_p), ("n", _i64),
+                ("eloc", _c_void_p), ("energy", _c_void_p)]
 
 
 class ModelDesc(ctypes.Structure):

@@ -107,8 +107,9 @@ class Table:
     def status(self, stream=None) -> int:
         return int(self._lib.nnqs_table_status(self.handle, _stream(stream)))
 
-    def set_tune(self, waves_per_block=0, blocks_per_cu=0, filter_log2_bits=0, splitter_levels=0):
-        t = Tune(waves_per_block, blocks_per_cu, filter_log2_bits, splitter_levels)
+    def set_tune(self, waves_per_block=0, blocks_per_cu=0, filter_log2_bits=0, splitter_levels=0, search=0,
+                 tile_samples=0):
+        t = Tune(waves_per_block, blocks_per_cu, filter_log2_bits, splitter_levels, search, tile_samples)
         L.check(self._lib.nnqs_table_set_tune(self.handle, ctypes.byref(t)))
 
     def get_tune(self) -> dict:
@@ -315,6 +316,77 @@ class Screen:
     def close(self):
         if getattr(self, "handle", None):
             self._lib.nnqs_screen_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------- batch
+class Batch:
+    """Many systems in one persistent sample-aware launch (``nnqs_batch_*``).
+
+    ``items`` is a list of dicts with keys ``system``, ``table``, ``keys``,
+    ``logabs``, ``phase`` (device tensors; with a ``model`` they are outputs),
+    ``eloc`` and optionally ``model``, ``counts``, ``energy``.  The tensors
+    must stay alive as long as the batch."""
+
+    def __init__(self, items):
+        self._lib = L.load()
+        arr = (L.BatchItem * len(items))()
+        self._keep = []
+        for k, it in enumerate(items):
+            n = it["keys"].shape[0]
+            _need(it["keys"], "keys", _KEY_DTYPES, (n, 2))
+            _need(it["logabs"], "logabs", (torch.float64,), (n,))
+            _need(it["phase"], "phase", (torch.float64,), (n,))
+            _need(it["eloc"], "eloc", (torch.float64,), (n, 2))
+            if it.get("counts") is not None:
+                _need(it["counts"], "counts", (torch.int32, torch.uint32), (n,))
+            if it.get("energy") is not None:
+                _need(it["energy"], "energy", (torch.float64,), (4,))
+            model = it.get("model")
+            arr[k] = L.BatchItem(it["system"].handle, it["table"].handle, model.handle if model is not None else None,
+                                 _ptr(it["keys"]), _ptr(it.get("counts")), _ptr(it["logabs"]), _ptr(it["phase"]), n,
+                                 _ptr(it["eloc"]), _ptr(it.get("energy")))
+            self._keep.append(it)
+        out = ctypes.c_void_p()
+        L.check(self._lib.nnqs_batch_create(ctypes.byref(out), arr, len(items)))
+        self.handle = out
+
+    def run(self, stream=None):
+        L.check(self._lib.nnqs_batch_run(self.handle, _stream(stream)))
+
+    def capture(self, stream):
+        L.check(self._lib.nnqs_batch_capture(self.handle, _stream(stream)))
+
+    def launch(self, stream):
+        L.check(self._lib.nnqs_batch_launch(self.handle, _stream(stream)))
+
+    def set_tune(self, **kw):
+        t = Tune(*[int(kw.get(f, 0)) for f, _ in Tune._fields_])
+        L.check(self._lib.nnqs_batch_set_tune(self.handle, ctypes.byref(t)))
+
+    def get_tune(self) -> dict:
+        t = Tune()
+        L.check(self._lib.nnqs_batch_get_tune(self.handle, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in Tune._fields_}
+
+    def autotune(self, reps: int = 2, stream=None):
+        """Times the candidate schedules and keeps the fastest; returns
+        ``(tune dict, best step ms)``."""
+        t = Tune()
+        ms = ctypes.c_double()
+        L.check(self._lib.nnqs_batch_autotune(self.handle, int(reps), ctypes.byref(t), ctypes.byref(ms),
+                                              _stream(stream)))
+        return {f: getattr(t, f) for f, _ in Tune._fields_}, ms.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.nnqs_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -63,14 +63,11 @@ __device__ __forceinline__ Key load_key(const uint64_t *k, int64_t i) {
     return r;
 }
 
-// Lower-bound search for t in the sorted table.  The first split_levels
-// levels read LDS copies of the keys they probe (every key at position
-// (m+1)*2^(L-s) - 1).  The remaining levels are taken up to three at a time
-// by 8-way rounds whose probes are independent loads; the last round loads
-// the eight keys from the current lower bound on, so the key the search
-// ends on is already in registers for the equality test.
+// Lower-bound search for t in the sorted table; both variants start with
+// the first split_levels levels from LDS copies of the keys they probe
+// (every key at position (m+1)*2^(L-s) - 1).
 template <int W>
-__device__ __forceinline__ int64_t table_find(const TableView &T, const uint64_t *s_lds, const Key &t) {
+__device__ __forceinline__ int64_t search_lds_levels(const TableView &T, const uint64_t *s_lds, const Key &t) {
     const int L = T.log2n, s = T.split_levels;
     int64_t lo = 0;
     for (int lvl = 0; lvl < s; lvl++) {
@@ -81,8 +78,33 @@ __device__ __forceinline__ int64_t table_find(const TableView &T, const uint64_t
         k.hi = (W == 2) ? s_lds[j * W + 1] : 0ull;
         if (key_less(k, t)) lo += step;
     }
+    return lo;
+}
+
+// Variant 1: the remaining levels one dependent load at a time, then the
+// key the search ends on.
+template <int W>
+__device__ __forceinline__ int64_t table_find_binary(const TableView &T, const uint64_t *s_lds, const Key &t) {
+    const int L = T.log2n;
+    int64_t lo = search_lds_levels<W>(T, s_lds, t);
+    for (int lvl = T.split_levels; lvl < L; lvl++) {
+        const int64_t step = int64_t(1) << (L - 1 - lvl);
+        const int64_t idx = lo + step - 1;
+        if (idx < T.n && key_less(load_key<W>(T.keys, idx), t)) lo += step;
+    }
+    if (lo < T.n && key_eq(load_key<W>(T.keys, lo), t)) return lo;
+    return -1;
+}
+
+// Variant 2: the remaining levels up to three at a time by 8-way rounds
+// whose probes are independent loads; the last round loads the eight keys
+// from the current lower bound on, so the key the search ends on is already
+// in registers for the equality test.
+template <int W>
+__device__ __forceinline__ int64_t table_find_8way(const TableView &T, const uint64_t *s_lds, const Key &t) {
+    int64_t lo = search_lds_levels<W>(T, s_lds, t);
     const int64_t last = T.n - 1;
-    int r = L - s;
+    int r = T.log2n - T.split_levels;
     if (r == 0) return (lo < T.n && key_eq(load_key<W>(T.keys, lo), t)) ? lo : -1;
     int q = r % 3 == 0 ? 3 : r % 3;  // levels taken by the first round
     while (r > q) {
@@ -118,13 +140,21 @@ __device__ __forceinline__ uint32_t wave_xor32(uint32_t v) {
     return v;
 }
 
+// LDS-resident per-system data of the sample-aware kernels.
+struct SaStage {
+    const uint32_t *f_lds;  // membership filter words
+    const uint64_t *s_lds;  // staged search keys
+    const uint32_t *h_lds;  // low 32 bits of the hash words
+    WaveLds *waves;         // one per wave
+    uint32_t wmask;         // filter words - 1
+};
+
+// Stage the filter (folded to the LDS size: OR of aliasing words keeps every
+// member), the top search levels and the hash words.  Block-wide; ends with a
+// barrier.
 template <int W>
-__global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView T, int lds_filter_log2,
-                                                  const uint64_t *__restrict__ keys,
-                                                  const double *__restrict__ logabs,
-                                                  const double *__restrict__ phase, int64_t n,
-                                                  double *__restrict__ eloc, int *status) {
-    extern __shared__ __align__(16) uint8_t smem[];
+__device__ __forceinline__ SaStage sa_stage(const SysView &S, const TableView &T, int lds_filter_log2,
+                                            uint8_t *smem) {
     const int nwords = 1 << (lds_filter_log2 - 5);
     const int big_words = 1 << (T.filter_log2 - 5);
     const int nsplit = (1 << T.split_levels) - 1;
@@ -132,10 +162,6 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView 
     uint32_t *f_lds = reinterpret_cast<uint32_t *>(smem);
     uint64_t *s_lds = reinterpret_cast<uint64_t *>(smem + lay.split);
     uint32_t *h_lds = reinterpret_cast<uint32_t *>(smem + lay.hash);
-    WaveLds *wl_all = reinterpret_cast<WaveLds *>(smem + lay.waves);
-
-    // Stage the filter (folded to the LDS size: OR of aliasing words keeps
-    // every member), the top search levels and the hash words.
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
         uint32_t v = 0;
         for (int k = i; k < big_words; k += nwords) v |= T.filter[k];
@@ -147,208 +173,267 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView 
     }
     for (int i = threadIdx.x; i < 128; i += blockDim.x) h_lds[i] = (uint32_t)S.hashT[i];
     __syncthreads();
+    SaStage G;
+    G.f_lds = f_lds;
+    G.s_lds = s_lds;
+    G.h_lds = h_lds;
+    G.waves = reinterpret_cast<WaveLds *>(smem + lay.waves);
+    G.wmask = (uint32_t)nwords - 1u;
+    return G;
+}
 
+// E_loc of sample smp by the calling wave (see the file comment).  S8 picks
+// the search variant of the queued candidates.
+template <int W, int S8>
+__device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, const SaStage &G, WaveLds &wl,
+                                          int64_t smp, const uint64_t *__restrict__ keys,
+                                          const double *__restrict__ logabs, const double *__restrict__ phase,
+                                          double *__restrict__ eloc, int *status) {
     const int lane = lane_id();
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
-    WaveLds &wl = wl_all[wid];
-    const uint32_t wmask = (uint32_t)nwords - 1u;
     const int K = S.K, nu = S.n_up, nd = S.n_dn, vu = K - nu, vd = K - nd;
-
-    for (int64_t smp = (int64_t)blockIdx.x * nw + wid; smp < n; smp += (int64_t)gridDim.x * nw) {
-        Key x;
-        x.lo = keys[2 * smp];
-        x.hi = keys[2 * smp + 1];
-        const double la = logabs[smp], ph = phase[smp];
-        if (!sample_conserves(S, x) || !isfinite(la) || !isfinite(ph)) {
-            if (lane == 0) {
-                eloc[2 * smp] = NAN;
-                eloc[2 * smp + 1] = NAN;
-                set_status(status, sample_conserves(S, x) ? NNQS_ERANGE : NNQS_ECONSERVE);
-            }
-            continue;
+    const uint32_t *f_lds = G.f_lds, *h_lds = G.h_lds;
+    const uint32_t wmask = G.wmask;
+    Key x;
+    x.lo = keys[2 * smp];
+    x.hi = keys[2 * smp + 1];
+    const double la = logabs[smp], ph = phase[smp];
+    if (!sample_conserves(S, x) || !isfinite(la) || !isfinite(ph)) {
+        if (lane == 0) {
+            eloc[2 * smp] = NAN;
+            eloc[2 * smp + 1] = NAN;
+            set_status(status, sample_conserves(S, x) ? NNQS_ERANGE : NNQS_ECONSERVE);
         }
-        build_lists(S, x, wl);
-        uint32_t part = 0;
-        if (lane < K) {
-            if (key_bit(x, 2 * lane)) part ^= h_lds[2 * lane];
-            if (key_bit(x, 2 * lane + 1)) part ^= h_lds[2 * lane + 1];
-        }
-        const uint32_t hx = wave_xor32(part);
-        const double diag = wave_diag(S, x, wl);
-        // Lane l holds entry l of the occupied-up, occupied-down and empty-up
-        // lists as (low hash bits | orbital << 25); the loops read them with
-        // wave-uniform readlane, which yields the orbital with a scalar shift.
-        auto pack = [&](int p) -> uint32_t { return (h_lds[p] & kFilterHashMask) | ((uint32_t)p << 25); };
-        const uint32_t po_u = lane < nu ? pack(wl.occ[0][lane]) : 0u;
-        const uint32_t po_d = lane < nd ? pack(wl.occ[1][lane]) : 0u;
-        const uint32_t pv_u = lane < vu ? pack(wl.vir[0][lane]) : 0u;
+        return;
+    }
+    build_lists(S, x, wl);
+    uint32_t part = 0;
+    if (lane < K) {
+        if (key_bit(x, 2 * lane)) part ^= h_lds[2 * lane];
+        if (key_bit(x, 2 * lane + 1)) part ^= h_lds[2 * lane + 1];
+    }
+    const uint32_t hx = wave_xor32(part);
+    const double diag = wave_diag(S, x, wl);
+    // Lane l holds entry l of the occupied-up, occupied-down and empty-up
+    // lists as (low hash bits | orbital << 25); the loops read them with
+    // wave-uniform readlane, which yields the orbital with a scalar shift.
+    auto pack = [&](int p) -> uint32_t { return (h_lds[p] & kFilterHashMask) | ((uint32_t)p << 25); };
+    const uint32_t po_u = lane < nu ? pack(wl.occ[0][lane]) : 0u;
+    const uint32_t po_d = lane < nd ? pack(wl.occ[1][lane]) : 0u;
+    const uint32_t pv_u = lane < vu ? pack(wl.vir[0][lane]) : 0u;
 
-        NSum are{0.0, 0.0}, aim{0.0, 0.0};
-        int qh = 0, qt = 0;  // wave-uniform ring counters (ring of 256)
+    NSum are{0.0, 0.0}, aim{0.0, 0.0};
+    int qh = 0, qt = 0;  // wave-uniform ring counters (ring of 256)
 
-        // Resolve one queued candidate: matrix element first (its integral
-        // loads overlap the search), then the lookup and, on a hit, the
-        // log-polar amplitude ratio into the lane's compensated sums.
-        auto process = [&](uint32_t e) {
-            const int i = e & 255, j = (e >> 8) & 255, a = (e >> 16) & 255, b = e >> 24;
-            Key xp = x;
-            if (i != 255) {
-                key_flip(xp, i);
-                key_flip(xp, a);
-                if (j != 255) {
-                    key_flip(xp, j);
-                    key_flip(xp, b);
-                }
+    // Resolve one queued candidate: lookup, then on a hit the Slater-Condon
+    // element and the log-polar amplitude ratio into the lane's compensated
+    // sums.
+    auto process = [&](uint32_t e) {
+        const int i = e & 255, j = (e >> 8) & 255, a = (e >> 16) & 255, b = e >> 24;
+        Key xp = x;
+        if (i != 255) {
+            key_flip(xp, i);
+            key_flip(xp, a);
+            if (j != 255) {
+                key_flip(xp, j);
+                key_flip(xp, b);
             }
+        }
+        const int64_t idx = S8 ? table_find_8way<W>(T, G.s_lds, xp) : table_find_binary<W>(T, G.s_lds, xp);
+        if (idx >= 0) {
             int sg;
             const double hv = excitation_element(S, x, diag, i, j, a, b, &sg);
-            const int64_t idx = table_find<W>(T, s_lds, xp);
-            if (idx >= 0) {
-                const double r = exp(T.logabs[idx] - la);
-                double sn, cs;
-                sincos(T.phase[idx] - ph, &sn, &cs);
-                are.add(hv * r * cs);
-                aim.add(hv * r * sn);
-            }
-        };
-        auto drain_full = [&]() {
-            while (qt - qh >= 64) {
-                wave_sync();
-                process(wl.queue[(qh + lane) & 255]);
-                qh += 64;
-                wave_sync();
-            }
-        };
-        // Append the candidates of ballot mask m (uniform) in lane order.
-        auto push = [&](uint64_t m, uint32_t code) {
-            if ((m >> lane) & 1ull) wl.queue[(qt + mbcnt(m)) & 255] = code;
-            qt += __popcll(m);
-        };
+            const double r = exp(T.logabs[idx] - la);
+            double sn, cs;
+            sincos(T.phase[idx] - ph, &sn, &cs);
+            are.add(hv * r * cs);
+            aim.add(hv * r * sn);
+        }
+    };
+    auto drain_full = [&]() {
+        while (qt - qh >= 64) {
+            wave_sync();
+            process(wl.queue[(qh + lane) & 255]);
+            qh += 64;
+            wave_sync();
+        }
+    };
+    // Append the candidates of ballot mask m (uniform) in lane order.
+    auto push = [&](uint64_t m, uint32_t code) {
+        if ((m >> lane) & 1ull) wl.queue[(qt + mbcnt(m)) & 255] = code;
+        qt += __popcll(m);
+    };
 
-        // diagonal: resolved through the table like any x'
-        push(1ull, 0xFFFFFFFFu);
+    // diagonal: resolved through the table like any x'
+    push(1ull, 0xFFFFFFFFu);
 
-        // singles
-        const int nsu = nu * vu, nsin = nsu + nd * vd;
-        for (int base = 0; base < nsin; base += 64) {
-            const int t = base + lane;
-            const bool ok = t < nsin;
-            int sp = 0, o = 0, v = 0;
-            if (ok) {
-                if (t < nsu) {
-                    o = t / vu;
-                    v = t - o * vu;
-                } else {
-                    sp = 1;
-                    o = (t - nsu) / vd;
-                    v = (t - nsu) - o * vd;
-                }
-            }
-            const int q = wl.occ[sp][o], p = wl.vir[sp][v];
-            const uint32_t hh = hx ^ h_lds[q] ^ h_lds[p];
-            const uint64_t m = __ballot(ok && filter_probe(f_lds, wmask, hh) != 0u);
-            if (m) {
-                push(m, (uint32_t)q | 0xFF00u | ((uint32_t)p << 16) | 0xFF000000u);
-                drain_full();
+    // singles
+    const int nsu = nu * vu, nsin = nsu + nd * vd;
+    for (int base = 0; base < nsin; base += 64) {
+        const int t = base + lane;
+        const bool ok = t < nsin;
+        int sp = 0, o = 0, v = 0;
+        if (ok) {
+            if (t < nsu) {
+                o = t / vu;
+                v = t - o * vu;
+            } else {
+                sp = 1;
+                o = (t - nsu) / vd;
+                v = (t - nsu) - o * vd;
             }
         }
+        const int q = wl.occ[sp][o], p = wl.vir[sp][v];
+        const uint32_t hh = hx ^ h_lds[q] ^ h_lds[p];
+        const uint64_t m = __ballot(ok && filter_probe(f_lds, wmask, hh) != 0u);
+        if (m) {
+            push(m, (uint32_t)q | 0xFF00u | ((uint32_t)p << 16) | 0xFF000000u);
+            drain_full();
+        }
+    }
 
-        // same-spin doubles: lane = empty pair (a<b), loops = occupied pair
-        // (i<j), the inner one two connections per step
-        for (int sp = 0; sp < 2; sp++) {
-            const int ns = sp ? nd : nu, nv = sp ? vd : vu;
-            const int npv = nv * (nv - 1) / 2;
-            const uint32_t po_s = sp ? po_d : po_u;
-            if (ns < 2 || npv == 0) continue;
-            for (int base = 0; base < npv; base += 64) {
-                const int vp = base + lane;
-                const uint64_t okm = __ballot(vp < npv);
-                int r1 = 0, rem = vp < npv ? vp : 0;
-                while (rem >= nv - 1 - r1) {
-                    rem -= nv - 1 - r1;
-                    r1++;
-                }
-                const int a = wl.vir[sp][r1], b = wl.vir[sp][r1 + 1 + rem];
-                const uint32_t hab = hx ^ h_lds[a] ^ h_lds[b];
-                const uint32_t cab = ((uint32_t)a << 16) | ((uint32_t)b << 24);
-                for (int o1 = 0; o1 < ns - 1; o1++) {
-                    const uint32_t s1 = (uint32_t)readlane32((int)po_s, o1);
-                    const uint32_t h1 = hab ^ s1, ci = s1 >> 25;
-                    for (int o2 = o1 + 1; o2 < ns; o2 += 2) {
-                        const bool two = o2 + 1 < ns;
-                        const uint32_t sa = (uint32_t)readlane32((int)po_s, o2);
-                        const uint32_t sb = (uint32_t)readlane32((int)po_s, two ? o2 + 1 : o2);
-                        const uint32_t ha = h1 ^ sa, hb = h1 ^ sb;
-                        const uint32_t wa = filter_load(f_lds, wmask, ha);
-                        const uint32_t wb = filter_load(f_lds, wmask, hb);
-                        __builtin_amdgcn_sched_barrier(0);  // both filter reads in flight before the tests
-                        const uint32_t pa = filter_test(wa, ha), pb = filter_test(wb, hb);
-                        const uint64_t ma = __ballot(pa != 0u) & okm;
-                        const uint64_t mb = __ballot(pb != 0u) & (two ? okm : 0ull);
-                        if (ma | mb) {
-                            push(ma, cab | ci | ((sa >> 25) << 8));
-                            push(mb, cab | ci | ((sb >> 25) << 8));
-                            drain_full();
-                        }
+    // same-spin doubles: lane = empty pair (a<b), loops = occupied pair
+    // (i<j), the inner one two connections per step
+    for (int sp = 0; sp < 2; sp++) {
+        const int ns = sp ? nd : nu, nv = sp ? vd : vu;
+        const int npv = nv * (nv - 1) / 2;
+        const uint32_t po_s = sp ? po_d : po_u;
+        if (ns < 2 || npv == 0) continue;
+        for (int base = 0; base < npv; base += 64) {
+            const int vp = base + lane;
+            const uint64_t okm = __ballot(vp < npv);
+            int r1 = 0, rem = vp < npv ? vp : 0;
+            while (rem >= nv - 1 - r1) {
+                rem -= nv - 1 - r1;
+                r1++;
+            }
+            const int a = wl.vir[sp][r1], b = wl.vir[sp][r1 + 1 + rem];
+            const uint32_t hab = hx ^ h_lds[a] ^ h_lds[b];
+            const uint32_t cab = ((uint32_t)a << 16) | ((uint32_t)b << 24);
+            for (int o1 = 0; o1 < ns - 1; o1++) {
+                const uint32_t s1 = (uint32_t)readlane32((int)po_s, o1);
+                const uint32_t h1 = hab ^ s1, ci = s1 >> 25;
+                for (int o2 = o1 + 1; o2 < ns; o2 += 2) {
+                    const bool two = o2 + 1 < ns;
+                    const uint32_t sa = (uint32_t)readlane32((int)po_s, o2);
+                    const uint32_t sb = (uint32_t)readlane32((int)po_s, two ? o2 + 1 : o2);
+                    const uint32_t ha = h1 ^ sa, hb = h1 ^ sb;
+                    const uint32_t wa = filter_load(f_lds, wmask, ha);
+                    const uint32_t wb = filter_load(f_lds, wmask, hb);
+                    __builtin_amdgcn_sched_barrier(0);  // both filter reads in flight before the tests
+                    const uint32_t pa = filter_test(wa, ha), pb = filter_test(wb, hb);
+                    const uint64_t ma = __ballot(pa != 0u) & okm;
+                    const uint64_t mb = __ballot(pb != 0u) & (two ? okm : 0ull);
+                    if (ma | mb) {
+                        push(ma, cab | ci | ((sa >> 25) << 8));
+                        push(mb, cab | ci | ((sb >> 25) << 8));
+                        drain_full();
                     }
                 }
             }
         }
+    }
 
-        // opposite-spin doubles: lane = down single (j -> b), loops = up
-        // single (i -> a), the inner one two connections per step
-        const int nsd = nd * vd;
-        if (nsu > 0 && nsd > 0) {
-            for (int base = 0; base < nsd; base += 64) {
-                const int d = base + lane;
-                const uint64_t okm = __ballot(d < nsd);
-                const int od = d < nsd ? d / vd : 0;
-                const int bd = d < nsd ? d - od * vd : 0;
-                const int j = wl.occ[1][od], b = wl.vir[1][bd];
-                const uint32_t hd = hx ^ h_lds[j] ^ h_lds[b];
-                const uint32_t cjb = ((uint32_t)j << 8) | ((uint32_t)b << 24);
-                for (int o = 0; o < nu; o++) {
-                    const uint32_t s1 = (uint32_t)readlane32((int)po_u, o);
-                    const uint32_t h1 = hd ^ s1, ci = s1 >> 25;
-                    for (int v = 0; v < vu; v += 2) {
-                        const bool two = v + 1 < vu;
-                        const uint32_t sa = (uint32_t)readlane32((int)pv_u, v);
-                        const uint32_t sb = (uint32_t)readlane32((int)pv_u, two ? v + 1 : v);
-                        const uint32_t ha = h1 ^ sa, hb = h1 ^ sb;
-                        const uint32_t wa = filter_load(f_lds, wmask, ha);
-                        const uint32_t wb = filter_load(f_lds, wmask, hb);
-                        __builtin_amdgcn_sched_barrier(0);  // both filter reads in flight before the tests
-                        const uint32_t pa = filter_test(wa, ha), pb = filter_test(wb, hb);
-                        const uint64_t ma = __ballot(pa != 0u) & okm;
-                        const uint64_t mb = __ballot(pb != 0u) & (two ? okm : 0ull);
-                        if (ma | mb) {
-                            push(ma, cjb | ci | ((sa >> 25) << 16));
-                            push(mb, cjb | ci | ((sb >> 25) << 16));
-                            drain_full();
-                        }
+    // opposite-spin doubles: lane = down single (j -> b), loops = up single
+    // (i -> a), the inner one two connections per step
+    const int nsd = nd * vd;
+    if (nsu > 0 && nsd > 0) {
+        for (int base = 0; base < nsd; base += 64) {
+            const int d = base + lane;
+            const uint64_t okm = __ballot(d < nsd);
+            const int od = d < nsd ? d / vd : 0;
+            const int bd = d < nsd ? d - od * vd : 0;
+            const int j = wl.occ[1][od], b = wl.vir[1][bd];
+            const uint32_t hd = hx ^ h_lds[j] ^ h_lds[b];
+            const uint32_t cjb = ((uint32_t)j << 8) | ((uint32_t)b << 24);
+            for (int o = 0; o < nu; o++) {
+                const uint32_t s1 = (uint32_t)readlane32((int)po_u, o);
+                const uint32_t h1 = hd ^ s1, ci = s1 >> 25;
+                for (int v = 0; v < vu; v += 2) {
+                    const bool two = v + 1 < vu;
+                    const uint32_t sa = (uint32_t)readlane32((int)pv_u, v);
+                    const uint32_t sb = (uint32_t)readlane32((int)pv_u, two ? v + 1 : v);
+                    const uint32_t ha = h1 ^ sa, hb = h1 ^ sb;
+                    const uint32_t wa = filter_load(f_lds, wmask, ha);
+                    const uint32_t wb = filter_load(f_lds, wmask, hb);
+                    __builtin_amdgcn_sched_barrier(0);  // both filter reads in flight before the tests
+                    const uint32_t pa = filter_test(wa, ha), pb = filter_test(wb, hb);
+                    const uint64_t ma = __ballot(pa != 0u) & okm;
+                    const uint64_t mb = __ballot(pb != 0u) & (two ? okm : 0ull);
+                    if (ma | mb) {
+                        push(ma, cjb | ci | ((sa >> 25) << 16));
+                        push(mb, cjb | ci | ((sb >> 25) << 16));
+                        drain_full();
                     }
                 }
             }
         }
-        while (qt > qh) {
-            const int cnt = qt - qh < 64 ? qt - qh : 64;
-            wave_sync();
-            if (lane < cnt) process(wl.queue[(qh + lane) & 255]);
-            qh += cnt;
-            wave_sync();
-        }
-
-        double rs = are.s, rc = are.c, is = aim.s, ic = aim.c;
-        wave_nsum(rs, rc);
-        wave_nsum(is, ic);
-        if (lane == 0) {
-            eloc[2 * smp] = rs + rc;
-            eloc[2 * smp + 1] = is + ic;
-        }
+    }
+    while (qt > qh) {
+        const int cnt = qt - qh < 64 ? qt - qh : 64;
+        wave_sync();
+        if (lane < cnt) process(wl.queue[(qh + lane) & 255]);
+        qh += cnt;
         wave_sync();
     }
+
+    double rs = are.s, rc = are.c, is = aim.s, ic = aim.c;
+    wave_nsum(rs, rc);
+    wave_nsum(is, ic);
+    if (lane == 0) {
+        eloc[2 * smp] = rs + rc;
+        eloc[2 * smp + 1] = is + ic;
+    }
+    wave_sync();
 }
+
+// One system: persistent grid, wave-strided samples.
+template <int W, int S8>
+__global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView T, int lds_filter_log2,
+                                                  const uint64_t *__restrict__ keys,
+                                                  const double *__restrict__ logabs,
+                                                  const double *__restrict__ phase, int64_t n,
+                                                  double *__restrict__ eloc, int *status) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const SaStage G = sa_stage<W>(S, T, lds_filter_log2, smem);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    for (int64_t smp = (int64_t)blockIdx.x * nw + wid; smp < n; smp += (int64_t)gridDim.x * nw)
+        sa_sample<W, S8>(S, T, G, G.waves[wid], smp, keys, logabs, phase, eloc, status);
+}
+
+// Many systems in one persistent launch: blocks pull tiles (a system and a
+// run of its samples, in system order) from a device counter, restage the
+// LDS data only when the system changes, and give each wave one sample at a
+// time.  Every block leaves the loop when the counter passes the last tile.
+template <int W, int S8>
+__global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa_batch(const SaBatchItem *__restrict__ items,
+                                                        const SaTile *__restrict__ tiles, int ntiles,
+                                                        int *counter) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ int next_tile;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    int staged = -1;
+    SaStage G{};
+    for (;;) {
+        if (threadIdx.x == 0) next_tile = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = next_tile;
+        __syncthreads();
+        if (t >= ntiles) break;
+        const SaTile tl = tiles[t];
+        const SaBatchItem &it = items[tl.item];
+        if (tl.item != staged) {
+            G = sa_stage<W>(it.S, it.T, it.lds_filter_log2, smem);
+            staged = tl.item;
+        }
+        for (int64_t smp = tl.begin + wid; smp < tl.begin + tl.count; smp += nw)
+            sa_sample<W, S8>(it.S, it.T, G, G.waves[wid], smp, it.keys, it.logabs, it.phase, it.eloc, it.status);
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset_counter(int *c) { *c = 0; }
 
 // Canonical-order export of every connection (tests): one wave per sample,
 // lanes stride over the canonical index.
@@ -436,8 +521,49 @@ __global__ void k_validate_samples(SysView S, const uint64_t *__restrict__ keys,
 
 __global__ void k_zero_int(int *p) { *p = 0; }
 
-static size_t sa_lds_bytes(int filter_log2, int split_levels, int W, int waves) {
+size_t sa_lds_bytes(int filter_log2, int split_levels, int W, int waves) {
     return sa_layout(filter_log2, split_levels, W, waves).total;
+}
+
+const void *sa_kernel_ptr(int W, int search) {
+    if (W == 1) return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa<1, 1>)
+                                   : reinterpret_cast<const void *>(k_eloc_sa<1, 0>);
+    return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa<2, 1>)
+                       : reinterpret_cast<const void *>(k_eloc_sa<2, 0>);
+}
+
+const void *sa_batch_kernel_ptr(int W, int search) {
+    if (W == 1) return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa_batch<1, 1>)
+                                   : reinterpret_cast<const void *>(k_eloc_sa_batch<1, 0>);
+    return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa_batch<2, 1>)
+                       : reinterpret_cast<const void *>(k_eloc_sa_batch<2, 0>);
+}
+
+// The sample-aware kernels are built to keep every value in registers; the
+// library refuses to run a build that spills to private memory.
+nnqs_status sa_check_no_spill(const void *fn) {
+    hipFuncAttributes fa;
+    NNQS_HIP_CHECK(hipFuncGetAttributes(&fa, fn));
+    if (fa.localSizeBytes != 0)
+        return fail(NNQS_EUNSUPPORTED, "sample-aware kernel uses %zu bytes of private memory per lane",
+                    (size_t)fa.localSizeBytes);
+    return NNQS_OK;
+}
+
+void sa_launch_batch(int W, int search, unsigned grid, int waves, size_t lds, hipStream_t st,
+                     const SaBatchItem *items, const SaTile *tiles, int ntiles, int *counter) {
+    const dim3 g(grid), b(waves * 64);
+    if (W == 1) {
+        if (search == 2) hipLaunchKernelGGL((k_eloc_sa_batch<1, 1>), g, b, lds, st, items, tiles, ntiles, counter);
+        else hipLaunchKernelGGL((k_eloc_sa_batch<1, 0>), g, b, lds, st, items, tiles, ntiles, counter);
+    } else {
+        if (search == 2) hipLaunchKernelGGL((k_eloc_sa_batch<2, 1>), g, b, lds, st, items, tiles, ntiles, counter);
+        else hipLaunchKernelGGL((k_eloc_sa_batch<2, 0>), g, b, lds, st, items, tiles, ntiles, counter);
+    }
+}
+
+void sa_launch_reset(int *counter, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, counter);
 }
 
 }  // namespace nnqs
@@ -492,19 +618,12 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
     }
     const TableView tv = table_view(tab);
     const int W = sys->view.N > 64 ? 2 : 1;
+    const int search = tab->tune.search;
     int waves = tab->tune.waves_per_block;
     if (waves * 64 > kSaMaxThreads) waves = kSaMaxThreads / 64;
-    // The kernel is built to keep every value in registers; refuse to run a
-    // build that spills to private memory.
-    {
-        hipFuncAttributes fa;
-        const void *fn = W == 1 ? reinterpret_cast<const void *>(k_eloc_sa<1>)
-                                : reinterpret_cast<const void *>(k_eloc_sa<2>);
-        NNQS_HIP_CHECK(hipFuncGetAttributes(&fa, fn));
-        if (fa.localSizeBytes != 0)
-            return fail(NNQS_EUNSUPPORTED, "sample-aware kernel uses %zu bytes of private memory per lane",
-                        (size_t)fa.localSizeBytes);
-    }
+    const void *fn = sa_kernel_ptr(W, search);
+    nnqs_status s0 = sa_check_no_spill(fn);
+    if (s0 != NNQS_OK) return s0;
     int fl = tv.filter_log2;
     size_t lds = sa_lds_bytes(fl, tv.split_levels, W, waves);
     while (lds > (size_t)sys->max_lds && fl > 10) {  // fold the filter to fit
@@ -513,16 +632,22 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
     }
     if (lds > (size_t)sys->max_lds) return fail(NNQS_EINVAL, "LDS budget exceeded (%zu bytes)", lds);
     const unsigned grid = (unsigned)(sys->cu_count * tab->tune.blocks_per_cu);
+    NNQS_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const dim3 g(grid), b(waves * 64);
     if (W == 1) {
-        NNQS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_eloc_sa<1>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(k_eloc_sa<1>, dim3(grid), dim3(waves * 64), lds, st, sys->view, tv, fl, keys, logabs, phase,
-                           n, eloc, tab->status);
+        if (search == 2)
+            hipLaunchKernelGGL((k_eloc_sa<1, 1>), g, b, lds, st, sys->view, tv, fl, keys, logabs, phase, n, eloc,
+                               tab->status);
+        else
+            hipLaunchKernelGGL((k_eloc_sa<1, 0>), g, b, lds, st, sys->view, tv, fl, keys, logabs, phase, n, eloc,
+                               tab->status);
     } else {
-        NNQS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_eloc_sa<2>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(k_eloc_sa<2>, dim3(grid), dim3(waves * 64), lds, st, sys->view, tv, fl, keys, logabs, phase,
-                           n, eloc, tab->status);
+        if (search == 2)
+            hipLaunchKernelGGL((k_eloc_sa<2, 1>), g, b, lds, st, sys->view, tv, fl, keys, logabs, phase, n, eloc,
+                               tab->status);
+        else
+            hipLaunchKernelGGL((k_eloc_sa<2, 0>), g, b, lds, st, sys->view, tv, fl, keys, logabs, phase, n, eloc,
+                               tab->status);
     }
     NNQS_HIP_CHECK(hipGetLastError());
     if (energy) return enqueue_energy(tab, counts, eloc, n, energy, st);

@@ -265,6 +265,41 @@ nnqs_status enqueue_energy_partials(double *partials, const uint32_t *counts, co
 nnqs_status read_status(nnqs_table *tab, hipStream_t st, bool clear);
 constexpr int kMaxFilterLog2 = 20;
 
+inline bool tune_valid(const nnqs_tune &d) {
+    return d.waves_per_block >= 1 && d.waves_per_block <= 16 && d.blocks_per_cu >= 1 && d.blocks_per_cu <= 64 &&
+           d.filter_log2_bits >= 10 && d.filter_log2_bits <= kMaxFilterLog2 && d.splitter_levels >= 1 &&
+           d.splitter_levels <= 13 && (d.search == 1 || d.search == 2) && d.tile_samples >= 1 &&
+           d.tile_samples <= 65536;
+}
+
+// One system of a batched sample-aware launch (device array).
+struct SaBatchItem {
+    SysView S;
+    TableView T;
+    int lds_filter_log2;
+    const uint64_t *keys;
+    const double *logabs, *phase;
+    double *eloc;
+    int *status;
+};
+
+// A run of samples of one system (device array, in system order).
+struct SaTile {
+    int32_t item, count;
+    int64_t begin;
+};
+
+// Sample-aware kernel plumbing shared by the single-system and batched
+// entry points (eloc_sa.hip).
+size_t sa_lds_bytes(int filter_log2, int split_levels, int W, int waves);
+const void *sa_kernel_ptr(int W, int search);
+const void *sa_batch_kernel_ptr(int W, int search);
+nnqs_status sa_check_no_spill(const void *fn);
+void sa_launch_batch(int W, int search, unsigned grid, int waves, size_t lds, hipStream_t st,
+                     const SaBatchItem *items, const SaTile *tiles, int ntiles, int *counter);
+void sa_launch_reset(int *counter, hipStream_t st);
+TableView table_view_planned(const nnqs_table *t, int64_t n);
+
 // Membership-filter geometry, read from the low 32 bits of the linear key
 // hash: bits 0-4 and 5-9 select two bits of a 32-bit filter word, bits
 // 10..(filter_log2 + 4) select the word.  Bits 25-31 are never read, which

@@ -46,6 +46,18 @@ TableView table_view(const nnqs_table *t) {
     return v;
 }
 
+// The view a build of n samples with the table's current tune will produce.
+TableView table_view_planned(const nnqs_table *t, int64_t n) {
+    TableView v = table_view(t);
+    v.n = n;
+    int L = 0;
+    while ((int64_t(1) << L) < n) L++;
+    v.log2n = L;
+    v.filter_log2 = t->tune.filter_log2_bits;
+    v.split_levels = t->tune.splitter_levels < L ? t->tune.splitter_levels : L;
+    return v;
+}
+
 // ------------------------------------------------------------- sorting
 // Total order on (key word 1, key word 0, original index): padding entries
 // carry index 0xFFFFFFFF and sort last even against an all-ones key.
@@ -449,16 +461,17 @@ nnqs_status nnqs_table_set_tune(nnqs_table *t, const nnqs_tune *tune) {
     d.blocks_per_cu = 1;
     d.filter_log2_bits = 20;
     d.splitter_levels = 10;
+    d.search = 1;
+    d.tile_samples = 256;
     if (tune) {
         if (tune->waves_per_block) d.waves_per_block = tune->waves_per_block;
         if (tune->blocks_per_cu) d.blocks_per_cu = tune->blocks_per_cu;
         if (tune->filter_log2_bits) d.filter_log2_bits = tune->filter_log2_bits;
         if (tune->splitter_levels) d.splitter_levels = tune->splitter_levels;
+        if (tune->search) d.search = tune->search;
+        if (tune->tile_samples) d.tile_samples = tune->tile_samples;
     }
-    if (d.waves_per_block < 1 || d.waves_per_block > 16 || d.blocks_per_cu < 1 || d.blocks_per_cu > 64 ||
-        d.filter_log2_bits < 10 || d.filter_log2_bits > kMaxFilterLog2 || d.splitter_levels < 0 ||
-        d.splitter_levels > kMaxSplitLevels)
-        return fail(NNQS_EINVAL, "tuning parameters out of range");
+    if (!tune_valid(d)) return fail(NNQS_EINVAL, "tuning parameters out of range");
     t->tune = d;
     return NNQS_OK;
 }

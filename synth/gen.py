@@ -296,14 +296,14 @@ _CONFIGS = {
 def batched_system_specs(n_systems: int = 32):
     """``(K, n_up, n_dn, n_unique)`` for the multi-system batch: ``N`` uniform
     over the even numbers 20..120, ``n = 2*round(N/6)`` split evenly, unique
-    sample count log-uniform in [1e3, 1e5]."""
+    sample count log-uniform in [1e3, 1e5], capped at half the sector size."""
     rng = np.random.default_rng([SEED_ROOT, 4])
     Ns = rng.integers(10, 61, size=n_systems) * 2
     nus = np.exp(rng.uniform(np.log(1e3), np.log(1e5), size=n_systems)).round().astype(int)
     specs = []
     for N, nu in zip(Ns.tolist(), nus.tolist()):
         half = int(round(N / 6))
-        specs.append((N // 2, half, half, int(nu)))
+        specs.append((N // 2, half, half, int(min(nu, sector_size(N // 2, half, half) // 2))))
     return specs
 
 
@@ -338,9 +338,11 @@ def config_inputs(cfg: int, sys: int = 0, *, K: int | None = None, n_up: int | N
         phase = rng.uniform(0.0, 2.0 * np.pi, size=keys.shape[0])
         counts = np.ones(keys.shape[0], dtype=np.uint32)
     else:
-        # model workloads draw moves near the Fermi level with the decay of
-        # the model's own logit bias (|psi|^2 falls by exp(-beta) per orbital)
-        keys, level = geometric_samples(K, n_up, n_dn, n_unique, rng, fermi_decay=beta if model else None)
+        # the full-E_loc workloads (3, 5) draw moves near the Fermi level with
+        # the decay of the model's own logit bias (|psi|^2 falls by
+        # exp(-beta) per orbital); the batch (4) keeps uniform moves
+        fermi = beta if (model and cfg in (3, 5)) else None
+        keys, level = geometric_samples(K, n_up, n_dn, n_unique, rng, fermi_decay=fermi)
         logabs, phase = sample_amplitudes(level, rng)
         counts = sample_counts(keys.shape[0], rng)
     out = dict(cfg=cfg, sys=sys, K=K, N=2 * K, n_up=n_up, n_dn=n_dn, h=h, g=g, e_core=e_core,

@@ -1,0 +1,148 @@
+"""GPU tests of the batched multi-system launch: parity with the single-system
+path and the oracle, graph capture and replay, the autotuner, and the
+network-fed variant."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import assert_eloc_close, dev, eloc_complex
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_16705_amd as nn
+    return nn
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} {kw}", flush=True)
+
+
+# uneven systems: N = 16 .. 120 (one- and two-word keys), ragged sample counts
+SYSTEMS = [dict(K=8, n_up=2, n_dn=2, n_unique=300), dict(K=12, n_up=4, n_dn=3, n_unique=1000),
+           dict(K=24, n_up=6, n_dn=6, n_unique=3001), dict(K=40, n_up=5, n_dn=6, n_unique=777),
+           dict(K=60, n_up=5, n_dn=5, n_unique=129)]
+
+
+def _items(nn, specs, with_model=False):
+    items = []
+    for k, kw in enumerate(specs):
+        d = synth.config_inputs(2, sys=k, model=with_model, **kw)
+        n = d["keys"].shape[0]
+        S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+        it = dict(d=d, system=S, table=nn.Table(S, capacity=n), keys=dev(d["keys"]),
+                  counts=dev(d["counts"], torch.int32), logabs=dev(d["logabs"]), phase=dev(d["phase"]),
+                  eloc=torch.full((n, 2), np.nan, dtype=torch.float64, device="cuda"),
+                  energy=torch.zeros(4, dtype=torch.float64, device="cuda"))
+        if with_model:
+            it["model"] = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+        items.append(it)
+    return items
+
+
+def _single(nn, it):
+    """The same system through the single-system entry points."""
+    T = nn.Table(it["system"], capacity=it["keys"].shape[0])
+    T.build(it["keys"], it["logabs"], it["phase"], validate=True)
+    return nn.eloc_table(it["system"], T, it["keys"], it["counts"], it["logabs"], it["phase"])
+
+
+def test_batch_matches_single_system_and_oracle(nn):
+    _print_case("batch_parity", systems=len(SYSTEMS))
+    items = _items(nn, SYSTEMS)
+    B = nn.Batch(items)
+    B.run()
+    torch.cuda.synchronize()
+    for it in items:
+        e1, en1 = _single(nn, it)
+        torch.cuda.synchronize()
+        a, b = eloc_complex(it["eloc"]), eloc_complex(e1)
+        assert np.all(np.abs(a - b) <= 1e-12 * np.maximum(1.0, np.abs(b))), it["d"]["K"]
+        assert abs(it["energy"][0].item() - en1[0].item()) <= 1e-12 * abs(en1[0].item())
+    # the two smallest systems against the FP64 oracle
+    for it in items[:2]:
+        d = it["d"]
+        ref, ab = oracle.eloc_table(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"], d["keys"],
+                                    d["logabs"], d["phase"], d["keys"], d["logabs"], d["phase"], with_absum=True)
+        assert_eloc_close(eloc_complex(it["eloc"]), ref, ab, label=f"K={d['K']}")
+
+
+def test_batch_graph_replays_match_eager(nn):
+    _print_case("batch_graph")
+    items = _items(nn, SYSTEMS[:4])
+    B = nn.Batch(items)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B.run(s)
+    s.synchronize()
+    ref = [it["eloc"].clone() for it in items]
+    ref_en = [it["energy"].clone() for it in items]
+    B.capture(s)
+    for rep in range(3):
+        for it in items:  # eager work between replays
+            it["eloc"].fill_(np.nan)
+            it["energy"].zero_()
+        torch.cuda.synchronize()
+        B.launch(s)
+        s.synchronize()
+        for it, r, re in zip(items, ref, ref_en):
+            assert torch.equal(it["eloc"], r), rep
+            assert torch.equal(it["energy"], re), rep
+
+
+def test_batch_autotune_keeps_results(nn):
+    _print_case("batch_autotune")
+    items = _items(nn, SYSTEMS[1:4])
+    B = nn.Batch(items)
+    B.run()
+    torch.cuda.synchronize()
+    ref = [eloc_complex(it["eloc"]) for it in items]
+    tune, ms = B.autotune(reps=1)
+    print(f"autotuned schedule {tune}, {ms:.3f} ms per step")
+    assert tune["waves_per_block"] in (8, 12) and tune["search"] in (1, 2)
+    assert tune["tile_samples"] in (64, 256, 1024) and tune["splitter_levels"] in (8, 10, 12)
+    assert B.get_tune() == tune
+    for it in items:
+        it["eloc"].fill_(np.nan)
+    B.run()
+    torch.cuda.synchronize()
+    for it, r in zip(items, ref):
+        g = eloc_complex(it["eloc"])
+        assert np.all(np.abs(g - r) <= 1e-12 * np.maximum(1.0, np.abs(r)))
+
+
+def test_batch_with_models_feeds_the_table_from_the_network(nn):
+    _print_case("batch_models")
+    specs = [dict(K=6, n_up=2, n_dn=3, n_unique=150), dict(K=12, n_up=3, n_dn=3, n_unique=700),
+             dict(K=20, n_up=4, n_dn=4, n_unique=333)]
+    items = _items(nn, specs, with_model=True)
+    B = nn.Batch(items)
+    B.run()
+    torch.cuda.synchronize()
+    for it in items:
+        la, ph = nn.model_logpsi(it["model"], it["keys"], nn.NNQS_BF16)
+        torch.cuda.synchronize()
+        assert torch.equal(la, it["logabs"]) and torch.equal(ph, it["phase"])
+        e1, en1 = _single(nn, it)
+        torch.cuda.synchronize()
+        a, b = eloc_complex(it["eloc"]), eloc_complex(e1)
+        assert np.all(np.abs(a - b) <= 1e-12 * np.maximum(1.0, np.abs(b)))
+
+
+def test_batch_rejects_bad_items(nn):
+    items = _items(nn, SYSTEMS[:1])
+    bad = dict(items[0])
+    bad["table"] = nn.Table(bad["system"], capacity=10)  # smaller than n
+    with pytest.raises(nn.NNQSError):
+        nn.Batch([bad])
+    B = nn.Batch(items)
+    with pytest.raises(nn.NNQSError):  # nothing captured yet
+        B.launch(torch.cuda.Stream())
+    with pytest.raises(nn.NNQSError):
+        B.set_tune(search=3)

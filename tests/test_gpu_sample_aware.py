@@ -162,7 +162,8 @@ def test_eloc_deterministic_and_tune_invariant(nn):
     assert torch.equal(e1, e2) and torch.equal(en1, en2)
     base = eloc_complex(e1)
     for tune in (dict(filter_log2_bits=12), dict(splitter_levels=0), dict(waves_per_block=4, blocks_per_cu=3),
-                 dict(filter_log2_bits=20, splitter_levels=13)):
+                 dict(filter_log2_bits=20, splitter_levels=13), dict(search=2, splitter_levels=7),
+                 dict(search=2, splitter_levels=12)):
         T.set_tune(**tune)
         T.build(dev(d["keys"]), dev(d["logabs"]), dev(d["phase"]))
         e3, _ = nn.eloc_table(S, T, *args)
