@@ -72,6 +72,8 @@ def main():
                     help="samples of the N=120 transformer workload timed in the full-E_loc leg (0 = skip)")
     ap.add_argument("--fp64-samples", type=int, default=1,
                     help="of these, samples also evaluated by the plain FP64 path (error reference)")
+    ap.add_argument("--schedule", type=str, default="",
+                    help="JSON launch schedule for the sample-aware kernel instead of autotuning (profiling runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
@@ -125,6 +127,14 @@ def main():
     T.build(keys, la, ph, validate=True)
     nn.eloc_table(S, T, keys, cnt, la, ph, eloc=eloc, energy=energy, validate=True)
     torch.cuda.synchronize()
+    if args.schedule:
+        T.set_tune(**json.loads(args.schedule))
+        tune = T.get_tune()
+        log(f"schedule {tune} (given)")
+    else:
+        log("autotuning the launch schedule")
+        tune, tune_ms = T.autotune(keys, la, ph, reps=2)
+        log(f"schedule {tune} ({tune_ms:.3f} ms per E_loc call)")
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
@@ -181,7 +191,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sample-aware E_loc, N=48 (K=24), 6 up + 6 down, 65,536 unique samples, "
                                "FP64, table build + E_loc + weighted energy per step",
-                   "n_unique": n, "connections_per_sample": C},
+                   "n_unique": n, "connections_per_sample": C, "schedule": tune},
         "connections_per_s": conns_s,
         "energy": float(en[0]),
         "max_abs_err_vs_oracle_ha": max_err,

@@ -49,6 +49,8 @@ SIGNATURES = {
     "nnqs_screen_gradient": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _i32, _c_void_p, _c_void_p,
                                     _c_void_p]),
     "nnqs_screen_adam_step": (_i32, [_c_void_p, _c_void_p, _f64, _f64, _f64, _f64, _c_void_p]),
+    "nnqs_table_autotune": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p, _i32,
+                                   _c_void_p, _c_void_p, _c_void_p]),
     "nnqs_batch_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p, _i32]),
     "nnqs_batch_destroy": (_i32, [_c_void_p]),
     "nnqs_batch_run": (_i32, [_c_void_p, _c_void_p]),

@@ -117,6 +117,23 @@ class Table:
         L.check(self._lib.nnqs_table_get_tune(self.handle, ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in Tune._fields_}
 
+    def autotune(self, keys, logabs, phase, reps: int = 2, eloc=None, stream=None):
+        """Times the candidate schedules of ``nnqs_eloc_table`` on these
+        samples, keeps the fastest (the table is left built from them) and
+        returns ``(tune dict, best ms)``."""
+        n = keys.shape[0]
+        _need(keys, "keys", _KEY_DTYPES, (n, 2))
+        _need(logabs, "logabs", (torch.float64,), (n,))
+        _need(phase, "phase", (torch.float64,), (n,))
+        if eloc is None:
+            eloc = torch.empty((n, 2), dtype=torch.float64, device=keys.device)
+        t = Tune()
+        ms = ctypes.c_double()
+        L.check(self._lib.nnqs_table_autotune(self.system.handle, self.handle, _ptr(keys), _ptr(logabs), _ptr(phase),
+                                              n, _ptr(eloc), int(reps), ctypes.byref(t), ctypes.byref(ms),
+                                              _stream(stream)))
+        return {f: getattr(t, f) for f, _ in Tune._fields_}, ms.value
+
     def close(self):
         if getattr(self, "handle", None):
             self._lib.nnqs_table_destroy(self.handle)

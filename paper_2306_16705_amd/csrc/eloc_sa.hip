@@ -23,6 +23,8 @@ namespace nnqs {
 // which leaves the kernel up to 168 VGPRs (it needs about 150) so that
 // nothing spills to private memory.
 constexpr int kSaMaxThreads = 768;
+// The one-word-search build fits 128 registers and also runs 16-wave blocks.
+constexpr int kSaWideThreads = 1024;
 
 // Dynamic LDS layout of the sample-aware kernel: the filter words, the staged
 // search keys, the low 32 bits of the 128 hash words, then one WaveLds per
@@ -386,9 +388,11 @@ __device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, 
     wave_sync();
 }
 
-// One system: persistent grid, wave-strided samples.
-template <int W, int S8>
-__global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa(SysView S, TableView T, int lds_filter_log2,
+// One system: persistent grid, wave-strided samples.  NT is the largest
+// block the build is for (1024 threads only for the variant that fits in 128
+// registers).
+template <int W, int S8, int NT>
+__global__ void __launch_bounds__(NT) k_eloc_sa(SysView S, TableView T, int lds_filter_log2,
                                                   const uint64_t *__restrict__ keys,
                                                   const double *__restrict__ logabs,
                                                   const double *__restrict__ phase, int64_t n,
@@ -525,11 +529,14 @@ size_t sa_lds_bytes(int filter_log2, int split_levels, int W, int waves) {
     return sa_layout(filter_log2, split_levels, W, waves).total;
 }
 
-const void *sa_kernel_ptr(int W, int search) {
-    if (W == 1) return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa<1, 1>)
-                                   : reinterpret_cast<const void *>(k_eloc_sa<1, 0>);
-    return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa<2, 1>)
-                       : reinterpret_cast<const void *>(k_eloc_sa<2, 0>);
+const void *sa_kernel_ptr(int W, int search, int waves) {
+    if (search == 1 && waves > kSaMaxThreads / 64)
+        return W == 1 ? reinterpret_cast<const void *>(k_eloc_sa<1, 0, kSaWideThreads>)
+                      : reinterpret_cast<const void *>(k_eloc_sa<2, 0, kSaWideThreads>);
+    if (W == 1) return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa<1, 1, kSaMaxThreads>)
+                                   : reinterpret_cast<const void *>(k_eloc_sa<1, 0, kSaMaxThreads>);
+    return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa<2, 1, kSaMaxThreads>)
+                       : reinterpret_cast<const void *>(k_eloc_sa<2, 0, kSaMaxThreads>);
 }
 
 const void *sa_batch_kernel_ptr(int W, int search) {
@@ -620,8 +627,9 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
     const int W = sys->view.N > 64 ? 2 : 1;
     const int search = tab->tune.search;
     int waves = tab->tune.waves_per_block;
-    if (waves * 64 > kSaMaxThreads) waves = kSaMaxThreads / 64;
-    const void *fn = sa_kernel_ptr(W, search);
+    const int max_waves = (search == 1 ? kSaWideThreads : kSaMaxThreads) / 64;
+    if (waves > max_waves) waves = max_waves;
+    const void *fn = sa_kernel_ptr(W, search, waves);
     nnqs_status s0 = sa_check_no_spill(fn);
     if (s0 != NNQS_OK) return s0;
     int fl = tv.filter_log2;
@@ -634,24 +642,101 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
     const unsigned grid = (unsigned)(sys->cu_count * tab->tune.blocks_per_cu);
     NNQS_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const dim3 g(grid), b(waves * 64);
+    const bool wide = waves > kSaMaxThreads / 64;
     if (W == 1) {
-        if (search == 2)
-            hipLaunchKernelGGL((k_eloc_sa<1, 1>), g, b, lds, st, sys->view, tv, fl, keys, logabs, phase, n, eloc,
-                               tab->status);
+        if (wide)
+            hipLaunchKernelGGL((k_eloc_sa<1, 0, kSaWideThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
+                               phase, n, eloc, tab->status);
+        else if (search == 2)
+            hipLaunchKernelGGL((k_eloc_sa<1, 1, kSaMaxThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
+                               phase, n, eloc, tab->status);
         else
-            hipLaunchKernelGGL((k_eloc_sa<1, 0>), g, b, lds, st, sys->view, tv, fl, keys, logabs, phase, n, eloc,
-                               tab->status);
+            hipLaunchKernelGGL((k_eloc_sa<1, 0, kSaMaxThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
+                               phase, n, eloc, tab->status);
     } else {
-        if (search == 2)
-            hipLaunchKernelGGL((k_eloc_sa<2, 1>), g, b, lds, st, sys->view, tv, fl, keys, logabs, phase, n, eloc,
-                               tab->status);
+        if (wide)
+            hipLaunchKernelGGL((k_eloc_sa<2, 0, kSaWideThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
+                               phase, n, eloc, tab->status);
+        else if (search == 2)
+            hipLaunchKernelGGL((k_eloc_sa<2, 1, kSaMaxThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
+                               phase, n, eloc, tab->status);
         else
-            hipLaunchKernelGGL((k_eloc_sa<2, 0>), g, b, lds, st, sys->view, tv, fl, keys, logabs, phase, n, eloc,
-                               tab->status);
+            hipLaunchKernelGGL((k_eloc_sa<2, 0, kSaMaxThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
+                               phase, n, eloc, tab->status);
     }
     NNQS_HIP_CHECK(hipGetLastError());
     if (energy) return enqueue_energy(tab, counts, eloc, n, energy, st);
     return NNQS_OK;
+}
+
+// Autotuner of the single-system path: for every candidate schedule the
+// table is rebuilt from the samples, one untimed call warms up, and the best
+// of `reps` timed calls counts.  Candidates: waves per block {8, 12, 16}
+// (16 only with search 1) x splitter levels {8, 10, 12} x search {1, 2}.
+nnqs_status nnqs_table_autotune(const nnqs_system *sys, nnqs_table *tab, const uint64_t *keys, const double *logabs,
+                                const double *phase, int64_t n, double *eloc, int32_t reps, nnqs_tune *best_out,
+                                double *best_ms, void *stream) {
+    clear_error();
+    if (!sys || !tab || !keys || !logabs || !phase || !eloc) return fail(NNQS_EINVAL, "null pointer argument");
+    if (n <= 0 || n > tab->capacity) return fail(NNQS_EINVAL, "n outside 1..table capacity");
+    if (reps < 1) reps = 1;
+    hipStream_t st = as_stream(stream);
+    hipEvent_t e0, e1;
+    NNQS_HIP_CHECK(hipEventCreate(&e0));
+    NNQS_HIP_CHECK(hipEventCreate(&e1));
+    const nnqs_tune start = tab->tune;
+    nnqs_tune best = start;
+    float best_t = 1e30f;
+    nnqs_status s = NNQS_OK;
+    for (int waves : {8, 12, 16})
+        for (int sl : {8, 10, 12})
+            for (int search : {1, 2}) {
+                if (waves > 12 && search != 1) continue;
+                nnqs_tune c = start;
+                c.waves_per_block = waves;
+                c.splitter_levels = sl;
+                c.search = search;
+                tab->tune = c;
+                s = nnqs_table_build(tab, keys, logabs, phase, n, 0, stream);
+                if (s != NNQS_OK) goto done;
+                s = nnqs_eloc_table(sys, tab, keys, nullptr, logabs, phase, n, eloc, nullptr, 0, stream);
+                if (s == NNQS_EINVAL) continue;  // does not fit: skip the candidate
+                if (s != NNQS_OK) goto done;
+                float tmin = 1e30f;
+                for (int r = 0; r < reps; r++) {
+                    if (hipEventRecord(e0, st) != hipSuccess) {
+                        s = fail(NNQS_EHIP, "event record failed");
+                        goto done;
+                    }
+                    s = nnqs_eloc_table(sys, tab, keys, nullptr, logabs, phase, n, eloc, nullptr, 0, stream);
+                    if (s != NNQS_OK) goto done;
+                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                        s = fail(NNQS_EHIP, "event timing failed");
+                        goto done;
+                    }
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    tmin = ms < tmin ? ms : tmin;
+                }
+                if (tmin < best_t) {
+                    best_t = tmin;
+                    best = c;
+                }
+            }
+    s = NNQS_OK;
+done:
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    tab->tune = best;
+    {
+        const nnqs_status s2 = nnqs_table_build(tab, keys, logabs, phase, n, 0, stream);
+        if (s == NNQS_OK) s = s2;
+    }
+    if (s == NNQS_OK) {
+        if (best_out) *best_out = best;
+        if (best_ms) *best_ms = best_t;
+    }
+    return s;
 }
 
 }  // extern "C"

@@ -292,7 +292,7 @@ struct SaTile {
 // Sample-aware kernel plumbing shared by the single-system and batched
 // entry points (eloc_sa.hip).
 size_t sa_lds_bytes(int filter_log2, int split_levels, int W, int waves);
-const void *sa_kernel_ptr(int W, int search);
+const void *sa_kernel_ptr(int W, int search, int waves);
 const void *sa_batch_kernel_ptr(int W, int search);
 nnqs_status sa_check_no_spill(const void *fn);
 void sa_launch_batch(int W, int search, unsigned grid, int waves, size_t lds, hipStream_t st,

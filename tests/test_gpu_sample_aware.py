@@ -163,13 +163,35 @@ def test_eloc_deterministic_and_tune_invariant(nn):
     base = eloc_complex(e1)
     for tune in (dict(filter_log2_bits=12), dict(splitter_levels=0), dict(waves_per_block=4, blocks_per_cu=3),
                  dict(filter_log2_bits=20, splitter_levels=13), dict(search=2, splitter_levels=7),
-                 dict(search=2, splitter_levels=12)):
+                 dict(search=2, splitter_levels=12), dict(waves_per_block=16), dict(waves_per_block=16, search=1,
+                                                                                       splitter_levels=12)):
         T.set_tune(**tune)
         T.build(dev(d["keys"]), dev(d["logabs"]), dev(d["phase"]))
         e3, _ = nn.eloc_table(S, T, *args)
         torch.cuda.synchronize()
         g = eloc_complex(e3)
         assert np.all(np.abs(g - base) <= 1e-12 * np.maximum(1.0, np.abs(base))), tune
+
+
+def test_autotune_picks_a_schedule_and_keeps_results(nn):
+    d = synth.config_inputs(2, n_unique=4096)
+    _print_case("autotune")
+    S = _system(nn, d)
+    T = nn.Table(S, capacity=4096)
+    args = (dev(d["keys"]), dev(d["counts"], torch.int32), dev(d["logabs"]), dev(d["phase"]))
+    T.build(args[0], args[2], args[3])
+    e1, _ = nn.eloc_table(S, T, *args)
+    torch.cuda.synchronize()
+    base = eloc_complex(e1)
+    tune, ms = T.autotune(args[0], args[2], args[3], reps=1)
+    print(f"autotuned {tune}: {ms:.3f} ms")
+    assert tune["waves_per_block"] in (8, 12, 16) and tune["splitter_levels"] in (8, 10, 12)
+    assert tune["search"] in (1, 2) and not (tune["waves_per_block"] == 16 and tune["search"] == 2)
+    assert T.get_tune() == tune
+    e2, _ = nn.eloc_table(S, T, *args)
+    torch.cuda.synchronize()
+    g = eloc_complex(e2)
+    assert np.all(np.abs(g - base) <= 1e-12 * np.maximum(1.0, np.abs(base)))
 
 
 # ---------------------------------------------------------- error model
