@@ -35,8 +35,8 @@ ALU_PEAK_GOPS = 256 * 64 * 2.4
 # counter reads for a plain device copy of known size.  The figures hold only
 # for the kernel sources they were taken with (hash below); otherwise the
 # bench reports no traffic.
-SA_COUNTERS = {"sources_sha256_16": None, "fetch_kib": None, "write_kib": None,
-               "fetch_scale": 2.0, "write_scale": 1.0}
+SA_COUNTERS = {"sources_sha256_16": "02822df7651b4dbb", "fetch_kib": 57321.2, "write_kib": 3944.2,
+               "fetch_scale": 262144.0 / 131085.3, "write_scale": 1.0}
 SA_SOURCES = ("paper_2306_16705_amd/csrc/eloc_sa.hip", "paper_2306_16705_amd/csrc/enumerate.hpp",
               "paper_2306_16705_amd/csrc/internal.hpp")
 
@@ -57,6 +57,12 @@ def sa_traffic_bytes():
     return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
 
 
+def sa_kernel_name(tune):
+    """Template instance of the sample-aware kernel a schedule runs (one-word keys)."""
+    wide = tune["search"] == 1 and tune["waves_per_block"] > 12
+    return f"k_eloc_sa<1, {tune['search'] - 1}, {1024 if wide else 768}>"
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -72,6 +78,8 @@ def main():
                     help="samples of the N=120 transformer workload timed in the full-E_loc leg (0 = skip)")
     ap.add_argument("--fp64-samples", type=int, default=1,
                     help="of these, samples also evaluated by the plain FP64 path (error reference)")
+    ap.add_argument("--screen-steps", type=int, default=1500,
+                    help="Adam steps of the screen training in the full-E_loc leg")
     ap.add_argument("--schedule", type=str, default="",
                     help="JSON launch schedule for the sample-aware kernel instead of autotuning (profiling runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -195,7 +203,7 @@ def main():
         "connections_per_s": conns_s,
         "energy": float(en[0]),
         "max_abs_err_vs_oracle_ha": max_err,
-        "roofline": {"bound": "alu", "kernel": "k_eloc_sa<1>", "achieved": achieved, "peak": ALU_PEAK_GOPS,
+        "roofline": {"bound": "alu", "kernel": sa_kernel_name(tune), "achieved": achieved, "peak": ALU_PEAK_GOPS,
                      "unit": "Gop/s", "frac": achieved / ALU_PEAK_GOPS, "traffic": sa_traffic_bytes(),
                      "traffic_unit": "bytes per launch", "sources_sha256_16": sa_sources_hash(),
                      "kernel_ms": kernel_ms, "ops_per_connection": ALU_OPS_PER_CONNECTION},
@@ -222,7 +230,7 @@ def full_path_leg(args, nn, synth, np, torch):
     t = time.perf_counter()
     xk, ex, lab = screen_train.connection_dataset(S, M, keys[n:], per_sample=8192, seed=1)
     scr = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=2))
-    losses = screen_train.train(scr, xk, ex, lab, steps=1500, batch=4096, lr=2e-3, seed=3)
+    losses = screen_train.train(scr, xk, ex, lab, steps=args.screen_steps, batch=4096, lr=2e-3, seed=3)
     t_train = time.perf_counter() - t
     log(f"screen trained in {t_train:.1f} s, loss {losses[0]:.4g} -> {float(np.mean(losses[-20:])):.4g}")
     tk, tc = keys[:n].contiguous(), cnt[:n].contiguous()
