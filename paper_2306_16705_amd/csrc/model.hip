@@ -48,29 +48,6 @@ ModelOffsets model_offsets(const nnqs_model_desc &m) {
     return o;
 }
 
-// Offsets inside one layer block.
-__host__ __device__ inline LayerOffsets layer_offsets(int d, int F) {
-    LayerOffsets L{};
-    int64_t at = 0;
-    L.ln1_g = at; at += d;
-    L.ln1_b = at; at += d;
-    L.wq = at; at += (int64_t)d * d;
-    L.bq = at; at += d;
-    L.wk = at; at += (int64_t)d * d;
-    L.bk = at; at += d;
-    L.wv = at; at += (int64_t)d * d;
-    L.bv = at; at += d;
-    L.wo = at; at += (int64_t)d * d;
-    L.bo = at; at += d;
-    L.ln2_g = at; at += d;
-    L.ln2_b = at; at += d;
-    L.w1 = at; at += (int64_t)d * F;
-    L.b1 = at; at += F;
-    L.w2 = at; at += (int64_t)F * d;
-    L.b2 = at; at += d;
-    return L;
-}
-
 __device__ __forceinline__ double gelu64(double v) { return 0.5 * v * (1.0 + erf(v * 0.70710678118654752440)); }
 
 // out[s][j] = b[j] + sum_i in[s][i] W[i][j] for s < rows, j < n (block-wide)
@@ -107,7 +84,8 @@ __device__ __forceinline__ int token_of(const Key &x, int K, int s) {
     return key_bit(x, 2 * i) + 2 * key_bit(x, 2 * i + 1);
 }
 
-// One block per configuration, FP64 throughout.
+// One block per configuration, FP64 throughout (model shapes the
+// layer-batched forward of model_f64.hip does not cover).
 __global__ void __launch_bounds__(256) k_logpsi_f64(ModelView M, const uint64_t *__restrict__ keys, int64_t n,
                                                     double *__restrict__ logabs, double *__restrict__ phase) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -294,6 +272,7 @@ nnqs_status nnqs_model_create(nnqs_model **out, const nnqs_model_desc *desc, con
 nnqs_status nnqs_model_destroy(nnqs_model *m) {
     if (!m) return NNQS_OK;
     hipFree(m->d_w64);
+    hipFree(m->d_f64s);
     bf16_model_free(m);
     eloc_model_free(m);
     delete m;
@@ -329,7 +308,8 @@ ModelView model_view(const nnqs_model *m) {
 
 nnqs_status enqueue_logpsi(const nnqs_model *m, const uint64_t *keys, int64_t n, int32_t precision,
                            double *logabs, double *phase, hipStream_t st) {
-    if (precision == NNQS_FP64) {
+    if (precision == NNQS_FP64 && f64_shape_ok(m->desc)) return enqueue_logpsi_f64(m, keys, n, logabs, phase, st);
+    if (precision == NNQS_FP64) {  // other shapes: one block per configuration
         const size_t lds = f64_lds_bytes(m->desc);
         NNQS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(k_logpsi_f64),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

@@ -22,6 +22,30 @@ struct ModelView {
 
 ModelOffsets model_offsets(const nnqs_model_desc &m);
 
+// Offsets inside one layer block.
+__host__ __device__ inline LayerOffsets layer_offsets(int d, int F) {
+    LayerOffsets L{};
+    int64_t at = 0;
+    L.ln1_g = at; at += d;
+    L.ln1_b = at; at += d;
+    L.wq = at; at += (int64_t)d * d;
+    L.bq = at; at += d;
+    L.wk = at; at += (int64_t)d * d;
+    L.bk = at; at += d;
+    L.wv = at; at += (int64_t)d * d;
+    L.bv = at; at += d;
+    L.wo = at; at += (int64_t)d * d;
+    L.bo = at; at += d;
+    L.ln2_g = at; at += d;
+    L.ln2_b = at; at += d;
+    L.w1 = at; at += (int64_t)d * F;
+    L.b1 = at; at += F;
+    L.w2 = at; at += (int64_t)F * d;
+    L.b2 = at; at += d;
+    return L;
+}
+
+
 }  // namespace nnqs
 
 struct nnqs_model {
@@ -29,6 +53,9 @@ struct nnqs_model {
     nnqs::ModelOffsets off{};
     double *d_w64 = nullptr;
     int max_lds = 0;
+    // scratch of the layer-batched FP64 forward (model_f64.hip), grown on demand
+    void *d_f64s = nullptr;
+    size_t f64cap = 0;
     // BF16 path: transposed BF16 matrices and FP32 vectors (model_bf16.hip)
     void *d_bf16 = nullptr;
     float *d_f32 = nullptr;
@@ -58,6 +85,9 @@ void bf16_model_free(nnqs_model *m);
 nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs,
                                 double *phase, hipStream_t st);
 void eloc_model_free(nnqs_model *m);
+bool f64_shape_ok(const nnqs_model_desc &m);
+nnqs_status enqueue_logpsi_f64(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, double *phase,
+                               hipStream_t st);
 nnqs_status screen_infer(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, int64_t n, float *pred,
                          hipStream_t st);
 }  // namespace nnqs

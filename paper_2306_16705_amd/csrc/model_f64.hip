@@ -1,0 +1,301 @@
+// FP64 network forward, layer by layer over batches of configurations (the
+// ansatz of Section 3.1, Eq. 11 and Fig. 2, with the Eq. 12 mask and the
+// phase MLP of Section 4.1).  Every step is a plain kernel over the rows of
+// a whole batch: LayerNorm one wave per row, the dense layers an LDS-tiled
+// FP64 product (64 x 64 output tile per block, 4 x 4 per thread) with bias,
+// GELU or residual-add epilogues, causal attention one thread per (config,
+// head, query).  Activations live in model-owned scratch between steps.
+// The arithmetic is the FP64 definition of the network; only the summation
+// order differs from a one-configuration-at-a-time evaluation.
+#include <cmath>
+
+#include "model.hpp"
+
+namespace nnqs {
+
+constexpr int64_t kF64Batch = 1024;  // configurations per pass
+
+__device__ __forceinline__ double gelu_f64(double v) { return 0.5 * v * (1.0 + erf(v * 0.70710678118654752440)); }
+
+// Tokens (previous-token input) and embeddings: h[b*K + s][c].
+__global__ void k64_embed(ModelView M, const uint64_t *__restrict__ keys, int64_t B, int8_t *__restrict__ tok,
+                          double *__restrict__ h) {
+    const int K = M.K, d = M.d;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B * K * d) return;
+    const int64_t row = e / d;
+    const int c = (int)(e - row * d);
+    const int64_t b = row / K;
+    const int s = (int)(row - b * K);
+    Key x;
+    x.lo = keys[2 * b];
+    x.hi = keys[2 * b + 1];
+    auto token = [&](int pos) {
+        const int i = K - 1 - pos;  // position s holds spatial orbital K-1-s
+        return key_bit(x, 2 * i) + 2 * key_bit(x, 2 * i + 1);
+    };
+    if (c == 0) tok[row] = (int8_t)token(s);
+    const int prev = s == 0 ? 4 : token(s - 1);
+    h[e] = M.w64[M.off.tok_emb + prev * d + c] + M.w64[M.off.pos_emb + (int64_t)s * d + c];
+}
+
+// LayerNorm (eps 1e-5) of rows of width 64: one wave per row, lane = column.
+__global__ void __launch_bounds__(256) k64_layernorm(const double *__restrict__ in, const double *__restrict__ g,
+                                                     const double *__restrict__ b, int64_t rows,
+                                                     double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= rows) return;
+    const double v = in[row * 64 + lane];
+    double s = v;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    const double mean = s / 64.0;
+    double q = (v - mean) * (v - mean);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off, 64);
+    const double r = 1.0 / sqrt(q / 64.0 + 1e-5);
+    out[row * 64 + lane] = (v - mean) * r * g[lane] + b[lane];
+}
+
+// C[r][j] = epi(bias[j] + sum_k A[r][k] W[k][j]) for r < M, j < N; EPI 0
+// stores, 1 adds to C (residual), 2 stores GELU.  Block: 64 x 64 tile of C,
+// 256 threads with 4 x 4 outputs each, k in steps of 16 through LDS.
+template <int EPI>
+__global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, int lda, const double *__restrict__ W,
+                                                int ldw, const double *__restrict__ bias, int64_t M, int N, int Kd,
+                                                double *__restrict__ C, int ldc) {
+    __shared__ double As[16][64 + 1];
+    __shared__ double Ws[16][64 + 1];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t r0 = (int64_t)blockIdx.y * 64;
+    const int c0 = blockIdx.x * 64;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < Kd; k0 += 16) {
+        // stage A[r0..r0+63][k0..k0+15] (transposed) and W[k0..k0+15][c0..c0+63]
+        for (int t = threadIdx.x; t < 16 * 64; t += 256) {
+            const int kk = t & 15, rr = t >> 4;
+            const int64_t r = r0 + rr;
+            As[kk][rr] = (r < M && k0 + kk < Kd) ? A[r * lda + k0 + kk] : 0.0;
+            const int kw = t >> 6, cc = t & 63;
+            Ws[kw][cc] = (k0 + kw < Kd && c0 + cc < N) ? W[(int64_t)(k0 + kw) * ldw + c0 + cc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++) {
+            double a[4], w[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; j++) w[j] = Ws[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[i][j] = fma(a[i], w[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int64_t r = r0 + ty * 4 + i;
+        if (r >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int c = c0 + tx * 4 + j;
+            if (c >= N) continue;
+            const double v = (bias ? bias[c] : 0.0) + acc[i][j];
+            double *dst = C + r * ldc + c;
+            if (EPI == 1) *dst += v;
+            else if (EPI == 2) *dst = gelu_f64(v);
+            else *dst = v;
+        }
+    }
+}
+
+// Causal attention, one thread per (config, head, query row); q, k, v and
+// the output are [B*K][64] with head hh in columns 16 hh .. 16 hh + 15.
+__global__ void k64_attention(const double *__restrict__ q, const double *__restrict__ k,
+                              const double *__restrict__ v, int64_t B, int K, double scale,
+                              double *__restrict__ o) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B * 4 * K) return;
+    const int s = (int)(t % K);
+    const int hh = (int)((t / K) % 4);
+    const int64_t b = t / (4 * K);
+    const double *qs = q + (b * K + s) * 64 + hh * 16;
+    double qv[16], out[16];
+#pragma unroll
+    for (int c = 0; c < 16; c++) {
+        qv[c] = qs[c];
+        out[c] = 0.0;
+    }
+    double mx = -INFINITY, den = 0.0;
+    for (int r = 0; r <= s; r++) {
+        const double *kr = k + (b * K + r) * 64 + hh * 16;
+        const double *vr = v + (b * K + r) * 64 + hh * 16;
+        double z = 0.0;
+#pragma unroll
+        for (int c = 0; c < 16; c++) z += qv[c] * kr[c];
+        z *= scale;
+        const double mn = z > mx ? z : mx;
+        const double corr = exp(mx - mn), p = exp(z - mn);
+        den = den * corr + p;
+#pragma unroll
+        for (int c = 0; c < 16; c++) out[c] = out[c] * corr + p * vr[c];
+        mx = mn;
+    }
+    double *os = o + (b * K + s) * 64 + hh * 16;
+#pragma unroll
+    for (int c = 0; c < 16; c++) os[c] = out[c] / den;
+}
+
+// Output head with the logit bias, the mask (Eq. 12, read with the lower
+// bound too) and the log-probability of the actual token: one thread per
+// (config, position).
+__global__ void k64_head(ModelView M, const double *__restrict__ a, const int8_t *__restrict__ tok, int64_t B,
+                         double *__restrict__ lp) {
+    const int K = M.K, d = M.d;
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= B * K) return;
+    const int64_t b = row / K;
+    const int s = (int)(row - b * K);
+    int up = 0, dn = 0;
+    for (int r = 0; r < s; r++) {
+        const int t = tok[b * K + r];
+        up += t & 1;
+        dn += t >> 1;
+    }
+    const int rem = K - 1 - s, orb = K - 1 - s;
+    const double *W = M.w64;
+    double z[4];
+    bool ok[4];
+    double mx = -INFINITY;
+    for (int t = 0; t < 4; t++) {
+        double acc = W[M.off.head_b + t] + W[M.off.bias + orb * 4 + t];
+        for (int c = 0; c < d; c++) acc += a[row * d + c] * W[M.off.head_w + c * 4 + t];
+        z[t] = acc;
+        const int bu = t & 1, bd = t >> 1;
+        ok[t] = (up + bu <= M.n_up) && (dn + bd <= M.n_dn) && (M.n_up - up - bu <= rem) && (M.n_dn - dn - bd <= rem);
+        if (ok[t] && z[t] > mx) mx = z[t];
+    }
+    double den = 0.0;
+    for (int t = 0; t < 4; t++)
+        if (ok[t]) den += exp(z[t] - mx);
+    const int ts = tok[row];
+    lp[row] = ok[ts] ? (z[ts] - mx) - log(den) : -INFINITY;
+}
+
+// First phase layer from the occupation bits: z1[b][j] = GELU(b1[j] + sum
+// over set bits p of W1[p][j]).
+__global__ void k64_phase1(ModelView M, const uint64_t *__restrict__ keys, int64_t B, double *__restrict__ z1) {
+    const int P = M.P;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B * P) return;
+    const int64_t b = e / P;
+    const int j = (int)(e - b * P);
+    Key x;
+    x.lo = keys[2 * b];
+    x.hi = keys[2 * b + 1];
+    double acc = M.w64[M.off.ph_b1 + j];
+    for (int p = 0; p < 2 * M.K; p++)
+        if (key_bit(x, p)) acc += M.w64[M.off.ph_w1 + (int64_t)p * P + j];
+    z1[e] = gelu_f64(acc);
+}
+
+// Per configuration: log|psi| = 1/2 sum_s lp, phase = b3 + z2 . w3 (one wave
+// each, fixed-order lane sums).
+__global__ void __launch_bounds__(256) k64_finish(ModelView M, const double *__restrict__ lp,
+                                                  const double *__restrict__ z2, int64_t B,
+                                                  double *__restrict__ logabs, double *__restrict__ phase) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (b >= B) return;
+    double s = 0.0;
+    for (int t = lane; t < M.K; t += 64) s += lp[b * M.K + t];
+    double ph = 0.0;
+    for (int i = lane; i < M.P; i += 64) ph += z2[b * M.P + i] * M.w64[M.off.ph_w3 + i];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        ph += __shfl_xor(ph, off, 64);
+    }
+    if (lane == 0) {
+        logabs[b] = 0.5 * s;
+        phase[b] = M.w64[M.off.ph_b3] + ph;
+    }
+}
+
+static unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+bool f64_shape_ok(const nnqs_model_desc &m) { return m.d_model == 64 && m.n_heads == 4 && m.d_ff % 64 == 0; }
+
+nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64_t n, double *logabs,
+                               double *phase, hipStream_t st) {
+    nnqs_model *m = const_cast<nnqs_model *>(cm);  // owns its scratch (one call at a time per model)
+    const ModelView M = model_view(m);
+    const int K = M.K, d = M.d, F = M.F, P = M.P;
+    const int64_t Bmax = n < kF64Batch ? n : kF64Batch;
+    const int64_t rows_max = Bmax * K;
+    // h, a, q, k, v [rows][64]; f [rows][F] (also z1, z2 [B][P]); lp [rows]; tok [rows]
+    const size_t need = (size_t)rows_max * (5 * d + (F > 2 * P / K + 1 ? F : 2 * P / K + 1) + 1) * 8 + rows_max + 256;
+    if (m->f64cap < need) {
+        NNQS_HIP_CHECK(hipStreamSynchronize(st));
+        hipFree(m->d_f64s);
+        m->d_f64s = nullptr;
+        m->f64cap = 0;
+        if (hipMalloc(&m->d_f64s, need) != hipSuccess) return fail(NNQS_ENOMEM, "FP64 forward scratch (%zu bytes)", need);
+        m->f64cap = need;
+    }
+    const size_t fcols = (size_t)(F > 2 * P / K + 1 ? F : 2 * P / K + 1);
+    double *h = reinterpret_cast<double *>(m->d_f64s);
+    double *a = h + rows_max * d, *q = a + rows_max * d, *kk = q + rows_max * d, *v = kk + rows_max * d;
+    double *f = v + rows_max * d;
+    double *lp = f + rows_max * fcols;
+    int8_t *tok = reinterpret_cast<int8_t *>(lp + rows_max);
+    const LayerOffsets LO = layer_offsets(d, F);
+    const double *W = m->d_w64;
+    const double scale = 1.0 / sqrt((double)(d / M.H));
+    for (int64_t b0 = 0; b0 < n; b0 += kF64Batch) {
+        const int64_t B = n - b0 < kF64Batch ? n - b0 : kF64Batch;
+        const int64_t R = B * K;
+        const unsigned gy = (unsigned)((R + 63) / 64);
+        hipLaunchKernelGGL(k64_embed, dim3(blocks_for(R * d)), dim3(256), 0, st, M, keys + 2 * b0, B, tok, h);
+        for (int l = 0; l < M.L; l++) {
+            const double *Lw = W + M.off.layer0 + (int64_t)l * M.off.layer_stride;
+            hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln1_g,
+                               Lw + LO.ln1_b, R, a);
+            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wq, d, Lw + LO.bq, R, d, d,
+                               q, d);
+            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wk, d, Lw + LO.bk, R, d, d,
+                               kk, d);
+            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wv, d, Lw + LO.bv, R, d, d,
+                               v, d);
+            hipLaunchKernelGGL(k64_attention, dim3(blocks_for(B * 4 * K)), dim3(256), 0, st, q, kk, v, B, K, scale, a);
+            hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wo, d, Lw + LO.bo, R, d, d,
+                               h, d);
+            hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,
+                               Lw + LO.ln2_b, R, a);
+            hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, d, Lw + LO.w1,
+                               F, Lw + LO.b1, R, F, d, f, (int)fcols);
+            hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, f, (int)fcols, Lw + LO.w2, d, Lw + LO.b2,
+                               R, d, F, h, d);
+        }
+        hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, W + M.off.lnf_g,
+                           W + M.off.lnf_b, R, a);
+        hipLaunchKernelGGL(k64_head, dim3(blocks_for(R)), dim3(256), 0, st, M, a, tok, B, lp);
+        double *z1 = f, *z2 = f + (size_t)B * P;
+        hipLaunchKernelGGL(k64_phase1, dim3(blocks_for(B * P)), dim3(256), 0, st, M, keys + 2 * b0, B, z1);
+        hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((P + 63) / 64), (unsigned)((B + 63) / 64)), dim3(256), 0, st,
+                           z1, P, W + M.off.ph_w2, P, W + M.off.ph_b2, B, P, P, z2, P);
+        hipLaunchKernelGGL(k64_finish, dim3(blocks_for(B, 4)), dim3(256), 0, st, M, lp, z2, B, logabs + b0,
+                           phase + b0);
+        NNQS_HIP_CHECK(hipGetLastError());
+    }
+    return NNQS_OK;
+}
+
+}  // namespace nnqs
