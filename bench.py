@@ -76,9 +76,9 @@ def main():
                     help="samples the oracle evaluates for the CPU baseline (0 = skip)")
     ap.add_argument("--full-samples", type=int, default=16,
                     help="samples of the N=120 transformer workload timed in the full-E_loc leg (0 = skip)")
-    ap.add_argument("--fp64-samples", type=int, default=1,
+    ap.add_argument("--fp64-samples", type=int, default=8,
                     help="of these, samples also evaluated by the plain FP64 path (error reference)")
-    ap.add_argument("--screen-steps", type=int, default=1500,
+    ap.add_argument("--screen-steps", type=int, default=5000,
                     help="Adam steps of the screen training in the full-E_loc leg")
     ap.add_argument("--schedule", type=str, default="",
                     help="JSON launch schedule for the sample-aware kernel instead of autotuning (profiling runs)")
@@ -213,11 +213,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+# Operating point of the screened full path: skip a connection when its
+# predicted contribution |H_xx' psi(x')/psi(x)| is below exp(-17) Ha, and
+# recompute in FP64 every evaluated term above exp(-7) Ha.
+SKIP_NATS = 17.0
+REFINE_NATS = 7.0
+
+
 def full_path_leg(args, nn, synth, np, torch):
     """Full E_loc on the N=120 (20 up + 20 down) transformer workload: plain
     FP64, plain BF16, and BF16 behind the learned screen with FP64
     refinement of the large terms.  The screen is trained first (untimed) on
-    connections of 16 further samples."""
+    connections of 16 further samples (16,384 each)."""
     log("full path: N=120 transformer workload")
     n = args.full_samples
     d = synth.config_inputs(3, n_unique=n + 16)
@@ -228,13 +235,13 @@ def full_path_leg(args, nn, synth, np, torch):
     cnt = torch.from_numpy(d["counts"].astype(np.int32)).cuda()
     from paper_2306_16705_amd import screen_train
     t = time.perf_counter()
-    xk, ex, lab = screen_train.connection_dataset(S, M, keys[n:], per_sample=8192, seed=1)
+    xk, ex, lab = screen_train.connection_dataset(S, M, keys[n:], per_sample=16384, seed=1)
     scr = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=2))
     losses = screen_train.train(scr, xk, ex, lab, steps=args.screen_steps, batch=4096, lr=2e-3, seed=3)
     t_train = time.perf_counter() - t
     log(f"screen trained in {t_train:.1f} s, loss {losses[0]:.4g} -> {float(np.mean(losses[-20:])):.4g}")
     tk, tc = keys[:n].contiguous(), cnt[:n].contiguous()
-    screened_kw = dict(screen=scr, skip_nats=18.0, skip_rule=nn.NNQS_SKIP_CONTRIBUTION, refine_nats=8.0)
+    screened_kw = dict(screen=scr, skip_nats=SKIP_NATS, skip_rule=nn.NNQS_SKIP_CONTRIBUTION, refine_nats=REFINE_NATS)
 
     def timed(prec, k, c, **kw):
         nn.eloc_model(S, M, k[:1], c[:1], prec, **kw)  # warm scratch
@@ -254,7 +261,8 @@ def full_path_leg(args, nn, synth, np, torch):
            "screened_bf16_refined": {"samples_per_s": n / dts, "connections_per_s": n * C / dts,
                                      "energy": float(ens[0]), "evaluated_fraction": sts["evaluated"] / sts["connections"],
                                      "refined_fraction": sts["refined"] / sts["connections"],
-                                     "skip_rule": "contribution", "skip_nats": 18.0, "refine_nats": 8.0},
+                                     "skip_rule": "contribution", "skip_nats": SKIP_NATS,
+                                     "refine_nats": REFINE_NATS},
            "screen_training_s": t_train,
            "speedup_screened_vs_plain_bf16": dt16 / dts}
     if m > 0:
