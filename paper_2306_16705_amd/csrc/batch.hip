@@ -101,10 +101,12 @@ static nnqs_status batch_plan(nnqs_batch *b) {
         return fail(NNQS_ENOMEM, "batch descriptor allocation failed");
     NNQS_HIP_CHECK(hipMemcpy(b->d_items, hi.data(), sizeof(SaBatchItem) * n_items, hipMemcpyHostToDevice));
     NNQS_HIP_CHECK(hipMemcpy(b->d_tiles, tiles.data(), sizeof(SaTile) * tiles.size(), hipMemcpyHostToDevice));
-    const void *fn = sa_batch_kernel_ptr(b->W, b->tune.search);
-    nnqs_status s = sa_check_no_spill(fn);
-    if (s != NNQS_OK) return s;
-    NNQS_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds));
+    for (bool exact : {false, true}) {
+        const void *fn = sa_batch_kernel_ptr(b->W, b->tune.search, exact);
+        nnqs_status s = sa_check_no_spill(fn);
+        if (s != NNQS_OK) return s;
+        NNQS_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds));
+    }
     b->grid = (unsigned)(b->cu_count * b->tune.blocks_per_cu);
     return NNQS_OK;
 }
@@ -119,7 +121,6 @@ static nnqs_status batch_step(nnqs_batch *b, hipStream_t st) {
         nnqs_status s = nnqs_table_build(it.table, it.keys, it.logabs, it.phase, it.n, 0, st);
         if (s != NNQS_OK) return s;
     }
-    sa_launch_reset(b->d_counter, st);
     sa_launch_batch(b->W, b->tune.search, b->grid, b->waves, b->lds, st, b->d_items, b->d_tiles, b->ntiles,
                     b->d_counter);
     NNQS_HIP_CHECK(hipGetLastError());

@@ -185,8 +185,12 @@ __device__ __forceinline__ SaStage sa_stage(const SysView &S, const TableView &T
 }
 
 // E_loc of sample smp by the calling wave (see the file comment).  S8 picks
-// the search variant of the queued candidates.
-template <int W, int S8>
+// the search variant of the queued candidates.  Hits take the amplitude
+// ratio from the table's scaled amplitudes (EX = 0), except for samples more
+// than 600 nats below the table's largest amplitude (or with a non-finite
+// one), which a second pass (EX = 1) evaluates with exp and sincos per hit;
+// each pass leaves the other pass's samples alone.
+template <int W, int S8, int EX>
 __device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, const SaStage &G, WaveLds &wl,
                                           int64_t smp, const uint64_t *__restrict__ keys,
                                           const double *__restrict__ logabs, const double *__restrict__ phase,
@@ -199,6 +203,8 @@ __device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, 
     x.lo = keys[2 * smp];
     x.hi = keys[2 * smp + 1];
     const double la = logabs[smp], ph = phase[smp];
+    const double lmax = T.lmax[0];
+    if ((la - lmax >= -600.0) == (EX == 1)) return;  // the other pass's sample
     if (!sample_conserves(S, x) || !isfinite(la) || !isfinite(ph)) {
         if (lane == 0) {
             eloc[2 * smp] = NAN;
@@ -215,6 +221,23 @@ __device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, 
     }
     const uint32_t hx = wave_xor32(part);
     const double diag = wave_diag(S, x, wl);
+    // Hit ratios of the scaled pass: psi(x')/psi(x) = amp[x'] exp(lmax -
+    // log|psi(x)|) e^{-i phase(x)} (amp cannot underflow for a term that
+    // counts, as the sample is within 600 nats of lmax).  The per-sample
+    // constants sit in LDS: they are read on hits only.
+    if (lane == 0) {
+        if (EX == 0) {
+            double xsn, xcs;
+            sincos(ph, &xsn, &xcs);
+            wl.hit[0] = exp(lmax - la);
+            wl.hit[1] = xcs;
+            wl.hit[2] = xsn;
+        } else {
+            wl.hit[3] = la;
+            wl.hit[4] = ph;
+        }
+    }
+    wave_sync();
     // Lane l holds entry l of the occupied-up, occupied-down and empty-up
     // lists as (low hash bits | orbital << 25); the loops read them with
     // wave-uniform readlane, which yields the orbital with a scalar shift.
@@ -244,11 +267,21 @@ __device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, 
         if (idx >= 0) {
             int sg;
             const double hv = excitation_element(S, x, diag, i, j, a, b, &sg);
-            const double r = exp(T.logabs[idx] - la);
-            double sn, cs;
-            sincos(T.phase[idx] - ph, &sn, &cs);
-            are.add(hv * r * cs);
-            aim.add(hv * r * sn);
+            double re, im;
+            if (EX == 0) {
+                const double ar = T.amp[2 * idx], ai = T.amp[2 * idx + 1];
+                const double xs = wl.hit[0], xcs = wl.hit[1], xsn = wl.hit[2];
+                re = xs * (ar * xcs + ai * xsn);
+                im = xs * (ai * xcs - ar * xsn);
+            } else {
+                const double r = exp(T.logabs[idx] - wl.hit[3]);
+                double sn, cs;
+                sincos(T.phase[idx] - wl.hit[4], &sn, &cs);
+                re = r * cs;
+                im = r * sn;
+            }
+            are.add(hv * re);
+            aim.add(hv * im);
         }
     };
     auto drain_full = [&]() {
@@ -402,14 +435,30 @@ __global__ void __launch_bounds__(NT) k_eloc_sa(SysView S, TableView T, int lds_
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     for (int64_t smp = (int64_t)blockIdx.x * nw + wid; smp < n; smp += (int64_t)gridDim.x * nw)
-        sa_sample<W, S8>(S, T, G, G.waves[wid], smp, keys, logabs, phase, eloc, status);
+        sa_sample<W, S8, 0>(S, T, G, G.waves[wid], smp, keys, logabs, phase, eloc, status);
+}
+
+// The exact pass of one system (samples far below the table's largest
+// amplitude; usually none, and then every wave only reads log|psi|).
+template <int W>
+__global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa_exact(SysView S, TableView T, int lds_filter_log2,
+                                                        const uint64_t *__restrict__ keys,
+                                                        const double *__restrict__ logabs,
+                                                        const double *__restrict__ phase, int64_t n,
+                                                        double *__restrict__ eloc, int *status) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const SaStage G = sa_stage<W>(S, T, lds_filter_log2, smem);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    for (int64_t smp = (int64_t)blockIdx.x * nw + wid; smp < n; smp += (int64_t)gridDim.x * nw)
+        sa_sample<W, 0, 1>(S, T, G, G.waves[wid], smp, keys, logabs, phase, eloc, status);
 }
 
 // Many systems in one persistent launch: blocks pull tiles (a system and a
 // run of its samples, in system order) from a device counter, restage the
 // LDS data only when the system changes, and give each wave one sample at a
 // time.  Every block leaves the loop when the counter passes the last tile.
-template <int W, int S8>
+template <int W, int S8, int EX>
 __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa_batch(const SaBatchItem *__restrict__ items,
                                                         const SaTile *__restrict__ tiles, int ntiles,
                                                         int *counter) {
@@ -432,7 +481,8 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa_batch(const SaBatchIt
             staged = tl.item;
         }
         for (int64_t smp = tl.begin + wid; smp < tl.begin + tl.count; smp += nw)
-            sa_sample<W, S8>(it.S, it.T, G, G.waves[wid], smp, it.keys, it.logabs, it.phase, it.eloc, it.status);
+            sa_sample<W, S8, EX>(it.S, it.T, G, G.waves[wid], smp, it.keys, it.logabs, it.phase, it.eloc,
+                                 it.status);
         __syncthreads();
     }
 }
@@ -539,11 +589,13 @@ const void *sa_kernel_ptr(int W, int search, int waves) {
                        : reinterpret_cast<const void *>(k_eloc_sa<2, 0, kSaMaxThreads>);
 }
 
-const void *sa_batch_kernel_ptr(int W, int search) {
-    if (W == 1) return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa_batch<1, 1>)
-                                   : reinterpret_cast<const void *>(k_eloc_sa_batch<1, 0>);
-    return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa_batch<2, 1>)
-                       : reinterpret_cast<const void *>(k_eloc_sa_batch<2, 0>);
+const void *sa_batch_kernel_ptr(int W, int search, bool exact) {
+    if (exact) return W == 1 ? reinterpret_cast<const void *>(k_eloc_sa_batch<1, 0, 1>)
+                             : reinterpret_cast<const void *>(k_eloc_sa_batch<2, 0, 1>);
+    if (W == 1) return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa_batch<1, 1, 0>)
+                                   : reinterpret_cast<const void *>(k_eloc_sa_batch<1, 0, 0>);
+    return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa_batch<2, 1, 0>)
+                       : reinterpret_cast<const void *>(k_eloc_sa_batch<2, 0, 0>);
 }
 
 // The sample-aware kernels are built to keep every value in registers; the
@@ -560,13 +612,18 @@ nnqs_status sa_check_no_spill(const void *fn) {
 void sa_launch_batch(int W, int search, unsigned grid, int waves, size_t lds, hipStream_t st,
                      const SaBatchItem *items, const SaTile *tiles, int ntiles, int *counter) {
     const dim3 g(grid), b(waves * 64);
+    // scaled pass, then the exact pass over the same tiles
+    sa_launch_reset(counter, st);
     if (W == 1) {
-        if (search == 2) hipLaunchKernelGGL((k_eloc_sa_batch<1, 1>), g, b, lds, st, items, tiles, ntiles, counter);
-        else hipLaunchKernelGGL((k_eloc_sa_batch<1, 0>), g, b, lds, st, items, tiles, ntiles, counter);
+        if (search == 2) hipLaunchKernelGGL((k_eloc_sa_batch<1, 1, 0>), g, b, lds, st, items, tiles, ntiles, counter);
+        else hipLaunchKernelGGL((k_eloc_sa_batch<1, 0, 0>), g, b, lds, st, items, tiles, ntiles, counter);
     } else {
-        if (search == 2) hipLaunchKernelGGL((k_eloc_sa_batch<2, 1>), g, b, lds, st, items, tiles, ntiles, counter);
-        else hipLaunchKernelGGL((k_eloc_sa_batch<2, 0>), g, b, lds, st, items, tiles, ntiles, counter);
+        if (search == 2) hipLaunchKernelGGL((k_eloc_sa_batch<2, 1, 0>), g, b, lds, st, items, tiles, ntiles, counter);
+        else hipLaunchKernelGGL((k_eloc_sa_batch<2, 0, 0>), g, b, lds, st, items, tiles, ntiles, counter);
     }
+    sa_launch_reset(counter, st);
+    if (W == 1) hipLaunchKernelGGL((k_eloc_sa_batch<1, 0, 1>), g, b, lds, st, items, tiles, ntiles, counter);
+    else hipLaunchKernelGGL((k_eloc_sa_batch<2, 0, 1>), g, b, lds, st, items, tiles, ntiles, counter);
 }
 
 void sa_launch_reset(int *counter, hipStream_t st) {
@@ -663,6 +720,22 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
         else
             hipLaunchKernelGGL((k_eloc_sa<2, 0, kSaMaxThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
                                phase, n, eloc, tab->status);
+    }
+    {  // exact pass (12-wave blocks, filter folded to fit)
+        const int ew = kSaMaxThreads / 64;
+        int efl = tv.filter_log2;
+        size_t elds = sa_lds_bytes(efl, tv.split_levels, W, ew);
+        while (elds > (size_t)sys->max_lds && efl > 10) elds = sa_lds_bytes(--efl, tv.split_levels, W, ew);
+        const void *efn = W == 1 ? reinterpret_cast<const void *>(k_eloc_sa_exact<1>)
+                                 : reinterpret_cast<const void *>(k_eloc_sa_exact<2>);
+        NNQS_HIP_CHECK(hipFuncSetAttribute(efn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)elds));
+        const dim3 eg((unsigned)sys->cu_count), eb(ew * 64);
+        if (W == 1)
+            hipLaunchKernelGGL((k_eloc_sa_exact<1>), eg, eb, elds, st, sys->view, tv, efl, keys, logabs, phase, n,
+                               eloc, tab->status);
+        else
+            hipLaunchKernelGGL((k_eloc_sa_exact<2>), eg, eb, elds, st, sys->view, tv, efl, keys, logabs, phase, n,
+                               eloc, tab->status);
     }
     NNQS_HIP_CHECK(hipGetLastError());
     if (energy) return enqueue_energy(tab, counts, eloc, n, energy, st);

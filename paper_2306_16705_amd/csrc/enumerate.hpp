@@ -10,6 +10,7 @@ struct WaveLds {
     uint8_t occ[2][64];  // occupied spin orbitals per spin, ascending
     uint8_t vir[2][64];  // empty spin orbitals per spin, ascending
     uint32_t queue[256]; // candidate ring: i | j<<8 | a<<16 | b<<24 (255 = none)
+    double hit[6];       // per-sample constants of the hit path (sample-aware kernel)
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -62,27 +63,27 @@ __device__ __forceinline__ void build_lists(const SysView &S, const Key &x, Wave
     wave_sync();
 }
 
-// Diagonal element, one occupied orbital per lane, fixed-order wave sum.
+// Diagonal element: E_core + sum_p h_pp + 1/2 sum_{p,q} [J_pq - delta_spin K_pq]
+// over occupied p, q.  Lanes take the (p, q) pairs, so that all their
+// integral loads are independent; fixed-order wave sum.
 __device__ __forceinline__ double wave_diag(const SysView &S, const Key &x, const WaveLds &wl) {
     const int lane = lane_id();
-    const int ntot = S.n_up + S.n_dn;
+    const int nu = S.n_up, ntot = S.n_up + S.n_dn;
     const int K = S.K;
+    auto occ = [&](int t) -> int { return t < nu ? wl.occ[0][t] : wl.occ[1][t - nu]; };
     double part = 0.0;
-    for (int base = 0; base < ntot; base += 64) {
-        const int t = base + lane;
-        if (t < ntot) {
-            const int p = t < S.n_up ? wl.occ[0][t] : wl.occ[1][t - S.n_up];
-            const int ip = p >> 1;
-            double acc = S.h[ip * K + ip];
-            for (int u = 0; u < ntot; u++) {
-                const int q = u < S.n_up ? wl.occ[0][u] : wl.occ[1][u - S.n_up];
-                const int iq = q >> 1;
-                double v = S.Jm[ip * K + iq];
-                if (((p ^ q) & 1) == 0) v -= S.Km[ip * K + iq];
-                acc += 0.5 * v;
-            }
-            part += acc;
-        }
+    for (int t = lane; t < ntot; t += 64) {
+        const int ip = occ(t) >> 1;
+        part += S.h[ip * K + ip];
+    }
+    const int npairs = ntot * ntot;
+    for (int t = lane; t < npairs; t += 64) {
+        const int a = t / ntot, b = t - a * ntot;
+        const int p = occ(a), q = occ(b);
+        const int ip = p >> 1, iq = q >> 1;
+        double v = S.Jm[ip * K + iq];
+        if (((p ^ q) & 1) == 0) v -= S.Km[ip * K + iq];
+        part += 0.5 * v;
     }
     return S.ecore + wave_sum_plain(part);
 }

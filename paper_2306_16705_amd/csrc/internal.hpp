@@ -46,6 +46,8 @@ struct TableView {
     const double *phase;     // [n]
     const uint32_t *filter;  // membership filter, 2^filter_log2 bits
     const uint64_t *split;   // [2^split_levels - 1][2] staged search keys
+    const double *amp;       // [n][2] exp(logabs - lmax) (cos phase, sin phase)
+    const double *lmax;      // [1] max logabs of the table
     int64_t n;
     int log2n;               // ceil(log2(n)), 0 for n == 1
     int filter_log2;         // bits of the filter = 2^filter_log2
@@ -249,6 +251,8 @@ struct nnqs_table {
     uint64_t *split = nullptr;     // [2^13 - 1][2] maximum
     int *status = nullptr;         // sticky device status
     double *partials = nullptr;    // energy reduction scratch
+    double *amp = nullptr;         // [capacity][2] scaled complex amplitudes
+    double *lmax = nullptr;        // [kPartialBlocks + 1]: block maxima, then the max at [0]
     int filter_log2 = 0;           // as built
     int split_levels = 0;          // as built
     nnqs_tune tune{};
@@ -293,7 +297,7 @@ struct SaTile {
 // entry points (eloc_sa.hip).
 size_t sa_lds_bytes(int filter_log2, int split_levels, int W, int waves);
 const void *sa_kernel_ptr(int W, int search, int waves);
-const void *sa_batch_kernel_ptr(int W, int search);
+const void *sa_batch_kernel_ptr(int W, int search, bool exact);
 nnqs_status sa_check_no_spill(const void *fn);
 void sa_launch_batch(int W, int search, unsigned grid, int waves, size_t lds, hipStream_t st,
                      const SaBatchItem *items, const SaTile *tiles, int ntiles, int *counter);

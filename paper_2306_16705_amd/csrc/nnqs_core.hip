@@ -37,6 +37,8 @@ TableView table_view(const nnqs_table *t) {
     v.phase = t->phase;
     v.filter = t->filter;
     v.split = t->split;
+    v.amp = t->amp;
+    v.lmax = t->lmax;
     v.n = t->n;
     int L = 0;
     while ((int64_t(1) << L) < t->n) L++;
@@ -194,6 +196,50 @@ __global__ void k_table_finalize(SysView S, const uint64_t *__restrict__ sk, con
     const uint32_t h = (uint32_t)key_hash(S, lo, hi);
     const uint32_t words_mask = (1u << (filter_log2 - 5)) - 1u;
     atomicOr(&filter[filter_word(h, words_mask)], filter_bits(h));
+}
+
+// Largest log-amplitude of the table: block maxima, then one block folds
+// them (max is exact, so the result does not depend on the order).
+__global__ void __launch_bounds__(256) k_table_max_partial(const double *__restrict__ la, int64_t n,
+                                                           double *__restrict__ part) {
+    __shared__ double sh[256];
+    double m = -INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, la[i]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[1 + blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_table_max_final(double *__restrict__ part, int nblocks) {
+    __shared__ double sh[256];
+    double m = -INFINITY;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmax(m, part[1 + b]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[0] = sh[0];
+}
+
+// amp[i] = exp(logabs[i] - lmax) (cos phase[i], sin phase[i]): the hit path
+// of the sample-aware kernel multiplies this by exp(lmax - log|psi(x)|)
+// e^{-i phase(x)} instead of evaluating exp and sincos per hit.
+__global__ void k_table_amp(const double *__restrict__ la, const double *__restrict__ ph, int64_t n,
+                            const double *__restrict__ lmax, double *__restrict__ amp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double r = exp(la[i] - lmax[0]);
+    double sn, cs;
+    sincos(ph[i], &sn, &cs);
+    amp[2 * i] = r * cs;
+    amp[2 * i + 1] = r * sn;
 }
 
 __global__ void k_table_split(const uint64_t *__restrict__ keys, int64_t n, int log2n, int levels,
@@ -429,7 +475,9 @@ nnqs_status nnqs_table_create(nnqs_table **out, const nnqs_system *sys, int64_t 
         hipMalloc(&t->filter, (size_t(1) << kMaxFilterLog2) / 8) != hipSuccess ||
         hipMalloc(&t->split, ((size_t(1) << kMaxSplitLevels) - 1) * 16) != hipSuccess ||
         hipMalloc(&t->status, sizeof(int)) != hipSuccess ||
-        hipMalloc(&t->partials, kPartialBlocks * 8 * sizeof(double)) != hipSuccess)
+        hipMalloc(&t->partials, kPartialBlocks * 8 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&t->amp, capacity * 16) != hipSuccess ||
+        hipMalloc(&t->lmax, (kPartialBlocks + 1) * sizeof(double)) != hipSuccess)
         return cleanup(fail(NNQS_ENOMEM, "device allocation of a table of %lld failed", (long long)capacity));
     if (hipMemset(t->status, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return cleanup(fail(NNQS_EHIP, "table initialisation failed"));
@@ -449,6 +497,8 @@ nnqs_status nnqs_table_destroy(nnqs_table *t) {
     hipFree(t->split);
     hipFree(t->status);
     hipFree(t->partials);
+    hipFree(t->amp);
+    hipFree(t->lmax);
     delete t;
     return NNQS_OK;
 }
@@ -514,6 +564,14 @@ nnqs_status nnqs_table_build(nnqs_table *t, const uint64_t *keys, const double *
     hipLaunchKernelGGL(k_table_finalize, dim3((unsigned)((n + thr - 1) / thr)), dim3(thr), 0, st, t->sys->view,
                        t->sort_keys, t->sort_idx, logabs, phase, n, t->keys, t->logabs, t->phase, t->filter, fl,
                        t->status);
+    {
+        int mb = (int)((n + thr - 1) / thr);
+        if (mb > kPartialBlocks) mb = kPartialBlocks;
+        hipLaunchKernelGGL(k_table_max_partial, dim3((unsigned)mb), dim3(thr), 0, st, t->logabs, n, t->lmax);
+        hipLaunchKernelGGL(k_table_max_final, dim3(1), dim3(thr), 0, st, t->lmax, mb);
+        hipLaunchKernelGGL(k_table_amp, dim3((unsigned)((n + thr - 1) / thr)), dim3(thr), 0, st, t->logabs,
+                           t->phase, n, t->lmax, t->amp);
+    }
     int L = 0;
     while ((int64_t(1) << L) < n) L++;
     int sl = t->tune.splitter_levels < L ? t->tune.splitter_levels : L;

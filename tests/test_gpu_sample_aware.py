@@ -173,6 +173,24 @@ def test_eloc_deterministic_and_tune_invariant(nn):
         assert np.all(np.abs(g - base) <= 1e-12 * np.maximum(1.0, np.abs(base))), tune
 
 
+def test_eloc_samples_far_below_the_table_maximum(nn):
+    """Samples 650 nats below the table's largest amplitude take the exact
+    (exp / sincos) pass; their local energies reach ~1e283 and still match the
+    oracle, as do the ordinary samples around them."""
+    d = synth.config_inputs(2, K=12, n_up=4, n_dn=3, n_unique=300)
+    _print_case("far_below")
+    la = d["logabs"].copy()
+    la[::7] -= 650.0
+    S = _system(nn, d)
+    T = nn.Table(S, capacity=300)
+    T.build(dev(d["keys"]), dev(la), dev(d["phase"]), validate=True)
+    e, _ = nn.eloc_table(S, T, dev(d["keys"]), dev(d["counts"], torch.int32), dev(la), dev(d["phase"]))
+    ref, ab = oracle.eloc_table(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"], d["keys"], la,
+                                d["phase"], d["keys"], la, d["phase"], with_absum=True)
+    assert np.abs(ref[::7]).max() > 1e200
+    assert_eloc_close(eloc_complex(e), ref, ab, label="far below")
+
+
 def test_autotune_picks_a_schedule_and_keeps_results(nn):
     d = synth.config_inputs(2, n_unique=4096)
     _print_case("autotune")
