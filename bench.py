@@ -80,6 +80,8 @@ def main():
                     help="of these, samples also evaluated by the plain FP64 path (error reference)")
     ap.add_argument("--screen-steps", type=int, default=5000,
                     help="Adam steps of the screen training in the full-E_loc leg")
+    ap.add_argument("--pauli", type=int, default=1,
+                    help="also time the Pauli-string backend on the same workload (0 = skip)")
     ap.add_argument("--schedule", type=str, default="",
                     help="JSON launch schedule for the sample-aware kernel instead of autotuning (profiling runs)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -182,6 +184,7 @@ def main():
                "sample": f"first {m} of the {n} samples against the full table, FP64, {dt:.2f} s wall",
                "connections_per_s": m * C / dt}
 
+    pauli = pauli_leg(args, nn, S, T, keys, cnt, la, ph, n, C, np, torch) if args.pauli else None
     full = full_path_leg(args, nn, synth, np, torch) if args.full_samples > 0 else None
 
     out = {
@@ -208,9 +211,39 @@ def main():
                      "traffic_unit": "bytes per launch", "sources_sha256_16": sa_sources_hash(),
                      "kernel_ms": kernel_ms, "ops_per_connection": ALU_OPS_PER_CONNECTION},
         "cpu_baseline": cpu,
+        "pauli_path": pauli,
         "full_path": full,
     }
     print(json.dumps(out), flush=True)
+
+
+def pauli_leg(args, nn, S, T, keys, cnt, la, ph, n, C, np, torch):
+    """The paper's own formulation (grouped Pauli strings, Algorithms 1 and
+    2) on the bench workload: build time, layout sizes, E_loc time and its
+    agreement with the Slater-Condon result."""
+    log("Pauli-string backend")
+    t0 = time.perf_counter()
+    P = nn.Pauli(S)
+    t_build = time.perf_counter() - t0
+    info = P.info()
+    T.build(keys, la, ph)
+    e1, _ = nn.eloc_pauli(P, T, keys, cnt, la, ph)
+    e2, _ = nn.eloc_table(S, T, keys, cnt, la, ph)
+    torch.cuda.synchronize()
+    a, b = e1.cpu().numpy(), e2.cpu().numpy()
+    diff = float(np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b))))
+    best = 1e30
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        nn.eloc_pauli(P, T, keys, cnt, la, ph)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t1)
+    log(f"Pauli: {info['groups']} groups, {info['strings']} strings, {best * 1e3:.2f} ms per E_loc")
+    return {"groups": info["groups"], "strings": info["strings"], "bytes_grouped": info["bytes_grouped"],
+            "bytes_flat": info["bytes_flat"], "layout_saving": 1.0 - info["bytes_grouped"] / info["bytes_flat"],
+            "build_s": t_build, "eloc_ms": best * 1e3, "samples_per_s": n / best,
+            "groups_per_s": n * info["groups"] / best, "max_rel_diff_vs_slater_condon": diff}
 
 
 # Operating point of the screened full path: skip a connection when its
@@ -236,12 +269,18 @@ def full_path_leg(args, nn, synth, np, torch):
     from paper_2306_16705_amd import screen_train
     t = time.perf_counter()
     xk, ex, lab = screen_train.connection_dataset(S, M, keys[n:], per_sample=16384, seed=1)
+    (xk, ex, lab), held = screen_train.split(xk, ex, lab, held_out=0.05, seed=4)
     scr = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=2))
     losses = screen_train.train(scr, xk, ex, lab, steps=args.screen_steps, batch=4096, lr=2e-3, seed=3)
     t_train = time.perf_counter() - t
     log(f"screen trained in {t_train:.1f} s, loss {losses[0]:.4g} -> {float(np.mean(losses[-20:])):.4g}")
     tk, tc = keys[:n].contiguous(), cnt[:n].contiguous()
-    screened_kw = dict(screen=scr, skip_nats=SKIP_NATS, skip_rule=nn.NNQS_SKIP_CONTRIBUTION, refine_nats=REFINE_NATS)
+    # held-out pairs (5 % kept out of training): a screen worse than 1 nat
+    # RMS falls back to the plain evaluation
+    scr_used, rmse = screen_train.screen_or_plain(scr, *held)
+    log(f"screen held-out RMSE {rmse:.3f} nats -> {'screened' if scr_used is not None else 'plain fallback'}")
+    screened_kw = dict(screen=scr_used, skip_nats=SKIP_NATS, skip_rule=nn.NNQS_SKIP_CONTRIBUTION,
+                       refine_nats=REFINE_NATS)
 
     def timed(prec, k, c, **kw):
         nn.eloc_model(S, M, k[:1], c[:1], prec, **kw)  # warm scratch
@@ -263,7 +302,7 @@ def full_path_leg(args, nn, synth, np, torch):
                                      "refined_fraction": sts["refined"] / sts["connections"],
                                      "skip_rule": "contribution", "skip_nats": SKIP_NATS,
                                      "refine_nats": REFINE_NATS},
-           "screen_training_s": t_train,
+           "screen_training_s": t_train, "screen_held_out_rmse_nats": rmse,
            "speedup_screened_vs_plain_bf16": dt16 / dts}
     if m > 0:
         dt64, e64, en64, _ = timed(nn.NNQS_FP64, tk[:m].contiguous(), tc[:m].contiguous())

@@ -353,6 +353,48 @@ nnqs_status nnqs_table_autotune(const nnqs_system *sys, nnqs_table *tab, const u
                                 const double *phase, int64_t n, double *eloc, int32_t reps, nnqs_tune *best,
                                 double *best_ms, void *stream);
 
+/* ------------------------------------------------- Pauli-string backend */
+/* The paper's own formulation of the sample-aware local energy (Section 3.4
+ * items 1, 2, 4, 5; Algorithms 1 and 2): the qubit Hamiltonian as Pauli
+ * strings X^x Z^z, grouped by their X part (every string of a group couples
+ * x to x ^ X), each group's strings listed with their Z part and a real
+ * coefficient that already holds the sign (-1)^{|X & Z|}; then
+ *   H_{x, x^X} = sum over the group of coef * (-1)^{|x & Z|}.
+ * Jordan-Wigner strings over lower indices, spin orbital p = 2i + spin. */
+typedef struct nnqs_pauli nnqs_pauli;
+
+/* Host-only builder (no GPU): the grouped Pauli form of the Hamiltonian of
+ * Eq. 9 from spatial chemists' integrals (layout as nnqs_system_create).
+ * With all four arrays NULL it only returns the sizes in *n_groups and
+ * *n_strings; otherwise *n_groups / *n_strings give the capacities on entry
+ * and receive the sizes: xy [n_groups][2] (X part, groups sorted by it),
+ * idx [n_groups + 1] (string ranges), zm [n_strings][2], coef [n_strings].
+ * Errors: EINVAL (arguments, complex coefficients), ERANGE (capacity). */
+nnqs_status nnqs_pauli_build_host(int32_t n_spin_orb, const double *h, const double *g, double e_core,
+                                  int64_t *n_groups, int64_t *n_strings, uint64_t *xy, int64_t *idx, uint64_t *zm,
+                                  double *coef);
+
+/* Builds the grouped Pauli form of `sys` on the host and uploads it.
+ * Synchronous.  Errors: EINVAL, ENOMEM, EHIP. */
+nnqs_status nnqs_pauli_create(nnqs_pauli **out, const nnqs_system *sys);
+
+/* Releases it.  NULL is accepted. */
+nnqs_status nnqs_pauli_destroy(nnqs_pauli *pauli);
+
+/* Sizes: groups, strings, bytes of the grouped layout (per group an X tuple
+ * and an index, per string a Z tuple and a coefficient) and of the flat
+ * layout (per string X and Z tuples, a Y count and a coefficient); tuples
+ * take 8 bytes for N <= 64, else 16.  Any output may be NULL. */
+nnqs_status nnqs_pauli_info(const nnqs_pauli *pauli, int64_t *n_groups, int64_t *n_strings, int64_t *bytes_grouped,
+                            int64_t *bytes_flat);
+
+/* Sample-aware E_loc over the Pauli groups (same inputs, outputs and error
+ * model as nnqs_eloc_table; the same operator, so the same result up to
+ * rounding).  Errors: EINVAL, EUNSUPPORTED, EHIP. */
+nnqs_status nnqs_eloc_pauli(const nnqs_pauli *pauli, nnqs_table *tab, const uint64_t *keys, const uint32_t *counts,
+                            const double *logabs, const double *phase, int64_t n, double *eloc, double *energy,
+                            uint32_t flags, void *stream);
+
 /* ------------------------------------------------------------ batching */
 /* Many systems (uneven N, electron and sample counts) evaluated by one
  * persistent sample-aware launch.  A step of a batch: for every item with a

@@ -15,13 +15,16 @@ from .api import (  # noqa: F401
     NNQS_SKIP_RATIO,
     NNQS_VALIDATE,
     Model,
+    Pauli,
     Screen,
     System,
     Table,
     connections,
     eloc_model,
+    eloc_pauli,
     eloc_table,
     energy,
     model_logpsi,
+    pauli_build_host,
     version,
 )

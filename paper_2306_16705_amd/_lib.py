@@ -51,6 +51,13 @@ SIGNATURES = {
     "nnqs_screen_adam_step": (_i32, [_c_void_p, _c_void_p, _f64, _f64, _f64, _f64, _c_void_p]),
     "nnqs_table_autotune": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p, _i32,
                                    _c_void_p, _c_void_p, _c_void_p]),
+    "nnqs_pauli_build_host": (_i32, [_i32, _c_void_p, _c_void_p, _f64, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                     _c_void_p, _c_void_p]),
+    "nnqs_pauli_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p]),
+    "nnqs_pauli_destroy": (_i32, [_c_void_p]),
+    "nnqs_pauli_info": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "nnqs_eloc_pauli": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p,
+                               _c_void_p, _u32, _c_void_p]),
     "nnqs_batch_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p, _i32]),
     "nnqs_batch_destroy": (_i32, [_c_void_p]),
     "nnqs_batch_run": (_i32, [_c_void_p, _c_void_p]),

@@ -342,6 +342,76 @@ class Screen:
             pass
 
 
+# ------------------------------------------------------------------- Pauli
+def pauli_build_host(n_spin_orb: int, h, g, e_core: float = 0.0):
+    """Grouped Pauli form of the Hamiltonian, built on the host
+    (``nnqs_pauli_build_host``): ``(xy [NK, 2] uint64, idx [NK + 1] int64,
+    zm [NT, 2] uint64, coef [NT] float64)``."""
+    lib = L.load()
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    nk, nt = ctypes.c_int64(0), ctypes.c_int64(0)
+    L.check(lib.nnqs_pauli_build_host(int(n_spin_orb), h.ctypes.data_as(ctypes.c_void_p),
+                                      g.ctypes.data_as(ctypes.c_void_p), float(e_core), ctypes.byref(nk),
+                                      ctypes.byref(nt), None, None, None, None))
+    xy = np.zeros((nk.value, 2), np.uint64)
+    idx = np.zeros(nk.value + 1, np.int64)
+    zm = np.zeros((nt.value, 2), np.uint64)
+    coef = np.zeros(nt.value, np.float64)
+    L.check(lib.nnqs_pauli_build_host(int(n_spin_orb), h.ctypes.data_as(ctypes.c_void_p),
+                                      g.ctypes.data_as(ctypes.c_void_p), float(e_core), ctypes.byref(nk),
+                                      ctypes.byref(nt), xy.ctypes.data_as(ctypes.c_void_p),
+                                      idx.ctypes.data_as(ctypes.c_void_p), zm.ctypes.data_as(ctypes.c_void_p),
+                                      coef.ctypes.data_as(ctypes.c_void_p)))
+    return xy, idx, zm, coef
+
+
+class Pauli:
+    """Grouped Pauli-string Hamiltonian of a system on the device (``nnqs_pauli_*``)."""
+
+    def __init__(self, system: System):
+        self._lib = L.load()
+        self.system = system
+        out = ctypes.c_void_p()
+        L.check(self._lib.nnqs_pauli_create(ctypes.byref(out), system.handle))
+        self.handle = out
+
+    def info(self) -> dict:
+        v = [ctypes.c_int64(0) for _ in range(4)]
+        L.check(self._lib.nnqs_pauli_info(self.handle, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("groups", "strings", "bytes_grouped", "bytes_flat"), [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.nnqs_pauli_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eloc_pauli(pauli: Pauli, table: Table, keys, counts, logabs, phase, eloc=None, energy=None,
+               with_energy: bool = True, stream=None):
+    """Sample-aware local energies over the Pauli groups (``nnqs_eloc_pauli``)."""
+    n = keys.shape[0]
+    _need(keys, "keys", _KEY_DTYPES, (n, 2))
+    _need(logabs, "logabs", (torch.float64,), (n,))
+    _need(phase, "phase", (torch.float64,), (n,))
+    if with_energy:
+        _need(counts, "counts", (torch.int32, torch.uint32), (n,))
+        if energy is None:
+            energy = torch.empty(4, dtype=torch.float64, device=keys.device)
+    if eloc is None:
+        eloc = torch.empty((n, 2), dtype=torch.float64, device=keys.device)
+    L.check(L.load().nnqs_eloc_pauli(pauli.handle, table.handle, _ptr(keys), _ptr(counts) if with_energy else None,
+                                     _ptr(logabs), _ptr(phase), n, _ptr(eloc), _ptr(energy) if with_energy else None,
+                                     0, _stream(stream)))
+    return eloc, (energy if with_energy else None)
+
+
 # ------------------------------------------------------------------- batch
 class Batch:
     """Many systems in one persistent sample-aware launch (``nnqs_batch_*``).

@@ -70,3 +70,29 @@ def train(screen: api.Screen, xkeys, exc, target, steps: int, batch: int = 4096,
                         grad=grad, loss=losses[s:s + 1])
         screen.adam_step(grad, lr=lr * decay ** s)
     return losses.cpu().numpy().tolist()
+
+
+def split(xkeys, exc, target, held_out: float = 0.05, seed: int = 0):
+    """Random split of a pair set into (train, held-out) triples."""
+    gen = torch.Generator(device=xkeys.device)
+    gen.manual_seed(seed)
+    perm = torch.randperm(xkeys.shape[0], generator=gen, device=xkeys.device)
+    m = max(1, int(round(held_out * xkeys.shape[0])))
+    ho, tr = perm[:m], perm[m:]
+    return ((xkeys[tr].contiguous(), exc[tr].contiguous(), target[tr].contiguous()),
+            (xkeys[ho].contiguous(), exc[ho].contiguous(), target[ho].contiguous()))
+
+
+def held_out_rmse(screen: api.Screen, xkeys, exc, target, precision: int = api.NNQS_BF16) -> float:
+    """Root-mean-square error (nats) of the screen's predictions on pairs it
+    was not trained on, in the precision the full evaluation uses."""
+    pred = screen.forward(xkeys, exc, precision)
+    return float(torch.sqrt(torch.mean((pred - target) ** 2)).item())
+
+
+def screen_or_plain(screen: api.Screen, xkeys, exc, target, max_rmse: float = 1.0):
+    """The screen if its held-out RMSE is at most ``max_rmse`` nats, else
+    ``None`` (the caller then runs the plain evaluation).  Returns
+    ``(screen or None, rmse)``."""
+    rmse = held_out_rmse(screen, xkeys, exc, target)
+    return (screen if rmse <= max_rmse else None), rmse

@@ -148,6 +148,7 @@ def test_trained_screen_cuts_evaluations_within_1e4_ha(nn):
     keys = dev(d["keys"])
     cnt = dev(d["counts"], torch.int32)
     xk, ex, lab = screen_train.connection_dataset(S, M, keys[:16], per_sample=8192, seed=1)
+    (xk, ex, lab), held = screen_train.split(xk, ex, lab, held_out=0.05, seed=4)
     scr = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=2))
     losses = screen_train.train(scr, xk, ex, lab, steps=1500, batch=4096, lr=2e-3, seed=3)
     print(f"screen training loss {losses[0]:.4g} -> {np.mean(losses[-20:]):.4g} on {xk.shape[0]} pairs")
@@ -170,6 +171,13 @@ def test_trained_screen_cuts_evaluations_within_1e4_ha(nn):
         print(f"rule {'ratio' if rule == nn.NNQS_SKIP_RATIO else 'contribution'} {thr}: evaluated "
               f"{st1['evaluated']} of {st1['connections']} ({frac:.3f}), |dE| {de:.3e} Ha, "
               f"max per-sample |dE_loc| {per:.3e}")
+    # held-out pairs kept out of training: the trained screen passes the
+    # 1-nat rule, an untrained one falls back to the plain evaluation
+    used, rmse = screen_train.screen_or_plain(scr, *held)
+    print(f"held-out RMSE {rmse:.3f} nats")
+    assert used is scr
+    raw = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=5))
+    assert screen_train.screen_or_plain(raw, *held)[0] is None
     frac, de = res[(nn.NNQS_SKIP_RATIO, 12.0)]
     assert frac < 0.5 and de < 0.05
     frac, de = res[(nn.NNQS_SKIP_CONTRIBUTION, 18.0)]
