@@ -80,6 +80,8 @@ def main():
                     help="of these, samples also evaluated by the plain FP64 path (error reference)")
     ap.add_argument("--screen-steps", type=int, default=5000,
                     help="Adam steps of the screen training in the full-E_loc leg")
+    ap.add_argument("--batch-systems", type=int, default=0,
+                    help="also time the batched launch over this many systems of the 32-system recipe (0 = skip)")
     ap.add_argument("--pauli", type=int, default=1,
                     help="also time the Pauli-string backend on the same workload (0 = skip)")
     ap.add_argument("--schedule", type=str, default="",
@@ -185,6 +187,7 @@ def main():
                "connections_per_s": m * C / dt}
 
     pauli = pauli_leg(args, nn, S, T, keys, cnt, la, ph, n, C, np, torch) if args.pauli else None
+    batch = batch_leg(args, nn, synth, np, torch) if args.batch_systems > 0 else None
     full = full_path_leg(args, nn, synth, np, torch) if args.full_samples > 0 else None
 
     out = {
@@ -212,9 +215,47 @@ def main():
                      "kernel_ms": kernel_ms, "ops_per_connection": ALU_OPS_PER_CONNECTION},
         "cpu_baseline": cpu,
         "pauli_path": pauli,
+        "batch_path": batch,
         "full_path": full,
     }
     print(json.dumps(out), flush=True)
+
+
+def batch_leg(args, nn, synth, np, torch):
+    """Systems of the multi-system recipe (N even in 20..120, 10^3-10^5
+    samples each, one transformer per system feeding the samples' amplitudes)
+    in one persistent launch: autotuned schedule, then timed graph replays."""
+    log(f"batch of {args.batch_systems} systems")
+    items, tot_s, tot_c = [], 0, 0
+    for k in range(args.batch_systems):
+        d = synth.config_inputs(4, k)
+        m = d["keys"].shape[0]
+        S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+        items.append(dict(system=S, table=nn.Table(S, capacity=m),
+                          model=nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"]),
+                          keys=torch.from_numpy(d["keys"].view(np.int64).copy()).cuda(),
+                          counts=torch.from_numpy(d["counts"].astype(np.int32)).cuda(),
+                          logabs=torch.empty(m, dtype=torch.float64, device="cuda"),
+                          phase=torch.empty(m, dtype=torch.float64, device="cuda"),
+                          eloc=torch.empty((m, 2), dtype=torch.float64, device="cuda"),
+                          energy=torch.empty(4, dtype=torch.float64, device="cuda")))
+        tot_s += m
+        tot_c += m * S.connection_count
+    B = nn.Batch(items)
+    st = torch.cuda.Stream()
+    tune, _ = B.autotune(reps=1, stream=st)
+    B.capture(st)
+    B.launch(st)
+    st.synchronize()
+    best = 1e30
+    for _ in range(3):
+        t0 = time.perf_counter()
+        B.launch(st)
+        st.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    log(f"batch: {best * 1e3:.1f} ms per graph step, {tot_s / best:.4g} samples/s")
+    return {"systems": args.batch_systems, "samples": tot_s, "connections": tot_c, "schedule": tune,
+            "ms_per_graph_step": best * 1e3, "samples_per_s": tot_s / best, "connections_per_s": tot_c / best}
 
 
 def pauli_leg(args, nn, S, T, keys, cnt, la, ph, n, C, np, torch):
