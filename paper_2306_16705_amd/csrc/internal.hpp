@@ -186,6 +186,23 @@ __device__ inline double excitation_element(const SysView &S, const Key &x, doub
     return s * (phys_el(S, a0, b0, i0, j0) - phys_el(S, a0, b0, j0, i0));
 }
 
+// erf in FP32 for the BF16 forwards: Abramowitz & Stegun 7.1.26 (Hastings'
+// rational approximation), |error| <= 1.5e-7, far below the BF16 rounding of
+// the results it feeds; one reciprocal, one exponential, no branches.
+__device__ __forceinline__ float erf_as(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float y = fmaf(1.061405429f, t, -1.453152027f);
+    y = fmaf(y, t, 1.421413741f);
+    y = fmaf(y, t, -0.284496736f);
+    y = fmaf(y, t, 0.254829592f);
+    y = 1.0f - y * t * __expf(-ax * ax);
+    return copysignf(y, x);
+}
+
+// GELU with the erf above (BF16 forwards and the screen's inference).
+__device__ __forceinline__ float gelu_bf16path(float v) { return 0.5f * v * (1.0f + erf_as(v * 0.70710678118654752f)); }
+
 // -------------------------------------------------- compensated summation
 struct NSum {  // Neumaier
     double s, c;

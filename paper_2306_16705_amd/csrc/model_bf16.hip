@@ -109,7 +109,7 @@ __device__ __forceinline__ float dpp_row_sum(float v) {
     return v;
 }
 
-__device__ __forceinline__ float gelu32(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu32(float v) { return gelu_bf16path(v); }
 
 // C tiles of a 64 x 64 product: tile (rb, cb) = acc[rb * 4 + cb].
 struct Tile64 {

@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(256) k_screen_infer(int N, const float *__rest
             for (int c = 0; c < 64; c++) acc[c] += row[c];
         }
 #pragma unroll
-        for (int c = 0; c < 64; c++) Z[c16 * ZLD + c0 + c] = (__bf16)gelu_t<float>(acc[c]);
+        for (int c = 0; c < 64; c++) Z[c16 * ZLD + c0 + c] = (__bf16)gelu_bf16path(acc[c]);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(256) k_screen_infer(int N, const float *__rest
             }
             const float bb = w32[o.b2 + nb * 16 + c16], ww = w32[o.w3 + nb * 16 + c16];
 #pragma unroll
-            for (int i = 0; i < 4; i++) part[i] += gelu_t<float>(a2[i] + bb) * ww;
+            for (int i = 0; i < 4; i++) part[i] += gelu_bf16path(a2[i] + bb) * ww;
         }
 #pragma unroll
         for (int i = 0; i < 4; i++) part[i] = dpp_sum16(part[i]);
