@@ -325,7 +325,7 @@ nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model, nnqs_scre
 /* ------------------------------------------------------------- tuning */
 /* Launch parameters of the sample-aware kernel (0 = library default). */
 typedef struct {
-    int32_t waves_per_block;   /* 1..16 (more than 12 only with search 1) */
+    int32_t waves_per_block;   /* 1..16 (the batched launch uses at most 12) */
     int32_t blocks_per_cu;     /* grid = blocks_per_cu * CU count */
     int32_t filter_log2_bits;  /* LDS membership filter size, 10..20 (2^k bits) */
     int32_t splitter_levels;   /* binary-search levels staged in LDS, 1..13 */
@@ -342,8 +342,7 @@ nnqs_status nnqs_table_set_tune(nnqs_table *tab, const nnqs_tune *tune);
 nnqs_status nnqs_table_get_tune(const nnqs_table *tab, nnqs_tune *tune);
 
 /* Autotuner of nnqs_eloc_table: times every candidate schedule (waves per
- * block {8, 12, 16}, the 16-wave build with search 1 only, x splitter levels
- * {8, 10, 12} x search {1, 2}) on the samples themselves (the table is
+ * block {8, 12, 16} x splitter levels {8, 10, 12} x search {1, 2}) on the samples themselves (the table is
  * rebuilt from keys / logabs / phase for each), best of `reps` calls after
  * one warm-up call, and leaves `tab` built with the fastest, which it
  * returns (best, best_ms may be NULL).  eloc [n][2] is scratch.  Results do

@@ -67,10 +67,11 @@ static nnqs_status batch_plan(nnqs_batch *b) {
         const TableView tv = table_view_planned(b->items[k].table, b->items[k].n);
         max_sl = std::max(max_sl, tv.split_levels);
     }
-    const int budget = b->max_lds - 64;  // static LDS of the batched kernel
+    const int budget = b->max_lds - 16;  // the kernel's next-tile slot follows the layout
     while (fl_min > 10 && sa_lds_bytes(fl_min, max_sl, b->W, b->waves) > (size_t)budget) fl_min--;
-    b->lds = sa_lds_bytes(fl_min, max_sl, b->W, b->waves);
-    if (b->lds > (size_t)budget) return fail(NNQS_EINVAL, "LDS budget exceeded (%zu bytes)", b->lds);
+    const size_t layout = sa_lds_bytes(fl_min, max_sl, b->W, b->waves);
+    if (layout > (size_t)budget) return fail(NNQS_EINVAL, "LDS budget exceeded (%zu bytes)", layout);
+    b->lds = ((layout + 15) & ~(size_t)15) + 16;
     for (int k = 0; k < n_items; k++) {
         const nnqs_batch_item &it = b->items[k];
         SaBatchItem &d = hi[k];

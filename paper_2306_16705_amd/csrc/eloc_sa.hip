@@ -19,11 +19,11 @@
 
 namespace nnqs {
 
-// Largest block of the sample-aware kernel: 12 waves, i.e. three per SIMD,
-// which leaves the kernel up to 168 VGPRs (it needs about 150) so that
-// nothing spills to private memory.
+// Block sizes of the sample-aware kernels: builds for up to 12 waves (three
+// per SIMD, up to 168 VGPRs: the exact pass and the batched kernels, which
+// need more than 128) and builds for up to 16 waves (four per SIMD, at most
+// 128 VGPRs: the single-system scaled pass, both search variants).
 constexpr int kSaMaxThreads = 768;
-// The one-word-search build fits 128 registers and also runs 16-wave blocks.
 constexpr int kSaWideThreads = 1024;
 
 // Dynamic LDS layout of the sample-aware kernel: the filter words, the staged
@@ -42,39 +42,44 @@ __host__ __device__ inline SaLayout sa_layout(int filter_log2, int split_levels,
     return L;
 }
 
-// Two-bit probe of the blocked filter (geometry in internal.hpp).  The bit
-// extracts use the low five bits of their offset operand, which are hash
-// bits 0-4 and 5-9.
-__device__ __forceinline__ uint32_t filter_load(const uint32_t *f, uint32_t wmask, uint32_t h) {
+// Two-bit probe of the blocked filter (geometry in internal.hpp).  The
+// filter is the first object of the kernel's dynamic LDS, and the kernels
+// that probe it declare no static LDS, so it starts at LDS address 0 and a
+// word's byte offset is its LDS address (sa_stage checks this): the probe
+// needs no base add.  The bit extracts use the low five bits of their offset
+// operand, which are hash bits 0-4 and 5-9.
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+__device__ __forceinline__ uint32_t filter_load(uint32_t wmask, uint32_t h) {
     // byte offset of word filter_word(h, wmask)
     const uint32_t off = (h >> (kFilterWordShift - 2)) & (wmask << 2);
-    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(f) + off);
+    return *reinterpret_cast<lds_u32 *>((size_t)off);
 }
 __device__ __forceinline__ uint32_t filter_test(uint32_t w, uint32_t h) {
     return __builtin_amdgcn_ubfe(w, h, 1u) & __builtin_amdgcn_ubfe(w, h >> 5, 1u);
 }
-__device__ __forceinline__ uint32_t filter_probe(const uint32_t *f, uint32_t wmask, uint32_t h) {
-    return filter_test(filter_load(f, wmask, h), h);
+__device__ __forceinline__ uint32_t filter_probe(uint32_t wmask, uint32_t h) {
+    return filter_test(filter_load(wmask, h), h);
 }
 
 template <int W>
-__device__ __forceinline__ Key load_key(const uint64_t *k, int64_t i) {
+__device__ __forceinline__ Key load_key(const uint64_t *k, uint32_t i) {
     Key r;
-    r.lo = k[2 * i];
-    r.hi = (W == 2) ? k[2 * i + 1] : 0ull;
+    r.lo = k[2 * (size_t)i];
+    r.hi = (W == 2) ? k[2 * (size_t)i + 1] : 0ull;
     return r;
 }
 
-// Lower-bound search for t in the sorted table; both variants start with
-// the first split_levels levels from LDS copies of the keys they probe
-// (every key at position (m+1)*2^(L-s) - 1).
+// Lower-bound search for t in the sorted table (positions fit 32 bits: a
+// table holds at most 2^31 keys); both variants start with the first
+// split_levels levels from LDS copies of the keys they probe (every key at
+// position (m+1)*2^(L-s) - 1).
 template <int W>
-__device__ __forceinline__ int64_t search_lds_levels(const TableView &T, const uint64_t *s_lds, const Key &t) {
+__device__ __forceinline__ uint32_t search_lds_levels(const TableView &T, const uint64_t *s_lds, const Key &t) {
     const int L = T.log2n, s = T.split_levels;
-    int64_t lo = 0;
+    uint32_t lo = 0;
     for (int lvl = 0; lvl < s; lvl++) {
-        const int64_t step = int64_t(1) << (L - 1 - lvl);
-        const int64_t j = ((lo + step) >> (L - s)) - 1;
+        const uint32_t step = 1u << (L - 1 - lvl);
+        const uint32_t j = ((lo + step) >> (L - s)) - 1u;
         Key k;
         k.lo = s_lds[j * W];
         k.hi = (W == 2) ? s_lds[j * W + 1] : 0ull;
@@ -88,52 +93,54 @@ __device__ __forceinline__ int64_t search_lds_levels(const TableView &T, const u
 template <int W>
 __device__ __forceinline__ int64_t table_find_binary(const TableView &T, const uint64_t *s_lds, const Key &t) {
     const int L = T.log2n;
-    int64_t lo = search_lds_levels<W>(T, s_lds, t);
+    const uint32_t n = (uint32_t)T.n;
+    uint32_t lo = search_lds_levels<W>(T, s_lds, t);
     for (int lvl = T.split_levels; lvl < L; lvl++) {
-        const int64_t step = int64_t(1) << (L - 1 - lvl);
-        const int64_t idx = lo + step - 1;
-        if (idx < T.n && key_less(load_key<W>(T.keys, idx), t)) lo += step;
+        const uint32_t step = 1u << (L - 1 - lvl);
+        const uint32_t idx = lo + step - 1u;
+        if (idx < n && key_less(load_key<W>(T.keys, idx), t)) lo += step;
     }
-    if (lo < T.n && key_eq(load_key<W>(T.keys, lo), t)) return lo;
+    if (lo < n && key_eq(load_key<W>(T.keys, lo), t)) return lo;
     return -1;
 }
 
 // Variant 2: the remaining levels up to three at a time by 8-way rounds
-// whose probes are independent loads; the last round loads the eight keys
-// from the current lower bound on, so the key the search ends on is already
-// in registers for the equality test.
+// whose probes are independent loads.  The last round loads the keys from
+// the current lower bound on and counts them as they arrive: the lower
+// bound moves past every key below t, and t is present exactly when one of
+// the keys of the final range equals it (keys are distinct), so no key has
+// to be kept for a separate equality test.
 template <int W>
 __device__ __forceinline__ int64_t table_find_8way(const TableView &T, const uint64_t *s_lds, const Key &t) {
-    int64_t lo = search_lds_levels<W>(T, s_lds, t);
-    const int64_t last = T.n - 1;
+    uint32_t lo = search_lds_levels<W>(T, s_lds, t);
+    const uint32_t n = (uint32_t)T.n, last = n - 1u;
     int r = T.log2n - T.split_levels;
-    if (r == 0) return (lo < T.n && key_eq(load_key<W>(T.keys, lo), t)) ? lo : -1;
+    if (r == 0) return (lo < n && key_eq(load_key<W>(T.keys, lo), t)) ? (int64_t)lo : -1;
     int q = r % 3 == 0 ? 3 : r % 3;  // levels taken by the first round
     while (r > q) {
-        const int64_t st = int64_t(1) << (r - q);
-        int c = 0;
+        const uint32_t st = 1u << (r - q);
+        uint32_t c = 0;
         for (int k = 1; k < (1 << q); k++) {
-            const int64_t idx = lo + k * st - 1;
+            const uint32_t idx = lo + k * st - 1u;
             const Key kk = load_key<W>(T.keys, idx < last ? idx : last);
-            c += (idx < T.n && key_less(kk, t)) ? 1 : 0;
+            c += (idx < n && key_less(kk, t)) ? 1u : 0u;
         }
         lo += c * st;
         r -= q;
         q = 3;
     }
-    Key kk[8];
+    const int probes = (1 << q) - 1;  // the final range is lo .. lo + probes
+    uint32_t c = 0;
+    bool eq = false;
 #pragma unroll
-    for (int k = 0; k < 8; k++) kk[k] = load_key<W>(T.keys, lo + k < last ? lo + k : last);
-    const int probes = (1 << q) - 1;
-    int c = 0;
-#pragma unroll
-    for (int k = 0; k < 7; k++) c += (k < probes && lo + k < T.n && key_less(kk[k], t)) ? 1 : 0;
-    Key e = kk[0];
-#pragma unroll
-    for (int k = 1; k < 8; k++)
-        if (c == k) e = kk[k];
-    const int64_t pos = lo + c;
-    return (pos < T.n && key_eq(e, t)) ? pos : -1;
+    for (int k = 0; k < 8; k++) {
+        const uint32_t p = lo + k;
+        const Key kk = load_key<W>(T.keys, p < last ? p : last);
+        const bool in = k <= probes && p < n;
+        c += (in && k < probes && key_less(kk, t)) ? 1u : 0u;
+        eq = eq || (in && key_eq(kk, t));
+    }
+    return eq ? (int64_t)(lo + c) : -1;
 }
 
 __device__ __forceinline__ uint32_t wave_xor32(uint32_t v) {
@@ -149,6 +156,7 @@ struct SaStage {
     const uint32_t *h_lds;  // low 32 bits of the hash words
     WaveLds *waves;         // one per wave
     uint32_t wmask;         // filter words - 1
+    bool at_zero;           // the filter starts at LDS address 0
 };
 
 // Stage the filter (folded to the LDS size: OR of aliasing words keeps every
@@ -181,6 +189,7 @@ __device__ __forceinline__ SaStage sa_stage(const SysView &S, const TableView &T
     G.h_lds = h_lds;
     G.waves = reinterpret_cast<WaveLds *>(smem + lay.waves);
     G.wmask = (uint32_t)nwords - 1u;
+    G.at_zero = (uint32_t)(size_t)(lds_u32 *)f_lds == 0u;  // address-space cast to an LDS address
     return G;
 }
 
@@ -263,25 +272,28 @@ __device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, 
                 key_flip(xp, b);
             }
         }
+        // The matrix element needs only x and the excitation, so its integral
+        // loads are issued before the search and overlap it.
+        int sg;
+        const double hv = excitation_element(S, x, diag, i, j, a, b, &sg);
         const int64_t idx = S8 ? table_find_8way<W>(T, G.s_lds, xp) : table_find_binary<W>(T, G.s_lds, xp);
-        if (idx >= 0) {
-            int sg;
-            const double hv = excitation_element(S, x, diag, i, j, a, b, &sg);
-            double re, im;
-            if (EX == 0) {
-                const double ar = T.amp[2 * idx], ai = T.amp[2 * idx + 1];
-                const double xs = wl.hit[0], xcs = wl.hit[1], xsn = wl.hit[2];
-                re = xs * (ar * xcs + ai * xsn);
-                im = xs * (ai * xcs - ar * xsn);
-            } else {
-                const double r = exp(T.logabs[idx] - wl.hit[3]);
-                double sn, cs;
-                sincos(T.phase[idx] - wl.hit[4], &sn, &cs);
-                re = r * cs;
-                im = r * sn;
-            }
-            are.add(hv * re);
-            aim.add(hv * im);
+        if (EX == 0) {
+            // branch-free: a miss reads entry 0 and adds an exact zero, which
+            // leaves the lane's compensated sums unchanged (the scaled
+            // amplitudes are finite)
+            const bool hit = idx >= 0;
+            const uint32_t k = hit ? (uint32_t)idx : 0u;
+            const double ar = T.amp[2 * (size_t)k], ai = T.amp[2 * (size_t)k + 1];
+            const double xs = wl.hit[0], xcs = wl.hit[1], xsn = wl.hit[2];
+            const double w = hit ? hv : 0.0;
+            are.add(w * (xs * (ar * xcs + ai * xsn)));
+            aim.add(w * (xs * (ai * xcs - ar * xsn)));
+        } else if (idx >= 0) {
+            const double r = exp(T.logabs[idx] - wl.hit[3]);
+            double sn, cs;
+            sincos(T.phase[idx] - wl.hit[4], &sn, &cs);
+            are.add(hv * (r * cs));
+            aim.add(hv * (r * sn));
         }
     };
     auto drain_full = [&]() {
@@ -292,9 +304,15 @@ __device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, 
             wave_sync();
         }
     };
-    // Append the candidates of ballot mask m (uniform) in lane order.
+    // Append the candidates of ballot mask m (uniform) in lane order: the
+    // mask itself selects the writing lanes (inverse ballot, no per-lane
+    // test) and the ring position is qt plus the count of set lanes below.
     auto push = [&](uint64_t m, uint32_t code) {
-        if ((m >> lane) & 1ull) wl.queue[(qt + mbcnt(m)) & 255] = code;
+        if (__builtin_amdgcn_inverse_ballot_w64(m)) {
+            const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)qt));
+            wl.queue[pos & 255] = code;
+        }
         qt += __popcll(m);
     };
 
@@ -319,7 +337,7 @@ __device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, 
         }
         const int q = wl.occ[sp][o], p = wl.vir[sp][v];
         const uint32_t hh = hx ^ h_lds[q] ^ h_lds[p];
-        const uint64_t m = __ballot(ok && filter_probe(f_lds, wmask, hh) != 0u);
+        const uint64_t m = __ballot(ok && filter_probe(wmask, hh) != 0u);
         if (m) {
             push(m, (uint32_t)q | 0xFF00u | ((uint32_t)p << 16) | 0xFF000000u);
             drain_full();
@@ -352,8 +370,8 @@ __device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, 
                     const uint32_t sa = (uint32_t)readlane32((int)po_s, o2);
                     const uint32_t sb = (uint32_t)readlane32((int)po_s, two ? o2 + 1 : o2);
                     const uint32_t ha = h1 ^ sa, hb = h1 ^ sb;
-                    const uint32_t wa = filter_load(f_lds, wmask, ha);
-                    const uint32_t wb = filter_load(f_lds, wmask, hb);
+                    const uint32_t wa = filter_load(wmask, ha);
+                    const uint32_t wb = filter_load(wmask, hb);
                     __builtin_amdgcn_sched_barrier(0);  // both filter reads in flight before the tests
                     const uint32_t pa = filter_test(wa, ha), pb = filter_test(wb, hb);
                     const uint64_t ma = __ballot(pa != 0u) & okm;
@@ -388,8 +406,8 @@ __device__ __forceinline__ void sa_sample(const SysView &S, const TableView &T, 
                     const uint32_t sa = (uint32_t)readlane32((int)pv_u, v);
                     const uint32_t sb = (uint32_t)readlane32((int)pv_u, two ? v + 1 : v);
                     const uint32_t ha = h1 ^ sa, hb = h1 ^ sb;
-                    const uint32_t wa = filter_load(f_lds, wmask, ha);
-                    const uint32_t wb = filter_load(f_lds, wmask, hb);
+                    const uint32_t wa = filter_load(wmask, ha);
+                    const uint32_t wb = filter_load(wmask, hb);
                     __builtin_amdgcn_sched_barrier(0);  // both filter reads in flight before the tests
                     const uint32_t pa = filter_test(wa, ha), pb = filter_test(wb, hb);
                     const uint64_t ma = __ballot(pa != 0u) & okm;
@@ -432,6 +450,10 @@ __global__ void __launch_bounds__(NT) k_eloc_sa(SysView S, TableView T, int lds_
                                                   double *__restrict__ eloc, int *status) {
     extern __shared__ __align__(16) uint8_t smem[];
     const SaStage G = sa_stage<W>(S, T, lds_filter_log2, smem);
+    if (!G.at_zero) {
+        if (threadIdx.x == 0) set_status(status, NNQS_EUNSUPPORTED);
+        return;
+    }
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     for (int64_t smp = (int64_t)blockIdx.x * nw + wid; smp < n; smp += (int64_t)gridDim.x * nw)
@@ -448,6 +470,10 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa_exact(SysView S, Tabl
                                                         double *__restrict__ eloc, int *status) {
     extern __shared__ __align__(16) uint8_t smem[];
     const SaStage G = sa_stage<W>(S, T, lds_filter_log2, smem);
+    if (!G.at_zero) {
+        if (threadIdx.x == 0) set_status(status, NNQS_EUNSUPPORTED);
+        return;
+    }
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     for (int64_t smp = (int64_t)blockIdx.x * nw + wid; smp < n; smp += (int64_t)gridDim.x * nw)
@@ -461,9 +487,11 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa_exact(SysView S, Tabl
 template <int W, int S8, int EX>
 __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa_batch(const SaBatchItem *__restrict__ items,
                                                         const SaTile *__restrict__ tiles, int ntiles,
-                                                        int *counter) {
+                                                        int *counter, uint32_t slot_off) {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ int next_tile;
+    // the next-tile slot sits after the largest system's layout (dynamic LDS,
+    // so that the filter keeps LDS address 0)
+    int &next_tile = *reinterpret_cast<int *>(smem + slot_off);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     int staged = -1;
@@ -479,6 +507,10 @@ __global__ void __launch_bounds__(kSaMaxThreads) k_eloc_sa_batch(const SaBatchIt
         if (tl.item != staged) {
             G = sa_stage<W>(it.S, it.T, it.lds_filter_log2, smem);
             staged = tl.item;
+            if (!G.at_zero) {  // uniform: every block of the launch sees the same layout
+                if (threadIdx.x == 0) set_status(it.status, NNQS_EUNSUPPORTED);
+                break;
+            }
         }
         for (int64_t smp = tl.begin + wid; smp < tl.begin + tl.count; smp += nw)
             sa_sample<W, S8, EX>(it.S, it.T, G, G.waves[wid], smp, it.keys, it.logabs, it.phase, it.eloc,
@@ -580,13 +612,27 @@ size_t sa_lds_bytes(int filter_log2, int split_levels, int W, int waves) {
 }
 
 const void *sa_kernel_ptr(int W, int search, int waves) {
-    if (search == 1 && waves > kSaMaxThreads / 64)
-        return W == 1 ? reinterpret_cast<const void *>(k_eloc_sa<1, 0, kSaWideThreads>)
-                      : reinterpret_cast<const void *>(k_eloc_sa<2, 0, kSaWideThreads>);
-    if (W == 1) return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa<1, 1, kSaMaxThreads>)
-                                   : reinterpret_cast<const void *>(k_eloc_sa<1, 0, kSaMaxThreads>);
-    return search == 2 ? reinterpret_cast<const void *>(k_eloc_sa<2, 1, kSaMaxThreads>)
-                       : reinterpret_cast<const void *>(k_eloc_sa<2, 0, kSaMaxThreads>);
+    const bool wide = waves > kSaMaxThreads / 64;
+    if (W == 1) {
+        if (search == 2)
+            return wide ? reinterpret_cast<const void *>(k_eloc_sa<1, 1, kSaWideThreads>)
+                        : reinterpret_cast<const void *>(k_eloc_sa<1, 1, kSaMaxThreads>);
+        return wide ? reinterpret_cast<const void *>(k_eloc_sa<1, 0, kSaWideThreads>)
+                    : reinterpret_cast<const void *>(k_eloc_sa<1, 0, kSaMaxThreads>);
+    }
+    if (search == 2)
+        return wide ? reinterpret_cast<const void *>(k_eloc_sa<2, 1, kSaWideThreads>)
+                    : reinterpret_cast<const void *>(k_eloc_sa<2, 1, kSaMaxThreads>);
+    return wide ? reinterpret_cast<const void *>(k_eloc_sa<2, 0, kSaWideThreads>)
+                : reinterpret_cast<const void *>(k_eloc_sa<2, 0, kSaMaxThreads>);
+}
+
+// Launch one build of the single-system kernel (the pointer from sa_kernel_ptr).
+template <int W, int S8, int NT>
+static void sa_launch_one(dim3 g, dim3 b, size_t lds, hipStream_t st, const SysView &S, const TableView &T, int fl,
+                          const uint64_t *keys, const double *logabs, const double *phase, int64_t n, double *eloc,
+                          int *status) {
+    hipLaunchKernelGGL((k_eloc_sa<W, S8, NT>), g, b, lds, st, S, T, fl, keys, logabs, phase, n, eloc, status);
 }
 
 const void *sa_batch_kernel_ptr(int W, int search, bool exact) {
@@ -612,18 +658,20 @@ nnqs_status sa_check_no_spill(const void *fn) {
 void sa_launch_batch(int W, int search, unsigned grid, int waves, size_t lds, hipStream_t st,
                      const SaBatchItem *items, const SaTile *tiles, int ntiles, int *counter) {
     const dim3 g(grid), b(waves * 64);
+    // lds = the largest layout + the 16-byte next-tile slot at its end
+    const uint32_t slot = (uint32_t)(lds - 16);
     // scaled pass, then the exact pass over the same tiles
     sa_launch_reset(counter, st);
     if (W == 1) {
-        if (search == 2) hipLaunchKernelGGL((k_eloc_sa_batch<1, 1, 0>), g, b, lds, st, items, tiles, ntiles, counter);
-        else hipLaunchKernelGGL((k_eloc_sa_batch<1, 0, 0>), g, b, lds, st, items, tiles, ntiles, counter);
+        if (search == 2) hipLaunchKernelGGL((k_eloc_sa_batch<1, 1, 0>), g, b, lds, st, items, tiles, ntiles, counter, slot);
+        else hipLaunchKernelGGL((k_eloc_sa_batch<1, 0, 0>), g, b, lds, st, items, tiles, ntiles, counter, slot);
     } else {
-        if (search == 2) hipLaunchKernelGGL((k_eloc_sa_batch<2, 1, 0>), g, b, lds, st, items, tiles, ntiles, counter);
-        else hipLaunchKernelGGL((k_eloc_sa_batch<2, 0, 0>), g, b, lds, st, items, tiles, ntiles, counter);
+        if (search == 2) hipLaunchKernelGGL((k_eloc_sa_batch<2, 1, 0>), g, b, lds, st, items, tiles, ntiles, counter, slot);
+        else hipLaunchKernelGGL((k_eloc_sa_batch<2, 0, 0>), g, b, lds, st, items, tiles, ntiles, counter, slot);
     }
     sa_launch_reset(counter, st);
-    if (W == 1) hipLaunchKernelGGL((k_eloc_sa_batch<1, 0, 1>), g, b, lds, st, items, tiles, ntiles, counter);
-    else hipLaunchKernelGGL((k_eloc_sa_batch<2, 0, 1>), g, b, lds, st, items, tiles, ntiles, counter);
+    if (W == 1) hipLaunchKernelGGL((k_eloc_sa_batch<1, 0, 1>), g, b, lds, st, items, tiles, ntiles, counter, slot);
+    else hipLaunchKernelGGL((k_eloc_sa_batch<2, 0, 1>), g, b, lds, st, items, tiles, ntiles, counter, slot);
 }
 
 void sa_launch_reset(int *counter, hipStream_t st) {
@@ -684,7 +732,7 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
     const int W = sys->view.N > 64 ? 2 : 1;
     const int search = tab->tune.search;
     int waves = tab->tune.waves_per_block;
-    const int max_waves = (search == 1 ? kSaWideThreads : kSaMaxThreads) / 64;
+    const int max_waves = kSaWideThreads / 64;
     if (waves > max_waves) waves = max_waves;
     const void *fn = sa_kernel_ptr(W, search, waves);
     nnqs_status s0 = sa_check_no_spill(fn);
@@ -700,26 +748,24 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
     NNQS_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const dim3 g(grid), b(waves * 64);
     const bool wide = waves > kSaMaxThreads / 64;
+    const SysView &SV = sys->view;
+    int *stt = tab->status;
     if (W == 1) {
-        if (wide)
-            hipLaunchKernelGGL((k_eloc_sa<1, 0, kSaWideThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
-                               phase, n, eloc, tab->status);
-        else if (search == 2)
-            hipLaunchKernelGGL((k_eloc_sa<1, 1, kSaMaxThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
-                               phase, n, eloc, tab->status);
-        else
-            hipLaunchKernelGGL((k_eloc_sa<1, 0, kSaMaxThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
-                               phase, n, eloc, tab->status);
+        if (search == 2) {
+            if (wide) sa_launch_one<1, 1, kSaWideThreads>(g, b, lds, st, SV, tv, fl, keys, logabs, phase, n, eloc, stt);
+            else sa_launch_one<1, 1, kSaMaxThreads>(g, b, lds, st, SV, tv, fl, keys, logabs, phase, n, eloc, stt);
+        } else {
+            if (wide) sa_launch_one<1, 0, kSaWideThreads>(g, b, lds, st, SV, tv, fl, keys, logabs, phase, n, eloc, stt);
+            else sa_launch_one<1, 0, kSaMaxThreads>(g, b, lds, st, SV, tv, fl, keys, logabs, phase, n, eloc, stt);
+        }
     } else {
-        if (wide)
-            hipLaunchKernelGGL((k_eloc_sa<2, 0, kSaWideThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
-                               phase, n, eloc, tab->status);
-        else if (search == 2)
-            hipLaunchKernelGGL((k_eloc_sa<2, 1, kSaMaxThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
-                               phase, n, eloc, tab->status);
-        else
-            hipLaunchKernelGGL((k_eloc_sa<2, 0, kSaMaxThreads>), g, b, lds, st, sys->view, tv, fl, keys, logabs,
-                               phase, n, eloc, tab->status);
+        if (search == 2) {
+            if (wide) sa_launch_one<2, 1, kSaWideThreads>(g, b, lds, st, SV, tv, fl, keys, logabs, phase, n, eloc, stt);
+            else sa_launch_one<2, 1, kSaMaxThreads>(g, b, lds, st, SV, tv, fl, keys, logabs, phase, n, eloc, stt);
+        } else {
+            if (wide) sa_launch_one<2, 0, kSaWideThreads>(g, b, lds, st, SV, tv, fl, keys, logabs, phase, n, eloc, stt);
+            else sa_launch_one<2, 0, kSaMaxThreads>(g, b, lds, st, SV, tv, fl, keys, logabs, phase, n, eloc, stt);
+        }
     }
     {  // exact pass (12-wave blocks, filter folded to fit)
         const int ew = kSaMaxThreads / 64;
@@ -744,8 +790,8 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
 
 // Autotuner of the single-system path: for every candidate schedule the
 // table is rebuilt from the samples, one untimed call warms up, and the best
-// of `reps` timed calls counts.  Candidates: waves per block {8, 12, 16}
-// (16 only with search 1) x splitter levels {8, 10, 12} x search {1, 2}.
+// of `reps` timed calls counts.  Candidates: waves per block {8, 12, 16} x
+// splitter levels {8, 10, 12} x search {1, 2}.
 nnqs_status nnqs_table_autotune(const nnqs_system *sys, nnqs_table *tab, const uint64_t *keys, const double *logabs,
                                 const double *phase, int64_t n, double *eloc, int32_t reps, nnqs_tune *best_out,
                                 double *best_ms, void *stream) {
@@ -764,7 +810,6 @@ nnqs_status nnqs_table_autotune(const nnqs_system *sys, nnqs_table *tab, const u
     for (int waves : {8, 12, 16})
         for (int sl : {8, 10, 12})
             for (int search : {1, 2}) {
-                if (waves > 12 && search != 1) continue;
                 nnqs_tune c = start;
                 c.waves_per_block = waves;
                 c.splitter_levels = sl;
