@@ -42,20 +42,16 @@ __host__ __device__ inline SaLayout sa_layout(int filter_log2, int split_levels,
     return L;
 }
 
-// Two-bit probe of the blocked filter (geometry in internal.hpp).  The
+// Probe of the blocked filter (geometry and bit test in internal.hpp).  The
 // filter is the first object of the kernel's dynamic LDS, and the kernels
 // that probe it declare no static LDS, so it starts at LDS address 0 and a
 // word's byte offset is its LDS address (sa_stage checks this): the probe
-// needs no base add.  The bit extracts use the low five bits of their offset
-// operand, which are hash bits 0-4 and 5-9.
+// needs no base add.
 typedef __attribute__((address_space(3))) const uint32_t lds_u32;
 __device__ __forceinline__ uint32_t filter_load(uint32_t wmask, uint32_t h) {
     // byte offset of word filter_word(h, wmask)
     const uint32_t off = (h >> (kFilterWordShift - 2)) & (wmask << 2);
     return *reinterpret_cast<lds_u32 *>((size_t)off);
-}
-__device__ __forceinline__ uint32_t filter_test(uint32_t w, uint32_t h) {
-    return __builtin_amdgcn_ubfe(w, h, 1u) & __builtin_amdgcn_ubfe(w, h >> 5, 1u);
 }
 __device__ __forceinline__ uint32_t filter_probe(uint32_t wmask, uint32_t h) {
     return filter_test(filter_load(wmask, h), h);

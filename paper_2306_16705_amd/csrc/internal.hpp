@@ -322,15 +322,26 @@ void sa_launch_reset(int *counter, hipStream_t st);
 TableView table_view_planned(const nnqs_table *t, int64_t n);
 
 // Membership-filter geometry, read from the low 32 bits of the linear key
-// hash: bits 0-4 and 5-9 select two bits of a 32-bit filter word, bits
-// 10..(filter_log2 + 4) select the word.  Bits 25-31 are never read, which
-// lets the enumeration kernel pack an orbital index into them.
+// hash: bits 0-4 and 5-9 give bit positions p1 and p2 of a 32-bit filter
+// word, and a third position is p1 + p2 mod 32 (double hashing: three bits
+// per member for one more add, which cuts the false-positive rate of the
+// blocked filter by about a third); bits 10..(filter_log2 + 4) select the
+// word.  Bits 25-31 are never read, which lets the enumeration kernel pack
+// an orbital index into them.
 constexpr int kFilterWordShift = 10;
 constexpr uint32_t kFilterHashMask = 0x01FFFFFFu;
 static_assert(kMaxFilterLog2 - 5 + kFilterWordShift <= 25, "filter word index must stay below bit 25");
 
 __device__ __forceinline__ uint32_t filter_word(uint32_t h, uint32_t wmask) { return (h >> kFilterWordShift) & wmask; }
-__device__ __forceinline__ uint32_t filter_bits(uint32_t h) { return (1u << (h & 31u)) | (1u << ((h >> 5) & 31u)); }
+__device__ __forceinline__ uint32_t filter_bits(uint32_t h) {
+    return (1u << (h & 31u)) | (1u << ((h >> 5) & 31u)) | (1u << ((h + (h >> 5)) & 31u));
+}
+// Nonzero when all three bits of h are set in filter word w (the bit
+// extracts read the low five bits of their offset operand).
+__device__ __forceinline__ uint32_t filter_test(uint32_t w, uint32_t h) {
+    const uint32_t h5 = h >> 5;
+    return __builtin_amdgcn_ubfe(w, h, 1u) & __builtin_amdgcn_ubfe(w, h5, 1u) & __builtin_amdgcn_ubfe(w, h + h5, 1u);
+}
 constexpr int kMaxSplitLevels = 13;
 constexpr int kPartialBlocks = 1024;
 }  // namespace nnqs

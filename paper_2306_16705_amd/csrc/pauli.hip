@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(768) k_eloc_pauli(SysView S, TableView T, int 
             const bool ok = k < NK;
             const uint32_t hh = hx ^ (ok ? ghash[k] : 0u);
             const uint32_t w = f_lds[filter_word(hh, wmask)];
-            const bool cand = ok && (__builtin_amdgcn_ubfe(w, hh, 1u) & __builtin_amdgcn_ubfe(w, hh >> 5, 1u));
+            const bool cand = ok && filter_test(w, hh) != 0u;
             const uint64_t m = __ballot(cand);
             if (m) {
                 if (cand) wl.queue[(qt + mbcnt(m)) & 255] = (uint32_t)k;

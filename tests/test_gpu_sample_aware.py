@@ -204,7 +204,7 @@ def test_autotune_picks_a_schedule_and_keeps_results(nn):
     tune, ms = T.autotune(args[0], args[2], args[3], reps=1)
     print(f"autotuned {tune}: {ms:.3f} ms")
     assert tune["waves_per_block"] in (8, 12, 16) and tune["splitter_levels"] in (8, 10, 12)
-    assert tune["search"] in (1, 2) and not (tune["waves_per_block"] == 16 and tune["search"] == 2)
+    assert tune["search"] in (1, 2)
     assert T.get_tune() == tune
     e2, _ = nn.eloc_table(S, T, *args)
     torch.cuda.synchronize()
