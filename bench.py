@@ -23,9 +23,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Per-connection work of the dominant kernel's hot loop, in 32-bit integer
-# lane operations: 64-bit hash update (2 XOR), filter word index (AND),
-# LDS address (shift), two bit extracts, their AND, and the candidate test.
-ALU_OPS_PER_CONNECTION = 8
+# lane operations: hash update (XOR), filter word address (shift, AND), the
+# third bit position (shift, add), three bit extracts, their two ANDs and the
+# candidate test.
+ALU_OPS_PER_CONNECTION = 11
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit integer VALU throughput.
 ALU_PEAK_GOPS = 256 * 64 * 2.4
 
@@ -35,7 +36,7 @@ ALU_PEAK_GOPS = 256 * 64 * 2.4
 # counter reads for a plain device copy of known size.  The figures hold only
 # for the kernel sources they were taken with (hash below); otherwise the
 # bench reports no traffic.
-SA_COUNTERS = {"sources_sha256_16": "ed8d52dfb579deb6", "fetch_kib": 47535.6, "write_kib": 4080.3,
+SA_COUNTERS = {"sources_sha256_16": "9afc6abc2966f154", "fetch_kib": 55967.9, "write_kib": 3973.9,
                "fetch_scale": 262144.0 / 131085.3, "write_scale": 1.0}
 SA_SOURCES = ("paper_2306_16705_amd/csrc/eloc_sa.hip", "paper_2306_16705_amd/csrc/enumerate.hpp",
               "paper_2306_16705_amd/csrc/internal.hpp")
@@ -59,7 +60,7 @@ def sa_traffic_bytes():
 
 def sa_kernel_name(tune):
     """Template instance of the sample-aware kernel a schedule runs (one-word keys)."""
-    wide = tune["search"] == 1 and tune["waves_per_block"] > 12
+    wide = tune["waves_per_block"] > 12
     return f"k_eloc_sa<1, {tune['search'] - 1}, {1024 if wide else 768}>"
 
 
