@@ -2,9 +2,9 @@
 // ansatz of Section 3.1, Eq. 11 and Fig. 2, with the Eq. 12 mask and the
 // phase MLP of Section 4.1).  Every step is a plain kernel over the rows of
 // a whole batch: LayerNorm one wave per row, the dense layers an LDS-tiled
-// FP64 product (64 x 64 output tile per block, 4 x 4 per thread) with bias,
-// GELU or residual-add epilogues, causal attention one thread per (config,
-// head, query).  Activations live in model-owned scratch between steps.
+// FP64 MFMA product (64 x 64 output tile per block) with bias, GELU or
+// residual-add epilogues, causal attention on FP64 MFMA one wave per
+// (configuration, head).  Activations live in model-owned scratch between steps.
 // The arithmetic is the FP64 definition of the network; only the summation
 // order differs from a one-configuration-at-a-time evaluation.
 #include <cmath>
@@ -58,56 +58,71 @@ __global__ void __launch_bounds__(256) k64_layernorm(const double *__restrict__ 
     out[row * 64 + lane] = (v - mean) * r * g[lane] + b[lane];
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 // C[r][j] = epi(bias[j] + sum_k A[r][k] W[k][j]) for r < M, j < N; EPI 0
 // stores, 1 adds to C (residual), 2 stores GELU.  Block: 64 x 64 tile of C,
-// 256 threads with 4 x 4 outputs each, k in steps of 16 through LDS.
+// four waves of 16 rows each, on v_mfma_f64_16x16x4_f64 (lane l holds
+// A[l & 15][l >> 4] and B[l >> 4][l & 15]; accumulator register i of lane l
+// holds row (l >> 4) + 4 i, column l & 15, unlike the BF16 16x16 variants);
+// k in slices of 32 through LDS, the next slice's global loads in flight
+// during the current slice's products.  FP64 throughout: only the summation order differs from a plain dot
+// product.
 template <int EPI>
 __global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, int lda, const double *__restrict__ W,
                                                 int ldw, const double *__restrict__ bias, int64_t M, int N, int Kd,
                                                 double *__restrict__ C, int ldc) {
-    __shared__ double As[16][64 + 1];
-    __shared__ double Ws[16][64 + 1];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    constexpr int KS = 32;  // k per slice
+    __shared__ double As[64][KS + 1];
+    __shared__ double Ws[KS][64 + 1];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = l & 15, lk = l >> 4;
     const int64_t r0 = (int64_t)blockIdx.y * 64;
     const int c0 = blockIdx.x * 64;
-    double acc[4][4];
+    // slice loads: thread t takes A[r0 + (t >> 5) + 8 e][k0 + (t & 31)] and
+    // W[k0 + (t >> 6) + 4 e][c0 + (t & 63)], e = 0..7 (coalesced rows)
+    const int at = threadIdx.x & 31, ar = threadIdx.x >> 5, wc = threadIdx.x & 63, wr = threadIdx.x >> 6;
+    double pa[8], pw[8];
+    auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+        for (int e = 0; e < 8; e++) {
+            const int64_t r = r0 + ar + 8 * e;
+            pa[e] = (r < M && k0 + at < Kd) ? A[r * lda + k0 + at] : 0.0;
+            const int kw = k0 + wr + 4 * e;
+            pw[e] = (kw < Kd && c0 + wc < N) ? W[(int64_t)kw * ldw + c0 + wc] : 0.0;
+        }
+    };
+    f64x4 acc[4];
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
-    for (int k0 = 0; k0 < Kd; k0 += 16) {
-        // stage A[r0..r0+63][k0..k0+15] (transposed) and W[k0..k0+15][c0..c0+63]
-        for (int t = threadIdx.x; t < 16 * 64; t += 256) {
-            const int kk = t & 15, rr = t >> 4;
-            const int64_t r = r0 + rr;
-            As[kk][rr] = (r < M && k0 + kk < Kd) ? A[r * lda + k0 + kk] : 0.0;
-            const int kw = t >> 6, cc = t & 63;
-            Ws[kw][cc] = (k0 + kw < Kd && c0 + cc < N) ? W[(int64_t)(k0 + kw) * ldw + c0 + cc] : 0.0;
+    for (int cb = 0; cb < 4; cb++) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+    load(0);
+    for (int k0 = 0; k0 < Kd; k0 += KS) {
+        __syncthreads();  // the previous slice is consumed
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            As[ar + 8 * e][at] = pa[e];
+            Ws[wr + 4 * e][wc] = pw[e];
         }
         __syncthreads();
+        if (k0 + KS < Kd) load(k0 + KS);  // the next slice's loads overlap this slice's products
 #pragma unroll
-        for (int kk = 0; kk < 16; kk++) {
-            double a[4], w[4];
+        for (int k4 = 0; k4 < KS; k4 += 4) {
+            const double a = As[16 * w + lr][k4 + lk];
 #pragma unroll
-            for (int i = 0; i < 4; i++) a[i] = As[kk][ty * 4 + i];
-#pragma unroll
-            for (int j = 0; j < 4; j++) w[j] = Ws[kk][tx * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int j = 0; j < 4; j++) acc[i][j] = fma(a[i], w[j], acc[i][j]);
+            for (int cb = 0; cb < 4; cb++)
+                acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ws[k4 + lk][cb * 16 + lr], acc[cb], 0, 0, 0);
         }
-        __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const int64_t r = r0 + ty * 4 + i;
-        if (r >= M) continue;
+    for (int cb = 0; cb < 4; cb++) {
+        const int c = c0 + cb * 16 + lr;
+        if (c >= N) continue;
+        const double bc = bias ? bias[c] : 0.0;
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int c = c0 + tx * 4 + j;
-            if (c >= N) continue;
-            const double v = (bias ? bias[c] : 0.0) + acc[i][j];
+        for (int i = 0; i < 4; i++) {
+            const int64_t r = r0 + 16 * w + lk + 4 * i;
+            if (r >= M) continue;
+            const double v = bc + acc[cb][i];
             double *dst = C + r * ldc + c;
             if (EPI == 1) *dst += v;
             else if (EPI == 2) *dst = gelu_f64(v);
@@ -116,41 +131,90 @@ __global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, in
     }
 }
 
-// Causal attention, one thread per (config, head, query row); q, k, v and
-// the output are [B*K][64] with head hh in columns 16 hh .. 16 hh + 15.
-__global__ void k64_attention(const double *__restrict__ q, const double *__restrict__ k,
-                              const double *__restrict__ v, int64_t B, int K, double scale,
-                              double *__restrict__ o) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= B * 4 * K) return;
-    const int s = (int)(t % K);
-    const int hh = (int)((t / K) % 4);
-    const int64_t b = t / (4 * K);
-    const double *qs = q + (b * K + s) * 64 + hh * 16;
-    double qv[16], out[16];
+// Causal attention on FP64 MFMA: one wave per (configuration, head), the four
+// heads of one configuration per block; q, k, v and the output are [B*K][64]
+// with head hh in columns 16 hh .. 16 hh + 15.  Per block of 16 queries:
+// S = Q K^T in 16 x 16 x 4 tiles (accumulator register i of lane l holds
+// query (l >> 4) + 4 i, key l & 15 of the tile), the softmax of each query
+// row over the 16 lanes that hold it (the largest score, then one
+// exponential per key), P through LDS into the A-operand layout, O = P V.
+// Rows at or beyond K read as zero and are never written.
+__global__ void __launch_bounds__(256) k64_attention(const double *__restrict__ q, const double *__restrict__ k,
+                                                     const double *__restrict__ v, int64_t B, int K, double scale,
+                                                     double *__restrict__ o) {
+    __shared__ double Ps[4][16][64 + 1];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = l & 15, lk = l >> 4;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= B * 4) return;  // wave-uniform; the kernel has no block barrier
+    const int64_t b = g >> 2;
+    const int hh = (int)(g & 3);
+    const double *qh = q + b * K * 64 + hh * 16, *kh = k + b * K * 64 + hh * 16, *vh = v + b * K * 64 + hh * 16;
+    auto ld = [&](const double *base, int s, int c) { return s < K ? base[(int64_t)s * 64 + c] : 0.0; };
+    // B operands: K^T tiles kf[kb][k4] = K[16 kb + lr][4 k4 + lk]; V tiles vf[kk] = V[4 kk + lk][lr]
+    double kf[4][4], vf[16];
 #pragma unroll
-    for (int c = 0; c < 16; c++) {
-        qv[c] = qs[c];
-        out[c] = 0.0;
+    for (int kb = 0; kb < 4; kb++)
+#pragma unroll
+        for (int k4 = 0; k4 < 4; k4++) kf[kb][k4] = ld(kh, kb * 16 + lr, 4 * k4 + lk);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) vf[kk] = ld(vh, 4 * kk + lk, lr);
+    double(*P)[64 + 1] = Ps[w];
+#pragma unroll
+    for (int qb = 0; qb < 4; qb++) {
+        double qf[4];
+#pragma unroll
+        for (int k4 = 0; k4 < 4; k4++) qf[k4] = ld(qh, qb * 16 + lr, 4 * k4 + lk);
+        f64x4 st[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++) {
+            st[kb] = f64x4{0.0, 0.0, 0.0, 0.0};
+            if (kb <= qb)
+#pragma unroll
+                for (int k4 = 0; k4 < 4; k4++)
+                    st[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(qf[k4], kf[kb][k4], st[kb], 0, 0, 0);
+        }
+        // key 16 kb + lr is visible to query 16 qb + lk + 4 i when kb < qb, or kb == qb and lr <= lk + 4 i
+        double mx[4], den[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            mx[i] = -INFINITY;
+#pragma unroll
+            for (int kb = 0; kb <= qb; kb++)
+                if (kb < qb || lr <= lk + 4 * i) mx[i] = fmax(mx[i], st[kb][i]);
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) mx[i] = fmax(mx[i], __shfl_xor(mx[i], off, 16));
+            den[i] = 0.0;
+#pragma unroll
+            for (int kb = 0; kb < 4; kb++) {
+                const double p =
+                    (kb < qb || (kb == qb && lr <= lk + 4 * i)) ? exp((st[kb][i] - mx[i]) * scale) : 0.0;
+                st[kb][i] = p;
+                den[i] += p;
+            }
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) den[i] += __shfl_xor(den[i], off, 16);
+        }
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) P[lk + 4 * i][kb * 16 + lr] = st[kb][i] / den[i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        f64x4 ot = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4 * (qb + 1); kk++)
+            ot = __builtin_amdgcn_mfma_f64_16x16x4f64(P[lr][4 * kk + lk], vf[kk], ot, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int s = qb * 16 + lk + 4 * i;
+            if (s < K) o[(b * K + s) * 64 + hh * 16 + lr] = ot[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    double mx = -INFINITY, den = 0.0;
-    for (int r = 0; r <= s; r++) {
-        const double *kr = k + (b * K + r) * 64 + hh * 16;
-        const double *vr = v + (b * K + r) * 64 + hh * 16;
-        double z = 0.0;
-#pragma unroll
-        for (int c = 0; c < 16; c++) z += qv[c] * kr[c];
-        z *= scale;
-        const double mn = z > mx ? z : mx;
-        const double corr = exp(mx - mn), p = exp(z - mn);
-        den = den * corr + p;
-#pragma unroll
-        for (int c = 0; c < 16; c++) out[c] = out[c] * corr + p * vr[c];
-        mx = mn;
-    }
-    double *os = o + (b * K + s) * 64 + hh * 16;
-#pragma unroll
-    for (int c = 0; c < 16; c++) os[c] = out[c] / den;
 }
 
 // Output head with the logit bias, the mask (Eq. 12, read with the lower
@@ -274,7 +338,7 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
                                kk, d);
             hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wv, d, Lw + LO.bv, R, d, d,
                                v, d);
-            hipLaunchKernelGGL(k64_attention, dim3(blocks_for(B * 4 * K)), dim3(256), 0, st, q, kk, v, B, K, scale, a);
+            hipLaunchKernelGGL(k64_attention, dim3((unsigned)B), dim3(256), 0, st, q, kk, v, B, K, scale, a);
             hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wo, d, Lw + LO.bo, R, d, d,
                                h, d);
             hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,

@@ -288,35 +288,105 @@ __global__ void __launch_bounds__(256) k_screen_infer(int N, const float *__rest
                                                       float *__restrict__ pred) {
     constexpr int H = kScreenH, ZLD = H + 8;
     __shared__ __align__(16) __bf16 zs[4][16 * ZLD];
+    __shared__ __align__(16) float basev[4][H];  // per wave: b1 + W1 rows of the reference configuration
     const int l = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c16 = l & 15, r0 = 4 * (l >> 4), kq = 8 * (l >> 4);
     __bf16 *Z = zs[w];
+    float *bv = basev[w];
     const ScreenOff o = screen_off(N, H);
-    for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * 16; base < n; base += (int64_t)gridDim.x * 64) {
+    // Each wave takes one contiguous run of connections.  The connections of
+    // one sample x are contiguous, and x' differs from x only in the
+    // excitation's bits, so the first layer is b1 + sum_{p in x} W1[p] (kept
+    // in LDS for the run's current x) plus one signed row per flipped bit,
+    // plus the one-hot rows: at most 8 weight rows per connection instead of
+    // one per occupied spin orbital.
+    const int64_t nwaves = (int64_t)gridDim.x * 4, wid = (int64_t)blockIdx.x * 4 + w;
+    const int64_t per = (((n + nwaves - 1) / nwaves) + 15) & ~(int64_t)15;
+    const int64_t beg = wid * per, end = beg + per < n ? beg + per : n;
+    Key ref;
+    ref.lo = ref.hi = 0ull;
+    bool have_ref = false;
+    for (int64_t base = beg; base < end; base += 16) {
         // layer 1: lane (row = c16, quarter = l >> 4) computes 64 of the 256 units of its row
         const int64_t k = base + c16;
-        const bool ok = k < n;
+        const bool ok = k < end;
         Key x;
         x.lo = ok ? keys[2 * k] : 0ull;
         x.hi = ok ? keys[2 * k + 1] : 0ull;
         uint8_t e4[4] = {255, 255, 255, 255};
         if (ok)
             for (int t = 0; t < 4; t++) e4[t] = exc[4 * k + t];
+        // flipped bits (codes below N; a code given twice cancels) and the sample x0 = x' ^ flips
+        Key fm;
+        fm.lo = fm.hi = 0ull;
+        for (int t = 0; t < 4; t++)
+            if (e4[t] < N) key_flip(fm, e4[t]);
+        Key x0;
+        x0.lo = x.lo ^ fm.lo;
+        x0.hi = x.hi ^ fm.hi;
+        // the run's reference sample is that of the group's first row (lane 0)
+        const uint64_t rlo = __builtin_amdgcn_readlane((unsigned long long)x0.lo, 0);
+        const uint64_t rhi = __builtin_amdgcn_readlane((unsigned long long)x0.hi, 0);
+        if (!have_ref || rlo != ref.lo || rhi != ref.hi) {
+            ref.lo = rlo;
+            ref.hi = rhi;
+            have_ref = true;
+            // lane l: units 4 l .. 4 l + 3, coalesced over the rows
+            float s4[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) s4[u] = w32[o.b1 + 4 * l + u];
+            for (int wd = 0; wd < 2; wd++) {
+                uint64_t m = wd ? ref.hi : ref.lo;
+                while (m) {
+                    const int bt = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    const int p = wd * 64 + bt;
+                    if (p >= N) break;  // bits above the spin orbitals carry no input
+                    const float *row = w32 + o.W1 + (int64_t)p * H + 4 * l;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) s4[u] += row[u];
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();  // earlier readers of bv are done
+#pragma unroll
+            for (int u = 0; u < 4; u++) bv[4 * l + u] = s4[u];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
         const int c0 = (l >> 4) * 64;
         float acc[64];
+        if (x0.lo == ref.lo && x0.hi == ref.hi) {
 #pragma unroll
-        for (int c = 0; c < 64; c++) acc[c] = w32[o.b1 + c0 + c];
-        for (int wd = 0; wd < 2; wd++) {
-            uint64_t m = wd ? x.hi : x.lo;
-            while (m) {
-                const int b = __ffsll((unsigned long long)m) - 1;
-                m &= m - 1;
-                const int p = wd * 64 + b;
-                if (p >= N) break;  // bits above the spin orbitals carry no input
-                const float *row = w32 + o.W1 + (int64_t)p * H + c0;
+            for (int c = 0; c < 64; c++) acc[c] = bv[c0 + c];
+            for (int wd = 0; wd < 2; wd++) {
+                uint64_t m = wd ? fm.hi : fm.lo;
+                while (m) {
+                    const int bt = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    const int p = wd * 64 + bt;
+                    const float sg = key_bit(x, p) ? 1.0f : -1.0f;  // bit set in x' (created) or cleared
+                    const float *row = w32 + o.W1 + (int64_t)p * H + c0;
 #pragma unroll
-                for (int c = 0; c < 64; c++) acc[c] += row[c];
+                    for (int c = 0; c < 64; c++) acc[c] = fmaf(sg, row[c], acc[c]);
+                }
+            }
+        } else {  // another sample inside the group: the plain sum over the bits of x'
+#pragma unroll
+            for (int c = 0; c < 64; c++) acc[c] = w32[o.b1 + c0 + c];
+            for (int wd = 0; wd < 2; wd++) {
+                uint64_t m = wd ? x.hi : x.lo;
+                while (m) {
+                    const int bt = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    const int p = wd * 64 + bt;
+                    if (p >= N) break;
+                    const float *row = w32 + o.W1 + (int64_t)p * H + c0;
+#pragma unroll
+                    for (int c = 0; c < 64; c++) acc[c] += row[c];
+                }
             }
         }
         for (int t = 0; t < 4; t++) {
@@ -350,7 +420,7 @@ __global__ void __launch_bounds__(256) k_screen_infer(int N, const float *__rest
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 const int64_t kk = base + r0 + i;
-                if (kk < n) pred[kk] = part[i] + w32[o.b3];
+                if (kk < end) pred[kk] = part[i] + w32[o.b3];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
