@@ -201,20 +201,38 @@ __global__ void k_back_out(const T *__restrict__ a2, const T *__restrict__ gy, c
 
 // column sums (fixed order): out[c] = sum_k M[k][c] (* vec[k] if vec)
 template <typename T>
-__global__ void k_colsum(const T *__restrict__ Mx, const T *__restrict__ vec, int64_t n, int H,
-                         double *__restrict__ out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= H) return;
+__global__ void __launch_bounds__(1024) k_colsum(const T *__restrict__ Mx, const T *__restrict__ vec, int64_t n,
+                                                 int H, double *__restrict__ out) {
+    // out[c] = sum_k Mx[k][c] (* vec[k]): block of 64 columns, 16 row phases
+    // per column, partials combined in a fixed order (deterministic)
+    __shared__ double part[16][64];
+    const int cl = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
     double s = 0.0;
-    for (int64_t k = 0; k < n; k++) s += (double)(vec ? Mx[k * H + c] * vec[k] : Mx[k * H + c]);
-    out[c] = s;
+    if (c < H)
+        for (int64_t k = ph; k < n; k += 16) s += (double)(vec ? Mx[k * H + c] * vec[k] : Mx[k * H + c]);
+    part[ph][cl] = s;
+    __syncthreads();
+    if (ph == 0 && c < H) {
+        double t = 0.0;
+        for (int q = 0; q < 16; q++) t += part[q][cl];
+        out[c] = t;
+    }
 }
 
-template <typename T> __global__ void k_sum(const T *__restrict__ v, int64_t n, double *__restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+template <typename T> __global__ void __launch_bounds__(1024) k_sum(const T *__restrict__ v, int64_t n,
+                                                                    double *__restrict__ out) {
+    // one block; strided partials, then a fixed-order tree
+    __shared__ double part[1024];
     double s = 0.0;
-    for (int64_t k = 0; k < n; k++) s += (double)v[k];
-    *out = s;
+    for (int64_t k = threadIdx.x; k < n; k += 1024) s += (double)v[k];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = part[0];
 }
 
 // d1 = dz1 * GELU'(a1) in place in dz1
@@ -223,22 +241,21 @@ template <typename T> __global__ void k_mul_gelu_grad(T *__restrict__ dz, const 
     if (e < cnt) dz[e] *= gelu_grad_t<T>(a[e]);
 }
 
-// gW1[p][c] = sum over examples with input p active of d1[k][c] (one thread per (p, c))
+// The screen input as a dense 0/1 matrix X[k][p] (p < 5N: bits of x', then
+// the one-hot fields of i, j, a, b), for the first-layer weight gradient
+// gW1 = X^T d1 as a plain product.
 template <typename T>
-__global__ void k_grad_w1(int N, int H, const uint64_t *__restrict__ keys, const uint8_t *__restrict__ exc, int64_t n,
-                          const T *__restrict__ d1, double *__restrict__ g) {
+__global__ void k_screen_input(int N, const uint64_t *__restrict__ keys, const uint8_t *__restrict__ exc, int64_t n,
+                               T *__restrict__ X) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)5 * N * H) return;
-    const int p = (int)(e / H), c = (int)(e % H);
+    if (e >= n * 5 * N) return;
+    const int64_t k = e / (5 * N);
+    const int p = (int)(e - k * 5 * N);
     const int field = p / N, q = p - field * N;
-    double s = 0.0;
-    for (int64_t k = 0; k < n; k++) {
-        bool on;
-        if (field == 0) on = ((q < 64 ? keys[2 * k] : keys[2 * k + 1]) >> (q & 63)) & 1ull;
-        else on = exc[4 * k + field - 1] == q;
-        if (on) s += (double)d1[k * H + c];
-    }
-    g[e] = s;
+    bool on;
+    if (field == 0) on = ((q < 64 ? keys[2 * k] : keys[2 * k + 1]) >> (q & 63)) & 1ull;
+    else on = exc[4 * k + field - 1] == q;
+    X[e] = on ? T(1) : T(0);
 }
 
 template <typename T> __global__ void k_store_grad(const T *__restrict__ s, double *__restrict__ d, int64_t n) {
@@ -472,17 +489,19 @@ __global__ void k_convert_f32(const double *__restrict__ s, float *__restrict__ 
 
 // Forward (and optionally the MSE gradient) in precision T.  Scratch holds
 // a1, z1, a2, d2, z2, dz1 ([n][H] each), y, gy ([n] each), the W2 gradient
-// ([H][H]) and, for FP32, a converted copy of W2 ([H][H]).
+// ([H][H]), for FP32 a converted copy of W2 ([H][H]) and, with the gradient,
+// the dense input X ([n][5N]) and the W1 gradient ([5N][H]).
 template <typename T>
 static nnqs_status screen_fwd_bwd(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, const double *target,
                                   int64_t n, double *pred, double *grad, double *loss, hipStream_t st) {
     const int N = s->N, H = s->H;
     const ScreenOff o = screen_off(N, H);
     const size_t nh = (size_t)n * H, hh = (size_t)H * H;
-    nnqs_status r = ensure_scratch(s, (6 * nh + 2 * (size_t)n + 2 * hh) * sizeof(T) + 256, st);
+    const size_t nx = (size_t)n * 5 * N, xh = (size_t)5 * N * H;
+    nnqs_status r = ensure_scratch(s, (6 * nh + 2 * (size_t)n + 2 * hh + (grad ? nx + xh : 0)) * sizeof(T) + 256, st);
     if (r != NNQS_OK) return r;
     T *a1 = static_cast<T *>(s->scratch), *z1 = a1 + nh, *a2 = z1 + nh, *d2 = a2 + nh, *z2 = d2 + nh, *dz1 = z2 + nh,
-      *y = dz1 + nh, *gy = y + n, *w2c = gy + n, *gw2 = w2c + hh;
+      *y = dz1 + nh, *gy = y + n, *w2c = gy + n, *gw2 = w2c + hh, *xin = gw2 + hh, *gw1 = xin + nx;
     const T *W2;
     if (sizeof(T) == 8) {
         W2 = reinterpret_cast<const T *>(s->w + o.W2);
@@ -504,9 +523,9 @@ static nnqs_status screen_fwd_bwd(nnqs_screen *s, const uint64_t *keys, const ui
                                loss);
         hipLaunchKernelGGL(k_mse_grad<T>, dim3(gridfor(n)), dim3(256), 0, st, y, target, n, gy);
         hipLaunchKernelGGL(k_back_out<T>, dim3(gridfor(nh)), dim3(256), 0, st, a2, gy, s->w, N, H, n, d2, z2);
-        hipLaunchKernelGGL(k_sum<T>, dim3(1), dim3(1), 0, st, gy, n, grad + o.b3);
-        hipLaunchKernelGGL(k_colsum<T>, dim3(gridfor(H)), dim3(256), 0, st, z2, gy, n, H, grad + o.w3);
-        hipLaunchKernelGGL(k_colsum<T>, dim3(gridfor(H)), dim3(256), 0, st, d2, (const T *)nullptr, n, H,
+        hipLaunchKernelGGL(k_sum<T>, dim3(1), dim3(1024), 0, st, gy, n, grad + o.b3);
+        hipLaunchKernelGGL(k_colsum<T>, dim3(gridfor(H, 64)), dim3(1024), 0, st, z2, gy, n, H, grad + o.w3);
+        hipLaunchKernelGGL(k_colsum<T>, dim3(gridfor(H, 64)), dim3(1024), 0, st, d2, (const T *)nullptr, n, H,
                            grad + o.b2);
         // gW2 = z1^T d2 ([H][H])
         hipLaunchKernelGGL(k_gemm<T>, dim3(gridfor(H, 16), gridfor(H, 16)), dim3(256), 0, st, z1, H, true, d2, H,
@@ -517,10 +536,14 @@ static nnqs_status screen_fwd_bwd(nnqs_screen *s, const uint64_t *keys, const ui
         hipLaunchKernelGGL(k_gemm<T>, dim3(gridfor(H, 16), (unsigned)((n + 15) / 16)), dim3(256), 0, st, d2, H,
                            false, W2, H, true, dz1, H, n, H, (int64_t)H);
         hipLaunchKernelGGL(k_mul_gelu_grad<T>, dim3(gridfor(nh)), dim3(256), 0, st, dz1, a1, (int64_t)nh);
-        hipLaunchKernelGGL(k_colsum<T>, dim3(gridfor(H)), dim3(256), 0, st, dz1, (const T *)nullptr, n, H,
+        hipLaunchKernelGGL(k_colsum<T>, dim3(gridfor(H, 64)), dim3(1024), 0, st, dz1, (const T *)nullptr, n, H,
                            grad + o.b1);
-        hipLaunchKernelGGL(k_grad_w1<T>, dim3(gridfor((int64_t)5 * N * H)), dim3(256), 0, st, N, H, keys, exc, n,
-                           dz1, grad + o.W1);
+        // gW1 = X^T d1 ([5N][H])
+        hipLaunchKernelGGL(k_screen_input<T>, dim3(gridfor((int64_t)nx)), dim3(256), 0, st, N, keys, exc, n, xin);
+        hipLaunchKernelGGL(k_gemm<T>, dim3(gridfor(H, 16), gridfor((int64_t)5 * N, 16)), dim3(256), 0, st, xin, 5 * N,
+                           true, dz1, H, false, gw1, H, (int64_t)5 * N, H, n);
+        hipLaunchKernelGGL(k_store_grad<T>, dim3(gridfor((int64_t)xh)), dim3(256), 0, st, gw1, grad + o.W1,
+                           (int64_t)xh);
     }
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;

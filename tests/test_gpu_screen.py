@@ -120,6 +120,35 @@ def test_bf16_inference_error_vs_oracle(nn, n):
     assert np.all(err <= 0.05 + 0.01 * np.abs(ref))
 
 
+def test_bf16_inference_on_contiguous_runs(nn):
+    """Connections in runs of one sample (the layout of the full local
+    energy), with run boundaries off the 16-row groups and a sample that
+    comes back after another: the first layer is then assembled from the
+    sample's sum plus signed flip rows.  The result stays within the BF16
+    bound against the FP64 oracle and agrees with the same rows in shuffled
+    order (every row assembled from its own bits) to FP32 rounding."""
+    K, H = 24, 256
+    N = 2 * K
+    _print_case("screen_bf16_runs", N=N, H=H)
+    d = synth.config_inputs(2, K=K, n_up=6, n_dn=6, n_unique=8)
+    runs = []
+    for k, (a, b) in ((0, (5, 700)), (1, (0, 333)), (2, (17, 420)), (1, (333, 900))):
+        xp, _, exc, _ = oracle.connections(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], 0.0, d["keys"][k])
+        runs.append((xp[a:b], exc[a:b]))
+    keys = np.concatenate([r[0] for r in runs])
+    exc = np.concatenate([r[1] for r in runs])
+    w = _weights(N, H, seed=7)
+    S = nn.Screen(N, H, w)
+    pred = S.forward(dev(keys), dev(exc), nn.NNQS_BF16).cpu().numpy()
+    ref = oracle.screen_forward(N, H, w, keys, exc)
+    err = np.abs(pred - ref)
+    print(f"BF16 screen runs n={len(keys)}: max err {err.max():.3e} over y range [{ref.min():.3f}, {ref.max():.3f}]")
+    assert np.all(err <= 0.05 + 0.01 * np.abs(ref))
+    perm = np.random.default_rng(3).permutation(len(keys))
+    pred_s = S.forward(dev(keys[perm]), dev(exc[perm]), nn.NNQS_BF16).cpu().numpy()
+    assert np.max(np.abs(pred_s - pred[perm])) <= 1e-2
+
+
 def test_screen_shape_errors(nn):
     w = _weights(24, 40, 0)
     S = nn.Screen(24, 40, w)
