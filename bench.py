@@ -79,6 +79,10 @@ def main():
                     help="samples of the N=120 transformer workload timed in the full-E_loc leg (0 = skip)")
     ap.add_argument("--fp64-samples", type=int, default=8,
                     help="of these, samples also evaluated by the plain FP64 path (error reference)")
+    ap.add_argument("--skip-nats", type=float, default=SKIP_NATS,
+                    help="contribution-rule threshold of the screened full path (nats below log|psi(x)|)")
+    ap.add_argument("--refine-nats", type=float, default=REFINE_NATS,
+                    help="FP64 refinement of terms above exp(-r) Ha in the screened full path")
     ap.add_argument("--screen-steps", type=int, default=5000,
                     help="Adam steps of the screen training in the full-E_loc leg")
     ap.add_argument("--batch-systems", type=int, default=0,
@@ -289,9 +293,9 @@ def pauli_leg(args, nn, S, T, keys, cnt, la, ph, n, C, np, torch):
 
 
 # Operating point of the screened full path: skip a connection when its
-# predicted contribution |H_xx' psi(x')/psi(x)| is below exp(-17) Ha, and
+# predicted contribution |H_xx' psi(x')/psi(x)| is below exp(-16.5) Ha, and
 # recompute in FP64 every evaluated term above exp(-7) Ha.
-SKIP_NATS = 17.0
+SKIP_NATS = 16.5
 REFINE_NATS = 7.0
 
 
@@ -321,8 +325,8 @@ def full_path_leg(args, nn, synth, np, torch):
     # RMS falls back to the plain evaluation
     scr_used, rmse = screen_train.screen_or_plain(scr, *held)
     log(f"screen held-out RMSE {rmse:.3f} nats -> {'screened' if scr_used is not None else 'plain fallback'}")
-    screened_kw = dict(screen=scr_used, skip_nats=SKIP_NATS, skip_rule=nn.NNQS_SKIP_CONTRIBUTION,
-                       refine_nats=REFINE_NATS)
+    screened_kw = dict(screen=scr_used, skip_nats=args.skip_nats, skip_rule=nn.NNQS_SKIP_CONTRIBUTION,
+                       refine_nats=args.refine_nats)
 
     def timed(prec, k, c, **kw):
         nn.eloc_model(S, M, k[:1], c[:1], prec, **kw)  # warm scratch
@@ -342,8 +346,8 @@ def full_path_leg(args, nn, synth, np, torch):
            "screened_bf16_refined": {"samples_per_s": n / dts, "connections_per_s": n * C / dts,
                                      "energy": float(ens[0]), "evaluated_fraction": sts["evaluated"] / sts["connections"],
                                      "refined_fraction": sts["refined"] / sts["connections"],
-                                     "skip_rule": "contribution", "skip_nats": SKIP_NATS,
-                                     "refine_nats": REFINE_NATS},
+                                     "skip_rule": "contribution", "skip_nats": args.skip_nats,
+                                     "refine_nats": args.refine_nats},
            "screen_training_s": t_train, "screen_held_out_rmse_nats": rmse,
            "speedup_screened_vs_plain_bf16": dt16 / dts}
     if m > 0:
