@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-samples", type=int, default=8192,
+    ap.add_argument("--cpu-samples", type=int, default=32768,
                     help="samples the oracle evaluates for the CPU baseline (0 = skip)")
     ap.add_argument("--full-samples", type=int, default=16,
                     help="samples of the N=120 transformer workload timed in the full-E_loc leg (0 = skip)")

@@ -13,7 +13,7 @@
 
 namespace nnqs {
 
-constexpr int64_t kF64Batch = 1024;  // configurations per pass
+constexpr int64_t kF64Batch = 4096;  // configurations per pass
 
 __device__ __forceinline__ double gelu_f64(double v) { return 0.5 * v * (1.0 + erf(v * 0.70710678118654752440)); }
 
