@@ -218,35 +218,43 @@ __global__ void __launch_bounds__(256) k64_attention(const double *__restrict__ 
 }
 
 // Output head with the logit bias, the mask (Eq. 12, read with the lower
-// bound too) and the log-probability of the actual token: one thread per
+// bound too) and the log-probability of the actual token: one wave per
 // (config, position).
-__global__ void k64_head(ModelView M, const double *__restrict__ a, const int8_t *__restrict__ tok, int64_t B,
-                         double *__restrict__ lp) {
-    const int K = M.K, d = M.d;
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= B * K) return;
+__global__ void __launch_bounds__(256) k64_head(ModelView M, const double *__restrict__ a,
+                                                const int8_t *__restrict__ tok, int64_t B, double *__restrict__ lp) {
+    // lane = model column (d = 64)
+    const int K = M.K;
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= B * K) return;  // wave-uniform
     const int64_t b = row / K;
     const int s = (int)(row - b * K);
-    int up = 0, dn = 0;
-    for (int r = 0; r < s; r++) {
-        const int t = tok[b * K + r];
-        up += t & 1;
-        dn += t >> 1;
-    }
-    const int rem = K - 1 - s, orb = K - 1 - s;
+    // electrons placed before position s (lanes r < s hold token r)
+    const int tr = lane < s ? tok[b * K + lane] : 0;
+    const int up = __popcll(__ballot(tr & 1)), dn = __popcll(__ballot(tr >> 1));
     const double *W = M.w64;
+    const double av = a[row * 64 + lane];
     double z[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        double v = av * W[M.off.head_w + lane * 4 + t];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        z[t] = v;
+    }
+    if (lane != 0) return;
+    const int rem = K - 1 - s, orb = K - 1 - s;
     bool ok[4];
     double mx = -INFINITY;
+#pragma unroll
     for (int t = 0; t < 4; t++) {
-        double acc = W[M.off.head_b + t] + W[M.off.bias + orb * 4 + t];
-        for (int c = 0; c < d; c++) acc += a[row * d + c] * W[M.off.head_w + c * 4 + t];
-        z[t] = acc;
+        z[t] += W[M.off.head_b + t] + W[M.off.bias + orb * 4 + t];
         const int bu = t & 1, bd = t >> 1;
         ok[t] = (up + bu <= M.n_up) && (dn + bd <= M.n_dn) && (M.n_up - up - bu <= rem) && (M.n_dn - dn - bd <= rem);
         if (ok[t] && z[t] > mx) mx = z[t];
     }
     double den = 0.0;
+#pragma unroll
     for (int t = 0; t < 4; t++)
         if (ok[t]) den += exp(z[t] - mx);
     const int ts = tok[row];
@@ -350,7 +358,7 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
         }
         hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, W + M.off.lnf_g,
                            W + M.off.lnf_b, R, a);
-        hipLaunchKernelGGL(k64_head, dim3(blocks_for(R)), dim3(256), 0, st, M, a, tok, B, lp);
+        hipLaunchKernelGGL(k64_head, dim3(blocks_for(R, 4)), dim3(256), 0, st, M, a, tok, B, lp);
         double *z1 = f, *z2 = f + (size_t)B * P;
         hipLaunchKernelGGL(k64_phase1, dim3(blocks_for(B * P)), dim3(256), 0, st, M, keys + 2 * b0, B, z1);
         hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((P + 63) / 64), (unsigned)((B + 63) / 64)), dim3(256), 0, st,
