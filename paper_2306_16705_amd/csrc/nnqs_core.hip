@@ -120,8 +120,12 @@ __global__ void k_bitonic_local(uint64_t *__restrict__ sk, uint32_t *__restrict_
         li[e] = si[base + e];
     }
     __syncthreads();
+    // A stage with stride j <= 64 pairs only elements of the 128-element
+    // block of one wave (thread t takes pair t), so two consecutive such
+    // stages need no block barrier, only the wave's own LDS ordering.
     for (int64_t k = k_lo; k <= k_hi; k <<= 1) {
         for (int64_t j = (k == k_lo ? j_start : k >> 1); j >= 1; j >>= 1) {
+            const int64_t jn = j > 1 ? j >> 1 : (k < k_hi ? k : 0);  // stride of the next stage (0: none)
             for (int t = threadIdx.x; t < tile / 2; t += blockDim.x) {
                 int i = (int)(((t & ~(j - 1)) << 1) | (t & (j - 1)));
                 int l = i + (int)j;
@@ -138,7 +142,13 @@ __global__ void k_bitonic_local(uint64_t *__restrict__ sk, uint32_t *__restrict_
                     li[l] = ai;
                 }
             }
-            __syncthreads();
+            if (j > 64 || jn > 64 || jn == 0 || tile / 2 > (int)blockDim.x) {
+                __syncthreads();
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
         }
     }
     for (int e = threadIdx.x; e < tile; e += blockDim.x) {
