@@ -34,7 +34,11 @@ def _random_connected(d, n_samples, per_sample, seed):
 
 
 @pytest.mark.parametrize("kw", [dict(cfg=1, model=True), dict(cfg=2, K=12, n_up=4, n_dn=3, n_unique=200, model=True),
-                                dict(cfg=3, n_unique=8)])
+                                dict(cfg=3, n_unique=8),
+                                # the largest sequence (64 positions, no padding rows, two-word keys)
+                                dict(cfg=2, K=64, n_up=8, n_dn=8, n_unique=40, model=True),
+                                # more configurations than one FP64 pass takes (4,096), ragged tail
+                                dict(cfg=2, K=16, n_up=3, n_dn=5, n_unique=5000, model=True)])
 def test_logpsi_fp64_matches_oracle(nn, kw):
     kw = dict(kw)
     cfg = kw.pop("cfg")
@@ -90,7 +94,9 @@ def test_eloc_model_whole_sector_equals_table_path(nn):
     assert np.max(np.abs(a - b)) <= 1e-11 * max(1.0, np.abs(a).max())
 
 
-@pytest.mark.parametrize("kw", [dict(cfg=1, model=True), dict(cfg=3, n_unique=16)])
+@pytest.mark.parametrize("kw", [dict(cfg=1, model=True), dict(cfg=3, n_unique=16),
+                                dict(cfg=2, K=64, n_up=8, n_dn=8, n_unique=64, model=True),
+                                dict(cfg=2, K=16, n_up=3, n_dn=5, n_unique=37, model=True)])
 def test_logpsi_bf16_error_vs_oracle(nn, kw):
     """BF16 MFMA forward: the error against the FP64 oracle is measured and
     bounded (|d log|psi|| <= 0.02 + 1e-3 |log|psi||, |d phase| <= 0.02)."""
