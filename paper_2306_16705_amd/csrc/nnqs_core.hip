@@ -106,6 +106,52 @@ __global__ void k_bitonic_global(uint64_t *__restrict__ sk, uint32_t *__restrict
     }
 }
 
+// Two consecutive global stages (k, j) and (k, j/2) in one pass: thread t
+// owns the four elements a, a + h, a + 2h, a + 3h (h = j/2; a has bits h and
+// j clear), which both stages only compare among themselves.
+__device__ __forceinline__ void bitonic_cas(uint64_t &alo, uint64_t &ahi, uint32_t &ai, uint64_t &blo, uint64_t &bhi,
+                                            uint32_t &bi, bool asc) {
+    if (elem_greater(ahi, alo, ai, bhi, blo, bi) == asc) {
+        uint64_t tl = alo, th = ahi;
+        uint32_t ti = ai;
+        alo = blo;
+        ahi = bhi;
+        ai = bi;
+        blo = tl;
+        bhi = th;
+        bi = ti;
+    }
+}
+__global__ void k_bitonic_global2(uint64_t *__restrict__ sk, uint32_t *__restrict__ si, int64_t P, int64_t k,
+                                  int64_t j) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P / 4) return;
+    const int64_t h = j >> 1;
+    const int64_t a = ((t & ~(h - 1)) << 2) | (t & (h - 1));
+    const bool asc = (a & k) == 0;
+    uint64_t lo[4], hi[4];
+    uint32_t ix[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int64_t e = a + q * h;
+        lo[q] = sk[2 * e];
+        hi[q] = sk[2 * e + 1];
+        ix[q] = si[e];
+    }
+    // stage j: (0, 2), (1, 3); stage j/2: (0, 1), (2, 3)
+    bitonic_cas(lo[0], hi[0], ix[0], lo[2], hi[2], ix[2], asc);
+    bitonic_cas(lo[1], hi[1], ix[1], lo[3], hi[3], ix[3], asc);
+    bitonic_cas(lo[0], hi[0], ix[0], lo[1], hi[1], ix[1], asc);
+    bitonic_cas(lo[2], hi[2], ix[2], lo[3], hi[3], ix[3], asc);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int64_t e = a + q * h;
+        sk[2 * e] = lo[q];
+        sk[2 * e + 1] = hi[q];
+        si[e] = ix[q];
+    }
+}
+
 // All stages with j < tile inside one LDS tile.  Runs k = k_lo..k_hi
 // (powers of two); the first k starts at j = j_start, later ones at k/2.
 __global__ void k_bitonic_local(uint64_t *__restrict__ sk, uint32_t *__restrict__ si, int tile, int64_t k_lo,
@@ -561,7 +607,11 @@ nnqs_status nnqs_table_build(nnqs_table *t, const uint64_t *keys, const double *
     hipLaunchKernelGGL(k_bitonic_local, dim3((unsigned)(P / tile)), dim3(lthreads), lds, st, t->sort_keys, t->sort_idx,
                        tile, (int64_t)2, (int64_t)tile, (int64_t)1);
     for (int64_t k = (int64_t)tile * 2; k <= P; k <<= 1) {
-        for (int64_t j = k >> 1; j >= tile; j >>= 1)
+        int64_t j = k >> 1;
+        for (; j >= 2 * (int64_t)tile; j >>= 2)  // stages j and j/2 together
+            hipLaunchKernelGGL(k_bitonic_global2, dim3((unsigned)((P / 4 + thr - 1) / thr)), dim3(thr), 0, st,
+                               t->sort_keys, t->sort_idx, P, k, j);
+        if (j >= tile)
             hipLaunchKernelGGL(k_bitonic_global, dim3((unsigned)((P / 2 + thr - 1) / thr)), dim3(thr), 0, st,
                                t->sort_keys, t->sort_idx, P, k, j);
         hipLaunchKernelGGL(k_bitonic_local, dim3((unsigned)(P / tile)), dim3(lthreads), lds, st, t->sort_keys,
