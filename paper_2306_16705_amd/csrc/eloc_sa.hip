@@ -770,6 +770,8 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
         while (elds > (size_t)sys->max_lds && efl > 10) elds = sa_lds_bytes(--efl, tv.split_levels, W, ew);
         const void *efn = W == 1 ? reinterpret_cast<const void *>(k_eloc_sa_exact<1>)
                                  : reinterpret_cast<const void *>(k_eloc_sa_exact<2>);
+        const nnqs_status se = sa_check_no_spill(efn);
+        if (se != NNQS_OK) return se;
         NNQS_HIP_CHECK(hipFuncSetAttribute(efn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)elds));
         const dim3 eg((unsigned)sys->cu_count), eb(ew * 64);
         if (W == 1)

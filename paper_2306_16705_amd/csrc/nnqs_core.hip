@@ -314,56 +314,23 @@ __global__ void k_table_split(const uint64_t *__restrict__ keys, int64_t n, int 
 }
 
 // ----------------------------------------------------- energy reduction
-// Stage 1: each block reduces a strided share of samples into compensated
-// partial sums of (c, c Re, c Im, c Re^2).
-__global__ void __launch_bounds__(256) k_energy_partial(const uint32_t *__restrict__ counts,
-                                                        const double *__restrict__ eloc, int64_t n,
-                                                        double *__restrict__ partials) {
-    NSum acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
-        double c = (double)counts[k];
-        double re = eloc[2 * k], im = eloc[2 * k + 1];
-        acc[0].add(c);
-        acc[1].add(c * re);
-        acc[2].add(c * im);
-        acc[3].add(c * re * re);
-    }
-    __shared__ double sh[256][8];
-    for (int q = 0; q < 4; q++) {
+// Eq. 6 over unique samples in two passes, each a deterministic compensated
+// tree: pass 1 sums (c, c Re, c Im) and fixes E = sum c Re / sum c; pass 2
+// sums c (Re - E)^2 with E read back from the device, so the variance keeps
+// its digits as it approaches zero (an eigenstate gives E_loc = E for every
+// sample).  Each pass: every block reduces a strided share of the samples
+// into partials (value and compensation per quantity), one block folds them
+// in a fixed order.
+template <int Q>
+__device__ __forceinline__ void block_fold(NSum (&acc)[Q], double (*sh)[8]) {
+    for (int q = 0; q < Q; q++) {
         sh[threadIdx.x][2 * q] = acc[q].s;
         sh[threadIdx.x][2 * q + 1] = acc[q].c;
     }
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
         if ((int)threadIdx.x < w) {
-            for (int q = 0; q < 4; q++) {
-                double s = sh[threadIdx.x][2 * q], c = sh[threadIdx.x][2 * q + 1];
-                nsum_merge(s, c, sh[threadIdx.x + w][2 * q], sh[threadIdx.x + w][2 * q + 1]);
-                sh[threadIdx.x][2 * q] = s;
-                sh[threadIdx.x][2 * q + 1] = c;
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < 8) partials[blockIdx.x * 8 + threadIdx.x] = sh[0][threadIdx.x];
-}
-
-// Stage 2: one block folds the partials in a fixed order.
-__global__ void __launch_bounds__(256) k_energy_final(const double *__restrict__ partials, int nblocks,
-                                                      double *__restrict__ energy) {
-    __shared__ double sh[256][8];
-    double s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-        for (int q = 0; q < 4; q++) nsum_merge(s[q], c[q], partials[b * 8 + 2 * q], partials[b * 8 + 2 * q + 1]);
-    for (int q = 0; q < 4; q++) {
-        sh[threadIdx.x][2 * q] = s[q];
-        sh[threadIdx.x][2 * q + 1] = c[q];
-    }
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            for (int q = 0; q < 4; q++) {
+            for (int q = 0; q < Q; q++) {
                 double a = sh[threadIdx.x][2 * q], ac = sh[threadIdx.x][2 * q + 1];
                 nsum_merge(a, ac, sh[threadIdx.x + w][2 * q], sh[threadIdx.x + w][2 * q + 1]);
                 sh[threadIdx.x][2 * q] = a;
@@ -372,26 +339,80 @@ __global__ void __launch_bounds__(256) k_energy_final(const double *__restrict__
         }
         __syncthreads();
     }
+}
+
+// Pass 1, stage 1: partials of (c, c Re, c Im), six doubles per block.
+__global__ void __launch_bounds__(256) k_energy_partial(const uint32_t *__restrict__ counts,
+                                                        const double *__restrict__ eloc, int64_t n,
+                                                        double *__restrict__ partials) {
+    __shared__ double sh[256][8];
+    NSum acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const double c = (double)counts[k];
+        acc[0].add(c);
+        acc[1].add(c * eloc[2 * k]);
+        acc[2].add(c * eloc[2 * k + 1]);
+    }
+    block_fold<3>(acc, sh);
+    if (threadIdx.x < 6) partials[blockIdx.x * 8 + threadIdx.x] = sh[0][threadIdx.x];
+}
+
+// Pass 1, stage 2: E, Im and the weight sum into energy[0..2].
+__global__ void __launch_bounds__(256) k_energy_mean(const double *__restrict__ partials, int nblocks,
+                                                     double *__restrict__ energy) {
+    __shared__ double sh[256][8];
+    NSum acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int q = 0; q < 3; q++) nsum_merge(acc[q].s, acc[q].c, partials[b * 8 + 2 * q], partials[b * 8 + 2 * q + 1]);
+    block_fold<3>(acc, sh);
     if (threadIdx.x == 0) {
-        double W = sh[0][0] + sh[0][1];
-        double SR = sh[0][2] + sh[0][3];
-        double SI = sh[0][4] + sh[0][5];
-        double S2 = sh[0][6] + sh[0][7];
-        double E = SR / W;
-        energy[0] = E;
-        energy[1] = SI / W;
+        const double W = sh[0][0] + sh[0][1];
+        energy[0] = (sh[0][2] + sh[0][3]) / W;
+        energy[1] = (sh[0][4] + sh[0][5]) / W;
         energy[2] = W;
-        energy[3] = (S2 - SR * E) / W;
     }
 }
 
+// Pass 2, stage 1: partials of c (Re - E)^2, E = energy[0].
+__global__ void __launch_bounds__(256) k_energy_var_partial(const uint32_t *__restrict__ counts,
+                                                            const double *__restrict__ eloc, int64_t n,
+                                                            const double *__restrict__ energy,
+                                                            double *__restrict__ partials) {
+    __shared__ double sh[256][8];
+    NSum acc[1] = {{0, 0}};
+    const double E = energy[0];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const double d = eloc[2 * k] - E;
+        acc[0].add((double)counts[k] * d * d);
+    }
+    block_fold<1>(acc, sh);
+    if (threadIdx.x < 2) partials[blockIdx.x * 8 + threadIdx.x] = sh[0][threadIdx.x];
+}
+
+// Pass 2, stage 2: the variance into energy[3].
+__global__ void __launch_bounds__(256) k_energy_var(const double *__restrict__ partials, int nblocks,
+                                                    double *__restrict__ energy) {
+    __shared__ double sh[256][8];
+    NSum acc[1] = {{0, 0}};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) nsum_merge(acc[0].s, acc[0].c, partials[b * 8], partials[b * 8 + 1]);
+    block_fold<1>(acc, sh);
+    if (threadIdx.x == 0) energy[3] = (sh[0][0] + sh[0][1]) / energy[2];
+}
+
+// Enqueues both passes with `partials` (>= 8 * kPartialBlocks doubles) as
+// scratch; the second pass reuses it after the first has been folded.
 nnqs_status enqueue_energy_partials(double *partials, const uint32_t *counts, const double *eloc, int64_t n,
                                     double *energy, hipStream_t st) {
     int64_t blocks = (n + 1023) / 1024;
     if (blocks < 1) blocks = 1;
     if (blocks > kPartialBlocks) blocks = kPartialBlocks;
     hipLaunchKernelGGL(k_energy_partial, dim3((unsigned)blocks), dim3(256), 0, st, counts, eloc, n, partials);
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, partials, (int)blocks, energy);
+    hipLaunchKernelGGL(k_energy_mean, dim3(1), dim3(256), 0, st, partials, (int)blocks, energy);
+    hipLaunchKernelGGL(k_energy_var_partial, dim3((unsigned)blocks), dim3(256), 0, st, counts, eloc, n,
+                       (const double *)energy, partials);
+    hipLaunchKernelGGL(k_energy_var, dim3(1), dim3(256), 0, st, partials, (int)blocks, energy);
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
 }
@@ -685,5 +706,6 @@ nnqs_status nnqs_energy(nnqs_table *t, const uint32_t *counts, const double *elo
     if (n <= 0) return fail(NNQS_EINVAL, "n must be positive");
     return enqueue_energy(t, counts, eloc, n, energy, as_stream(stream));
 }
+
 
 }  // extern "C"
