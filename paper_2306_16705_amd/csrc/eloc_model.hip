@@ -19,6 +19,7 @@ namespace nnqs {
 
 constexpr int kConnPerBlock = 4096;            // connections handled by one block
 constexpr int64_t kMaxChunkConnections = 1 << 24;
+constexpr int64_t kMaxChunkSamplesBf16 = 4096;  // samples whose key / value cache is kept at once
 
 __global__ void __launch_bounds__(256) k_enum_keys(SysView S, const uint64_t *__restrict__ keys, int64_t m,
                                                    int64_t blocks_per_sample, uint64_t *__restrict__ out,
@@ -154,6 +155,129 @@ __global__ void k_scatter_sel(const int32_t *__restrict__ sel, const int64_t *__
     xph[sel[k]] = cph[k];
 }
 
+// ------------------------------------------------ prefix classes (BF16)
+// Class of a connection x' of sample x for the prefix-reusing BF16 forward:
+// min(3, s0 / 16) with s0 the first sequence position whose token differs
+// (position s holds orbital K-1-s, so s0 = K-1-(highest differing orbital);
+// the diagonal has none and gets min(3, K / 16)).
+__device__ __forceinline__ int conn_class(int K, const uint64_t *x, const uint64_t *xp) {
+    const uint64_t d0 = x[0] ^ xp[0], d1 = x[1] ^ xp[1];
+    const int p = d1 ? 127 - __clzll(d1) : (d0 ? 63 - __clzll(d0) : -2);
+    const int s0 = K - 1 - (p >> 1);
+    return s0 >= 48 ? 3 : s0 >> 4;
+}
+
+struct ClsArgs {
+    SelRule R;                  // keep rule, used when `rule`
+    bool rule;
+    const uint64_t *keys;       // chunk samples [m][2]
+    const uint64_t *xkeys;      // chunk connections [m*C][2]
+    int64_t total;
+    int K;
+};
+
+__device__ __forceinline__ bool cls_keep(const ClsArgs &a, int64_t e) { return !a.rule || sel_keep(a.R, e); }
+
+// Kept connections per class in each block of kSelBlock connections.
+__global__ void __launch_bounds__(256) k_cls_count(ClsArgs a, int32_t *__restrict__ cnt) {
+    __shared__ int sh[4][256];
+    const int64_t b0 = (int64_t)blockIdx.x * kSelBlock;
+    int c[4] = {0, 0, 0, 0};
+    for (int64_t e = b0 + threadIdx.x; e < b0 + kSelBlock && e < a.total; e += 256) {
+        if (!cls_keep(a, e)) continue;
+        const int64_t smp = e / a.R.C;
+        const int k = conn_class(a.K, a.keys + 2 * smp, a.xkeys + 2 * e);
+        c[0] += k == 0;
+        c[1] += k == 1;
+        c[2] += k == 2;
+        c[3] += k == 3;
+    }
+    for (int k = 0; k < 4; k++) sh[k][threadIdx.x] = c[k];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 4; k++) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) cnt[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Turns the per-block counts into absolute list positions (classes stored
+// one after another), writes hdr = {count[4], offset[4]} and adds the kept
+// total to *evaluated.  One block; each thread scans a contiguous run of
+// blocks.
+__global__ void __launch_bounds__(256) k_cls_scan(int32_t *__restrict__ cnt, int nblocks, int64_t *__restrict__ hdr,
+                                                  int64_t *__restrict__ evaluated) {
+    __shared__ int64_t part[4][257];
+    const int per = (nblocks + 255) / 256;
+    const int b0 = threadIdx.x * per, b1 = min(nblocks, b0 + per);
+    int64_t run[4] = {0, 0, 0, 0};
+    for (int b = b0; b < b1; b++)
+        for (int k = 0; k < 4; k++) run[k] += cnt[b * 4 + k];
+    for (int k = 0; k < 4; k++) part[k][threadIdx.x + 1] = run[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        part[k][0] = 0;
+        for (int t = 1; t <= 256; t++) part[k][t] += part[k][t - 1];
+    }
+    __syncthreads();
+    int64_t off[4], tot[4];
+    int64_t acc = 0;
+    for (int k = 0; k < 4; k++) {
+        tot[k] = part[k][256];
+        off[k] = acc;
+        acc += tot[k];
+    }
+    int64_t pos[4];
+    for (int k = 0; k < 4; k++) pos[k] = off[k] + part[k][threadIdx.x];
+    for (int b = b0; b < b1; b++)
+        for (int k = 0; k < 4; k++) {
+            const int v = cnt[b * 4 + k];
+            cnt[b * 4 + k] = (int32_t)pos[k];
+            pos[k] += v;
+        }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 4; k++) {
+            hdr[k] = tot[k];
+            hdr[4 + k] = off[k];
+        }
+        if (evaluated) *evaluated += acc;
+    }
+}
+
+// One wave walks its block's connections in order and appends the kept ones
+// to their class list (ballots keep canonical order within a class).  With
+// `clear`, connections left out get log|psi| = -inf (they contribute zero).
+__global__ void __launch_bounds__(64) k_cls_write(ClsArgs a, const int32_t *__restrict__ pos0,
+                                                  int32_t *__restrict__ list, bool clear, double *__restrict__ xla,
+                                                  double *__restrict__ xph) {
+    const int lane = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * kSelBlock;
+    int64_t pos[4];
+    for (int k = 0; k < 4; k++) pos[k] = pos0[blockIdx.x * 4 + k];
+    for (int64_t e0 = b0; e0 < b0 + kSelBlock && e0 < a.total; e0 += 64) {
+        const int64_t e = e0 + lane;
+        int k = -1;
+        if (e < a.total && e < b0 + kSelBlock) {
+            if (cls_keep(a, e)) {
+                const int64_t smp = e / a.R.C;
+                k = conn_class(a.K, a.keys + 2 * smp, a.xkeys + 2 * e);
+            } else if (clear) {
+                xla[e] = -INFINITY;
+                xph[e] = 0.0;
+            }
+        }
+        for (int q = 0; q < 4; q++) {
+            const uint64_t m = __ballot(k == q);
+            if (k == q) list[pos[q] + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)e;
+            pos[q] += __popcll(m);
+        }
+    }
+}
+
+__global__ void k_zero_i64(int64_t *p) { *p = 0; }
+
 __global__ void __launch_bounds__(256) k_eloc_partial(SysView S, const uint64_t *__restrict__ keys,
                                                       const double *__restrict__ sla,
                                                       const double *__restrict__ sph, int64_t m,
@@ -260,6 +384,14 @@ void eloc_model_free(nnqs_model *m) {
     hipFree(m->d_cla);
     hipFree(m->d_cph);
     hipFree(m->d_nsel);
+    hipFree(m->d_kv);
+    hipFree(m->d_pre);
+    hipFree(m->d_csla);
+    hipFree(m->d_hdr);
+    m->d_kv = nullptr;
+    m->d_pre = m->d_csla = nullptr;
+    m->d_hdr = nullptr;
+    m->kvcap = 0;
     m->d_xexc = nullptr;
     m->d_pred = nullptr;
     m->d_sel = m->d_blockcnt = nullptr;
@@ -332,8 +464,10 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (h) return fail(h, "a sample violates the particle numbers");
     }
     const int64_t C = sys->view.C;
+    const bool bf16 = precision == NNQS_BF16;
     int64_t chunk = kMaxChunkConnections / C;
     if (chunk < 1) chunk = 1;
+    if (bf16 && chunk > kMaxChunkSamplesBf16) chunk = kMaxChunkSamplesBf16;  // bounds the key / value cache
     if (chunk > n) chunk = n;
     const int64_t bps = (C + kConnPerBlock - 1) / kConnPerBlock;
     if (model->xcap < chunk * C) {
@@ -349,16 +483,29 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_pred), cc * 4);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_loghx), cc * 4);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_sel), cc * 4);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_blockcnt), (cc / kSelBlock + 2) * 4);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_blockcnt), (cc / kSelBlock + 2) * 16);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_ckeys), cc * 16);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cla), cc * 8);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cph), cc * 8);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_nsel), 8);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_hdr), 16 * 8);
         if (s1 != NNQS_OK) {
             eloc_model_free(model);
             return s1;
         }
         model->xcap = chunk * C;
+    }
+    if (bf16 && model->kvcap < chunk) {
+        NNQS_HIP_CHECK(hipStreamSynchronize(st));
+        nnqs_status s1 =
+            grow(reinterpret_cast<void **>(&model->d_kv), (size_t)chunk * bf16_cache_elems(model) * sizeof(__bf16));
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_pre), (size_t)chunk * 4 * 8);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_csla), (size_t)chunk * 8);
+        if (s1 != NNQS_OK) {
+            eloc_model_free(model);
+            return s1;
+        }
+        model->kvcap = chunk;
     }
     if (model->scap < n) {
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
@@ -375,6 +522,8 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         enqueue_logpsi(model, keys, n, refine ? NNQS_FP64 : precision, model->d_sla, model->d_sph, st);
     if (s1 != NNQS_OK) return s1;
     int64_t evaluated = 0, refined = 0;
+    int64_t *d_evalcnt = model->d_hdr + 8;
+    if (bf16) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, st, d_evalcnt);
     for (int64_t s0 = 0; s0 < n; s0 += chunk) {
         const int64_t m = n - s0 < chunk ? n - s0 : chunk;
         const int64_t total = m * C;
@@ -382,7 +531,35 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         hipLaunchKernelGGL(k_enum_keys, dim3(grid), dim3(256), 0, st, sys->view, keys + 2 * s0, m, bps,
                            model->d_xkeys, screen ? model->d_xexc : (uint8_t *)nullptr,
                            need_lh ? model->d_loghx : (float *)nullptr);
-        if (!screen) {
+        if (bf16) {
+            // the chunk's samples once through the forward, keeping their keys,
+            // values and log-probability prefix sums; then every kept x'
+            // evaluates only the row blocks from its first changed position on
+            s1 = enqueue_bf16_cached(model, keys + 2 * s0, m, model->d_csla, model->d_kv, model->d_pre, st);
+            if (s1 != NNQS_OK) return s1;
+            if (screen) {
+                s1 = screen_infer(screen, model->d_xkeys, model->d_xexc, total, model->d_pred, st);
+                if (s1 != NNQS_OK) return s1;
+            }
+            ClsArgs ca{};
+            ca.R = SelRule{screen ? model->d_pred : nullptr, nullptr,
+                           screen && o.skip_rule == NNQS_SKIP_CONTRIBUTION ? model->d_loghx : nullptr,
+                           model->d_sla + s0, C, o.skip_nats};
+            ca.rule = screen != nullptr;
+            ca.keys = keys + 2 * s0;
+            ca.xkeys = model->d_xkeys;
+            ca.total = total;
+            ca.K = sys->view.K;
+            const int nb = (int)((total + kSelBlock - 1) / kSelBlock);
+            hipLaunchKernelGGL(k_cls_count, dim3(nb), dim3(256), 0, st, ca, model->d_blockcnt);
+            hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, model->d_blockcnt, nb, model->d_hdr, d_evalcnt);
+            hipLaunchKernelGGL(k_cls_write, dim3(nb), dim3(64), 0, st, ca, model->d_blockcnt, model->d_sel,
+                               screen != nullptr, model->d_xla, model->d_xph);
+            NNQS_HIP_CHECK(hipGetLastError());
+            s1 = enqueue_bf16_list(model, model->d_xkeys, C, model->d_sel, model->d_hdr, total, model->d_kv,
+                                   model->d_pre, model->d_xla, model->d_xph, st);
+            if (s1 != NNQS_OK) return s1;
+        } else if (!screen) {
             s1 = enqueue_logpsi(model, model->d_xkeys, total, precision, model->d_xla, model->d_xph, st);
             if (s1 != NNQS_OK) return s1;
             evaluated += total;
@@ -415,6 +592,7 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (s1 != NNQS_OK) return s1;
     }
     if (stats) {
+        if (bf16) NNQS_HIP_CHECK(hipMemcpyAsync(&evaluated, d_evalcnt, 8, hipMemcpyDeviceToHost, st));
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
         stats->connections = n * C;
         stats->evaluated = evaluated;

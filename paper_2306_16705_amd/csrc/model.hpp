@@ -74,6 +74,13 @@ struct nnqs_model {
     uint64_t *d_ckeys = nullptr;    // compacted survivor keys
     double *d_cla = nullptr, *d_cph = nullptr;
     int64_t *d_nsel = nullptr;
+    // prefix-reusing BF16 path (eloc_model.hip): the chunk samples' key /
+    // value cache and prefix sums, their BF16 log|psi|, the class header
+    // {count[4], offset[4]} and the evaluated-connection counter
+    __bf16 *d_kv = nullptr;
+    double *d_pre = nullptr, *d_csla = nullptr;
+    int64_t *d_hdr = nullptr;
+    int64_t kvcap = 0;
 };
 
 namespace nnqs {
@@ -84,6 +91,17 @@ nnqs_status bf16_model_init(nnqs_model *m, const float *weights);
 void bf16_model_free(nnqs_model *m);
 nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs,
                                 double *phase, hipStream_t st);
+// BF16 cache of sample-mode forwards for the prefix-reusing list mode: per
+// configuration bf16_cache_elems(m) BF16 values (keys and values of every
+// layer and head) and 4 doubles of prefix log-probability sums.
+int64_t bf16_cache_elems(const nnqs_model *m);
+nnqs_status enqueue_bf16_cached(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, __bf16 *kv,
+                                double *pre, hipStream_t st);
+// log|psi| and phase of the connections listed by class (hdr on the device:
+// count[4], offset[4]; at most max_entries in total) into xla / xph.
+nnqs_status enqueue_bf16_list(const nnqs_model *m, const uint64_t *xkeys, int64_t C, const int32_t *list,
+                              const int64_t *hdr, int64_t max_entries, const __bf16 *kv, const double *pre,
+                              double *xla, double *xph, hipStream_t st);
 void eloc_model_free(nnqs_model *m);
 bool f64_shape_ok(const nnqs_model_desc &m);
 nnqs_status enqueue_logpsi_f64(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, double *phase,

@@ -142,31 +142,80 @@ __device__ __forceinline__ void stage_rows(__bf16 *dst, int lld, const __bf16 *s
 }
 
 // ------------------------------------------------------ transformer forward
-// Two waves per configuration: wave half hf owns row blocks {hf, 3 - hf}
-// (16 rows each), which balances the causal attention (row block b attends
-// to b + 1 key blocks, and 1 + 4 = 2 + 3).  Eight waves per block serve four
-// configurations.  With half the rows a wave holds half the residual stream
-// and half the FFN tile, so two waves share a SIMD and hide each other's LDS,
-// MFMA and barrier latency (one configuration per wave leaves one wave per
-// SIMD).  The LayerNorm, attention and GELU outputs are per row and stay with
-// the wave that owns the rows; only each head's K and V cross between the
-// two waves, with block barriers around the attention of every head.
-constexpr int kRsWaves = 8;             // waves per block
-constexpr int kRsCfg = kRsWaves / 2;    // configurations per block
-
-struct Tile32 {
-    f32x4 t[8];  // tile (j, cb) = t[j * 4 + cb]: own row block j, column block cb
+// Work of one launch, in one of two modes.
+//  * Sample mode: configurations keys[0..n), every row evaluated; log|psi|
+//    to logabs[i].  With `kv_out` and `pre_out` it also keeps, per configuration,
+//    every layer's keys and values (BF16, as the attention used them) and the
+//    prefix sums pre[i][b] of its per-position log-probabilities over the
+//    first 16 b positions: the cache that list mode reads.
+//  * List mode: connected configurations x' of cached samples, as chunk-local
+//    connection indices e (key xkeys[e], sample e / C) sorted into four
+//    classes (hdr = {count[4], offset[4]} on the device).  Class b holds the
+//    x' whose first position that differs from their sample lies at or after
+//    16 b: by causality the rows s <= 16 b of x' equal the sample's, so only
+//    row blocks b..3 are evaluated; their attention reads the keys and values
+//    of blocks < b from the sample's cache, and the log-probabilities of
+//    positions < 16 b are the sample's prefix sum.  log|psi| goes to xla[e].
+//    Results are bit-identical to sample mode on x' (same per-row arithmetic,
+//    same summation order).
+struct TfArgs {
+    const uint64_t *keys;
+    int64_t n;
+    double *logabs;
+    __bf16 *kv_out;        // sample mode: cache written (may be null)
+    double *pre_out;
+    const __bf16 *kv_in;   // list mode: cache read
+    const double *pre_in;
+    const int32_t *list;
+    const int64_t *hdr;
+    const uint64_t *xkeys;
+    int64_t C;
+    double *xla;
+    int list_mode;
 };
 
-// acc += X[own rows][0..k_len) (LDS, BF16, row stride kLd) @ W, Wt[n][k] in LDS.
-__device__ __forceinline__ void gemm_rows(Tile32 &acc, const __bf16 *X, int rb0, int rb1, const __bf16 *Wt, int wld,
-                                          int k_len) {
+// A block evaluates one tile of 16 row-block slots (16 rows each), two per
+// wave.  Class-0 tiles hold four configurations, wave pair (2c, 2c+1) owning
+// configuration c's row blocks {0, 3} and {1, 2} (row block b attends to
+// b + 1 key blocks, and 1 + 4 = 2 + 3); class b > 0 tiles hold
+// floor(16 / (4 - b)) configurations whose blocks b..3 fill consecutive slots.
+constexpr int kSlots = 16;
+constexpr int kVLd = 24;  // padded row length of a slot's V^T (16 keys)
+constexpr int kKvPerHead = 64 * kDh + kDh * 64;  // cached K [64][16] then V^T [16][64]
+
+__device__ __forceinline__ int cls_cpt(int cls) { return cls == 0 ? 4 : cls == 1 ? 5 : cls == 2 ? 8 : 16; }
+
+__device__ __forceinline__ void slot_info(int cls, int q, int &c, int &rb) {
+    if (cls == 0) {
+        c = q >> 2;
+        const int r = q & 3;
+        rb = r == 0 ? 0 : r == 1 ? 3 : r == 2 ? 1 : 2;
+    } else {
+        const int nb = 4 - cls;
+        c = q / nb;
+        rb = cls + (q - c * nb);
+    }
+}
+
+__device__ __forceinline__ int slot_of(int cls, int c, int kb) {
+    if (cls == 0) return 4 * c + (kb == 0 ? 0 : kb == 1 ? 2 : kb == 2 ? 3 : 1);
+    return c * (4 - cls) + (kb - cls);
+}
+
+struct Tile32 {
+    f32x4 t[8];  // tile (j, cb) = t[j * 4 + cb]: own slot j, column block cb
+};
+
+// acc += X_j[16 rows][0..k_len) (LDS, BF16, row stride kLd) @ W for both own
+// slots, Wt[n][k] in LDS.
+__device__ __forceinline__ void gemm_slots(Tile32 &acc, const __bf16 *X0, const __bf16 *X1, const __bf16 *Wt,
+                                           int wld, int k_len) {
     const int l = threadIdx.x & 63;
     const int r = l & 15, kq = 8 * (l >> 4);
     for (int ks = 0; ks < k_len; ks += 32) {
         bf16x8 a[2], b[4];
-        a[0] = lds_frag(X, rb0 * 16 + r, kLd, ks + kq);
-        a[1] = lds_frag(X, rb1 * 16 + r, kLd, ks + kq);
+        a[0] = lds_frag(X0, r, kLd, ks + kq);
+        a[1] = lds_frag(X1, r, kLd, ks + kq);
 #pragma unroll
         for (int cb = 0; cb < 4; cb++) b[cb] = lds_frag(Wt, cb * 16 + r, wld, ks + kq);
 #pragma unroll
@@ -176,37 +225,30 @@ __device__ __forceinline__ void gemm_rows(Tile32 &acc, const __bf16 *X, int rb0,
     }
 }
 
-// LayerNorm of the own rows (C layout) into X (LDS, BF16).
-__device__ __forceinline__ void layer_norm_rows(const Tile32 &h, const float *g, const float *b, __bf16 *X, int rb0,
-                                                int rb1) {
+// Normalised rows (h - mean) / sqrt(var + eps) of both own slots into X_j
+// (LDS, BF16).  The LayerNorm's scale and shift are folded into the weights
+// of the product that reads X.
+__device__ __forceinline__ void normalize_rows(const Tile32 &h, __bf16 *X0, __bf16 *X1) {
     const int l = threadIdx.x & 63;
     const int c = l & 15, r0 = 4 * (l >> 4);
-    float gg[4], bb[4];
-#pragma unroll
-    for (int cb = 0; cb < 4; cb++) {
-        gg[cb] = g[cb * 16 + c];
-        bb[cb] = b[cb * 16 + c];
-    }
 #pragma unroll
     for (int j = 0; j < 2; j++) {
-        const int rb = j ? rb1 : rb0;
+        __bf16 *X = j ? X1 : X0;
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            float s = 0.f;
-#pragma unroll
-            for (int cb = 0; cb < 4; cb++) s += h.t[j * 4 + cb][i];
-            const float mean = dpp_row_sum(s) * (1.0f / kD);
-            float v = 0.f;
+            float s = 0.f, s2 = 0.f;
 #pragma unroll
             for (int cb = 0; cb < 4; cb++) {
-                const float dlt = h.t[j * 4 + cb][i] - mean;
-                v += dlt * dlt;
+                const float v = h.t[j * 4 + cb][i];
+                s += v;
+                s2 = fmaf(v, v, s2);
             }
-            const float rstd = rsqrtf(dpp_row_sum(v) * (1.0f / kD) + 1e-5f);
-            const int row = rb * 16 + r0 + i;
+            const float mean = dpp_row_sum(s) * (1.0f / kD);
+            const float var = fmaxf(dpp_row_sum(s2) * (1.0f / kD) - mean * mean, 0.0f);
+            const float rstd = rsqrtf(var + 1e-5f);
+            const float sh = -mean * rstd;
 #pragma unroll
-            for (int cb = 0; cb < 4; cb++)
-                X[row * kLd + cb * 16 + c] = (__bf16)((h.t[j * 4 + cb][i] - mean) * rstd * gg[cb] + bb[cb]);
+            for (int cb = 0; cb < 4; cb++) X[(r0 + i) * kLd + cb * 16 + c] = (__bf16)fmaf(h.t[j * 4 + cb][i], rstd, sh);
         }
     }
 }
@@ -217,24 +259,43 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Causal attention of query block QB for head hh: S^T[key][query] = K Q^T
-// (lane owns query c16 + 16 QB and keys 16 kb + r0 + i), softmax over keys
-// in base 2 (the scale and log2(e) are folded into Q), P[query][key] -> Pb,
-// then O^T[c][query] = V^T P^T into Ob[query][16 hh + c].
+__device__ __forceinline__ bf16x4 cvt4(const f32x4 &v) {
+    bf16x4 o;
+#pragma unroll
+    for (int i = 0; i < 4; i++) o[i] = (__bf16)v[i];
+    return o;
+}
+
+// Where the keys and values of one configuration's key blocks live for
+// one head: blocks < sb in the sample's cache (global), the others in the
+// tile's slots (LDS).
+struct KvSrc {
+    const __bf16 *kc, *vc;  // cached K [64][16] and V^T [16][64] of this head (blocks < sb)
+    const __bf16 *ks, *vt;  // LDS slot arrays of the tile
+    int cls, c, sb;
+};
+
+// Causal attention of query block QB (a slot of configuration c) for one
+// head: S^T[key][query] = K Q^T (the lane owns query c16 + 16 QB and keys
+// 16 kb + r0 + i), softmax over keys in base 2 (scale and log2(e) are folded
+// into Q), P[query][key] -> Pb, then O^T[c][query] = V^T P^T into
+// Oq[query][16 hh + c].
 template <int QB>
-__device__ __forceinline__ void attend_block(const __bf16 *Qs, const __bf16 *Ks, const __bf16 *Vt, __bf16 *Pb,
-                                             __bf16 *Ob, int hh) {
+__device__ __forceinline__ void attend_block(const __bf16 *Qq, const KvSrc &S, __bf16 *Pb, __bf16 *Oq, int hh) {
     const int l = threadIdx.x & 63;
     const int c16 = l & 15, r0 = 4 * (l >> 4), kq = 8 * (l >> 4);
-    const int qi = QB * 16 + c16;
     const bf16x8 zero8 = {};
-    const bf16x8 bqf = l < 32 ? lds_frag(Qs, qi, kQLd, kq) : zero8;
+    const bf16x8 bqf = l < 32 ? lds_frag(Qq, c16, kQLd, kq) : zero8;
     f32x4 st[4];
 #pragma unroll
     for (int kb = 0; kb < 4; kb++) {
         st[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
         if (kb <= QB) {
-            const bf16x8 akf = l < 32 ? lds_frag(Ks, kb * 16 + c16, kQLd, kq) : zero8;
+            bf16x8 akf = zero8;
+            if (l < 32) {
+                if (kb < S.sb) akf = *reinterpret_cast<const bf16x8 *>(S.kc + (kb * 16 + c16) * kDh + kq);
+                else akf = lds_frag(S.ks + slot_of(S.cls, S.c, kb) * (16 * kQLd), c16, kQLd, kq);
+            }
             st[kb] = mfma16(akf, bqf, st[kb]);
         }
     }
@@ -272,62 +333,124 @@ __device__ __forceinline__ void attend_block(const __bf16 *Qs, const __bf16 *Ks,
 #pragma unroll
     for (int ks = 0; ks < 64; ks += 32) {
         if (ks <= QB * 16 + 15) {
-            const bf16x8 av = lds_frag(Vt, c16, kLd, ks + kq);
+            const int kb = (ks >> 4) + (kq >> 4);  // key block of this lane's eight keys
+            bf16x8 av;
+            if (kb < S.sb) av = *reinterpret_cast<const bf16x8 *>(S.vc + c16 * 64 + ks + kq);
+            else av = *reinterpret_cast<const bf16x8 *>(S.vt + slot_of(S.cls, S.c, kb) * (kDh * kVLd) + c16 * kVLd + (kq & 15));
             const bf16x8 bp = lds_frag(Pb, c16, kLd, ks + kq);
             ot = mfma16(av, bp, ot);
         }
     }
-    bf16x4 o4;
-#pragma unroll
-    for (int i = 0; i < 4; i++) o4[i] = (__bf16)ot[i];
-    *reinterpret_cast<bf16x4 *>(Ob + qi * kLd + hh * kDh + r0) = o4;
+    *reinterpret_cast<bf16x4 *>(Oq + c16 * kLd + hh * kDh + r0) = cvt4(ot);
     wave_lds_sync();  // Pb is rewritten by the next block
 }
 
-__global__ void __launch_bounds__(kRsWaves * 64) k_transformer_bf16(Bf16View M, const uint64_t *__restrict__ keys,
-                                                                       int64_t n, double *__restrict__ logabs) {
+__device__ __forceinline__ void attend(int QB, const __bf16 *Qq, const KvSrc &S, __bf16 *Pb, __bf16 *Oq, int hh) {
+    switch (QB) {
+        case 0: attend_block<0>(Qq, S, Pb, Oq, hh); break;
+        case 1: attend_block<1>(Qq, S, Pb, Oq, hh); break;
+        case 2: attend_block<2>(Qq, S, Pb, Oq, hh); break;
+        default: attend_block<3>(Qq, S, Pb, Oq, hh); break;
+    }
+}
+
+__global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) {
     __shared__ __align__(16) __bf16 wbuf[192 * kLd];
     __shared__ __align__(16) float2 gtab[kGeluN];
-    __shared__ __align__(16) __bf16 xs[kRsCfg][kRows * kLd];
-    __shared__ __align__(16) __bf16 os[kRsCfg][kRows * kLd];
-    __shared__ __align__(16) __bf16 qs[kRsCfg][kRows * kQLd];
-    __shared__ __align__(16) __bf16 ks_[kRsCfg][kRows * kQLd];
-    __shared__ __align__(16) __bf16 vt[kRsCfg][kDh * kLd];
-    __shared__ __align__(16) __bf16 ps[kRsWaves][16 * kLd];
-    __shared__ float red[kRsWaves];
+    __shared__ __align__(16) __bf16 xs[kSlots][16 * kLd];
+    __shared__ __align__(16) __bf16 os[kSlots][16 * kLd];
+    __shared__ __align__(16) __bf16 qs[kSlots][16 * kQLd];
+    __shared__ __align__(16) __bf16 ks_[kSlots][16 * kQLd];
+    __shared__ __align__(16) __bf16 vt[kSlots][kDh * kVLd];
+    __shared__ __align__(16) __bf16 ps[8][16 * kLd];
+    __shared__ double slot_lp[kSlots];
+    __shared__ int64_t sh_hdr[8];
 
     const int l = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int cs = w >> 1, hf = w & 1;
-    const int rb0 = hf, rb1 = 3 - hf;  // own row blocks
     const int c16 = l & 15, r0 = 4 * (l >> 4), kq = 8 * (l >> 4);
     const int K = M.K;
-    __bf16 *X = xs[cs], *Ob = os[cs], *Qs = qs[cs], *Ks = ks_[cs], *Vt = vt[cs], *Pb = ps[w];
     const float *wf = M.wf;
+    __bf16 *Pb = ps[w];
     for (int i = threadIdx.x; i < kGeluN; i += blockDim.x)
         gtab[i] = make_float2(wf[M.fl.gelu + 2 * i], wf[M.fl.gelu + 2 * i + 1]);
+    if (A.list_mode && threadIdx.x < 8) sh_hdr[threadIdx.x] = A.hdr[threadIdx.x];
     __syncthreads();
+    int64_t tiles[4] = {0, 0, 0, 0}, T;
+    if (A.list_mode) {
+        T = 0;
+        for (int c = 0; c < 4; c++) {
+            tiles[c] = (sh_hdr[c] + cls_cpt(c) - 1) / cls_cpt(c);
+            T += tiles[c];
+        }
+    } else {
+        T = (A.n + 3) / 4;
+    }
+    const int64_t kv_cfg = (int64_t)M.L * kH * kKvPerHead;  // cache elements per configuration
+    // head weights (the final LayerNorm's scale folded in) held in registers
+    float hw[4][4];
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+        for (int t = 0; t < 4; t++) hw[cb][t] = wf[M.fl.head_w + (cb * 16 + c16) * 4 + t];
 
-    for (int64_t base = (int64_t)blockIdx.x * kRsCfg; base < n; base += (int64_t)gridDim.x * kRsCfg) {
-        const int64_t cfg = base + cs;
-        const bool active = cfg < n;
-        Key x;
-        x.lo = active ? keys[2 * cfg] : 0ull;
-        x.hi = active ? keys[2 * cfg + 1] : 0ull;
-        // token of position q (orbital K-1-q) = up bit + 2 down bit, as two
-        // wave-uniform 64-bit masks over positions
-        const bool inq = l < K;
-        const uint64_t upm = __ballot(inq && key_bit(x, 2 * (K - 1 - l)));
-        const uint64_t dnm = __ballot(inq && key_bit(x, 2 * (K - 1 - l) + 1));
-        auto token = [&](int q) -> int { return (int)((upm >> q) & 1ull) | ((int)((dnm >> q) & 1ull) << 1); };
+    for (int64_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
+        int cls = 0;
+        int64_t tb = tile * 4, cnt = A.n, lbase = 0;
+        if (A.list_mode) {
+            int64_t tt = tile;
+            cls = 3;
+            for (int c = 0; c < 3; c++) {
+                if (tt < tiles[c]) {
+                    cls = c;
+                    break;
+                }
+                tt -= tiles[c];
+            }
+            tb = tt * cls_cpt(cls);
+            cnt = sh_hdr[cls];
+            lbase = sh_hdr[4 + cls];
+        }
+        const int cpt = cls_cpt(cls);
+        // the wave's two slots: configuration, row block, key, sample
+        int sc[2], srb[2];
+        uint64_t upm[2], dnm[2];
+        int64_t ssmp[2];
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            slot_info(cls, 2 * w + j, sc[j], srb[j]);
+            const bool valid = sc[j] < cpt && tb + sc[j] < cnt;
+            Key x{0ull, 0ull};
+            ssmp[j] = 0;
+            if (valid) {
+                if (A.list_mode) {
+                    const int64_t e = A.list[lbase + tb + sc[j]];
+                    x.lo = A.xkeys[2 * e];
+                    x.hi = A.xkeys[2 * e + 1];
+                    ssmp[j] = e / A.C;
+                } else {
+                    x.lo = A.keys[2 * (tb + sc[j])];
+                    x.hi = A.keys[2 * (tb + sc[j]) + 1];
+                }
+            }
+            // token of position q (orbital K-1-q) = up bit + 2 down bit, as
+            // two wave-uniform 64-bit masks over positions
+            const bool inq = l < K;
+            upm[j] = __ballot(inq && key_bit(x, 2 * (K - 1 - l)));
+            dnm[j] = __ballot(inq && key_bit(x, 2 * (K - 1 - l) + 1));
+        }
+        auto token = [&](int j, int q) -> int {
+            return (int)((upm[j] >> q) & 1ull) | ((int)((dnm[j] >> q) & 1ull) << 1);
+        };
+        __bf16 *X0 = xs[2 * w], *X1 = xs[2 * w + 1], *O0 = os[2 * w], *O1 = os[2 * w + 1];
         // embeddings of the own rows: h[s][c] = tok_emb[prev token][c] + pos_emb[s][c], padding rows 0
         Tile32 h;
 #pragma unroll
         for (int j = 0; j < 2; j++)
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                const int s = (j ? rb1 : rb0) * 16 + r0 + i;
-                const int prev = s == 0 ? 4 : (s < K ? token(s - 1) : 0);
+                const int s = srb[j] * 16 + r0 + i;
+                const int prev = s == 0 ? 4 : (s < K ? token(j, s - 1) : 0);
 #pragma unroll
                 for (int cb = 0; cb < 4; cb++) {
                     const int c = cb * 16 + c16;
@@ -338,62 +461,79 @@ __global__ void __launch_bounds__(kRsWaves * 64) k_transformer_bf16(Bf16View M, 
         for (int layer = 0; layer < M.L; layer++) {
             const float *lv = wf + M.fl.layer0 + layer * M.fl.layer_stride;
             const __bf16 *lw = M.wb + M.bl.layer0 + layer * M.bl.layer_stride;
-            layer_norm_rows(h, lv + kV_ln1_g, lv + kV_ln1_b, X, rb0, rb1);
+            normalize_rows(h, X0, X1);
             __syncthreads();  // previous users of wbuf are done
             stage_rows(wbuf, kLd, lw, 64, 192, 64);
             __syncthreads();
             for (int hh = 0; hh < kH; hh++) {
-                // q, k, v columns of this head for the own rows: one column tile each
-                f32x4 q[2], kk[2], v[2];
+                // Q^T and K^T (dims x positions) and V (positions x dims) of the
+                // own slots, biases in the accumulators
+                f32x4 qt[2], kt[2], v[2];
+                const float bv = lv[kV_bqkv + 128 + hh * kDh + c16];
+                f32x4 bq, bk;
 #pragma unroll
-                for (int j = 0; j < 2; j++) q[j] = kk[j] = v[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int i = 0; i < 4; i++) {
+                    bq[i] = lv[kV_bqkv + hh * kDh + r0 + i];
+                    bk[i] = lv[kV_bqkv + 64 + hh * kDh + r0 + i];
+                }
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    qt[j] = bq;
+                    kt[j] = bk;
+                    v[j] = f32x4{bv, bv, bv, bv};
+                }
 #pragma unroll
                 for (int ks = 0; ks < 64; ks += 32) {
-                    const bf16x8 bq = lds_frag(wbuf, hh * kDh + c16, kLd, ks + kq);
-                    const bf16x8 bk = lds_frag(wbuf, 64 + hh * kDh + c16, kLd, ks + kq);
-                    const bf16x8 bv = lds_frag(wbuf, 128 + hh * kDh + c16, kLd, ks + kq);
+                    const bf16x8 wq = lds_frag(wbuf, hh * kDh + c16, kLd, ks + kq);
+                    const bf16x8 wk = lds_frag(wbuf, 64 + hh * kDh + c16, kLd, ks + kq);
+                    const bf16x8 wv = lds_frag(wbuf, 128 + hh * kDh + c16, kLd, ks + kq);
 #pragma unroll
                     for (int j = 0; j < 2; j++) {
-                        const bf16x8 a = lds_frag(X, (j ? rb1 : rb0) * 16 + c16, kLd, ks + kq);
-                        q[j] = mfma16(a, bq, q[j]);
-                        kk[j] = mfma16(a, bk, kk[j]);
-                        v[j] = mfma16(a, bv, v[j]);
+                        const bf16x8 a = lds_frag(j ? X1 : X0, c16, kLd, ks + kq);
+                        qt[j] = mfma16(wq, a, qt[j]);
+                        kt[j] = mfma16(wk, a, kt[j]);
+                        v[j] = mfma16(a, wv, v[j]);
                     }
                 }
-                const float bqc = lv[kV_bqkv + hh * kDh + c16], bkc = lv[kV_bqkv + 64 + hh * kDh + c16],
-                            bvc = lv[kV_bqkv + 128 + hh * kDh + c16];
-                // Q, K row-major [position][dim]; V transposed [dim][position]
 #pragma unroll
-                for (int j = 0; j < 2; j++)
-#pragma unroll
-                    for (int i = 0; i < 4; i++) {
-                        const int s = (j ? rb1 : rb0) * 16 + r0 + i;
-                        // 1/sqrt(16) and log2(e) folded into Q: the scores come out in
-                        // base-2 units and the softmax takes exp2 directly
-                        Qs[s * kQLd + c16] = (__bf16)((q[j][i] + bqc) * (0.25f * 1.44269504f));
-                        Ks[s * kQLd + c16] = (__bf16)(kk[j][i] + bkc);
-                        Vt[c16 * kLd + s] = (__bf16)(v[j][i] + bvc);
+                for (int j = 0; j < 2; j++) {
+                    const int q = 2 * w + j;
+                    const bf16x4 k4 = cvt4(kt[j]), v4 = cvt4(v[j]);
+                    *reinterpret_cast<bf16x4 *>(qs[q] + c16 * kQLd + r0) = cvt4(qt[j]);
+                    *reinterpret_cast<bf16x4 *>(ks_[q] + c16 * kQLd + r0) = k4;
+                    *reinterpret_cast<bf16x4 *>(vt[q] + c16 * kVLd + r0) = v4;
+                    if (A.kv_out && sc[j] < cpt && tb + sc[j] < cnt) {  // sample mode: keep them for list mode
+                        __bf16 *kc = A.kv_out + (tb + sc[j]) * kv_cfg + ((int64_t)layer * kH + hh) * kKvPerHead;
+                        *reinterpret_cast<bf16x4 *>(kc + (srb[j] * 16 + c16) * kDh + r0) = k4;
+                        *reinterpret_cast<bf16x4 *>(kc + 64 * kDh + c16 * 64 + srb[j] * 16 + r0) = v4;
                     }
-                __syncthreads();  // K and V of both halves written
-                if (hf == 0) {
-                    attend_block<0>(Qs, Ks, Vt, Pb, Ob, hh);
-                    attend_block<3>(Qs, Ks, Vt, Pb, Ob, hh);
-                } else {
-                    attend_block<1>(Qs, Ks, Vt, Pb, Ob, hh);
-                    attend_block<2>(Qs, Ks, Vt, Pb, Ob, hh);
                 }
-                __syncthreads();  // both halves done with this head's K and V (and the QKV weights)
+                __syncthreads();  // K and V of every slot written
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    KvSrc S;
+                    const __bf16 *kc = A.kv_in ? A.kv_in + ssmp[j] * kv_cfg + ((int64_t)layer * kH + hh) * kKvPerHead : nullptr;
+                    S.kc = kc;
+                    S.vc = kc + 64 * kDh;
+                    S.ks = &ks_[0][0];
+                    S.vt = &vt[0][0];
+                    S.cls = cls;
+                    S.c = sc[j];
+                    S.sb = A.list_mode ? cls : 0;
+                    attend(srb[j], qs[2 * w + j], S, Pb, j ? O1 : O0, hh);
+                }
+                __syncthreads();  // every slot done with this head's K and V (and the QKV weights)
             }
             stage_rows(wbuf, kLd, lw + 192 * 64, 64, 64, 64);
             __syncthreads();
-            gemm_rows(h, Ob, rb0, rb1, wbuf, kLd, 64);
 #pragma unroll
             for (int cb = 0; cb < 4; cb++) {
                 const float bo = lv[kV_bo + cb * 16 + c16];
 #pragma unroll
                 for (int j = 0; j < 2; j++) h.t[j * 4 + cb] += bo;
             }
-            layer_norm_rows(h, lv + kV_ln2_g, lv + kV_ln2_b, X, rb0, rb1);
+            gemm_slots(h, O0, O1, wbuf, kLd, 64);
+            normalize_rows(h, X0, X1);
             // FFN in four hidden chunks of 64
             for (int chunk = 0; chunk < 4; chunk++) {
                 __syncthreads();
@@ -402,20 +542,22 @@ __global__ void __launch_bounds__(kRsWaves * 64) k_transformer_bf16(Bf16View M, 
                 __syncthreads();
                 Tile32 f;
 #pragma unroll
-                for (int t = 0; t < 8; t++) f.t[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-                gemm_rows(f, X, rb0, rb1, wbuf, kLd, 64);
-#pragma unroll
                 for (int cb = 0; cb < 4; cb++) {
                     const float b1 = lv[kV_b1 + chunk * 64 + cb * 16 + c16];
 #pragma unroll
-                    for (int j = 0; j < 2; j++)
+                    for (int j = 0; j < 2; j++) f.t[j * 4 + cb] = f32x4{b1, b1, b1, b1};
+                }
+                gemm_slots(f, X0, X1, wbuf, kLd, 64);
 #pragma unroll
-                        for (int i = 0; i < 4; i++)
-                            Ob[((j ? rb1 : rb0) * 16 + r0 + i) * kLd + cb * 16 + c16] =
-                                (__bf16)gelu_tab(gtab, f.t[j * 4 + cb][i] + b1);
+                for (int j = 0; j < 2; j++) {
+                    __bf16 *O = j ? O1 : O0;
+#pragma unroll
+                    for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+                        for (int i = 0; i < 4; i++) O[(r0 + i) * kLd + cb * 16 + c16] = (__bf16)gelu_tab(gtab, f.t[j * 4 + cb][i]);
                 }
                 wave_lds_sync();
-                gemm_rows(h, Ob, rb0, rb1, wbuf + 64 * kLd, kLd, 64);
+                gemm_slots(h, O0, O1, wbuf + 64 * kLd, kLd, 64);
             }
 #pragma unroll
             for (int cb = 0; cb < 4; cb++) {
@@ -424,71 +566,87 @@ __global__ void __launch_bounds__(kRsWaves * 64) k_transformer_bf16(Bf16View M, 
                 for (int j = 0; j < 2; j++) h.t[j * 4 + cb] += b2;
             }
         }
-        // final LayerNorm, head, mask, log-probability of the actual tokens (own rows)
-        float lsum = 0.f;
-        {
-            const float *g = wf + M.fl.lnf_g, *b = wf + M.fl.lnf_b, *hw = wf + M.fl.head_w;
+        // final LayerNorm (scale folded into the head), head, mask and the
+        // log-probability of the actual token, per own slot
 #pragma unroll
-            for (int j = 0; j < 2; j++)
+        for (int j = 0; j < 2; j++) {
+            float lsum = 0.f;
 #pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    float rs = 0.f;
+            for (int i = 0; i < 4; i++) {
+                float rs = 0.f, rs2 = 0.f;
 #pragma unroll
-                    for (int cb = 0; cb < 4; cb++) rs += h.t[j * 4 + cb][i];
-                    const float mean = dpp_row_sum(rs) * (1.0f / kD);
-                    float v = 0.f;
-#pragma unroll
-                    for (int cb = 0; cb < 4; cb++) {
-                        const float dlt = h.t[j * 4 + cb][i] - mean;
-                        v += dlt * dlt;
-                    }
-                    const float rstd = rsqrtf(dpp_row_sum(v) * (1.0f / kD) + 1e-5f);
-                    float z[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int cb = 0; cb < 4; cb++) {
-                        const int c = cb * 16 + c16;
-                        const float y = (h.t[j * 4 + cb][i] - mean) * rstd * g[c] + b[c];
-#pragma unroll
-                        for (int t = 0; t < 4; t++) z[t] += y * hw[c * 4 + t];
-                    }
-#pragma unroll
-                    for (int t = 0; t < 4; t++) z[t] = dpp_row_sum(z[t]);
-                    const int s = (j ? rb1 : rb0) * 16 + r0 + i;
-                    if (c16 == 0 && s < K) {
-                        const uint64_t below = (1ull << s) - 1ull;  // s < K <= 64
-                        const int up = __popcll(upm & below), dn = __popcll(dnm & below);
-                        const int rem = K - 1 - s, orb = K - 1 - s;
-                        float mx = -INFINITY;
-                        bool ok[4];
-#pragma unroll
-                        for (int t = 0; t < 4; t++) {
-                            z[t] += wf[M.fl.head_b + t] + wf[M.fl.bias + orb * 4 + t];
-                            const int bu = t & 1, bd = t >> 1;
-                            ok[t] = (up + bu <= M.n_up) && (dn + bd <= M.n_dn) && (M.n_up - up - bu <= rem) &&
-                                    (M.n_dn - dn - bd <= rem);
-                            if (ok[t]) mx = fmaxf(mx, z[t]);
-                        }
-                        float den = 0.f;
-#pragma unroll
-                        for (int t = 0; t < 4; t++)
-                            if (ok[t]) den += __expf(z[t] - mx);
-                        const int ts = token(s);
-                        lsum += ok[ts] ? (z[ts] - mx) - __logf(den) : -INFINITY;
-                    }
+                for (int cb = 0; cb < 4; cb++) {
+                    const float v = h.t[j * 4 + cb][i];
+                    rs += v;
+                    rs2 = fmaf(v, v, rs2);
                 }
+                const float mean = dpp_row_sum(rs) * (1.0f / kD);
+                const float var = fmaxf(dpp_row_sum(rs2) * (1.0f / kD) - mean * mean, 0.0f);
+                const float rstd = rsqrtf(var + 1e-5f);
+                const float sh = -mean * rstd;
+                float z[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int cb = 0; cb < 4; cb++) {
+                    const float y = fmaf(h.t[j * 4 + cb][i], rstd, sh);
+#pragma unroll
+                    for (int t = 0; t < 4; t++) z[t] = fmaf(y, hw[cb][t], z[t]);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; t++) z[t] = dpp_row_sum(z[t]);
+                const int s = srb[j] * 16 + r0 + i;
+                if (c16 == 0 && s < K) {
+                    const uint64_t below = (1ull << s) - 1ull;  // s < K <= 64
+                    const int up = __popcll(upm[j] & below), dn = __popcll(dnm[j] & below);
+                    const int rem = K - 1 - s, orb = K - 1 - s;
+                    float mx = -INFINITY;
+                    bool ok[4];
+#pragma unroll
+                    for (int t = 0; t < 4; t++) {
+                        z[t] += wf[M.fl.head_b + t] + wf[M.fl.bias + orb * 4 + t];
+                        const int bu = t & 1, bd = t >> 1;
+                        ok[t] = (up + bu <= M.n_up) && (dn + bd <= M.n_dn) && (M.n_up - up - bu <= rem) &&
+                                (M.n_dn - dn - bd <= rem);
+                        if (ok[t]) mx = fmaxf(mx, z[t]);
+                    }
+                    float den = 0.f;
+#pragma unroll
+                    for (int t = 0; t < 4; t++)
+                        if (ok[t]) den += __expf(z[t] - mx);
+                    const int ts = token(j, s);
+                    lsum += ok[ts] ? (z[ts] - mx) - __logf(den) : -INFINITY;
+                }
+            }
+            // rows live in lanes 0, 16, 32, 48
+            lsum += __shfl_xor(lsum, 16, 64);
+            lsum += __shfl_xor(lsum, 32, 64);
+            if (l == 0) slot_lp[2 * w + j] = (double)lsum;
         }
-        // rows live in lanes 0, 16, 32, 48; then the two halves of the configuration
-        lsum += __shfl_xor(lsum, 16, 64);
-        lsum += __shfl_xor(lsum, 32, 64);
-        if (l == 0) red[w] = lsum;
         __syncthreads();
-        if (active && hf == 0 && l == 0) logabs[cfg] = 0.5 * ((double)red[w] + (double)red[w + 1]);
+        // per configuration: sum of its row blocks in block order
+        if ((int)threadIdx.x < cpt && tb + (int)threadIdx.x < cnt) {
+            const int c = threadIdx.x;
+            if (A.list_mode) {
+                const int64_t e = A.list[lbase + tb + c];
+                double acc = A.pre_in[(e / A.C) * 4 + cls];
+                for (int kb = cls; kb < 4; kb++) acc += slot_lp[slot_of(cls, c, kb)];
+                A.xla[e] = 0.5 * acc;
+            } else {
+                double acc = 0.0;
+                for (int kb = 0; kb < 4; kb++) {
+                    if (A.pre_out) A.pre_out[(tb + c) * 4 + kb] = acc;
+                    acc += slot_lp[slot_of(0, c, kb)];
+                }
+                A.logabs[tb + c] = 0.5 * acc;
+            }
+        }
+        __syncthreads();  // slot_lp and the slots are reused by the next tile
     }
 }
 
 // Phase MLP: 16 configurations per wave, B tiles from global (L2) memory.
-__global__ void __launch_bounds__(256) k_phase_bf16(Bf16View M, const uint64_t *__restrict__ keys, int64_t n,
-                                                    double *__restrict__ phase) {
+// In list mode (see TfArgs) the configurations are xkeys[list[k]] for k
+// below the total of the four class counts, and phase[list[k]] receives them.
+__global__ void __launch_bounds__(256) k_phase_bf16(Bf16View M, TfArgs A, double *__restrict__ phase) {
     __shared__ __align__(16) __bf16 zs[kWaves][16 * (kP + 8)];
     const int l = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -498,12 +656,16 @@ __global__ void __launch_bounds__(256) k_phase_bf16(Bf16View M, const uint64_t *
     const __bf16 *w1T = M.wb + M.bl.ph_w1T, *w2T = M.wb + M.bl.ph_w2T;
     const float *b1 = M.wf + M.fl.ph_b1, *b2 = M.wf + M.fl.ph_b2, *w3 = M.wf + M.fl.ph_w3;
     const int nbits = 2 * M.K;
+    const int64_t n = A.list_mode ? A.hdr[0] + A.hdr[1] + A.hdr[2] + A.hdr[3] : A.n;
     for (int64_t base = ((int64_t)blockIdx.x * kWaves + w) * 16; base < n; base += (int64_t)gridDim.x * kWaves * 16) {
         // A tiles of the bit matrix: row = configuration (c16), k = bit index
         const int64_t cr = base + c16;
-        Key x;
-        x.lo = cr < n ? keys[2 * cr] : 0ull;
-        x.hi = cr < n ? keys[2 * cr + 1] : 0ull;
+        Key x{0ull, 0ull};
+        if (cr < n) {
+            const uint64_t *kp = A.list_mode ? A.xkeys + 2 * (int64_t)A.list[cr] : A.keys + 2 * cr;
+            x.lo = kp[0];
+            x.hi = kp[1];
+        }
         bf16x8 abits[kPhaseBits / 32];
 #pragma unroll
         for (int ks = 0; ks < kPhaseBits / 32; ks++)
@@ -546,7 +708,7 @@ __global__ void __launch_bounds__(256) k_phase_bf16(Bf16View M, const uint64_t *
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 const int64_t cfg = base + r0 + i;
-                if (cfg < n) phase[cfg] = (double)(part[i] + M.wf[M.fl.ph_b3]);
+                if (cfg < n) phase[A.list_mode ? (int64_t)A.list[cfg] : cfg] = (double)(part[i] + M.wf[M.fl.ph_b3]);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -593,38 +755,63 @@ nnqs_status bf16_model_init(nnqs_model *m, const float *weights) {
         for (int k = 0; k < kdim; k++)
             for (int nn = 0; nn < ndim; nn++) wb[dst + (int64_t)(row0 + nn) * dst_ld + k] = to_bf16_bits(src[k * ndim + nn]);
     };
+    // A LayerNorm's scale g and shift b fold into the product y W + c that
+    // reads it: (n * g + b) W + c = n (diag(g) W) + (b W + c), n = the
+    // normalised row; the attention scale 1/sqrt(16) and log2(e) (the softmax
+    // runs in base 2) fold into W_q and b_q.  Folded in FP64, then rounded.
+    auto fold = [&](const float *Wm, const float *bm, const float *g, const float *beta, int kdim, int ndim,
+                    double scale, std::vector<float> &Wf, std::vector<float> &bf) {
+        Wf.assign((size_t)kdim * ndim, 0.f);
+        bf.assign((size_t)ndim, 0.f);
+        for (int nn = 0; nn < ndim; nn++) {
+            double acc = bm[nn];
+            for (int k = 0; k < kdim; k++) {
+                Wf[(size_t)k * ndim + nn] = (float)(scale * (double)g[k] * (double)Wm[(size_t)k * ndim + nn]);
+                acc += (double)beta[k] * (double)Wm[(size_t)k * ndim + nn];
+            }
+            bf[nn] = (float)(scale * acc);
+        }
+    };
+    const double qscale = 0.25 * 1.4426950408889634;
+    std::vector<float> fw, fb;
     for (int l = 0; l < L; l++) {
         const int64_t lo = o.layer0 + l * o.layer_stride;
         const int64_t base = bl.layer0 + l * bl.layer_stride;
         const int64_t dd = kD * kD;
         // layer block layout of the FP32 weights: ln1_g ln1_b wq bq wk bk wv bv wo bo ln2_g ln2_b w1 b1 w2 b2
+        const float *ln1g = W(lo), *ln1b = W(lo + kD);
         const float *wq = W(lo + 2 * kD), *bq = wq + dd, *wk = bq + kD, *bk = wk + dd, *wv = bk + kD, *bv = wv + dd,
                     *wo = bv + kD, *bo = wo + dd, *ln2g = bo + kD, *ln2b = ln2g + kD, *w1 = ln2b + kD,
                     *b1 = w1 + kD * kF, *w2 = b1 + kF, *b2 = w2 + kF * kD;
-        put_t(base, 64, wq, kD, kD, 0);
-        put_t(base, 64, wk, kD, kD, 64);
-        put_t(base, 64, wv, kD, kD, 128);
-        put_t(base + 192 * 64, 64, wo, kD, kD, 0);
-        put_t(base + 192 * 64 + 64 * 64, 64, w1, kD, kF, 0);
-        put_t(base + 192 * 64 + 64 * 64 + 256 * 64, 256, w2, kF, kD, 0);
         float *lv = wf.data() + fl.layer0 + l * fl.layer_stride;
-        std::memcpy(lv + kV_ln1_g, W(lo), kD * 4);
-        std::memcpy(lv + kV_ln1_b, W(lo + kD), kD * 4);
-        std::memcpy(lv + kV_bqkv, bq, kD * 4);
-        std::memcpy(lv + kV_bqkv + 64, bk, kD * 4);
-        std::memcpy(lv + kV_bqkv + 128, bv, kD * 4);
+        fold(wq, bq, ln1g, ln1b, kD, kD, qscale, fw, fb);
+        put_t(base, 64, fw.data(), kD, kD, 0);
+        std::memcpy(lv + kV_bqkv, fb.data(), kD * 4);
+        fold(wk, bk, ln1g, ln1b, kD, kD, 1.0, fw, fb);
+        put_t(base, 64, fw.data(), kD, kD, 64);
+        std::memcpy(lv + kV_bqkv + 64, fb.data(), kD * 4);
+        fold(wv, bv, ln1g, ln1b, kD, kD, 1.0, fw, fb);
+        put_t(base, 64, fw.data(), kD, kD, 128);
+        std::memcpy(lv + kV_bqkv + 128, fb.data(), kD * 4);
+        put_t(base + 192 * 64, 64, wo, kD, kD, 0);
+        fold(w1, b1, ln2g, ln2b, kD, kF, 1.0, fw, fb);
+        put_t(base + 192 * 64 + 64 * 64, 64, fw.data(), kD, kF, 0);
+        std::memcpy(lv + kV_b1, fb.data(), kF * 4);
+        put_t(base + 192 * 64 + 64 * 64 + 256 * 64, 256, w2, kF, kD, 0);
+        std::memcpy(lv + kV_ln1_g, ln1g, kD * 4);
+        std::memcpy(lv + kV_ln1_b, ln1b, kD * 4);
         std::memcpy(lv + kV_bo, bo, kD * 4);
         std::memcpy(lv + kV_ln2_g, ln2g, kD * 4);
         std::memcpy(lv + kV_ln2_b, ln2b, kD * 4);
-        std::memcpy(lv + kV_b1, b1, kF * 4);
         std::memcpy(lv + kV_b2, b2, kD * 4);
     }
     std::memcpy(wf.data() + fl.tok_emb, W(o.tok_emb), 5 * kD * 4);
     std::memcpy(wf.data() + fl.pos_emb, W(o.pos_emb), (size_t)K * kD * 4);
     std::memcpy(wf.data() + fl.lnf_g, W(o.lnf_g), kD * 4);
     std::memcpy(wf.data() + fl.lnf_b, W(o.lnf_b), kD * 4);
-    std::memcpy(wf.data() + fl.head_w, W(o.head_w), 4 * kD * 4);
-    std::memcpy(wf.data() + fl.head_b, W(o.head_b), 4 * 4);
+    fold(W(o.head_w), W(o.head_b), W(o.lnf_g), W(o.lnf_b), kD, 4, 1.0, fw, fb);
+    std::memcpy(wf.data() + fl.head_w, fw.data(), 4 * kD * 4);
+    std::memcpy(wf.data() + fl.head_b, fb.data(), 4 * 4);
     std::memcpy(wf.data() + fl.bias, W(o.bias), (size_t)4 * K * 4);
     std::memcpy(wf.data() + fl.ph_b1, W(o.ph_b1), kP * 4);
     std::memcpy(wf.data() + fl.ph_b2, W(o.ph_b2), kP * 4);
@@ -654,20 +841,72 @@ void bf16_model_free(nnqs_model *m) {
     m->d_f32 = nullptr;
 }
 
+static int cu_count() {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess) return cus;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    return cus;
+}
+
+// One block per CU is resident (the slots take 157 KB of LDS); blocks loop
+// over tiles.
+static unsigned tf_grid(int64_t tiles) {
+    const int64_t cap = cu_count();
+    return (unsigned)(tiles < 1 ? 1 : tiles < cap ? tiles : cap);
+}
+
+static unsigned phase_grid(int64_t n) {
+    const int64_t cap = (int64_t)cu_count() * 8;
+    const int64_t b = (n + kWaves * 16 - 1) / (kWaves * 16);
+    return (unsigned)(b < 1 ? 1 : b < cap ? b : cap);
+}
+
 nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, double *phase,
                                 hipStream_t st) {
     if (!m->bf16_ok) return fail(NNQS_EUNSUPPORTED, "BF16 forward needs d_model 64, 4 heads, FFN 256, P 512, K <= 64");
     const Bf16View v = bf16_view(m);
-    int dev = 0, cus = 256;
-    NNQS_HIP_CHECK(hipGetDevice(&dev));
-    NNQS_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t cap = (int64_t)cus * 8;
-    int64_t blocks = (n + kRsCfg - 1) / kRsCfg;
-    if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(k_transformer_bf16, dim3((unsigned)blocks), dim3(kRsWaves * 64), 0, st, v, keys, n, logabs);
-    int64_t pblocks = (n + kWaves * 16 - 1) / (kWaves * 16);
-    if (pblocks > cap) pblocks = cap;
-    hipLaunchKernelGGL(k_phase_bf16, dim3((unsigned)pblocks), dim3(kWaves * 64), 0, st, v, keys, n, phase);
+    TfArgs A{};
+    A.keys = keys;
+    A.n = n;
+    A.logabs = logabs;
+    hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, v, A);
+    hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(n)), dim3(kWaves * 64), 0, st, v, A, phase);
+    NNQS_HIP_CHECK(hipGetLastError());
+    return NNQS_OK;
+}
+
+int64_t bf16_cache_elems(const nnqs_model *m) { return (int64_t)m->desc.n_layers * kH * kKvPerHead; }
+
+nnqs_status enqueue_bf16_cached(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, __bf16 *kv,
+                                double *pre, hipStream_t st) {
+    if (!m->bf16_ok) return fail(NNQS_EUNSUPPORTED, "BF16 forward needs d_model 64, 4 heads, FFN 256, P 512, K <= 64");
+    TfArgs A{};
+    A.keys = keys;
+    A.n = n;
+    A.logabs = logabs;
+    A.kv_out = kv;
+    A.pre_out = pre;
+    hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, bf16_view(m), A);
+    NNQS_HIP_CHECK(hipGetLastError());
+    return NNQS_OK;
+}
+
+nnqs_status enqueue_bf16_list(const nnqs_model *m, const uint64_t *xkeys, int64_t C, const int32_t *list,
+                              const int64_t *hdr, int64_t max_entries, const __bf16 *kv, const double *pre,
+                              double *xla, double *xph, hipStream_t st) {
+    if (!m->bf16_ok) return fail(NNQS_EUNSUPPORTED, "BF16 forward needs d_model 64, 4 heads, FFN 256, P 512, K <= 64");
+    const Bf16View v = bf16_view(m);
+    TfArgs A{};
+    A.kv_in = kv;
+    A.pre_in = pre;
+    A.list = list;
+    A.hdr = hdr;
+    A.xkeys = xkeys;
+    A.C = C;
+    A.xla = xla;
+    A.list_mode = 1;  // kv_out / pre_out stay null: list mode only reads the cache
+    hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((max_entries + 3) / 4)), dim3(512), 0, st, v, A);
+    hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(max_entries)), dim3(kWaves * 64), 0, st, v, A, xph);
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
 }

@@ -160,3 +160,65 @@ def test_eloc_model_refinement_shrinks_bf16_error(nn):
           f"{enr[0].item() - en64[0].item():.3e} Ha")
     assert dr.max() <= 0.1 * d16.max()
     assert frac < 1.0
+
+
+@pytest.mark.parametrize("kw,take", [(dict(cfg=2, K=16, n_up=4, n_dn=4, n_unique=20, model=True), 6),
+                                     (dict(cfg=2, K=64, n_up=8, n_dn=8, n_unique=4, model=True), 1),
+                                     (dict(cfg=3, n_unique=2), 1)])
+def test_bf16_prefix_reuse_equals_whole_forward(nn, kw, take):
+    """The BF16 full path evaluates each x' from its first changed position on,
+    with the sample's cached keys and values for the rows before; by causality
+    that is the same computation as the whole forward of x'.  E_loc from
+    nnqs_eloc_model must equal E_loc assembled from the whole-sequence BF16
+    amplitudes of every x' (nnqs_model_logpsi) and the exact matrix elements
+    (nnqs_connections), up to FP64 summation order: a difference of one FP32
+    rounding in any log|psi(x')| would show at ~1e-8."""
+    kw = dict(kw)
+    cfg = kw.pop("cfg")
+    d = synth.config_inputs(cfg, **kw)
+    _print_case("bf16_prefix_vs_whole", K=d["K"], take=take)
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    keys = dev(d["keys"][:take])
+    cnt = dev(d["counts"][:take], torch.int32)
+    e, _, st = nn.eloc_model(S, M, keys, cnt, nn.NNQS_BF16, with_stats=True)
+    con = nn.connections(S, keys)
+    C = S.connection_count
+    xla, xph = nn.model_logpsi(M, con["xprime"].reshape(-1, 2), nn.NNQS_BF16)
+    sla, sph = nn.model_logpsi(M, keys, nn.NNQS_BF16)
+    torch.cuda.synchronize()
+    hv = con["hxx"].cpu().numpy()
+    xla, xph = xla.cpu().numpy().reshape(take, C), xph.cpu().numpy().reshape(take, C)
+    sla, sph = sla.cpu().numpy(), sph.cpu().numpy()
+    terms = hv * np.exp(xla - sla[:, None]) * np.exp(1j * (xph - sph[:, None]))
+    ref = terms.sum(axis=1)
+    absum = np.abs(terms).sum(axis=1)
+    g = eloc_complex(e)
+    assert st["evaluated"] == take * C
+    err = np.abs(g - ref) / absum
+    print(f"prefix vs whole-forward BF16 K={d['K']}: max |dE|/A = {err.max():.3e}")
+    assert err.max() <= 1e-12
+
+
+def test_bf16_eloc_model_chunks_and_tail(nn):
+    """More samples than one prefix-cache chunk at a small C (N=8, 27
+    connections: 4,096 samples per chunk), ragged tail; equal to the
+    whole-forward assembly as above."""
+    d = synth.config_inputs(2, K=4, n_up=2, n_dn=2, n_unique=30, model=True)
+    _print_case("bf16_chunks")
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, len(d["keys"]), size=5000)   # repeated samples are fine for the full path
+    k = d["keys"][idx]
+    keys, cnt = dev(k), dev(np.ones(len(k), np.uint32), torch.int32)
+    e, _, _ = nn.eloc_model(S, M, keys, cnt, nn.NNQS_BF16)
+    ref, _, _ = nn.eloc_model(S, M, keys[:7].contiguous(), cnt[:7].contiguous(), nn.NNQS_BF16)
+    torch.cuda.synchronize()
+    g = eloc_complex(e)
+    first = {}
+    for i, kk in enumerate(idx):
+        first.setdefault(int(kk), i)
+    for i, kk in enumerate(idx):
+        assert g[i] == g[first[int(kk)]], i
+    assert np.allclose(g[:7], eloc_complex(ref), rtol=0, atol=0)
