@@ -172,6 +172,24 @@ nnqs_status nnqs_eloc_table(const nnqs_system *sys, nnqs_table *tab, const uint6
 nnqs_status nnqs_energy(nnqs_table *tab, const uint32_t *counts, const double *eloc, int64_t n,
                         double *energy, void *stream);
 
+/* Largest n that nnqs_energy_noalloc accepts. */
+#define NNQS_ENERGY_NOALLOC_MAX_N 2147483647LL
+
+/* nnqs_energy for callers that cannot allocate device memory or that need a
+ * call free of allocations (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same weighted energy (Eq. 6,
+ * same kernels, same reduction order, so bit-identical results) without a
+ * table.  Its scratch, the block partials of the two reduction passes, is a
+ * library-owned 64 KiB device array per GPU, held until the process ends;
+ * the call allocates and frees nothing.  Inputs (device): counts [n],
+ * eloc [n][2]; output (device): energy [4] as in nnqs_eloc_table.  The
+ * scratch is shared by every call on one GPU, so calls that overlap on one
+ * GPU (different streams without ordering, or several host threads) race:
+ * order them on one stream.  Errors: EINVAL (null pointer, n <= 0), ERANGE
+ * (n > NNQS_ENERGY_NOALLOC_MAX_N), EHIP, EUNSUPPORTED (device ordinal >= 64). */
+nnqs_status nnqs_energy_noalloc(const uint32_t *counts, const double *eloc, int64_t n, double *energy,
+                                void *stream);
+
 /* ------------------------------------------------------------------ model */
 /* Wave-function ansatz of Section 3.1 (Eq. 11, Fig. 2): a decoder-only
  * transformer gives |psi|^2 autoregressively (Eq. 8) over tokens that are

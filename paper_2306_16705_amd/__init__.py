@@ -24,6 +24,7 @@ from .api import (  # noqa: F401
     eloc_pauli,
     eloc_table,
     energy,
+    energy_noalloc,
     model_logpsi,
     pauli_build_host,
     version,

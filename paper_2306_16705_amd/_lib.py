@@ -33,6 +33,7 @@ SIGNATURES = {
     "nnqs_eloc_table": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p,
                                _c_void_p, _u32, _c_void_p]),
     "nnqs_energy": (_i32, [_c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p]),
+    "nnqs_energy_noalloc": (_i32, [_c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p]),
     "nnqs_table_set_tune": (_i32, [_c_void_p, _c_void_p]),
     "nnqs_table_get_tune": (_i32, [_c_void_p, _c_void_p]),
     "nnqs_model_weight_count": (_i64, [_c_void_p]),

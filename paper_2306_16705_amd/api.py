@@ -198,6 +198,19 @@ def energy(table: Table, counts, eloc, out=None, stream=None):
     return out
 
 
+def energy_noalloc(counts, eloc, out=None, stream=None):
+    """Weighted energy of Eq. 6 without a table, with the library's static
+    per-GPU scratch (``nnqs_energy_noalloc``; allocates nothing)."""
+    n = eloc.shape[0]
+    _need(counts, "counts", (torch.int32, torch.uint32), (n,))
+    _need(eloc, "eloc", (torch.float64,), (n, 2))
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=eloc.device)
+    _need(out, "energy", (torch.float64,), (4,))
+    L.check(L.load().nnqs_energy_noalloc(_ptr(counts), _ptr(eloc), n, _ptr(out), _stream(stream)))
+    return out
+
+
 # ------------------------------------------------------------------- model
 _LAYER_KEYS = ("ln1_g", "ln1_b", "wq", "bq", "wk", "bk", "wv", "bv", "wo", "bo", "ln2_g", "ln2_b", "w1", "b1",
                "w2", "b2")

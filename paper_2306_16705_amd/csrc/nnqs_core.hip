@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -422,6 +423,34 @@ nnqs_status enqueue_energy(nnqs_table *tab, const uint32_t *counts, const double
     return enqueue_energy_partials(tab->partials, counts, eloc, n, energy, st);
 }
 
+// Scratch of nnqs_energy_noalloc: the block partials of both reduction
+// passes (8 doubles for each of at most kPartialBlocks blocks, 64 KiB).
+// Every GPU the library runs on holds its own copy until the process ends;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device (the array's name is a host-side stand-in).
+static __device__ __align__(256) double scratch[kPartialBlocks * 8];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+
+// Address of `scratch` on the current device, looked up once per device.
+static nnqs_status noalloc_scratch(double **out) {
+    int dev = 0;
+    NNQS_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(NNQS_EUNSUPPORTED, "device ordinal %d >= %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(NNQS_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return NNQS_OK;
+}
+
 nnqs_status read_status(nnqs_table *tab, hipStream_t st, bool clear) {
     int h = 0;
     NNQS_HIP_CHECK(hipMemcpyAsync(&h, tab->status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -707,5 +736,18 @@ nnqs_status nnqs_energy(nnqs_table *t, const uint32_t *counts, const double *elo
     return enqueue_energy(t, counts, eloc, n, energy, as_stream(stream));
 }
 
+
+nnqs_status nnqs_energy_noalloc(const uint32_t *counts, const double *eloc, int64_t n, double *energy, void *stream) {
+    clear_error();
+    if (!counts || !eloc || !energy) return fail(NNQS_EINVAL, "null pointer argument");
+    if (n <= 0) return fail(NNQS_EINVAL, "n must be positive");
+    if (n > NNQS_ENERGY_NOALLOC_MAX_N)
+        return fail(NNQS_ERANGE, "n=%lld exceeds the no-allocation limit of %lld samples", (long long)n,
+                    (long long)NNQS_ENERGY_NOALLOC_MAX_N);
+    double *sc = nullptr;
+    const nnqs_status s = noalloc_scratch(&sc);
+    if (s != NNQS_OK) return s;
+    return enqueue_energy_partials(sc, counts, eloc, n, energy, as_stream(stream));
+}
 
 }  // extern "C"
