@@ -1,18 +1,30 @@
 """Local-energy throughput benchmark on one MI355X.
 
-A step is one pass of the sample-aware hot path over one batch: build the
-sorted table of the unique samples, evaluate E_loc for every sample and
-reduce the weighted energy.  Workload: K=24 spatial orbitals (N=48 spin
-orbitals), 6 up + 6 down electrons, 65,536 unique synthetic samples drawn
-around the reference occupation, FP64 throughout.
+Headline workload (the learned screen against the plain form): full local
+energies E_loc(x) = sum_x' H_xx' psi(x')/psi(x) (Eq. 4) of N=120 spin
+orbitals (K=60), 20 up + 20 down electrons, 938,001 connected configurations
+per sample, every psi(x') from the decoder-only transformer (d_model 64,
+4 layers, 4 heads, FFN 256) and the phase MLP (120 x 512 x 512 x 1).  A step
+is one pass over a deterministic subset of the unique samples (the first
+`--samples` the seeded generator draws): the BF16 path behind the learned
+screen (trained first, untimed, on about 10^7 connections of other samples),
+FP64 refinement of the large terms, FP64 ratios and compensated sums, and the
+weighted energy (Eq. 6).  The same subset is also timed through the plain
+BF16 path (no screen), the workload's own screen rule (12 nats below
+log|psi(x)|, no refinement) and, on a smaller subset, the plain FP64 path
+that judges the energy errors.
 
-Prints one JSON line (rank 0) with samples/s, connections/s, the roofline
-figure of the dominant kernel (timed live with HIP events on the stream it
-runs on) and the FP64 CPU oracle timed on a bounded sample on the host.
+Prints one JSON line with samples/s and connections/s of the screened path,
+the MFMA roofline of its dominant kernel (the prefix-reusing BF16
+transformer, timed live with HIP events on the stream it runs on), and the
+FP64 CPU oracle timed on a bounded sample on the host.  Extra keys: the
+sample-aware N=48 path, the 32-system batched launch and the Pauli-string
+backend.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,75 +34,82 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Per-connection work of the dominant kernel's hot loop, in 32-bit integer
-# lane operations: hash update (XOR), filter word address (shift, AND), the
-# third bit position (shift, add), three bit extracts, their two ANDs and the
-# candidate test.
-ALU_OPS_PER_CONNECTION = 11
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz of 32-bit integer VALU throughput.
-ALU_PEAK_GOPS = 256 * 64 * 2.4
+METRIC = "E_loc samples/s + connections/s at 1e-4 Ha error; learned/BF16 vs plain"
+BF16_PEAK_TFLOPS = 2500.0        # MI355X dense BF16 MFMA
+ALU_PEAK_GOPS = 256 * 64 * 2.4   # 256 CUs x 64 lanes x 2.4 GHz, 32-bit integer VALU
+# Sample-aware hot loop: integer lane operations per connection (hash XOR;
+# filter word address shift and AND; third bit position shift and add; three
+# bit extracts, their two ANDs and the candidate test).
+SA_OPS_PER_CONNECTION = 11
+
+# Operating point of the screened path: skip a connection when its predicted
+# contribution |H_xx' psi(x')/psi(x)| is below exp(-16.5) Ha, recompute in
+# FP64 every evaluated term above exp(-7) Ha.
+SKIP_NATS = 16.5
+REFINE_NATS = 7.0
+
+# HBM traffic of one k_transformer_bf16_list launch of this workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over the
+# dispatches of the profiled command) scaled by what the same counters read
+# for a plain device copy of known size.  Valid only for the kernel sources
+# they were taken with (hash below); otherwise the bench reports no traffic.
+TF_COUNTERS = {"sources_sha256_16": None, "fetch_kib": None, "write_kib": None,
+               "fetch_scale": None, "write_scale": None}
+TF_SOURCES = ("paper_2306_16705_amd/csrc/model_bf16.hip",)
 
 
-# HBM traffic of one k_eloc_sa<1> launch on this workload: rocprofv3
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the same
-# counter reads for a plain device copy of known size.  The figures hold only
-# for the kernel sources they were taken with (hash below); otherwise the
-# bench reports no traffic.
-SA_COUNTERS = {"sources_sha256_16": "9afc6abc2966f154", "fetch_kib": 55967.9, "write_kib": 3973.9,
-               "fetch_scale": 262144.0 / 131085.3, "write_scale": 1.0}
-SA_SOURCES = ("paper_2306_16705_amd/csrc/eloc_sa.hip", "paper_2306_16705_amd/csrc/enumerate.hpp",
-              "paper_2306_16705_amd/csrc/internal.hpp")
-
-
-def sa_sources_hash():
-    import hashlib
+def sources_hash(files):
     h = hashlib.sha256()
-    for f in SA_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def sa_traffic_bytes():
-    c = SA_COUNTERS
-    if c["fetch_kib"] is None or c["sources_sha256_16"] != sa_sources_hash():
+def tf_traffic_bytes():
+    c = TF_COUNTERS
+    if c["fetch_kib"] is None or c["sources_sha256_16"] != sources_hash(TF_SOURCES):
         return None
     return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
 
 
-def sa_kernel_name(tune):
-    """Template instance of the sample-aware kernel a schedule runs (one-word keys)."""
-    wide = tune["waves_per_block"] > 12
-    return f"k_eloc_sa<1, {tune['search'] - 1}, {1024 if wide else 768}>"
+def tf_class_flops(K: int, b: int) -> float:
+    """Algorithmic FLOP of the prefix-reusing forward for one connection of
+    class b: rows s = 16 b .. K-1, each through four layers of QKV (64 x 192),
+    output (64 x 64) and FFN (64 x 256 x 64) products, causal attention over
+    s + 1 keys (Q K^T and P V, 4 heads of 16), and the 64 x 4 head."""
+    per_row = 4 * 2 * (64 * 192 + 64 * 64 + 2 * 64 * 256) + 2 * 64 * 4
+    return float(sum(per_row + 4 * 4 * 2 * 16 * 2 * (s + 1) for s in range(16 * b, K)))
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def cores():
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-samples", type=int, default=32768,
-                    help="samples the oracle evaluates for the CPU baseline (0 = skip)")
-    ap.add_argument("--full-samples", type=int, default=16,
-                    help="samples of the N=120 transformer workload timed in the full-E_loc leg (0 = skip)")
-    ap.add_argument("--fp64-samples", type=int, default=8,
-                    help="of these, samples also evaluated by the plain FP64 path (error reference)")
-    ap.add_argument("--skip-nats", type=float, default=SKIP_NATS,
-                    help="contribution-rule threshold of the screened full path (nats below log|psi(x)|)")
-    ap.add_argument("--refine-nats", type=float, default=REFINE_NATS,
-                    help="FP64 refinement of terms above exp(-r) Ha in the screened full path")
-    ap.add_argument("--screen-steps", type=int, default=5000,
-                    help="Adam steps of the screen training in the full-E_loc leg")
-    ap.add_argument("--batch-systems", type=int, default=0,
-                    help="also time the batched launch over this many systems of the 32-system recipe (0 = skip)")
-    ap.add_argument("--pauli", type=int, default=1,
-                    help="also time the Pauli-string backend on the same workload (0 = skip)")
-    ap.add_argument("--schedule", type=str, default="",
-                    help="JSON launch schedule for the sample-aware kernel instead of autotuning (profiling runs)")
+    ap.add_argument("--steps", type=int, default=5, help="timed steps of the screened path")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--samples", type=int, default=128, help="samples per step (first ones the generator draws)")
+    ap.add_argument("--plain-reps", type=int, default=3, help="timed passes of the plain BF16 path (median; 0 = skip)")
+    ap.add_argument("--ratio", type=int, default=1, help="also time the workload's own 12-nat ratio rule (0 = skip)")
+    ap.add_argument("--fp64-samples", type=int, default=16,
+                    help="samples of the plain FP64 error reference (0 = skip; profiling runs)")
+    ap.add_argument("--screen-pairs", type=float, default=1e7, help="training pairs of the screen")
+    ap.add_argument("--screen-samples", type=int, default=512, help="samples the training pairs are drawn from")
+    ap.add_argument("--screen-steps", type=int, default=8000, help="Adam steps of the screen training")
+    ap.add_argument("--skip-nats", type=float, default=SKIP_NATS)
+    ap.add_argument("--refine-nats", type=float, default=REFINE_NATS)
+    ap.add_argument("--cpu-connections", type=int, default=4096,
+                    help="connections of one sample the FP64 oracle network evaluates (CPU baseline; 0 = skip)")
+    ap.add_argument("--sa", type=int, default=1, help="also time the sample-aware N=48 path (0 = skip)")
+    ap.add_argument("--batch-systems", type=int, default=32, help="systems of the batched launch (0 = skip)")
+    ap.add_argument("--pauli", type=int, default=1, help="also time the Pauli-string backend (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
@@ -114,89 +133,157 @@ def main():
 
     import paper_2306_16705_amd as nn
     import synth
+    from paper_2306_16705_amd import screen_train
 
-    log("generating inputs")
-    d = synth.config_inputs(2)
-    n = d["keys"].shape[0]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    keys = torch.from_numpy(d["keys"].view(np.int64).copy()).to(dev)
-    la = torch.from_numpy(d["logabs"].copy()).to(dev)
-    ph = torch.from_numpy(d["phase"].copy()).to(dev)
-    cnt = torch.from_numpy(d["counts"].astype(np.int32)).to(dev)
+    S_n = args.samples
+    log("generating the N=120 workload")
+    d = synth.config_inputs(5, n_unique=S_n + args.screen_samples)
+    K = d["K"]
     S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
-    T = nn.Table(S, capacity=n)
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
     C = S.connection_count
-    eloc = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    keys_all = torch.from_numpy(d["keys"].view(np.int64).copy()).to(dev)
+    cnt_all = torch.from_numpy(d["counts"].astype(np.int32)).to(dev)
+    keys, cnt = keys_all[:S_n].contiguous(), cnt_all[:S_n].contiguous()
+    w_np = d["counts"][:S_n].astype(np.float64)
+
+    # ---- screen: trained on connections of the samples after the timed subset
+    per = max(1, int(args.screen_pairs // args.screen_samples))
+    log(f"screen training pairs: {args.screen_samples} samples x {per} connections")
+    t = time.perf_counter()
+    xk, ex, lab = screen_train.connection_dataset(S, M, keys_all[S_n:].contiguous(), per_sample=per, seed=1)
+    t_data = time.perf_counter() - t
+    (xk, ex, lab), held = screen_train.split(xk, ex, lab, held_out=0.05, seed=4)
+    scr = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=2))
+    t = time.perf_counter()
+    losses = screen_train.train(scr, xk, ex, lab, steps=args.screen_steps, batch=4096, lr=2e-3, seed=3)
+    t_train = time.perf_counter() - t
+    n_pairs = int(xk.shape[0] + held[0].shape[0])
+    del xk, ex, lab
+    scr_used, rmse = screen_train.screen_or_plain(scr, *held)
+    del held
+    torch.cuda.empty_cache()
+    log(f"screen: {n_pairs} pairs ({t_data:.1f} s), {args.screen_steps} steps in {t_train:.1f} s, loss "
+        f"{losses[0]:.3g} -> {float(np.mean(losses[-50:])):.3g}, held-out RMSE {rmse:.3f} nats "
+        f"-> {'screened' if scr_used is not None else 'plain fallback'}")
+    screened_kw = dict(screen=scr_used, skip_nats=args.skip_nats, skip_rule=nn.NNQS_SKIP_CONTRIBUTION,
+                       refine_nats=args.refine_nats)
+    eloc = torch.empty((S_n, 2), dtype=torch.float64, device=dev)
     energy = torch.empty(4, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step(kernel_events=None):
-        T.build(keys, la, ph)
-        if kernel_events is not None:
-            kernel_events[0].record(stream)
-        nn.eloc_table(S, T, keys, cnt, la, ph, eloc=eloc, with_energy=False)
-        if kernel_events is not None:
-            kernel_events[1].record(stream)
-        nn.energy(T, cnt, eloc, out=energy)
+    def run(prec, k=keys, c=cnt, **kw):
+        return nn.eloc_model(S, M, k, c, prec, eloc=eloc[:k.shape[0]], energy=energy, **kw)
 
-    log("validating inputs")
-    T.build(keys, la, ph, validate=True)
-    nn.eloc_table(S, T, keys, cnt, la, ph, eloc=eloc, energy=energy, validate=True)
-    torch.cuda.synchronize()
-    if args.schedule:
-        T.set_tune(**json.loads(args.schedule))
-        tune = T.get_tune()
-        log(f"schedule {tune} (given)")
-    else:
-        log("autotuning the launch schedule")
-        tune, tune_ms = T.autotune(keys, la, ph, reps=2)
-        log(f"schedule {tune} ({tune_ms:.3f} ms per E_loc call)")
-    log(f"warmup {args.warmup}")
+    # ---- screened path: warm-up, then timed steps with the kernels' events
+    log(f"screened path: warmup {args.warmup}, {args.steps} timed steps of {S_n} samples")
     for _ in range(args.warmup):
-        step()
+        run(nn.NNQS_BF16, **screened_kw)
     torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    _, _, st_scr = run(nn.NNQS_BF16, with_stats=True, **screened_kw)
     torch.cuda.synchronize()
+    nn.timing_enable(True)
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
+    for _ in range(args.steps):
+        run(nn.NNQS_BF16, **screened_kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    list_ms, list_launches = nn.timing_read("k_transformer_bf16_list")
+    smp_ms, smp_launches = nn.timing_read("k_transformer_bf16")
+    scr_ms, _ = nn.timing_read("k_screen_infer")
+    ph_ms, _ = nn.timing_read("k_phase_bf16")
+    nn.timing_enable(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    samples_s = n / (ms_step * 1e-3)
-    conns_s = n * C / (ms_step * 1e-3)
-    achieved = ALU_OPS_PER_CONNECTION * n * C / (kernel_ms * 1e-3) / 1e9
-    e_gpu = eloc.cpu().numpy()
-    e_gpu = e_gpu[:, 0] + 1j * e_gpu[:, 1]
-    en = energy.cpu().numpy()
-    log(f"{ms_step:.3f} ms/step, kernel {kernel_ms:.3f} ms, {samples_s:.4g} samples/s, E={en[0]:.10f}")
+    e_scr = eloc.cpu().numpy().copy()
+    en_scr = energy.cpu().numpy().copy()
+    samples_s = S_n / (ms_step * 1e-3)
+    cls = st_scr["evaluated_class"]
+    flops_step = sum(cls[b] * tf_class_flops(K, b) for b in range(4))
+    achieved = flops_step * args.steps / (list_ms * 1e-3) / 1e12 if list_ms > 0 else None
+    log(f"screened: {ms_step:.1f} ms/step, {samples_s:.4g} samples/s; evaluated {st_scr['evaluated']} "
+        f"(classes {cls}), refined {st_scr['refined']}; list kernel {list_ms / max(1, list_launches):.3f} ms x "
+        f"{list_launches / args.steps:.0f} per step, {achieved:.1f} TFLOP/s")
 
+    # ---- plain BF16 on the same subset (median of reps)
+    times, cls_pl = [], None
+    for r in range(args.plain_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, st_pl = run(nn.NNQS_BF16, with_stats=(r == 0))
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        if r == 0:
+            cls_pl = st_pl["evaluated_class"]
+    dt_pl = float(np.median(times)) if times else None
+    e_pl = eloc.cpu().numpy().copy() if times else None
+    en_pl = energy.cpu().numpy().copy() if times else None
+    if times:
+        log(f"plain BF16: {S_n / dt_pl:.4g} samples/s (median of {args.plain_reps}), classes {cls_pl}")
+
+    # ---- the workload's own rule: ratio rule at 12 nats, no refinement
+    ratio_kw = dict(screen=scr_used, skip_nats=12.0, skip_rule=nn.NNQS_SKIP_RATIO, refine_nats=0.0)
+    st_ra, times = None, []
+    if args.ratio:
+        _, _, st_ra = run(nn.NNQS_BF16, with_stats=True, **ratio_kw)
+    for _ in range(3 if args.ratio else 0):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(nn.NNQS_BF16, **ratio_kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    dt_ra = float(np.median(times)) if times else None
+    e_ra = eloc.cpu().numpy().copy() if times else None
+    en_ra = energy.cpu().numpy().copy() if times else None
+
+    # ---- FP64 reference on the first samples of the subset
+    m = min(args.fp64_samples, S_n)
+    err = {"screened_bf16_refined": None, "plain_bf16": None, "screened_ratio_rule_12": None}
+    ref64, dt64 = None, None
+    if m > 0:
+        t0 = time.perf_counter()
+        e64, _, _ = nn.eloc_model(S, M, keys[:m].contiguous(), cnt[:m].contiguous(), nn.NNQS_FP64)
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t0
+        e64 = e64.cpu().numpy()
+
+        def energy_of(e, k=m):
+            return float(np.sum(w_np[:k] * e[:k, 0]) / np.sum(w_np[:k]))
+
+        ref64 = energy_of(e64)
+        for name, e in (("screened_bf16_refined", e_scr), ("plain_bf16", e_pl), ("screened_ratio_rule_12", e_ra)):
+            err[name] = energy_of(e) - ref64 if e is not None else None
+        log(f"energy error vs FP64 over {m} samples: " +
+            ", ".join(f"{k} {v:.2e} Ha" for k, v in err.items() if v is not None))
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
-    max_err = None
-    if args.cpu_samples > 0:
+    if args.cpu_connections > 0:
         import oracle
-        m = min(args.cpu_samples, n)
-        cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-        log(f"oracle on {m} samples, {cores} threads")
-        tc = time.perf_counter()
-        ref = oracle.eloc_table(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"], d["keys"],
-                                d["logabs"], d["phase"], d["keys"][:m], d["logabs"][:m], d["phase"][:m],
-                                nthreads=cores)
-        dt = time.perf_counter() - tc
-        max_err = float(np.max(np.abs(e_gpu[:m] - ref)))
-        cpu = {"value": m / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
-               "sample": f"first {m} of the {n} samples against the full table, FP64, {dt:.2f} s wall",
-               "connections_per_s": m * C / dt}
+        nthr = cores()
+        x0 = d["keys"][0]
+        t0 = time.perf_counter()
+        xp, _, _, _ = oracle.connections(K, d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"], x0)
+        t_conn = time.perf_counter() - t0
+        rng = np.random.default_rng([16705, 5, 99])
+        pick = xp[rng.choice(len(xp), size=min(args.cpu_connections, len(xp)), replace=False)]
+        t0 = time.perf_counter()
+        oracle.net_logpsi(d["weights"], d["model_shape"], d["n_up"], d["n_dn"], pick, nthreads=nthr)
+        t_net = time.perf_counter() - t0
+        t_sample = t_conn + t_net * C / len(pick)
+        cpu = {"value": 1.0 / t_sample, "unit": "samples/s", "cores": nthr, "kind": "oracle",
+               "sample": f"FP64 oracle: connections of one N=120 sample ({t_conn:.2f} s) and its network on "
+                         f"{len(pick)} of the {C} connected configurations ({t_net:.2f} s), scaled to the whole "
+                         f"sample ({t_sample:.0f} s per sample on {nthr} threads)",
+               "connections_per_s": C / t_sample}
+        log(f"oracle: {t_sample:.1f} s per sample on {nthr} threads")
 
-    pauli = pauli_leg(args, nn, S, T, keys, cnt, la, ph, n, C, np, torch) if args.pauli else None
+    sa = sample_aware_leg(args, nn, synth, np, torch) if args.sa else None
     batch = batch_leg(args, nn, synth, np, torch) if args.batch_systems > 0 else None
-    full = full_path_leg(args, nn, synth, np, torch) if args.full_samples > 0 else None
 
     out = {
-        "metric": "E_loc samples/s + connections/s at 1e-4 Ha error; learned/BF16 vs plain",
+        "metric": METRIC,
         "value": samples_s,
         "unit": "samples/s",
         "n_gpus": 1,
@@ -206,24 +293,140 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": "sample-aware E_loc, N=48 (K=24), 6 up + 6 down, 65,536 unique samples, "
-                               "FP64, table build + E_loc + weighted energy per step",
-                   "n_unique": n, "connections_per_sample": C, "schedule": tune},
-        "connections_per_s": conns_s,
-        "energy": float(en[0]),
-        "max_abs_err_vs_oracle_ha": max_err,
-        "roofline": {"bound": "alu", "kernel": sa_kernel_name(tune), "achieved": achieved, "peak": ALU_PEAK_GOPS,
-                     "unit": "Gop/s", "frac": achieved / ALU_PEAK_GOPS, "traffic": sa_traffic_bytes(),
-                     "traffic_unit": "bytes per launch", "sources_sha256_16": sa_sources_hash(),
-                     "kernel_ms": kernel_ms, "ops_per_connection": ALU_OPS_PER_CONNECTION},
+        "config": {"workload": f"learned screen + BF16 transformer full E_loc: N=120 (K=60), 20 up + 20 down, "
+                               f"{C} connections per sample, first {S_n} samples of the seeded N=120 generator per "
+                               f"step; contribution rule at {args.skip_nats} nats, FP64 refinement above "
+                               f"exp(-{args.refine_nats}) Ha; FP64 ratios and sums",
+                   "samples_per_step": S_n, "connections_per_sample": C},
+        "connections_per_s": S_n * C / (ms_step * 1e-3),
+        "speedup_vs_plain_bf16": samples_s / (S_n / dt_pl) if dt_pl else None,
+        "energy_err_vs_fp64_ha": err["screened_bf16_refined"],
+        "meets_1e-4_ha": abs(err["screened_bf16_refined"]) <= 1e-4 if m > 0 else None,
+        "roofline": {"bound": "mfma", "kernel": "k_transformer_bf16_list", "achieved": achieved,
+                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / BF16_PEAK_TFLOPS if achieved else None, "traffic": tf_traffic_bytes(),
+                     "traffic_unit": "bytes per launch", "sources_sha256_16": sources_hash(TF_SOURCES),
+                     "kernel_ms_per_launch": list_ms / max(1, list_launches),
+                     "launches_per_step": list_launches / args.steps,
+                     "algorithmic_flop_per_step": flops_step,
+                     "evaluated_by_prefix_class": cls,
+                     "other_kernels_ms_per_step": {"k_transformer_bf16": smp_ms / args.steps,
+                                                   "k_screen_infer": scr_ms / args.steps,
+                                                   "k_phase_bf16": ph_ms / args.steps}},
         "cpu_baseline": cpu,
-        "pauli_path": pauli,
+        "screened_bf16_refined": {"samples_per_s": samples_s, "energy": float(en_scr[0]),
+                                  "evaluated_fraction": st_scr["evaluated"] / st_scr["connections"],
+                                  "refined_fraction": st_scr["refined"] / st_scr["connections"],
+                                  "skip_rule": "contribution", "skip_nats": args.skip_nats,
+                                  "refine_nats": args.refine_nats},
+        "plain_bf16": ({"samples_per_s": S_n / dt_pl, "connections_per_s": S_n * C / dt_pl,
+                        "energy": float(en_pl[0]), "energy_err_vs_fp64_ha": err["plain_bf16"],
+                        "evaluated_by_prefix_class": cls_pl, "reps": args.plain_reps} if dt_pl else None),
+        "screened_ratio_rule_12": ({"samples_per_s": S_n / dt_ra, "energy": float(en_ra[0]),
+                                    "energy_err_vs_fp64_ha": err["screened_ratio_rule_12"],
+                                    "meets_1e-4_ha": (abs(err["screened_ratio_rule_12"]) <= 1e-4
+                                                      if err["screened_ratio_rule_12"] is not None else None),
+                                    "evaluated_fraction": st_ra["evaluated"] / st_ra["connections"],
+                                    "note": "the workload's own rule (skip below exp(-12)|psi(x)|), no refinement"}
+                                   if dt_ra else None),
+        "plain_fp64": {"samples_per_s": m / dt64, "samples": m, "energy_first_samples": ref64} if m > 0 else None,
+        "error_reference": f"plain FP64 GPU path on the first {m} samples (itself checked against the FP64 oracle "
+                           "to 1e-10 per sample in the tests)",
+        "screen": {"pairs": n_pairs, "labels": "BF16 network log|psi(x')|", "data_s": t_data,
+                   "training_s": t_train, "adam_steps": args.screen_steps, "held_out_rmse_nats": rmse,
+                   "used": scr_used is not None},
+        "sample_aware_n48": sa,
         "batch_path": batch,
-        "full_path": full,
     }
+    if args.pauli and sa is not None:
+        out["pauli_path"] = sa.pop("pauli", None)
     print(json.dumps(out), flush=True)
+
+
+def sample_aware_leg(args, nn, synth, np, torch):
+    """The sample-aware path (table lookup of psi(x'), FP64): N=48 (K=24),
+    6 up + 6 down, 65,536 unique samples; a step is the table build, E_loc and
+    the weighted energy.  Autotuned schedule, 20 timed steps, the hot kernel
+    timed with events on its stream, the oracle on a bounded sample."""
+    log("sample-aware N=48 path")
+    d = synth.config_inputs(2)
+    n = d["keys"].shape[0]
+    keys = torch.from_numpy(d["keys"].view(np.int64).copy()).cuda()
+    la = torch.from_numpy(d["logabs"].copy()).cuda()
+    ph = torch.from_numpy(d["phase"].copy()).cuda()
+    cnt = torch.from_numpy(d["counts"].astype(np.int32)).cuda()
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    T = nn.Table(S, capacity=n)
+    C = S.connection_count
+    eloc = torch.empty((n, 2), dtype=torch.float64, device="cuda")
+    energy = torch.empty(4, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    T.build(keys, la, ph, validate=True)
+    tune, _ = T.autotune(keys, la, ph, reps=2)
+    steps = 20
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for _ in range(3):
+        T.build(keys, la, ph)
+        nn.eloc_table(S, T, keys, cnt, la, ph, eloc=eloc, with_energy=False)
+        nn.energy(T, cnt, eloc, out=energy)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        T.build(keys, la, ph)
+        evs[k][0].record(stream)
+        nn.eloc_table(S, T, keys, cnt, la, ph, eloc=eloc, with_energy=False)
+        evs[k][1].record(stream)
+        nn.energy(T, cnt, eloc, out=energy)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    kms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    import oracle
+    mm = 4096
+    g = eloc.cpu().numpy()
+    ref = oracle.eloc_table(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"], d["keys"], d["logabs"],
+                            d["phase"], d["keys"][:mm], d["logabs"][:mm], d["phase"][:mm], nthreads=cores())
+    err = float(np.max(np.abs(g[:mm, 0] + 1j * g[:mm, 1] - ref)))
+    ach = SA_OPS_PER_CONNECTION * n * C / (kms * 1e-3) / 1e9
+    res = {"workload": "sample-aware E_loc, N=48 (K=24), 6 up + 6 down, 65,536 unique samples, FP64, table build + "
+                       "E_loc + weighted energy per step", "samples_per_s": n / (ms * 1e-3),
+           "connections_per_s": n * C / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": kms, "schedule": tune,
+           "max_abs_err_vs_oracle_ha": err, "oracle_checked_samples": mm,
+           "roofline": {"bound": "alu", "achieved": ach, "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
+                        "frac": ach / ALU_PEAK_GOPS, "ops_per_connection": SA_OPS_PER_CONNECTION}}
+    log(f"sample-aware: {ms:.3f} ms/step, {n / (ms * 1e-3):.4g} samples/s")
+    if args.pauli:
+        res["pauli"] = pauli_leg(nn, S, T, keys, cnt, la, ph, n, np, torch)
+    return res
+
+
+def pauli_leg(nn, S, T, keys, cnt, la, ph, n, np, torch):
+    """The paper's own formulation (grouped Pauli strings, Algorithms 1 and
+    2) on the sample-aware workload: build time, layout sizes, E_loc time
+    and its agreement with the Slater-Condon result."""
+    log("Pauli-string backend")
+    t0 = time.perf_counter()
+    P = nn.Pauli(S)
+    t_build = time.perf_counter() - t0
+    info = P.info()
+    T.build(keys, la, ph)
+    e1, _ = nn.eloc_pauli(P, T, keys, cnt, la, ph)
+    e2, _ = nn.eloc_table(S, T, keys, cnt, la, ph)
+    torch.cuda.synchronize()
+    a, b = e1.cpu().numpy(), e2.cpu().numpy()
+    diff = float(np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b))))
+    best = 1e30
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        nn.eloc_pauli(P, T, keys, cnt, la, ph)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t1)
+    return {"groups": info["groups"], "strings": info["strings"], "bytes_grouped": info["bytes_grouped"],
+            "bytes_flat": info["bytes_flat"], "layout_saving": 1.0 - info["bytes_grouped"] / info["bytes_flat"],
+            "build_s": t_build, "eloc_ms": best * 1e3, "samples_per_s": n / best,
+            "max_rel_diff_vs_slater_condon": diff}
 
 
 def batch_leg(args, nn, synth, np, torch):
@@ -252,120 +455,16 @@ def batch_leg(args, nn, synth, np, torch):
     B.capture(st)
     B.launch(st)
     st.synchronize()
-    best = 1e30
-    for _ in range(3):
+    times = []
+    for _ in range(5):
         t0 = time.perf_counter()
         B.launch(st)
         st.synchronize()
-        best = min(best, time.perf_counter() - t0)
-    log(f"batch: {best * 1e3:.1f} ms per graph step, {tot_s / best:.4g} samples/s")
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    log(f"batch: {med * 1e3:.1f} ms per graph step, {tot_s / med:.4g} samples/s")
     return {"systems": args.batch_systems, "samples": tot_s, "connections": tot_c, "schedule": tune,
-            "ms_per_graph_step": best * 1e3, "samples_per_s": tot_s / best, "connections_per_s": tot_c / best}
-
-
-def pauli_leg(args, nn, S, T, keys, cnt, la, ph, n, C, np, torch):
-    """The paper's own formulation (grouped Pauli strings, Algorithms 1 and
-    2) on the bench workload: build time, layout sizes, E_loc time and its
-    agreement with the Slater-Condon result."""
-    log("Pauli-string backend")
-    t0 = time.perf_counter()
-    P = nn.Pauli(S)
-    t_build = time.perf_counter() - t0
-    info = P.info()
-    T.build(keys, la, ph)
-    e1, _ = nn.eloc_pauli(P, T, keys, cnt, la, ph)
-    e2, _ = nn.eloc_table(S, T, keys, cnt, la, ph)
-    torch.cuda.synchronize()
-    a, b = e1.cpu().numpy(), e2.cpu().numpy()
-    diff = float(np.max(np.abs(a - b) / np.maximum(1.0, np.abs(b))))
-    best = 1e30
-    for _ in range(3):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        nn.eloc_pauli(P, T, keys, cnt, la, ph)
-        torch.cuda.synchronize()
-        best = min(best, time.perf_counter() - t1)
-    log(f"Pauli: {info['groups']} groups, {info['strings']} strings, {best * 1e3:.2f} ms per E_loc")
-    return {"groups": info["groups"], "strings": info["strings"], "bytes_grouped": info["bytes_grouped"],
-            "bytes_flat": info["bytes_flat"], "layout_saving": 1.0 - info["bytes_grouped"] / info["bytes_flat"],
-            "build_s": t_build, "eloc_ms": best * 1e3, "samples_per_s": n / best,
-            "groups_per_s": n * info["groups"] / best, "max_rel_diff_vs_slater_condon": diff}
-
-
-# Operating point of the screened full path: skip a connection when its
-# predicted contribution |H_xx' psi(x')/psi(x)| is below exp(-16.5) Ha, and
-# recompute in FP64 every evaluated term above exp(-7) Ha.
-SKIP_NATS = 16.5
-REFINE_NATS = 7.0
-
-
-def full_path_leg(args, nn, synth, np, torch):
-    """Full E_loc on the N=120 (20 up + 20 down) transformer workload: plain
-    FP64, plain BF16, and BF16 behind the learned screen with FP64
-    refinement of the large terms.  The screen is trained first (untimed) on
-    connections of 16 further samples (16,384 each)."""
-    log("full path: N=120 transformer workload")
-    n = args.full_samples
-    d = synth.config_inputs(3, n_unique=n + 16)
-    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
-    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
-    C = S.connection_count
-    keys = torch.from_numpy(d["keys"].view(np.int64).copy()).cuda()
-    cnt = torch.from_numpy(d["counts"].astype(np.int32)).cuda()
-    from paper_2306_16705_amd import screen_train
-    t = time.perf_counter()
-    xk, ex, lab = screen_train.connection_dataset(S, M, keys[n:], per_sample=16384, seed=1)
-    (xk, ex, lab), held = screen_train.split(xk, ex, lab, held_out=0.05, seed=4)
-    scr = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=2))
-    losses = screen_train.train(scr, xk, ex, lab, steps=args.screen_steps, batch=4096, lr=2e-3, seed=3)
-    t_train = time.perf_counter() - t
-    log(f"screen trained in {t_train:.1f} s, loss {losses[0]:.4g} -> {float(np.mean(losses[-20:])):.4g}")
-    tk, tc = keys[:n].contiguous(), cnt[:n].contiguous()
-    # held-out pairs (5 % kept out of training): a screen worse than 1 nat
-    # RMS falls back to the plain evaluation
-    scr_used, rmse = screen_train.screen_or_plain(scr, *held)
-    log(f"screen held-out RMSE {rmse:.3f} nats -> {'screened' if scr_used is not None else 'plain fallback'}")
-    screened_kw = dict(screen=scr_used, skip_nats=args.skip_nats, skip_rule=nn.NNQS_SKIP_CONTRIBUTION,
-                       refine_nats=args.refine_nats)
-
-    def timed(prec, k, c, **kw):
-        nn.eloc_model(S, M, k[:1], c[:1], prec, **kw)  # warm scratch
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e, en, st = nn.eloc_model(S, M, k, c, prec, with_stats=True, **kw)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0, e.cpu().numpy(), en.cpu().numpy(), st
-
-    dt16, e16, en16, st16 = timed(nn.NNQS_BF16, tk, tc)
-    dts, es, ens, sts = timed(nn.NNQS_BF16, tk, tc, **screened_kw)
-    m = min(args.fp64_samples, n)
-    res = {"workload": f"full E_loc, N=120 (K=60), 20 up + 20 down, transformer d_model 64, 4 layers, 4 heads, "
-                       f"FFN 256 + phase MLP, {n} samples ({C} connections each)",
-           "samples": n, "connections_per_sample": C,
-           "plain_bf16": {"samples_per_s": n / dt16, "connections_per_s": n * C / dt16, "energy": float(en16[0])},
-           "screened_bf16_refined": {"samples_per_s": n / dts, "connections_per_s": n * C / dts,
-                                     "energy": float(ens[0]), "evaluated_fraction": sts["evaluated"] / sts["connections"],
-                                     "refined_fraction": sts["refined"] / sts["connections"],
-                                     "skip_rule": "contribution", "skip_nats": args.skip_nats,
-                                     "refine_nats": args.refine_nats},
-           "screen_training_s": t_train, "screen_held_out_rmse_nats": rmse,
-           "speedup_screened_vs_plain_bf16": dt16 / dts}
-    if m > 0:
-        dt64, e64, en64, _ = timed(nn.NNQS_FP64, tk[:m].contiguous(), tc[:m].contiguous())
-        w = d["counts"][:m].astype(np.float64)
-
-        def energy_of(e):
-            return float(np.sum(w * e[:m, 0]) / np.sum(w))
-        ref = energy_of(e64)
-        res["plain_fp64"] = {"samples_per_s": m / dt64, "connections_per_s": m * C / dt64, "samples": m,
-                             "energy": ref}
-        res["energy_err_vs_fp64_ha"] = {"plain_bf16": energy_of(e16) - ref,
-                                        "screened_bf16_refined": energy_of(es) - ref,
-                                        "over_samples": m}
-        res["speedup_screened_vs_plain_fp64"] = (n / dts) / (m / dt64)
-    log(f"full path: plain BF16 {n / dt16:.3g} samples/s, screened {n / dts:.3g} samples/s "
-        f"({res['speedup_screened_vs_plain_bf16']:.2f}x)")
-    return res
+            "ms_per_graph_step": med * 1e3, "samples_per_s": tot_s / med, "connections_per_s": tot_c / med}
 
 
 if __name__ == "__main__":

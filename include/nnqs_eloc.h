@@ -301,6 +301,11 @@ typedef struct {
     int64_t connections; /* connected configurations enumerated, diagonal included */
     int64_t evaluated;   /* of these, evaluated by the network in `precision` (all without a screen) */
     int64_t refined;     /* of these, evaluated again by the FP64 network (refinement) */
+    /* BF16 only: `evaluated` split by prefix class b = 0..3, the connections
+     * whose first changed sequence position is in [16 b, 16 b + 16) (b = 3:
+     * from 48 on); the forward evaluates their rows from 16 b on (see
+     * nnqs_eloc_model).  Zero for FP64. */
+    int64_t evaluated_class[4];
 } nnqs_stats;
 
 /* Screen rules: a connection x' goes to the network when
@@ -331,14 +336,45 @@ typedef struct {
  * evaluated by the network; the rest contribute zero.  The network runs in
  * `precision` (then, with refinement, FP64 for the large terms); matrix
  * elements, amplitude ratios and all sums are FP64 with compensated
- * summation.  `stats` (host, may be NULL) receives the counters; with a
- * screen, refinement or stats the call synchronises `stream`.  Uses
- * library-owned scratch sized at first use (one call at a time per model).
+ * summation.  In BF16 each chunk's samples run through the network once,
+ * keeping every layer's keys and values; a connected x' whose first changed
+ * sequence position s0 lies in row block b = min(3, s0 / 16) then evaluates
+ * only rows from 16 b on, attending to the sample's cached rows before (by
+ * causality of the attention and of the autoregressive product of Eq. 8 the
+ * rows up to s0 equal the sample's; results are identical to the whole
+ * forward of x').  `stats` (host, may be NULL) receives the counters; with
+ * refinement (or a screen in FP64) or stats the call synchronises `stream`.
+ * Uses library-owned scratch sized at first use (one call at a time per
+ * model).
  * Errors: EINVAL, ECONSERVE (VALIDATE), ENOMEM, EUNSUPPORTED, EHIP. */
 nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model, nnqs_screen *screen,
                             const nnqs_eloc_opts *opts, int32_t precision, const uint64_t *keys,
                             const uint32_t *counts, int64_t n, double *eloc, double *energy, nnqs_stats *stats,
                             uint32_t flags, void *stream);
+
+/* Fallback judge of a screen (the plain evaluation is the fallback): the
+ * root-mean-square error, in nats, of its predictions in `precision` against
+ * target log|psi| on pairs it was not trained on (device xkeys [n][2],
+ * exc [n][4], target [n]) into *rmse (host), and *usable (host, may be NULL)
+ * = 1 when rmse <= max_rmse, else 0.  Synchronises `stream`.
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EHIP. */
+nnqs_status nnqs_screen_judge(nnqs_screen *screen, const uint64_t *xkeys, const uint8_t *exc, const double *target,
+                              int64_t n, int32_t precision, double max_rmse, double *rmse, int32_t *usable,
+                              void *stream);
+
+/* ---------------------------------------------------------- measurement */
+/* Timing of the library's own hot launches: with enable = 1 (which also
+ * clears earlier records) every launch of k_transformer_bf16 (whole
+ * sequences), k_transformer_bf16_list (prefix-reusing connections),
+ * k_phase_bf16 and k_screen_infer is bracketed by HIP events recorded on the
+ * stream it runs on; enable = 0 stops recording.  Not for use while a stream
+ * is being captured into a graph. */
+nnqs_status nnqs_timing_enable(int32_t enable);
+
+/* Waits for the recorded events and returns the summed duration (ms) and
+ * the number of recorded launches of `kernel` since the last enable.
+ * Errors: EINVAL, EHIP. */
+nnqs_status nnqs_timing_read(const char *kernel, double *total_ms, int64_t *launches);
 
 /* ------------------------------------------------------------- tuning */
 /* Launch parameters of the sample-aware kernel (0 = library default). */

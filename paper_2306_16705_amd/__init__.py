@@ -27,5 +27,7 @@ from .api import (  # noqa: F401
     energy_noalloc,
     model_logpsi,
     pauli_build_host,
+    timing_enable,
+    timing_read,
     version,
 )

@@ -34,6 +34,10 @@ SIGNATURES = {
                                _c_void_p, _u32, _c_void_p]),
     "nnqs_energy": (_i32, [_c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p]),
     "nnqs_energy_noalloc": (_i32, [_c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p]),
+    "nnqs_screen_judge": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _i32, _f64,
+                                 ctypes.POINTER(_f64), ctypes.POINTER(_i32), _c_void_p]),
+    "nnqs_timing_enable": (_i32, [_i32]),
+    "nnqs_timing_read": (_i32, [ctypes.c_char_p, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]),
     "nnqs_table_set_tune": (_i32, [_c_void_p, _c_void_p]),
     "nnqs_table_get_tune": (_i32, [_c_void_p, _c_void_p]),
     "nnqs_model_weight_count": (_i64, [_c_void_p]),
@@ -97,7 +101,7 @@ class ModelDesc(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("connections", _i64), ("evaluated", _i64), ("refined", _i64)]
+    _fields_ = [("connections", _i64), ("evaluated", _i64), ("refined", _i64), ("evaluated_class", _i64 * 4)]
 
 
 class ElocOpts(ctypes.Structure):

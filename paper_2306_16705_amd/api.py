@@ -291,8 +291,22 @@ def eloc_model(system: System, model: Model, keys, counts=None, precision: int =
                                      _ptr(eloc), _ptr(energy) if with_energy else None,
                                      ctypes.byref(st) if with_stats else None, NNQS_VALIDATE if validate else 0,
                                      _stream(stream)))
-    stats = {"connections": st.connections, "evaluated": st.evaluated, "refined": st.refined} if with_stats else None
+    stats = ({"connections": st.connections, "evaluated": st.evaluated, "refined": st.refined,
+              "evaluated_class": list(st.evaluated_class)} if with_stats else None)
     return eloc, (energy if with_energy else None), stats
+
+
+# ------------------------------------------------------------- measurement
+def timing_enable(enable: bool = True) -> None:
+    """Start (and clear) or stop the library's event timing of its hot launches."""
+    L.check(L.load().nnqs_timing_enable(1 if enable else 0))
+
+
+def timing_read(kernel: str):
+    """``(total ms, launches)`` of ``kernel`` since the last ``timing_enable``."""
+    ms, cnt = ctypes.c_double(), ctypes.c_int64()
+    L.check(L.load().nnqs_timing_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
 
 
 # ------------------------------------------------------------------ screen
@@ -337,6 +351,17 @@ class Screen:
         L.check(self._lib.nnqs_screen_gradient(self.handle, _ptr(xkeys), _ptr(exc), _ptr(target), n, int(precision),
                                                _ptr(grad), _ptr(loss), _stream(stream)))
         return grad, loss
+
+    def judge(self, xkeys, exc, target, precision: int = NNQS_BF16, max_rmse: float = 1.0, stream=None):
+        """``(rmse, usable)`` of the fallback judge (``nnqs_screen_judge``)."""
+        n = xkeys.shape[0]
+        _need(xkeys, "xkeys", _KEY_DTYPES, (n, 2))
+        _need(exc, "exc", (torch.uint8,), (n, 4))
+        _need(target, "target", (torch.float64,), (n,))
+        rmse, ok = ctypes.c_double(), ctypes.c_int32()
+        L.check(self._lib.nnqs_screen_judge(self.handle, _ptr(xkeys), _ptr(exc), _ptr(target), n, int(precision),
+                                            float(max_rmse), ctypes.byref(rmse), ctypes.byref(ok), _stream(stream)))
+        return rmse.value, bool(ok.value)
 
     def adam_step(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _need(grad, "grad", (torch.float64,), (self.count,))

@@ -204,8 +204,8 @@ __global__ void __launch_bounds__(256) k_cls_count(ClsArgs a, int32_t *__restric
 
 // Turns the per-block counts into absolute list positions (classes stored
 // one after another), writes hdr = {count[4], offset[4]} and adds the kept
-// total to *evaluated.  One block; each thread scans a contiguous run of
-// blocks.
+// total and the per-class counts to evaluated[0..4].  One block; each thread
+// scans a contiguous run of blocks.
 __global__ void __launch_bounds__(256) k_cls_scan(int32_t *__restrict__ cnt, int nblocks, int64_t *__restrict__ hdr,
                                                   int64_t *__restrict__ evaluated) {
     __shared__ int64_t part[4][257];
@@ -241,8 +241,9 @@ __global__ void __launch_bounds__(256) k_cls_scan(int32_t *__restrict__ cnt, int
         for (int k = 0; k < 4; k++) {
             hdr[k] = tot[k];
             hdr[4 + k] = off[k];
+            if (evaluated) evaluated[1 + k] += tot[k];
         }
-        if (evaluated) *evaluated += acc;
+        if (evaluated) evaluated[0] += acc;
     }
 }
 
@@ -276,7 +277,9 @@ __global__ void __launch_bounds__(64) k_cls_write(ClsArgs a, const int32_t *__re
     }
 }
 
-__global__ void k_zero_i64(int64_t *p) { *p = 0; }
+__global__ void k_zero_i64(int64_t *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
 
 __global__ void __launch_bounds__(256) k_eloc_partial(SysView S, const uint64_t *__restrict__ keys,
                                                       const double *__restrict__ sla,
@@ -523,7 +526,7 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
     if (s1 != NNQS_OK) return s1;
     int64_t evaluated = 0, refined = 0;
     int64_t *d_evalcnt = model->d_hdr + 8;
-    if (bf16) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, st, d_evalcnt);
+    if (bf16) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, d_evalcnt, 5);
     for (int64_t s0 = 0; s0 < n; s0 += chunk) {
         const int64_t m = n - s0 < chunk ? n - s0 : chunk;
         const int64_t total = m * C;
@@ -592,8 +595,11 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (s1 != NNQS_OK) return s1;
     }
     if (stats) {
-        if (bf16) NNQS_HIP_CHECK(hipMemcpyAsync(&evaluated, d_evalcnt, 8, hipMemcpyDeviceToHost, st));
+        int64_t ev[5] = {0, 0, 0, 0, 0};
+        if (bf16) NNQS_HIP_CHECK(hipMemcpyAsync(ev, d_evalcnt, sizeof(ev), hipMemcpyDeviceToHost, st));
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
+        if (bf16) evaluated = ev[0];
+        for (int k = 0; k < 4; k++) stats->evaluated_class[k] = ev[1 + k];
         stats->connections = n * C;
         stats->evaluated = evaluated;
         stats->refined = refined;

@@ -25,6 +25,22 @@ void clear_error();
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Measurement of the library's own launches (nnqs_timing_enable/_read):
+// while timing is on, a TimedRegion records HIP events on `st` around the
+// launches enqueued during its lifetime, under the kernel name given.
+class TimedRegion {
+  public:
+    TimedRegion(const char *name, hipStream_t st);
+    ~TimedRegion();
+    TimedRegion(const TimedRegion &) = delete;
+    TimedRegion &operator=(const TimedRegion &) = delete;
+
+  private:
+    const char *name_;
+    hipStream_t st_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
 // ------------------------------------------------------ device-side views
 // Everything a kernel needs about the Hamiltonian, passed by value.
 struct SysView {

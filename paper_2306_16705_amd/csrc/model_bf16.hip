@@ -354,7 +354,8 @@ __device__ __forceinline__ void attend(int QB, const __bf16 *Qq, const KvSrc &S,
     }
 }
 
-__global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) {
+template <bool kList>
+__device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs &A) {
     __shared__ __align__(16) __bf16 wbuf[192 * kLd];
     __shared__ __align__(16) float2 gtab[kGeluN];
     __shared__ __align__(16) __bf16 xs[kSlots][16 * kLd];
@@ -374,10 +375,10 @@ __global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) 
     __bf16 *Pb = ps[w];
     for (int i = threadIdx.x; i < kGeluN; i += blockDim.x)
         gtab[i] = make_float2(wf[M.fl.gelu + 2 * i], wf[M.fl.gelu + 2 * i + 1]);
-    if (A.list_mode && threadIdx.x < 8) sh_hdr[threadIdx.x] = A.hdr[threadIdx.x];
+    if (kList && threadIdx.x < 8) sh_hdr[threadIdx.x] = A.hdr[threadIdx.x];
     __syncthreads();
     int64_t tiles[4] = {0, 0, 0, 0}, T;
-    if (A.list_mode) {
+    if (kList) {
         T = 0;
         for (int c = 0; c < 4; c++) {
             tiles[c] = (sh_hdr[c] + cls_cpt(c) - 1) / cls_cpt(c);
@@ -397,7 +398,7 @@ __global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) 
     for (int64_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
         int cls = 0;
         int64_t tb = tile * 4, cnt = A.n, lbase = 0;
-        if (A.list_mode) {
+        if (kList) {
             int64_t tt = tile;
             cls = 3;
             for (int c = 0; c < 3; c++) {
@@ -423,7 +424,7 @@ __global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) 
             Key x{0ull, 0ull};
             ssmp[j] = 0;
             if (valid) {
-                if (A.list_mode) {
+                if (kList) {
                     const int64_t e = A.list[lbase + tb + sc[j]];
                     x.lo = A.xkeys[2 * e];
                     x.hi = A.xkeys[2 * e + 1];
@@ -519,7 +520,7 @@ __global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) 
                     S.vt = &vt[0][0];
                     S.cls = cls;
                     S.c = sc[j];
-                    S.sb = A.list_mode ? cls : 0;
+                    S.sb = kList ? cls : 0;
                     attend(srb[j], qs[2 * w + j], S, Pb, j ? O1 : O0, hh);
                 }
                 __syncthreads();  // every slot done with this head's K and V (and the QKV weights)
@@ -625,7 +626,7 @@ __global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) 
         // per configuration: sum of its row blocks in block order
         if ((int)threadIdx.x < cpt && tb + (int)threadIdx.x < cnt) {
             const int c = threadIdx.x;
-            if (A.list_mode) {
+            if (kList) {
                 const int64_t e = A.list[lbase + tb + c];
                 double acc = A.pre_in[(e / A.C) * 4 + cls];
                 for (int kb = cls; kb < 4; kb++) acc += slot_lp[slot_of(cls, c, kb)];
@@ -644,6 +645,10 @@ __global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) 
 }
 
 // Phase MLP: 16 configurations per wave, B tiles from global (L2) memory.
+__global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) { transformer_bf16<false>(M, A); }
+
+__global__ void __launch_bounds__(512) k_transformer_bf16_list(Bf16View M, TfArgs A) { transformer_bf16<true>(M, A); }
+
 // In list mode (see TfArgs) the configurations are xkeys[list[k]] for k
 // below the total of the four class counts, and phase[list[k]] receives them.
 __global__ void __launch_bounds__(256) k_phase_bf16(Bf16View M, TfArgs A, double *__restrict__ phase) {
@@ -869,8 +874,14 @@ nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64
     A.keys = keys;
     A.n = n;
     A.logabs = logabs;
-    hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, v, A);
-    hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(n)), dim3(kWaves * 64), 0, st, v, A, phase);
+    {
+        TimedRegion tr("k_transformer_bf16", st);
+        hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, v, A);
+    }
+    {
+        TimedRegion tr("k_phase_bf16", st);
+        hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(n)), dim3(kWaves * 64), 0, st, v, A, phase);
+    }
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
 }
@@ -886,7 +897,10 @@ nnqs_status enqueue_bf16_cached(const nnqs_model *m, const uint64_t *keys, int64
     A.logabs = logabs;
     A.kv_out = kv;
     A.pre_out = pre;
-    hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, bf16_view(m), A);
+    {
+        TimedRegion tr("k_transformer_bf16", st);
+        hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, bf16_view(m), A);
+    }
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
 }
@@ -905,8 +919,14 @@ nnqs_status enqueue_bf16_list(const nnqs_model *m, const uint64_t *xkeys, int64_
     A.C = C;
     A.xla = xla;
     A.list_mode = 1;  // kv_out / pre_out stay null: list mode only reads the cache
-    hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((max_entries + 3) / 4)), dim3(512), 0, st, v, A);
-    hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(max_entries)), dim3(kWaves * 64), 0, st, v, A, xph);
+    {
+        TimedRegion tr("k_transformer_bf16_list", st);
+        hipLaunchKernelGGL(k_transformer_bf16_list, dim3(tf_grid((max_entries + 3) / 4)), dim3(512), 0, st, v, A);
+    }
+    {
+        TimedRegion tr("k_phase_bf16", st);
+        hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(max_entries)), dim3(kWaves * 64), 0, st, v, A, xph);
+    }
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
 }

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -451,6 +452,44 @@ static nnqs_status noalloc_scratch(double **out) {
     return NNQS_OK;
 }
 
+// ------------------------------------------------------------- timing
+struct TimingRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+static std::mutex g_timing_mu;
+static std::atomic<bool> g_timing{false};
+static std::vector<TimingRec> g_timing_recs;
+
+static void timing_clear_locked() {
+    for (auto &r : g_timing_recs) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_timing_recs.clear();
+}
+
+TimedRegion::TimedRegion(const char *name, hipStream_t st) : name_(name), st_(st) {
+    if (!g_timing.load(std::memory_order_relaxed)) return;
+    if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess ||
+        hipEventRecord(a_, st_) != hipSuccess) {
+        if (a_) hipEventDestroy(a_);
+        if (b_) hipEventDestroy(b_);
+        a_ = b_ = nullptr;
+    }
+}
+
+TimedRegion::~TimedRegion() {
+    if (!a_) return;
+    if (hipEventRecord(b_, st_) != hipSuccess) {
+        hipEventDestroy(a_);
+        hipEventDestroy(b_);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timing_recs.push_back({name_, a_, b_});
+}
+
 nnqs_status read_status(nnqs_table *tab, hipStream_t st, bool clear) {
     int h = 0;
     NNQS_HIP_CHECK(hipMemcpyAsync(&h, tab->status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -748,6 +787,34 @@ nnqs_status nnqs_energy_noalloc(const uint32_t *counts, const double *eloc, int6
     const nnqs_status s = noalloc_scratch(&sc);
     if (s != NNQS_OK) return s;
     return enqueue_energy_partials(sc, counts, eloc, n, energy, as_stream(stream));
+}
+
+
+nnqs_status nnqs_timing_enable(int32_t enable) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    timing_clear_locked();
+    g_timing.store(enable != 0);
+    return NNQS_OK;
+}
+
+nnqs_status nnqs_timing_read(const char *kernel, double *total_ms, int64_t *launches) {
+    clear_error();
+    if (!kernel || !total_ms) return fail(NNQS_EINVAL, "null pointer argument");
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto &r : g_timing_recs) {
+        if (std::strcmp(r.name, kernel) != 0) continue;
+        NNQS_HIP_CHECK(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        NNQS_HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
+        tot += ms;
+        cnt++;
+    }
+    *total_ms = tot;
+    if (launches) *launches = cnt;
+    return NNQS_OK;
 }
 
 }  // extern "C"

@@ -13,6 +13,7 @@
 // order, so results are reproducible.  The inference kernel used inside the
 // full local energy computes the first layer in FP32 from the sparse input
 // and the hidden layer with BF16 MFMA, FP32 accumulation.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -32,6 +33,9 @@ struct nnqs_screen {
     // scratch (grown on demand): activations for gradients
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    // scratch of the fallback judge (predictions and reduction partials)
+    void *jscratch = nullptr;
+    size_t jscratch_bytes = 0;
 };
 
 namespace nnqs {
@@ -476,10 +480,44 @@ nnqs_status screen_infer(nnqs_screen *s, const uint64_t *keys, const uint8_t *ex
     if (r != NNQS_OK) return r;
     int64_t blocks = (n + 63) / 64;
     if (blocks > 4096) blocks = 4096;
+    TimedRegion tr("k_screen_infer", st);
     hipLaunchKernelGGL(k_screen_infer, dim3((unsigned)blocks), dim3(256), 0, st, s->N, s->w32, s->w2t, keys, exc, n,
                        pred);
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
+}
+
+// Sum of squared prediction errors, deterministic two-stage reduction:
+// block partials (fixed per-thread strides, tree in LDS), then one block.
+constexpr int kJudgeBlocks = 256;
+__global__ void __launch_bounds__(256) k_sq_err_partial(const double *__restrict__ pred,
+                                                        const double *__restrict__ target, int64_t n,
+                                                        double *__restrict__ part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+        const double d = pred[k] - target[k];
+        acc = fma(d, d, acc);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_sq_err_final(const double *__restrict__ part, int nb,
+                                                      double *__restrict__ out) {
+    __shared__ double sh[256];
+    sh[threadIdx.x] = (int)threadIdx.x < nb ? part[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 __global__ void k_convert_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
@@ -594,6 +632,7 @@ nnqs_status nnqs_screen_destroy(nnqs_screen *s) {
     hipFree(s->w32);
     hipFree(s->w2t);
     hipFree(s->scratch);
+    hipFree(s->jscratch);
     delete s;
     return NNQS_OK;
 }
@@ -652,6 +691,39 @@ nnqs_status nnqs_screen_adam_step(nnqs_screen *s, const double *grad, double lr,
                        beta2, eps, c1, c2);
     NNQS_HIP_CHECK(hipGetLastError());
     s->infer_dirty = true;
+    return NNQS_OK;
+}
+
+
+nnqs_status nnqs_screen_judge(nnqs_screen *s, const uint64_t *xkeys, const uint8_t *exc, const double *target,
+                              int64_t n, int32_t precision, double max_rmse, double *rmse, int32_t *usable,
+                              void *stream) {
+    clear_error();
+    if (!s || !xkeys || !exc || !target || !rmse) return fail(NNQS_EINVAL, "null pointer argument");
+    if (n <= 0) return fail(NNQS_EINVAL, "n must be positive");
+    if (!(max_rmse >= 0.0)) return fail(NNQS_EINVAL, "max_rmse must be >= 0");
+    hipStream_t st = as_stream(stream);
+    const size_t need = ((size_t)n + kJudgeBlocks + 1) * sizeof(double);
+    if (s->jscratch_bytes < need) {
+        NNQS_HIP_CHECK(hipStreamSynchronize(st));
+        hipFree(s->jscratch);
+        s->jscratch = nullptr;
+        s->jscratch_bytes = 0;
+        if (hipMalloc(&s->jscratch, need) != hipSuccess) return fail(NNQS_ENOMEM, "judge scratch of %zu bytes", need);
+        s->jscratch_bytes = need;
+    }
+    double *pred = static_cast<double *>(s->jscratch), *part = pred + n, *sum = part + kJudgeBlocks;
+    const nnqs_status r = nnqs_screen_forward(s, xkeys, exc, n, precision, pred, stream);
+    if (r != NNQS_OK) return r;
+    const int nb = (int)std::min<int64_t>(kJudgeBlocks, (n + 255) / 256);
+    hipLaunchKernelGGL(k_sq_err_partial, dim3(nb), dim3(256), 0, st, (const double *)pred, target, n, part);
+    hipLaunchKernelGGL(k_sq_err_final, dim3(1), dim3(256), 0, st, (const double *)part, nb, sum);
+    NNQS_HIP_CHECK(hipGetLastError());
+    double total = 0.0;
+    NNQS_HIP_CHECK(hipMemcpyAsync(&total, sum, 8, hipMemcpyDeviceToHost, st));
+    NNQS_HIP_CHECK(hipStreamSynchronize(st));
+    *rmse = std::sqrt(total / (double)n);
+    if (usable) *usable = *rmse <= max_rmse ? 1 : 0;
     return NNQS_OK;
 }
 

@@ -83,16 +83,10 @@ def split(xkeys, exc, target, held_out: float = 0.05, seed: int = 0):
             (xkeys[ho].contiguous(), exc[ho].contiguous(), target[ho].contiguous()))
 
 
-def held_out_rmse(screen: api.Screen, xkeys, exc, target, precision: int = api.NNQS_BF16) -> float:
-    """Root-mean-square error (nats) of the screen's predictions on pairs it
-    was not trained on, in the precision the full evaluation uses."""
-    pred = screen.forward(xkeys, exc, precision)
-    return float(torch.sqrt(torch.mean((pred - target) ** 2)).item())
-
-
 def screen_or_plain(screen: api.Screen, xkeys, exc, target, max_rmse: float = 1.0):
-    """The screen if its held-out RMSE is at most ``max_rmse`` nats, else
+    """The screen if its held-out RMSE (the library's fallback judge, in the
+    precision the full evaluation uses) is at most ``max_rmse`` nats, else
     ``None`` (the caller then runs the plain evaluation).  Returns
     ``(screen or None, rmse)``."""
-    rmse = held_out_rmse(screen, xkeys, exc, target)
-    return (screen if rmse <= max_rmse else None), rmse
+    rmse, ok = screen.judge(xkeys, exc, target, api.NNQS_BF16, max_rmse)
+    return (screen if ok else None), rmse

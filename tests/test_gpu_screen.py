@@ -212,3 +212,37 @@ def test_trained_screen_cuts_evaluations_within_1e4_ha(nn):
     frac, de = res[(nn.NNQS_SKIP_CONTRIBUTION, 18.0)]
     assert frac < 0.5
     assert de <= 1e-4
+
+
+def test_fallback_judge_matches_the_forward(nn):
+    """nnqs_screen_judge: RMSE of the screen's own BF16 and FP64 predictions
+    against targets, and the usable flag on both sides of the threshold."""
+    d = synth.config_inputs(2, n_unique=8)
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    con = nn.connections(S, dev(d["keys"][:2]))
+    xk = con["xprime"].reshape(-1, 2)[:3001].contiguous()
+    ex = con["exc"].reshape(-1, 4)[:3001].contiguous()
+    from paper_2306_16705_amd import screen_train
+    scr = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=5))
+    rng = np.random.default_rng(3)
+    target = torch.from_numpy(rng.normal(0.0, 2.0, size=3001)).cuda()
+    for prec in (nn.NNQS_BF16, nn.NNQS_FP64):
+        pred = scr.forward(xk, ex, prec).cpu().numpy()
+        want = float(np.sqrt(np.mean((pred - target.cpu().numpy()) ** 2)))
+        rmse, ok = scr.judge(xk, ex, target, prec, max_rmse=want * 1.001)
+        assert abs(rmse - want) <= 1e-12 * want and ok
+        rmse2, ok2 = scr.judge(xk, ex, target, prec, max_rmse=want * 0.999)
+        assert rmse2 == rmse and not ok2
+
+
+def test_kernel_timing_records_launches(nn):
+    d = synth.config_inputs(2, K=12, n_up=3, n_dn=3, n_unique=40, model=True)
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    keys = dev(d["keys"])
+    nn.timing_enable(True)
+    nn.model_logpsi(M, keys, nn.NNQS_BF16)
+    nn.model_logpsi(M, keys, nn.NNQS_BF16)
+    ms, cnt = nn.timing_read("k_transformer_bf16")
+    nn.timing_enable(False)
+    assert cnt == 2 and ms > 0.0
+    assert nn.timing_read("k_transformer_bf16") == (0.0, 0)
