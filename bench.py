@@ -43,9 +43,9 @@ ALU_PEAK_GOPS = 256 * 64 * 2.4   # 256 CUs x 64 lanes x 2.4 GHz, 32-bit integer 
 SA_OPS_PER_CONNECTION = 11
 
 # Operating point of the screened path: skip a connection when its predicted
-# contribution |H_xx' psi(x')/psi(x)| is below exp(-16.5) Ha, recompute in
+# contribution |H_xx' psi(x')/psi(x)| is below exp(-15) Ha, recompute in
 # FP64 every evaluated term above exp(-7) Ha.
-SKIP_NATS = 16.5
+SKIP_NATS = 15.0
 REFINE_NATS = 7.0
 
 # HBM traffic of one k_transformer_bf16_list launch of this workload, from
@@ -98,7 +98,8 @@ def main():
     ap.add_argument("--samples", type=int, default=128, help="samples per step (first ones the generator draws)")
     ap.add_argument("--plain-reps", type=int, default=3, help="timed passes of the plain BF16 path (median; 0 = skip)")
     ap.add_argument("--ratio", type=int, default=1, help="also time the workload's own 12-nat ratio rule (0 = skip)")
-    ap.add_argument("--fp64-samples", type=int, default=16,
+    ap.add_argument("--fp8", type=int, default=1, help="also time the FP8 rung (screen and network on FP8 MFMA)")
+    ap.add_argument("--fp64-samples", type=int, default=32,
                     help="samples of the plain FP64 error reference (0 = skip; profiling runs)")
     ap.add_argument("--screen-pairs", type=float, default=1e7, help="training pairs of the screen")
     ap.add_argument("--screen-samples", type=int, default=512, help="samples the training pairs are drawn from")
@@ -237,9 +238,38 @@ def main():
     e_ra = eloc.cpu().numpy().copy() if times else None
     en_ra = energy.cpu().numpy().copy() if times else None
 
+    # ---- FP8 rung: screen and network on FP8 MFMA (same rule and refinement), and plain FP8
+    e_f8 = e_f8p = None
+    fp8 = None
+    if args.fp8:
+        f8_kw = dict(screened_kw, screen_precision=nn.NNQS_FP8)
+        run(nn.NNQS_FP8, **f8_kw)
+        _, _, st_f8 = run(nn.NNQS_FP8, with_stats=True, **f8_kw)
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run(nn.NNQS_FP8, **f8_kw)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        dt_f8 = float(np.median(times))
+        e_f8 = eloc.cpu().numpy().copy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(nn.NNQS_FP8)
+        torch.cuda.synchronize()
+        dt_f8p = time.perf_counter() - t0
+        e_f8p = eloc.cpu().numpy().copy()
+        fp8 = {"screened_fp8_refined": {"samples_per_s": S_n / dt_f8,
+                                        "evaluated_fraction": st_f8["evaluated"] / st_f8["connections"],
+                                        "refined_fraction": st_f8["refined"] / st_f8["connections"]},
+               "plain_fp8": {"samples_per_s": S_n / dt_f8p, "connections_per_s": S_n * C / dt_f8p}}
+        log(f"FP8: screened {S_n / dt_f8:.4g} samples/s, plain {S_n / dt_f8p:.4g} samples/s")
+
     # ---- FP64 reference on the first samples of the subset
     m = min(args.fp64_samples, S_n)
-    err = {"screened_bf16_refined": None, "plain_bf16": None, "screened_ratio_rule_12": None}
+    err = {"screened_bf16_refined": None, "plain_bf16": None, "screened_ratio_rule_12": None,
+           "screened_fp8_refined": None, "plain_fp8": None}
     ref64, dt64 = None, None
     if m > 0:
         t0 = time.perf_counter()
@@ -252,7 +282,8 @@ def main():
             return float(np.sum(w_np[:k] * e[:k, 0]) / np.sum(w_np[:k]))
 
         ref64 = energy_of(e64)
-        for name, e in (("screened_bf16_refined", e_scr), ("plain_bf16", e_pl), ("screened_ratio_rule_12", e_ra)):
+        for name, e in (("screened_bf16_refined", e_scr), ("plain_bf16", e_pl), ("screened_ratio_rule_12", e_ra),
+                        ("screened_fp8_refined", e_f8), ("plain_fp8", e_f8p)):
             err[name] = energy_of(e) - ref64 if e is not None else None
         log(f"energy error vs FP64 over {m} samples: " +
             ", ".join(f"{k} {v:.2e} Ha" for k, v in err.items() if v is not None))
@@ -332,6 +363,8 @@ def main():
                                     "note": "the workload's own rule (skip below exp(-12)|psi(x)|), no refinement"}
                                    if dt_ra else None),
         "plain_fp64": {"samples_per_s": m / dt64, "samples": m, "energy_first_samples": ref64} if m > 0 else None,
+        "fp8": (dict(fp8, energy_err_vs_fp64_ha={"screened_fp8_refined": err["screened_fp8_refined"],
+                                                  "plain_fp8": err["plain_fp8"]}) if fp8 else None),
         "error_reference": f"plain FP64 GPU path on the first {m} samples (itself checked against the FP64 oracle "
                            "to 1e-10 per sample in the tests)",
         "screen": {"pairs": n_pairs, "labels": "BF16 network log|psi(x')|", "data_s": t_data,

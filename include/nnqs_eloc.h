@@ -222,7 +222,10 @@ enum {
     NNQS_BF16 = 1, /* BF16 MFMA with FP32 accumulation and FP32 normalisation
                       and softmax; log|psi| and phase returned as FP64.
                       Needs d_model 64, n_heads 4, d_ff 256, P 512. */
-    NNQS_FP32 = 2  /* FP32 arithmetic (screen training) */
+    NNQS_FP32 = 2, /* FP32 arithmetic (screen training) */
+    NNQS_FP8 = 3   /* OCP FP8 E4M3 MFMA operands (activations unscaled, each weight
+                      matrix with a power-of-two scale) and FP32 accumulation;
+                      the rest as NNQS_BF16 */
 };
 
 /* Number of FP32 weights the layout below holds for `desc`; -1 if invalid. */
@@ -277,8 +280,8 @@ nnqs_status nnqs_screen_get_weights(const nnqs_screen *screen, double *host_out,
 
 /* Predictions for n connections (device xkeys [n][2], exc [n][4]) into device
  * pred [n].  Key bits at or above N and excitation codes >= N (255 included)
- * contribute no input.  precision: NNQS_FP64, NNQS_FP32, or NNQS_BF16 (the inference
- * kernel of nnqs_eloc_model; needs H = 256).  Errors: EINVAL, EUNSUPPORTED,
+ * contribute no input.  precision: NNQS_FP64, NNQS_FP32, NNQS_BF16 or NNQS_FP8 (the
+ * inference kernels of nnqs_eloc_model; need H = 256).  Errors: EINVAL, EUNSUPPORTED,
  * ENOMEM, EHIP. */
 nnqs_status nnqs_screen_forward(nnqs_screen *screen, const uint64_t *xkeys, const uint8_t *exc, int64_t n,
                                 int32_t precision, double *pred, void *stream);
@@ -315,7 +318,9 @@ typedef struct {
  * exp(-skip_nats) Ha when the prediction is right). */
 enum { NNQS_SKIP_RATIO = 0, NNQS_SKIP_CONTRIBUTION = 1 };
 
-/* Options of nnqs_eloc_model (NULL = {12, NNQS_SKIP_RATIO, 0}).
+/* Options of nnqs_eloc_model (NULL = {12, NNQS_SKIP_RATIO, 0, NNQS_BF16}).
+ * screen_precision selects the screen's inference: NNQS_BF16 or NNQS_FP8
+ * (hidden layer on FP8 MFMA).
  * refine_nats > 0 turns on the precision ladder for a lower-precision
  * network: the samples' own amplitudes come from the FP64 network, and every
  * connection whose first-pass contribution |H_xx' psi(x')/psi(x)| is at
@@ -326,6 +331,7 @@ typedef struct {
     double skip_nats;
     int32_t skip_rule;
     double refine_nats;
+    int32_t screen_precision;
 } nnqs_eloc_opts;
 
 /* Full local energies (Eq. 4 over every connected x', psi from the model,

@@ -10,6 +10,7 @@ from .api import (  # noqa: F401
     NNQSError,
     NNQS_BF16,
     NNQS_FP32,
+    NNQS_FP8,
     NNQS_FP64,
     NNQS_SKIP_CONTRIBUTION,
     NNQS_SKIP_RATIO,

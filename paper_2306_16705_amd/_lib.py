@@ -105,7 +105,7 @@ class Stats(ctypes.Structure):
 
 
 class ElocOpts(ctypes.Structure):
-    _fields_ = [("skip_nats", _f64), ("skip_rule", _i32), ("refine_nats", _f64)]
+    _fields_ = [("skip_nats", _f64), ("skip_rule", _i32), ("refine_nats", _f64), ("screen_precision", _i32)]
 
 
 NNQS_SKIP_RATIO = 0
@@ -115,6 +115,7 @@ NNQS_SKIP_CONTRIBUTION = 1
 NNQS_FP64 = 0
 NNQS_BF16 = 1
 NNQS_FP32 = 2
+NNQS_FP8 = 3
 
 _lib = None
 

@@ -7,7 +7,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from ._lib import (NNQS_BF16, NNQS_FP32, NNQS_FP64, NNQS_SKIP_CONTRIBUTION, NNQS_SKIP_RATIO,  # noqa: F401
+from ._lib import (NNQS_BF16, NNQS_FP8, NNQS_FP32, NNQS_FP64, NNQS_SKIP_CONTRIBUTION, NNQS_SKIP_RATIO,  # noqa: F401
                    NNQS_VALIDATE, ModelDesc, NNQSError, Stats, Tune)
 
 _KEY_DTYPES = (torch.int64, torch.uint64)
@@ -268,7 +268,7 @@ def model_logpsi(model: Model, keys, precision: int = NNQS_FP64, logabs=None, ph
 def eloc_model(system: System, model: Model, keys, counts=None, precision: int = NNQS_FP64, eloc=None,
                energy=None, with_energy: bool = True, with_stats: bool = False, validate: bool = False,
                screen=None, skip_nats: float = 12.0, skip_rule: int = L.NNQS_SKIP_RATIO, refine_nats: float = 0.0,
-               stream=None):
+               screen_precision: int = NNQS_BF16, stream=None):
     """Full local energies with every x' from the network (``nnqs_eloc_model``).
 
     With a learned ``screen`` only connections kept by ``skip_rule`` at
@@ -285,7 +285,7 @@ def eloc_model(system: System, model: Model, keys, counts=None, precision: int =
     if eloc is None:
         eloc = torch.empty((n, 2), dtype=torch.float64, device=keys.device)
     st = Stats()
-    opts = L.ElocOpts(float(skip_nats), int(skip_rule), float(refine_nats))
+    opts = L.ElocOpts(float(skip_nats), int(skip_rule), float(refine_nats), int(screen_precision))
     L.check(L.load().nnqs_eloc_model(system.handle, model.handle, screen.handle if screen is not None else None,
                                      ctypes.byref(opts), int(precision), _ptr(keys), _ptr(counts), n,
                                      _ptr(eloc), _ptr(energy) if with_energy else None,

@@ -446,10 +446,13 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
     if (n <= 0) return fail(NNQS_EINVAL, "n must be positive");
     if (model->desc.n_orb != sys->view.K || model->desc.n_up != sys->view.n_up || model->desc.n_dn != sys->view.n_dn)
         return fail(NNQS_EINVAL, "model and system disagree on orbitals or electron numbers");
-    if (precision != NNQS_FP64 && precision != NNQS_BF16) return fail(NNQS_EUNSUPPORTED, "unknown precision");
-    if (precision == NNQS_BF16 && !model->bf16_ok) return fail(NNQS_EUNSUPPORTED, "model shape has no BF16 path");
-    nnqs_eloc_opts o{12.0, NNQS_SKIP_RATIO, 0.0};
+    if (precision != NNQS_FP64 && precision != NNQS_BF16 && precision != NNQS_FP8)
+        return fail(NNQS_EUNSUPPORTED, "unknown precision");
+    if (precision != NNQS_FP64 && !model->bf16_ok) return fail(NNQS_EUNSUPPORTED, "model shape has no BF16 / FP8 path");
+    nnqs_eloc_opts o{12.0, NNQS_SKIP_RATIO, 0.0, NNQS_BF16};
     if (opts) o = *opts;
+    if (o.screen_precision != NNQS_BF16 && o.screen_precision != NNQS_FP8)
+        return fail(NNQS_EINVAL, "screen precision must be NNQS_BF16 or NNQS_FP8");
     if (screen && !(o.skip_nats > 0.0)) return fail(NNQS_EINVAL, "skip_nats must be positive");
     if (o.skip_rule != NNQS_SKIP_RATIO && o.skip_rule != NNQS_SKIP_CONTRIBUTION)
         return fail(NNQS_EINVAL, "unknown skip rule %d", o.skip_rule);
@@ -467,7 +470,8 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (h) return fail(h, "a sample violates the particle numbers");
     }
     const int64_t C = sys->view.C;
-    const bool bf16 = precision == NNQS_BF16;
+    const bool bf16 = precision == NNQS_BF16 || precision == NNQS_FP8;  // prefix-reusing MFMA paths
+    const bool fp8 = precision == NNQS_FP8;
     int64_t chunk = kMaxChunkConnections / C;
     if (chunk < 1) chunk = 1;
     if (bf16 && chunk > kMaxChunkSamplesBf16) chunk = kMaxChunkSamplesBf16;  // bounds the key / value cache
@@ -538,10 +542,10 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
             // the chunk's samples once through the forward, keeping their keys,
             // values and log-probability prefix sums; then every kept x'
             // evaluates only the row blocks from its first changed position on
-            s1 = enqueue_bf16_cached(model, keys + 2 * s0, m, model->d_csla, model->d_kv, model->d_pre, st);
+            s1 = enqueue_bf16_cached(model, keys + 2 * s0, m, model->d_csla, model->d_kv, model->d_pre, st, fp8);
             if (s1 != NNQS_OK) return s1;
             if (screen) {
-                s1 = screen_infer(screen, model->d_xkeys, model->d_xexc, total, model->d_pred, st);
+                s1 = screen_infer(screen, model->d_xkeys, model->d_xexc, total, model->d_pred, st, o.screen_precision == NNQS_FP8);
                 if (s1 != NNQS_OK) return s1;
             }
             ClsArgs ca{};
@@ -560,14 +564,14 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
                                screen != nullptr, model->d_xla, model->d_xph);
             NNQS_HIP_CHECK(hipGetLastError());
             s1 = enqueue_bf16_list(model, model->d_xkeys, C, model->d_sel, model->d_hdr, total, model->d_kv,
-                                   model->d_pre, model->d_xla, model->d_xph, st);
+                                   model->d_pre, model->d_xla, model->d_xph, st, fp8);
             if (s1 != NNQS_OK) return s1;
         } else if (!screen) {
             s1 = enqueue_logpsi(model, model->d_xkeys, total, precision, model->d_xla, model->d_xph, st);
             if (s1 != NNQS_OK) return s1;
             evaluated += total;
         } else {
-            s1 = screen_infer(screen, model->d_xkeys, model->d_xexc, total, model->d_pred, st);
+            s1 = screen_infer(screen, model->d_xkeys, model->d_xexc, total, model->d_pred, st, o.screen_precision == NNQS_FP8);
             if (s1 != NNQS_OK) return s1;
             SelRule R{model->d_pred, nullptr, o.skip_rule == NNQS_SKIP_CONTRIBUTION ? model->d_loghx : nullptr,
                       model->d_sla + s0, C, o.skip_nats};

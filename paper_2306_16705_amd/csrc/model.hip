@@ -319,7 +319,8 @@ nnqs_status enqueue_logpsi(const nnqs_model *m, const uint64_t *keys, int64_t n,
         NNQS_HIP_CHECK(hipGetLastError());
         return NNQS_OK;
     }
-    if (precision == NNQS_BF16) return enqueue_logpsi_bf16(m, keys, n, logabs, phase, st);
+    if (precision == NNQS_BF16) return enqueue_logpsi_bf16(m, keys, n, logabs, phase, st, false);
+    if (precision == NNQS_FP8) return enqueue_logpsi_bf16(m, keys, n, logabs, phase, st, true);
     return fail(NNQS_EUNSUPPORTED, "unknown precision %d", precision);
 }
 

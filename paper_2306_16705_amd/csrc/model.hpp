@@ -59,6 +59,7 @@ struct nnqs_model {
     // BF16 path: transposed BF16 matrices and FP32 vectors (model_bf16.hip)
     void *d_bf16 = nullptr;
     float *d_f32 = nullptr;
+    void *d_fp8 = nullptr;  // FP8 E4M3 transformer matrices (same layout as d_bf16)
     bool bf16_ok = false;
     // full-E_loc scratch (eloc_model.hip), grown on demand
     uint64_t *d_xkeys = nullptr;
@@ -90,22 +91,22 @@ nnqs_status enqueue_logpsi(const nnqs_model *m, const uint64_t *keys, int64_t n,
 nnqs_status bf16_model_init(nnqs_model *m, const float *weights);
 void bf16_model_free(nnqs_model *m);
 nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs,
-                                double *phase, hipStream_t st);
+                                double *phase, hipStream_t st, bool fp8 = false);
 // BF16 cache of sample-mode forwards for the prefix-reusing list mode: per
 // configuration bf16_cache_elems(m) BF16 values (keys and values of every
 // layer and head) and 4 doubles of prefix log-probability sums.
 int64_t bf16_cache_elems(const nnqs_model *m);
 nnqs_status enqueue_bf16_cached(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, __bf16 *kv,
-                                double *pre, hipStream_t st);
+                                double *pre, hipStream_t st, bool fp8);
 // log|psi| and phase of the connections listed by class (hdr on the device:
 // count[4], offset[4]; at most max_entries in total) into xla / xph.
 nnqs_status enqueue_bf16_list(const nnqs_model *m, const uint64_t *xkeys, int64_t C, const int32_t *list,
                               const int64_t *hdr, int64_t max_entries, const __bf16 *kv, const double *pre,
-                              double *xla, double *xph, hipStream_t st);
+                              double *xla, double *xph, hipStream_t st, bool fp8);
 void eloc_model_free(nnqs_model *m);
 bool f64_shape_ok(const nnqs_model_desc &m);
 nnqs_status enqueue_logpsi_f64(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, double *phase,
                                hipStream_t st);
 nnqs_status screen_infer(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, int64_t n, float *pred,
-                         hipStream_t st);
+                         hipStream_t st, bool fp8);
 }  // namespace nnqs

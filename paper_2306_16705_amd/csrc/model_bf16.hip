@@ -17,6 +17,7 @@
 // Phase MLP: a second kernel runs 16 configurations per wave through
 // bits[16x128] @ W1 and GELU(z1)[16x512] @ W2 on the same MFMA, B tiles read
 // from the L2-resident BF16 weights.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -72,7 +73,7 @@ static F32Layout f32_layout(int K, int L) {
     o.tok_emb = at; at += 5 * kD;
     o.pos_emb = at; at += (int64_t)K * kD;
     o.layer0 = at;
-    o.layer_stride = 2 * kD + 192 + kD + 2 * kD + kF + kD;
+    o.layer_stride = 2 * kD + 192 + kD + 2 * kD + kF + kD + 12;
     at += L * o.layer_stride;
     o.lnf_g = at; at += kD;
     o.lnf_b = at; at += kD;
@@ -91,10 +92,14 @@ static F32Layout f32_layout(int K, int L) {
 // per-layer FP32 vector offsets
 constexpr int kV_ln1_g = 0, kV_ln1_b = 64, kV_bqkv = 128, kV_bo = 320, kV_ln2_g = 384, kV_ln2_b = 448,
               kV_b1 = 512, kV_b2 = 768;
+// FP8 scales of one layer's six weight matrices (q, k, v, o, w1, w2): for
+// each, the power of two s applied before quantisation and 1/s.
+constexpr int kV_f8 = 832;
 
 struct Bf16View {
     int K, L, n_up, n_dn;
     const __bf16 *wb;
+    const uint8_t *w8;  // FP8 E4M3 copy of the transformer matrices, same element layout as wb
     const float *wf;
     Bf16Layout bl;
     F32Layout fl;
@@ -138,6 +143,61 @@ __device__ __forceinline__ void stage_rows(__bf16 *dst, int lld, const __bf16 *s
     for (int e = threadIdx.x; e < rows * per_row; e += blockDim.x) {
         const int rr = e / per_row, cc = (e - rr * per_row) * 8;
         *reinterpret_cast<bf16x8 *>(dst + rr * lld + cc) = *reinterpret_cast<const bf16x8 *>(src + (int64_t)rr * gld + cc);
+    }
+}
+
+// Operands of the four weight products (QKV, output, FFN in and out):
+// BF16 on v_mfma_f32_16x16x32_bf16, or OCP FP8 E4M3 bytes on
+// v_mfma_f32_16x16x32_fp8_fp8 (same lane layout, eight 1-byte elements per
+// lane; activations are not scaled, each weight matrix has a power-of-two
+// scale that the accumulators undo).
+template <bool kF8>
+struct Op;
+
+template <>
+struct Op<false> {
+    typedef __bf16 T;
+    typedef bf16x8 Frag;
+    static constexpr int ld = kLd;  // padded LDS row length of 64-wide tiles
+    static __device__ __forceinline__ Frag frag(const T *base, int row, int k0) { return lds_frag(base, row, ld, k0); }
+    static __device__ __forceinline__ f32x4 mma(const Frag &a, const Frag &b, const f32x4 &c) { return mfma16(a, b, c); }
+    static __device__ __forceinline__ T cvt(float v) { return (__bf16)v; }
+};
+
+template <>
+struct Op<true> {
+    typedef uint8_t T;
+    typedef long Frag;
+    static constexpr int ld = 80;  // bytes; keeps 16-byte staging stores aligned
+    static __device__ __forceinline__ Frag frag(const T *base, int row, int k0) {
+        return *reinterpret_cast<const long *>(base + row * ld + k0);
+    }
+    static __device__ __forceinline__ f32x4 mma(const Frag &a, const Frag &b, const f32x4 &c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ T cvt(float v) {  // E4M3, round to nearest even, saturated at 448
+        return (T)(__builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(v, -448.f, 448.f), 0.f, 0, false) & 0xff);
+    }
+};
+
+__device__ __forceinline__ uint32_t fp8x4(const f32x4 &v) {
+    int r = 0;
+    r = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(v[0], -448.f, 448.f),
+                                        __builtin_amdgcn_fmed3f(v[1], -448.f, 448.f), r, false);
+    r = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(v[2], -448.f, 448.f),
+                                        __builtin_amdgcn_fmed3f(v[3], -448.f, 448.f), r, true);
+    return (uint32_t)r;
+}
+
+// Cooperative copy of `rows` rows of `cols` operands (global, row stride
+// gld) into LDS rows of stride lld, in 16-byte pieces.
+template <typename T>
+__device__ __forceinline__ void stage_rows_t(T *dst, int lld, const T *src, int gld, int rows, int cols) {
+    constexpr int per16 = 16 / (int)sizeof(T);
+    const int per_row = cols / per16;
+    for (int e = threadIdx.x; e < rows * per_row; e += blockDim.x) {
+        const int rr = e / per_row, cc = (e - rr * per_row) * per16;
+        *reinterpret_cast<uint4 *>(dst + rr * lld + cc) = *reinterpret_cast<const uint4 *>(src + (int64_t)rr * gld + cc);
     }
 }
 
@@ -206,34 +266,38 @@ struct Tile32 {
     f32x4 t[8];  // tile (j, cb) = t[j * 4 + cb]: own slot j, column block cb
 };
 
-// acc += X_j[16 rows][0..k_len) (LDS, BF16, row stride kLd) @ W for both own
+// acc += X_j[16 rows][0..k_len) (LDS, row stride Op::ld) @ W for both own
 // slots, Wt[n][k] in LDS.
-__device__ __forceinline__ void gemm_slots(Tile32 &acc, const __bf16 *X0, const __bf16 *X1, const __bf16 *Wt,
-                                           int wld, int k_len) {
+template <bool kF8>
+__device__ __forceinline__ void gemm_slots(Tile32 &acc, const typename Op<kF8>::T *X0, const typename Op<kF8>::T *X1,
+                                           const typename Op<kF8>::T *Wt, int k_len) {
+    typedef Op<kF8> OP;
     const int l = threadIdx.x & 63;
     const int r = l & 15, kq = 8 * (l >> 4);
     for (int ks = 0; ks < k_len; ks += 32) {
-        bf16x8 a[2], b[4];
-        a[0] = lds_frag(X0, r, kLd, ks + kq);
-        a[1] = lds_frag(X1, r, kLd, ks + kq);
+        typename OP::Frag a[2], b[4];
+        a[0] = OP::frag(X0, r, ks + kq);
+        a[1] = OP::frag(X1, r, ks + kq);
 #pragma unroll
-        for (int cb = 0; cb < 4; cb++) b[cb] = lds_frag(Wt, cb * 16 + r, wld, ks + kq);
+        for (int cb = 0; cb < 4; cb++) b[cb] = OP::frag(Wt, cb * 16 + r, ks + kq);
 #pragma unroll
         for (int j = 0; j < 2; j++)
 #pragma unroll
-            for (int cb = 0; cb < 4; cb++) acc.t[j * 4 + cb] = mfma16(a[j], b[cb], acc.t[j * 4 + cb]);
+            for (int cb = 0; cb < 4; cb++) acc.t[j * 4 + cb] = OP::mma(a[j], b[cb], acc.t[j * 4 + cb]);
     }
 }
 
 // Normalised rows (h - mean) / sqrt(var + eps) of both own slots into X_j
-// (LDS, BF16).  The LayerNorm's scale and shift are folded into the weights
-// of the product that reads X.
-__device__ __forceinline__ void normalize_rows(const Tile32 &h, __bf16 *X0, __bf16 *X1) {
+// (LDS).  The LayerNorm's scale and shift are folded into the weights of the
+// product that reads X.
+template <bool kF8>
+__device__ __forceinline__ void normalize_rows(const Tile32 &h, typename Op<kF8>::T *X0, typename Op<kF8>::T *X1) {
+    typedef Op<kF8> OP;
     const int l = threadIdx.x & 63;
     const int c = l & 15, r0 = 4 * (l >> 4);
 #pragma unroll
     for (int j = 0; j < 2; j++) {
-        __bf16 *X = j ? X1 : X0;
+        typename OP::T *X = j ? X1 : X0;
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             float s = 0.f, s2 = 0.f;
@@ -248,7 +312,7 @@ __device__ __forceinline__ void normalize_rows(const Tile32 &h, __bf16 *X0, __bf
             const float rstd = rsqrtf(var + 1e-5f);
             const float sh = -mean * rstd;
 #pragma unroll
-            for (int cb = 0; cb < 4; cb++) X[(r0 + i) * kLd + cb * 16 + c] = (__bf16)fmaf(h.t[j * 4 + cb][i], rstd, sh);
+            for (int cb = 0; cb < 4; cb++) X[(r0 + i) * OP::ld + cb * 16 + c] = OP::cvt(fmaf(h.t[j * 4 + cb][i], rstd, sh));
         }
     }
 }
@@ -280,8 +344,9 @@ struct KvSrc {
 // 16 kb + r0 + i), softmax over keys in base 2 (scale and log2(e) are folded
 // into Q), P[query][key] -> Pb, then O^T[c][query] = V^T P^T into
 // Oq[query][16 hh + c].
-template <int QB>
-__device__ __forceinline__ void attend_block(const __bf16 *Qq, const KvSrc &S, __bf16 *Pb, __bf16 *Oq, int hh) {
+template <int QB, bool kF8>
+__device__ __forceinline__ void attend_block(const __bf16 *Qq, const KvSrc &S, __bf16 *Pb, typename Op<kF8>::T *Oq,
+                                             int hh) {
     const int l = threadIdx.x & 63;
     const int c16 = l & 15, r0 = 4 * (l >> 4), kq = 8 * (l >> 4);
     const bf16x8 zero8 = {};
@@ -341,25 +406,33 @@ __device__ __forceinline__ void attend_block(const __bf16 *Qq, const KvSrc &S, _
             ot = mfma16(av, bp, ot);
         }
     }
-    *reinterpret_cast<bf16x4 *>(Oq + c16 * kLd + hh * kDh + r0) = cvt4(ot);
+    if constexpr (kF8)
+        *reinterpret_cast<uint32_t *>(Oq + c16 * Op<true>::ld + hh * kDh + r0) = fp8x4(ot);
+    else
+        *reinterpret_cast<bf16x4 *>(Oq + c16 * kLd + hh * kDh + r0) = cvt4(ot);
     wave_lds_sync();  // Pb is rewritten by the next block
 }
 
-__device__ __forceinline__ void attend(int QB, const __bf16 *Qq, const KvSrc &S, __bf16 *Pb, __bf16 *Oq, int hh) {
+template <bool kF8>
+__device__ __forceinline__ void attend(int QB, const __bf16 *Qq, const KvSrc &S, __bf16 *Pb, typename Op<kF8>::T *Oq,
+                                       int hh) {
     switch (QB) {
-        case 0: attend_block<0>(Qq, S, Pb, Oq, hh); break;
-        case 1: attend_block<1>(Qq, S, Pb, Oq, hh); break;
-        case 2: attend_block<2>(Qq, S, Pb, Oq, hh); break;
-        default: attend_block<3>(Qq, S, Pb, Oq, hh); break;
+        case 0: attend_block<0, kF8>(Qq, S, Pb, Oq, hh); break;
+        case 1: attend_block<1, kF8>(Qq, S, Pb, Oq, hh); break;
+        case 2: attend_block<2, kF8>(Qq, S, Pb, Oq, hh); break;
+        default: attend_block<3, kF8>(Qq, S, Pb, Oq, hh); break;
     }
 }
 
-template <bool kList>
+template <bool kList, bool kF8>
 __device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs &A) {
-    __shared__ __align__(16) __bf16 wbuf[192 * kLd];
+    typedef Op<kF8> OP;
+    typedef typename OP::T AT;
+    constexpr int kLdA = OP::ld;
+    __shared__ __align__(16) AT wbuf[192 * kLdA];
     __shared__ __align__(16) float2 gtab[kGeluN];
-    __shared__ __align__(16) __bf16 xs[kSlots][16 * kLd];
-    __shared__ __align__(16) __bf16 os[kSlots][16 * kLd];
+    __shared__ __align__(16) AT xs[kSlots][16 * kLdA];
+    __shared__ __align__(16) AT os[kSlots][16 * kLdA];
     __shared__ __align__(16) __bf16 qs[kSlots][16 * kQLd];
     __shared__ __align__(16) __bf16 ks_[kSlots][16 * kQLd];
     __shared__ __align__(16) __bf16 vt[kSlots][kDh * kVLd];
@@ -443,7 +516,7 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs
         auto token = [&](int j, int q) -> int {
             return (int)((upm[j] >> q) & 1ull) | ((int)((dnm[j] >> q) & 1ull) << 1);
         };
-        __bf16 *X0 = xs[2 * w], *X1 = xs[2 * w + 1], *O0 = os[2 * w], *O1 = os[2 * w + 1];
+        AT *X0 = xs[2 * w], *X1 = xs[2 * w + 1], *O0 = os[2 * w], *O1 = os[2 * w + 1];
         // embeddings of the own rows: h[s][c] = tok_emb[prev token][c] + pos_emb[s][c], padding rows 0
         Tile32 h;
 #pragma unroll
@@ -461,21 +534,24 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs
 
         for (int layer = 0; layer < M.L; layer++) {
             const float *lv = wf + M.fl.layer0 + layer * M.fl.layer_stride;
-            const __bf16 *lw = M.wb + M.bl.layer0 + layer * M.bl.layer_stride;
-            normalize_rows(h, X0, X1);
+            const AT *lw = (kF8 ? reinterpret_cast<const AT *>(M.w8) : reinterpret_cast<const AT *>(M.wb)) +
+                           M.bl.layer0 + layer * M.bl.layer_stride;
+            // FP8: power-of-two scale s of each weight matrix and 1/s
+            const float *f8 = lv + kV_f8;
+            normalize_rows<kF8>(h, X0, X1);
             __syncthreads();  // previous users of wbuf are done
-            stage_rows(wbuf, kLd, lw, 64, 192, 64);
+            stage_rows_t(wbuf, kLdA, lw, 64, 192, 64);
             __syncthreads();
             for (int hh = 0; hh < kH; hh++) {
                 // Q^T and K^T (dims x positions) and V (positions x dims) of the
                 // own slots, biases in the accumulators
                 f32x4 qt[2], kt[2], v[2];
-                const float bv = lv[kV_bqkv + 128 + hh * kDh + c16];
+                const float bv = lv[kV_bqkv + 128 + hh * kDh + c16] * (kF8 ? f8[4] : 1.0f);
                 f32x4 bq, bk;
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
-                    bq[i] = lv[kV_bqkv + hh * kDh + r0 + i];
-                    bk[i] = lv[kV_bqkv + 64 + hh * kDh + r0 + i];
+                    bq[i] = lv[kV_bqkv + hh * kDh + r0 + i] * (kF8 ? f8[0] : 1.0f);
+                    bk[i] = lv[kV_bqkv + 64 + hh * kDh + r0 + i] * (kF8 ? f8[2] : 1.0f);
                 }
 #pragma unroll
                 for (int j = 0; j < 2; j++) {
@@ -485,15 +561,23 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs
                 }
 #pragma unroll
                 for (int ks = 0; ks < 64; ks += 32) {
-                    const bf16x8 wq = lds_frag(wbuf, hh * kDh + c16, kLd, ks + kq);
-                    const bf16x8 wk = lds_frag(wbuf, 64 + hh * kDh + c16, kLd, ks + kq);
-                    const bf16x8 wv = lds_frag(wbuf, 128 + hh * kDh + c16, kLd, ks + kq);
+                    const typename OP::Frag wq = OP::frag(wbuf, hh * kDh + c16, ks + kq);
+                    const typename OP::Frag wk = OP::frag(wbuf, 64 + hh * kDh + c16, ks + kq);
+                    const typename OP::Frag wv = OP::frag(wbuf, 128 + hh * kDh + c16, ks + kq);
 #pragma unroll
                     for (int j = 0; j < 2; j++) {
-                        const bf16x8 a = lds_frag(j ? X1 : X0, c16, kLd, ks + kq);
-                        qt[j] = mfma16(wq, a, qt[j]);
-                        kt[j] = mfma16(wk, a, kt[j]);
-                        v[j] = mfma16(a, wv, v[j]);
+                        const typename OP::Frag a = OP::frag(j ? X1 : X0, c16, ks + kq);
+                        qt[j] = OP::mma(wq, a, qt[j]);
+                        kt[j] = OP::mma(wk, a, kt[j]);
+                        v[j] = OP::mma(a, wv, v[j]);
+                    }
+                }
+                if constexpr (kF8) {
+#pragma unroll
+                    for (int j = 0; j < 2; j++) {
+                        qt[j] *= f8[1];
+                        kt[j] *= f8[3];
+                        v[j] *= f8[5];
                     }
                 }
 #pragma unroll
@@ -521,11 +605,11 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs
                     S.cls = cls;
                     S.c = sc[j];
                     S.sb = kList ? cls : 0;
-                    attend(srb[j], qs[2 * w + j], S, Pb, j ? O1 : O0, hh);
+                    attend<kF8>(srb[j], qs[2 * w + j], S, Pb, j ? O1 : O0, hh);
                 }
                 __syncthreads();  // every slot done with this head's K and V (and the QKV weights)
             }
-            stage_rows(wbuf, kLd, lw + 192 * 64, 64, 64, 64);
+            stage_rows_t(wbuf, kLdA, lw + 192 * 64, 64, 64, 64);
             __syncthreads();
 #pragma unroll
             for (int cb = 0; cb < 4; cb++) {
@@ -533,32 +617,52 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs
 #pragma unroll
                 for (int j = 0; j < 2; j++) h.t[j * 4 + cb] += bo;
             }
-            gemm_slots(h, O0, O1, wbuf, kLd, 64);
-            normalize_rows(h, X0, X1);
+            // FP8: the products come out scaled by the matrix's power of two s;
+            // the residual is scaled by s around them (exact)
+            if constexpr (kF8) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) h.t[q] *= f8[6];
+            }
+            gemm_slots<kF8>(h, O0, O1, wbuf, 64);
+            if constexpr (kF8) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) h.t[q] *= f8[7];
+            }
+            normalize_rows<kF8>(h, X0, X1);
+            if constexpr (kF8) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) h.t[q] *= f8[10];
+            }
             // FFN in four hidden chunks of 64
             for (int chunk = 0; chunk < 4; chunk++) {
                 __syncthreads();
-                stage_rows(wbuf, kLd, lw + 192 * 64 + 64 * 64 + chunk * 64 * 64, 64, 64, 64);  // w1T rows
-                stage_rows(wbuf + 64 * kLd, kLd, lw + 192 * 64 + 64 * 64 + 256 * 64 + chunk * 64, 256, 64, 64);
+                stage_rows_t(wbuf, kLdA, lw + 192 * 64 + 64 * 64 + chunk * 64 * 64, 64, 64, 64);  // w1T rows
+                stage_rows_t(wbuf + 64 * kLdA, kLdA, lw + 192 * 64 + 64 * 64 + 256 * 64 + chunk * 64, 256, 64, 64);
                 __syncthreads();
                 Tile32 f;
 #pragma unroll
                 for (int cb = 0; cb < 4; cb++) {
-                    const float b1 = lv[kV_b1 + chunk * 64 + cb * 16 + c16];
+                    const float b1 = lv[kV_b1 + chunk * 64 + cb * 16 + c16] * (kF8 ? f8[8] : 1.0f);
 #pragma unroll
                     for (int j = 0; j < 2; j++) f.t[j * 4 + cb] = f32x4{b1, b1, b1, b1};
                 }
-                gemm_slots(f, X0, X1, wbuf, kLd, 64);
+                gemm_slots<kF8>(f, X0, X1, wbuf, 64);
 #pragma unroll
                 for (int j = 0; j < 2; j++) {
-                    __bf16 *O = j ? O1 : O0;
+                    AT *O = j ? O1 : O0;
 #pragma unroll
                     for (int cb = 0; cb < 4; cb++)
 #pragma unroll
-                        for (int i = 0; i < 4; i++) O[(r0 + i) * kLd + cb * 16 + c16] = (__bf16)gelu_tab(gtab, f.t[j * 4 + cb][i]);
+                        for (int i = 0; i < 4; i++)
+                            O[(r0 + i) * kLdA + cb * 16 + c16] =
+                                OP::cvt(gelu_tab(gtab, kF8 ? f.t[j * 4 + cb][i] * f8[9] : f.t[j * 4 + cb][i]));
                 }
                 wave_lds_sync();
-                gemm_slots(h, O0, O1, wbuf + 64 * kLd, kLd, 64);
+                gemm_slots<kF8>(h, O0, O1, wbuf + 64 * kLdA, 64);
+            }
+            if constexpr (kF8) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) h.t[q] *= f8[11];
             }
 #pragma unroll
             for (int cb = 0; cb < 4; cb++) {
@@ -645,9 +749,15 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs
 }
 
 // Phase MLP: 16 configurations per wave, B tiles from global (L2) memory.
-__global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) { transformer_bf16<false>(M, A); }
+__global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) { transformer_bf16<false, false>(M, A); }
 
-__global__ void __launch_bounds__(512) k_transformer_bf16_list(Bf16View M, TfArgs A) { transformer_bf16<true>(M, A); }
+__global__ void __launch_bounds__(512) k_transformer_bf16_list(Bf16View M, TfArgs A) {
+    transformer_bf16<true, false>(M, A);
+}
+
+__global__ void __launch_bounds__(512) k_transformer_fp8(Bf16View M, TfArgs A) { transformer_bf16<false, true>(M, A); }
+
+__global__ void __launch_bounds__(512) k_transformer_fp8_list(Bf16View M, TfArgs A) { transformer_bf16<true, true>(M, A); }
 
 // In list mode (see TfArgs) the configurations are xkeys[list[k]] for k
 // below the total of the four class counts, and phase[list[k]] receives them.
@@ -729,6 +839,7 @@ static Bf16View bf16_view(const nnqs_model *m) {
     v.n_up = m->desc.n_up;
     v.n_dn = m->desc.n_dn;
     v.wb = reinterpret_cast<const __bf16 *>(m->d_bf16);
+    v.w8 = reinterpret_cast<const uint8_t *>(m->d_fp8);
     v.wf = m->d_f32;
     v.bl = bf16_layout(v.L);
     v.fl = f32_layout(v.K, v.L);
@@ -743,6 +854,34 @@ static uint16_t to_bf16_bits(float f) {  // round to nearest even
     return (uint16_t)(u >> 16);
 }
 
+// OCP FP8 E4M3 (bias 7, 3 mantissa bits, largest finite 448), round to
+// nearest even, saturated at +-448.
+static uint8_t to_e4m3(float f) {
+    const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
+    double a = std::fabs((double)f);
+    if (!(a == a)) return 0x7F;
+    if (a >= 448.0) return sign | 0x7E;
+    auto rne = [](double v) {  // round half to even
+        const double fl = std::floor(v), d = v - fl;
+        if (d > 0.5) return fl + 1.0;
+        if (d < 0.5) return fl;
+        return std::fmod(fl, 2.0) == 0.0 ? fl : fl + 1.0;
+    };
+    if (a < std::ldexp(1.0, -6)) {  // subnormal: m * 2^-9 (m = 8 carries into the smallest normal)
+        return sign | (uint8_t)rne(a * 512.0);
+    }
+    int e = 0;
+    const double fr = std::frexp(a, &e);  // a = fr * 2^e, fr in [0.5, 1)
+    e -= 1;                               // a = (2 fr) * 2^e, 2 fr in [1, 2)
+    double q = rne((2.0 * fr - 1.0) * 8.0);
+    if (q >= 8.0) {
+        q = 0.0;
+        e += 1;
+    }
+    const int code = ((e + 7) << 3) | (int)q;
+    return sign | (uint8_t)(code > 0x7E ? 0x7E : code);
+}
+
 nnqs_status bf16_model_init(nnqs_model *m, const float *weights) {
     const nnqs_model_desc &d = m->desc;
     m->bf16_ok = d.d_model == kD && d.n_heads == kH && d.d_ff == kF && d.phase_hidden == kP && d.n_orb <= 64 &&
@@ -753,12 +892,27 @@ nnqs_status bf16_model_init(nnqs_model *m, const float *weights) {
     const Bf16Layout bl = bf16_layout(L);
     const F32Layout fl = f32_layout(K, L);
     std::vector<uint16_t> wb((size_t)bl.total, 0);
+    std::vector<uint8_t> w8((size_t)bl.total, 0);
     std::vector<float> wf((size_t)fl.total, 0.f);
     auto W = [&](int64_t off) { return weights + off; };
     // transposed copy: dst[n][k] = src[k][n] for a [kdim][ndim] source matrix
     auto put_t = [&](int64_t dst, int dst_ld, const float *src, int kdim, int ndim, int row0) {
         for (int k = 0; k < kdim; k++)
             for (int nn = 0; nn < ndim; nn++) wb[dst + (int64_t)(row0 + nn) * dst_ld + k] = to_bf16_bits(src[k * ndim + nn]);
+    };
+    // FP8 copy of a [kdim][ndim] matrix, transposed like put_t, with the power
+    // of two s that brings its largest magnitude to at most 448; stores s, 1/s
+    auto put_t8 = [&](int64_t dst, int dst_ld, const float *src, int kdim, int ndim, int row0, float *sc) {
+        double mx = 0.0;
+        for (int64_t e = 0; e < (int64_t)kdim * ndim; e++) mx = std::max(mx, std::fabs((double)src[e]));
+        int k2 = mx > 0.0 ? (int)std::floor(std::log2(448.0 / mx)) : 0;
+        k2 = std::min(60, std::max(-60, k2));
+        const double s = std::ldexp(1.0, k2);
+        for (int k = 0; k < kdim; k++)
+            for (int nn = 0; nn < ndim; nn++)
+                w8[dst + (int64_t)(row0 + nn) * dst_ld + k] = to_e4m3((float)(s * src[k * ndim + nn]));
+        sc[0] = (float)s;
+        sc[1] = (float)(1.0 / s);
     };
     // A LayerNorm's scale g and shift b fold into the product y W + c that
     // reads it: (n * g + b) W + c = n (diag(g) W) + (b W + c), n = the
@@ -791,18 +945,24 @@ nnqs_status bf16_model_init(nnqs_model *m, const float *weights) {
         float *lv = wf.data() + fl.layer0 + l * fl.layer_stride;
         fold(wq, bq, ln1g, ln1b, kD, kD, qscale, fw, fb);
         put_t(base, 64, fw.data(), kD, kD, 0);
+        put_t8(base, 64, fw.data(), kD, kD, 0, lv + kV_f8 + 0);
         std::memcpy(lv + kV_bqkv, fb.data(), kD * 4);
         fold(wk, bk, ln1g, ln1b, kD, kD, 1.0, fw, fb);
         put_t(base, 64, fw.data(), kD, kD, 64);
+        put_t8(base, 64, fw.data(), kD, kD, 64, lv + kV_f8 + 2);
         std::memcpy(lv + kV_bqkv + 64, fb.data(), kD * 4);
         fold(wv, bv, ln1g, ln1b, kD, kD, 1.0, fw, fb);
         put_t(base, 64, fw.data(), kD, kD, 128);
+        put_t8(base, 64, fw.data(), kD, kD, 128, lv + kV_f8 + 4);
         std::memcpy(lv + kV_bqkv + 128, fb.data(), kD * 4);
         put_t(base + 192 * 64, 64, wo, kD, kD, 0);
+        put_t8(base + 192 * 64, 64, wo, kD, kD, 0, lv + kV_f8 + 6);
         fold(w1, b1, ln2g, ln2b, kD, kF, 1.0, fw, fb);
         put_t(base + 192 * 64 + 64 * 64, 64, fw.data(), kD, kF, 0);
+        put_t8(base + 192 * 64 + 64 * 64, 64, fw.data(), kD, kF, 0, lv + kV_f8 + 8);
         std::memcpy(lv + kV_b1, fb.data(), kF * 4);
         put_t(base + 192 * 64 + 64 * 64 + 256 * 64, 256, w2, kF, kD, 0);
+        put_t8(base + 192 * 64 + 64 * 64 + 256 * 64, 256, w2, kF, kD, 0, lv + kV_f8 + 10);
         std::memcpy(lv + kV_ln1_g, ln1g, kD * 4);
         std::memcpy(lv + kV_ln1_b, ln1b, kD * 4);
         std::memcpy(lv + kV_bo, bo, kD * 4);
@@ -831,9 +991,11 @@ nnqs_status bf16_model_init(nnqs_model *m, const float *weights) {
     // phase W1 [2K][512] -> ph_w1T[512][128] (bits beyond 2K stay zero)
     put_t(bl.ph_w1T, kPhaseBits, W(o.ph_w1), 2 * K, kP, 0);
     put_t(bl.ph_w2T, kP, W(o.ph_w2), kP, kP, 0);
-    if (hipMalloc(&m->d_bf16, wb.size() * 2) != hipSuccess || hipMalloc(&m->d_f32, wf.size() * 4) != hipSuccess)
+    if (hipMalloc(&m->d_bf16, wb.size() * 2) != hipSuccess || hipMalloc(&m->d_f32, wf.size() * 4) != hipSuccess ||
+        hipMalloc(&m->d_fp8, w8.size()) != hipSuccess)
         return fail(NNQS_ENOMEM, "device allocation of the BF16 model failed");
-    if (hipMemcpy(m->d_bf16, wb.data(), wb.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+    if (hipMemcpy(m->d_fp8, w8.data(), w8.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->d_bf16, wb.data(), wb.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(m->d_f32, wf.data(), wf.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
         return fail(NNQS_EHIP, "copy of the BF16 model failed");
     return NNQS_OK;
@@ -842,6 +1004,8 @@ nnqs_status bf16_model_init(nnqs_model *m, const float *weights) {
 void bf16_model_free(nnqs_model *m) {
     hipFree(m->d_bf16);
     hipFree(m->d_f32);
+    hipFree(m->d_fp8);
+    m->d_fp8 = nullptr;
     m->d_bf16 = nullptr;
     m->d_f32 = nullptr;
 }
@@ -867,14 +1031,17 @@ static unsigned phase_grid(int64_t n) {
 }
 
 nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, double *phase,
-                                hipStream_t st) {
+                                hipStream_t st, bool fp8) {
     if (!m->bf16_ok) return fail(NNQS_EUNSUPPORTED, "BF16 forward needs d_model 64, 4 heads, FFN 256, P 512, K <= 64");
     const Bf16View v = bf16_view(m);
     TfArgs A{};
     A.keys = keys;
     A.n = n;
     A.logabs = logabs;
-    {
+    if (fp8) {
+        TimedRegion tr("k_transformer_fp8", st);
+        hipLaunchKernelGGL(k_transformer_fp8, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, v, A);
+    } else {
         TimedRegion tr("k_transformer_bf16", st);
         hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, v, A);
     }
@@ -889,7 +1056,7 @@ nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64
 int64_t bf16_cache_elems(const nnqs_model *m) { return (int64_t)m->desc.n_layers * kH * kKvPerHead; }
 
 nnqs_status enqueue_bf16_cached(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, __bf16 *kv,
-                                double *pre, hipStream_t st) {
+                                double *pre, hipStream_t st, bool fp8) {
     if (!m->bf16_ok) return fail(NNQS_EUNSUPPORTED, "BF16 forward needs d_model 64, 4 heads, FFN 256, P 512, K <= 64");
     TfArgs A{};
     A.keys = keys;
@@ -897,7 +1064,10 @@ nnqs_status enqueue_bf16_cached(const nnqs_model *m, const uint64_t *keys, int64
     A.logabs = logabs;
     A.kv_out = kv;
     A.pre_out = pre;
-    {
+    if (fp8) {
+        TimedRegion tr("k_transformer_fp8", st);
+        hipLaunchKernelGGL(k_transformer_fp8, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, bf16_view(m), A);
+    } else {
         TimedRegion tr("k_transformer_bf16", st);
         hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, bf16_view(m), A);
     }
@@ -907,7 +1077,7 @@ nnqs_status enqueue_bf16_cached(const nnqs_model *m, const uint64_t *keys, int64
 
 nnqs_status enqueue_bf16_list(const nnqs_model *m, const uint64_t *xkeys, int64_t C, const int32_t *list,
                               const int64_t *hdr, int64_t max_entries, const __bf16 *kv, const double *pre,
-                              double *xla, double *xph, hipStream_t st) {
+                              double *xla, double *xph, hipStream_t st, bool fp8) {
     if (!m->bf16_ok) return fail(NNQS_EUNSUPPORTED, "BF16 forward needs d_model 64, 4 heads, FFN 256, P 512, K <= 64");
     const Bf16View v = bf16_view(m);
     TfArgs A{};
@@ -919,7 +1089,10 @@ nnqs_status enqueue_bf16_list(const nnqs_model *m, const uint64_t *xkeys, int64_
     A.C = C;
     A.xla = xla;
     A.list_mode = 1;  // kv_out / pre_out stay null: list mode only reads the cache
-    {
+    if (fp8) {
+        TimedRegion tr("k_transformer_fp8_list", st);
+        hipLaunchKernelGGL(k_transformer_fp8_list, dim3(tf_grid((max_entries + 3) / 4)), dim3(512), 0, st, v, A);
+    } else {
         TimedRegion tr("k_transformer_bf16_list", st);
         hipLaunchKernelGGL(k_transformer_bf16_list, dim3(tf_grid((max_entries + 3) / 4)), dim3(512), 0, st, v, A);
     }

@@ -15,11 +15,13 @@
 // and the hidden layer with BF16 MFMA, FP32 accumulation.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct nnqs_screen {
@@ -29,6 +31,10 @@ struct nnqs_screen {
     int64_t t = 0;                                     // Adam step count
     float *w32 = nullptr;                              // FP32 copy (W1 b1 b2 w3 b3 read by inference)
     __bf16 *w2t = nullptr;                             // BF16 W2 transposed [H][H] (n-major)
+    float *cw1 = nullptr;                              // combined first-layer rows [4][N][H] (inference)
+    uint8_t *w2f8 = nullptr;                           // FP8 E4M3 W2 transposed [H][H], scaled
+    float *w2scale = nullptr;                          // {2^k applied to W2, 2^-k applied to products}
+    float *gelu_tab = nullptr;                         // GELU table (512 pairs) of the inference kernel
     bool infer_dirty = true;
     // scratch (grown on demand): activations for gradients
     void *scratch = nullptr;
@@ -302,152 +308,269 @@ __device__ __forceinline__ float dpp_sum16(float v) {
     return v;
 }
 
+// GELU of the inference kernel, v * Phi(v), with the normal CDF Phi from a
+// 512-entry table of (value, step) pairs on [-8, 8) and linear
+// interpolation (error <= 3e-5, far below the BF16 / FP8 rounding of the
+// result); the table lives in LDS.
+constexpr int kSGeluN = 512;
+constexpr float kSGeluScale = 32.0f, kSGeluOff = 256.0f, kSGeluMaxU = 511.99997f;
+
+__device__ __forceinline__ float sgelu(const float2 *tab, float v) {
+    const float u = __builtin_amdgcn_fmed3f(fmaf(v, kSGeluScale, kSGeluOff), 0.0f, kSGeluMaxU);
+    const float2 e = tab[(int)u];
+    return v * fmaf(__builtin_amdgcn_fractf(u), e.y, e.x);
+}
+
+__device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) {  // OCP E4M3, saturated
+    a = __builtin_amdgcn_fmed3f(a, -448.f, 448.f);
+    b = __builtin_amdgcn_fmed3f(b, -448.f, 448.f);
+    c = __builtin_amdgcn_fmed3f(c, -448.f, 448.f);
+    d = __builtin_amdgcn_fmed3f(d, -448.f, 448.f);
+    int v = 0;
+    v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, v, false);
+    v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);
+    return (uint32_t)v;
+}
+
+// Inference: each wave takes one contiguous run of connections, 32 at a
+// time.  The connections of one sample x are contiguous and x' differs from
+// x only in the excitation's bits, so the first layer is
+//   b1 + sum_{p in x} W1[p]   (per run sample, kept in LDS)
+//   + sum_t C_t[e_t],  C_t = W1[one-hot block t + 1] + s_t W1[bit block],
+// s_t = -1 for the annihilated i, j and +1 for the created a, b: four
+// precombined rows per connection.  GELU outputs go to LDS as BF16 (or FP8
+// E4M3); the hidden layer runs on v_mfma_f32_16x16x32_bf16 (or _fp8_fp8 with
+// a per-tensor power-of-two scale of W2), each B fragment read from L2 once
+// for 32 connections; the output dot product by DPP row sums.
+template <bool kFp8>
 __global__ void __launch_bounds__(256) k_screen_infer(int N, const float *__restrict__ w32,
-                                                      const __bf16 *__restrict__ w2t,
+                                                      const float *__restrict__ cw1, const __bf16 *__restrict__ w2t,
+                                                      const uint8_t *__restrict__ w2f8,
+                                                      const float *__restrict__ w2inv,
+                                                      const float *__restrict__ gelu_tab,
                                                       const uint64_t *__restrict__ keys,
                                                       const uint8_t *__restrict__ exc, int64_t n,
                                                       float *__restrict__ pred) {
-    constexpr int H = kScreenH, ZLD = H + 8;
-    __shared__ __align__(16) __bf16 zs[4][16 * ZLD];
-    __shared__ __align__(16) float basev[4][H];  // per wave: b1 + W1 rows of the reference configuration
+    constexpr int H = kScreenH;
+    constexpr int ZLD = kFp8 ? H + 16 : H + 8;  // row length (elements) of the activation tile
+    typedef typename std::conditional<kFp8, uint8_t, __bf16>::type ZT;
+    __shared__ __align__(16) ZT zs[4][32 * ZLD];
+    __shared__ __align__(16) float basev[4][H];  // per wave: b1 + W1 rows of the run's sample
+    __shared__ __align__(16) float2 gtab[kSGeluN];
     const int l = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c16 = l & 15, r0 = 4 * (l >> 4), kq = 8 * (l >> 4);
-    __bf16 *Z = zs[w];
+    for (int i = threadIdx.x; i < kSGeluN; i += blockDim.x) gtab[i] = make_float2(gelu_tab[2 * i], gelu_tab[2 * i + 1]);
+    __syncthreads();
+    ZT *Z = zs[w];
     float *bv = basev[w];
     const ScreenOff o = screen_off(N, H);
-    // Each wave takes one contiguous run of connections.  The connections of
-    // one sample x are contiguous, and x' differs from x only in the
-    // excitation's bits, so the first layer is b1 + sum_{p in x} W1[p] (kept
-    // in LDS for the run's current x) plus one signed row per flipped bit,
-    // plus the one-hot rows: at most 8 weight rows per connection instead of
-    // one per occupied spin orbital.
+    const float inv2 = kFp8 ? w2inv[0] : 1.0f;
     const int64_t nwaves = (int64_t)gridDim.x * 4, wid = (int64_t)blockIdx.x * 4 + w;
-    const int64_t per = (((n + nwaves - 1) / nwaves) + 15) & ~(int64_t)15;
+    const int64_t per = (((n + nwaves - 1) / nwaves) + 31) & ~(int64_t)31;
     const int64_t beg = wid * per, end = beg + per < n ? beg + per : n;
     Key ref;
     ref.lo = ref.hi = 0ull;
     bool have_ref = false;
-    for (int64_t base = beg; base < end; base += 16) {
-        // layer 1: lane (row = c16, quarter = l >> 4) computes 64 of the 256 units of its row
-        const int64_t k = base + c16;
-        const bool ok = k < end;
-        Key x;
-        x.lo = ok ? keys[2 * k] : 0ull;
-        x.hi = ok ? keys[2 * k + 1] : 0ull;
-        uint8_t e4[4] = {255, 255, 255, 255};
-        if (ok)
-            for (int t = 0; t < 4; t++) e4[t] = exc[4 * k + t];
-        // flipped bits (codes below N; a code given twice cancels) and the sample x0 = x' ^ flips
-        Key fm;
-        fm.lo = fm.hi = 0ull;
-        for (int t = 0; t < 4; t++)
-            if (e4[t] < N) key_flip(fm, e4[t]);
-        Key x0;
-        x0.lo = x.lo ^ fm.lo;
-        x0.hi = x.hi ^ fm.hi;
-        // the run's reference sample is that of the group's first row (lane 0)
-        const uint64_t rlo = __builtin_amdgcn_readlane((unsigned long long)x0.lo, 0);
-        const uint64_t rhi = __builtin_amdgcn_readlane((unsigned long long)x0.hi, 0);
-        if (!have_ref || rlo != ref.lo || rhi != ref.hi) {
-            ref.lo = rlo;
-            ref.hi = rhi;
-            have_ref = true;
-            // lane l: units 4 l .. 4 l + 3, coalesced over the rows
-            float s4[4];
+    const int c0 = (l >> 4) * 64;  // this lane's 64 first-layer units
+    for (int64_t base = beg; base < end; base += 32) {
 #pragma unroll
-            for (int u = 0; u < 4; u++) s4[u] = w32[o.b1 + 4 * l + u];
-            for (int wd = 0; wd < 2; wd++) {
-                uint64_t m = wd ? ref.hi : ref.lo;
-                while (m) {
-                    const int bt = __ffsll((unsigned long long)m) - 1;
-                    m &= m - 1;
-                    const int p = wd * 64 + bt;
-                    if (p >= N) break;  // bits above the spin orbitals carry no input
-                    const float *row = w32 + o.W1 + (int64_t)p * H + 4 * l;
+        for (int hf = 0; hf < 2; hf++) {
+            // layer 1: lane (row = 16 hf + c16, quarter l >> 4) computes 64 of the 256 units of its row
+            const int64_t k = base + 16 * hf + c16;
+            const bool ok = k < end;
+            Key x;
+            x.lo = ok ? keys[2 * k] : 0ull;
+            x.hi = ok ? keys[2 * k + 1] : 0ull;
+            uint8_t e4[4] = {255, 255, 255, 255};
+            if (ok)
+                for (int t = 0; t < 4; t++) e4[t] = exc[4 * k + t];
+            // flipped bits (codes below N) and the sample x0 = x' ^ flips
+            Key fm;
+            fm.lo = fm.hi = 0ull;
+            for (int t = 0; t < 4; t++)
+                if (e4[t] < N) key_flip(fm, e4[t]);
+            Key x0;
+            x0.lo = x.lo ^ fm.lo;
+            x0.hi = x.hi ^ fm.hi;
+            // the run's reference sample is that of the group's first row (lane 0)
+            const uint64_t rlo = __builtin_amdgcn_readlane((unsigned long long)x0.lo, 0);
+            const uint64_t rhi = __builtin_amdgcn_readlane((unsigned long long)x0.hi, 0);
+            if (!have_ref || rlo != ref.lo || rhi != ref.hi) {
+                ref.lo = rlo;
+                ref.hi = rhi;
+                have_ref = true;
+                float s4[4];
 #pragma unroll
-                    for (int u = 0; u < 4; u++) s4[u] += row[u];
+                for (int u = 0; u < 4; u++) s4[u] = w32[o.b1 + 4 * l + u];
+                for (int wd = 0; wd < 2; wd++) {
+                    uint64_t m = wd ? ref.hi : ref.lo;
+                    while (m) {
+                        const int bt = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        const int p = wd * 64 + bt;
+                        if (p >= N) break;  // bits above the spin orbitals carry no input
+                        const float *row = w32 + o.W1 + (int64_t)p * H + 4 * l;
+#pragma unroll
+                        for (int u = 0; u < 4; u++) s4[u] += row[u];
+                    }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();  // earlier readers of bv are done
+#pragma unroll
+                for (int u = 0; u < 4; u++) bv[4 * l + u] = s4[u];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();  // earlier readers of bv are done
+            float acc[64];
+            if (x0.lo == ref.lo && x0.hi == ref.hi) {
 #pragma unroll
-            for (int u = 0; u < 4; u++) bv[4 * l + u] = s4[u];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-        const int c0 = (l >> 4) * 64;
-        float acc[64];
-        if (x0.lo == ref.lo && x0.hi == ref.hi) {
+                for (int c = 0; c < 64; c++) acc[c] = bv[c0 + c];
+                for (int t = 0; t < 4; t++) {
+                    if (e4[t] >= N) continue;  // absent
+                    const float *row = cw1 + ((int64_t)t * N + e4[t]) * H + c0;
 #pragma unroll
-            for (int c = 0; c < 64; c++) acc[c] = bv[c0 + c];
-            for (int wd = 0; wd < 2; wd++) {
-                uint64_t m = wd ? fm.hi : fm.lo;
-                while (m) {
-                    const int bt = __ffsll((unsigned long long)m) - 1;
-                    m &= m - 1;
-                    const int p = wd * 64 + bt;
-                    const float sg = key_bit(x, p) ? 1.0f : -1.0f;  // bit set in x' (created) or cleared
-                    const float *row = w32 + o.W1 + (int64_t)p * H + c0;
-#pragma unroll
-                    for (int c = 0; c < 64; c++) acc[c] = fmaf(sg, row[c], acc[c]);
+                    for (int c = 0; c < 64; c += 4) {
+                        const float4 r4 = *reinterpret_cast<const float4 *>(row + c);
+                        acc[c] += r4.x;
+                        acc[c + 1] += r4.y;
+                        acc[c + 2] += r4.z;
+                        acc[c + 3] += r4.w;
+                    }
                 }
-            }
-        } else {  // another sample inside the group: the plain sum over the bits of x'
+            } else {  // another sample inside the group: the plain sum over the bits of x' and the one-hots
 #pragma unroll
-            for (int c = 0; c < 64; c++) acc[c] = w32[o.b1 + c0 + c];
-            for (int wd = 0; wd < 2; wd++) {
-                uint64_t m = wd ? x.hi : x.lo;
-                while (m) {
-                    const int bt = __ffsll((unsigned long long)m) - 1;
-                    m &= m - 1;
-                    const int p = wd * 64 + bt;
-                    if (p >= N) break;
-                    const float *row = w32 + o.W1 + (int64_t)p * H + c0;
+                for (int c = 0; c < 64; c++) acc[c] = w32[o.b1 + c0 + c];
+                for (int wd = 0; wd < 2; wd++) {
+                    uint64_t m = wd ? x.hi : x.lo;
+                    while (m) {
+                        const int bt = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        const int p = wd * 64 + bt;
+                        if (p >= N) break;
+                        const float *row = w32 + o.W1 + (int64_t)p * H + c0;
+#pragma unroll
+                        for (int c = 0; c < 64; c++) acc[c] += row[c];
+                    }
+                }
+                for (int t = 0; t < 4; t++) {
+                    if (e4[t] >= N) continue;
+                    const float *row = w32 + o.W1 + (int64_t)((t + 1) * N + e4[t]) * H + c0;
 #pragma unroll
                     for (int c = 0; c < 64; c++) acc[c] += row[c];
                 }
             }
-        }
-        for (int t = 0; t < 4; t++) {
-            if (e4[t] >= N) continue;  // absent
-            const float *row = w32 + o.W1 + (int64_t)((t + 1) * N + e4[t]) * H + c0;
+            ZT *zr = Z + (16 * hf + c16) * ZLD + c0;
+            if constexpr (kFp8) {
 #pragma unroll
-            for (int c = 0; c < 64; c++) acc[c] += row[c];
-        }
+                for (int c = 0; c < 64; c += 4)
+                    *reinterpret_cast<uint32_t *>(zr + c) = fp8x4(sgelu(gtab, acc[c]), sgelu(gtab, acc[c + 1]),
+                                                                  sgelu(gtab, acc[c + 2]), sgelu(gtab, acc[c + 3]));
+            } else {
 #pragma unroll
-        for (int c = 0; c < 64; c++) Z[c16 * ZLD + c0 + c] = (__bf16)gelu_bf16path(acc[c]);
+                for (int c = 0; c < 64; c += 4) {
+                    bf16x4 z4;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) z4[u] = (__bf16)sgelu(gtab, acc[c + u]);
+                    *reinterpret_cast<bf16x4 *>(zr + c) = z4;
+                }
+            }
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // layer 2 + output
-        float part[4] = {0.f, 0.f, 0.f, 0.f};
+        // layer 2 + output, both row blocks per B fragment
+        float part[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
         for (int nb = 0; nb < H / 16; nb++) {
-            f32x4 a2 = {0.f, 0.f, 0.f, 0.f};
+            f32x4 a2[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
             for (int ks = 0; ks < H; ks += 32) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(Z + c16 * ZLD + ks + kq);
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(w2t + (int64_t)(nb * 16 + c16) * H + ks + kq);
-                a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, a2, 0, 0, 0);
+                if constexpr (kFp8) {
+                    const long b = *reinterpret_cast<const long *>(w2f8 + (int64_t)(nb * 16 + c16) * H + ks + kq);
+#pragma unroll
+                    for (int hf = 0; hf < 2; hf++) {
+                        const long a = *reinterpret_cast<const long *>(Z + (16 * hf + c16) * ZLD + ks + kq);
+                        a2[hf] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, a2[hf], 0, 0, 0);
+                    }
+                } else {
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(w2t + (int64_t)(nb * 16 + c16) * H + ks + kq);
+#pragma unroll
+                    for (int hf = 0; hf < 2; hf++) {
+                        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(Z + (16 * hf + c16) * ZLD + ks + kq);
+                        a2[hf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, a2[hf], 0, 0, 0);
+                    }
+                }
             }
             const float bb = w32[o.b2 + nb * 16 + c16], ww = w32[o.w3 + nb * 16 + c16];
 #pragma unroll
-            for (int i = 0; i < 4; i++) part[i] += gelu_bf16path(a2[i] + bb) * ww;
+            for (int hf = 0; hf < 2; hf++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) part[hf][i] = fmaf(sgelu(gtab, fmaf(a2[hf][i], inv2, bb)), ww, part[hf][i]);
         }
 #pragma unroll
-        for (int i = 0; i < 4; i++) part[i] = dpp_sum16(part[i]);
+        for (int hf = 0; hf < 2; hf++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) part[hf][i] = dpp_sum16(part[hf][i]);
         if (c16 == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int64_t kk = base + r0 + i;
-                if (kk < end) pred[kk] = part[i] + w32[o.b3];
-            }
+            for (int hf = 0; hf < 2; hf++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int64_t kk = base + 16 * hf + r0 + i;
+                    if (kk < end) pred[kk] = part[hf][i] + w32[o.b3];
+                }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+}
+
+// Combined first-layer rows C_t[p] = W1[(t + 1) N + p] + s_t W1[p] (FP64 sums, one rounding).
+__global__ void k_refresh_combined(const double *__restrict__ w, int N, int H, float *__restrict__ cw1) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)4 * N * H) return;
+    const int t = (int)(e / ((int64_t)N * H));
+    const int64_t pu = e - (int64_t)t * N * H;  // p * H + u
+    const double sgn = t < 2 ? -1.0 : 1.0;
+    cw1[e] = (float)(w[(int64_t)(t + 1) * N * H + pu] + sgn * w[pu]);
+}
+
+// Per-tensor scale of the FP8 W2: the power of two 2^k with max|W2| 2^k <= 448
+// (one block), then W2^T quantised to E4M3 (RNE, saturated).
+__global__ void __launch_bounds__(256) k_w2_scale(const double *__restrict__ w, int N, int H,
+                                                  float *__restrict__ scale2) {
+    __shared__ double sh[256];
+    const ScreenOff o = screen_off(N, H);
+    double m = 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)H * H; e += 256) m = fmax(m, fabs(w[o.W2 + e]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int k = 0;
+        if (sh[0] > 0.0) k = (int)floor(log2(448.0 / sh[0]));
+        if (k > 60) k = 60;
+        if (k < -60) k = -60;
+        scale2[0] = (float)ldexp(1.0, k);   // applied to W2 before quantisation
+        scale2[1] = (float)ldexp(1.0, -k);  // applied to the products
+    }
+}
+
+__global__ void k_w2_fp8(const double *__restrict__ w, int N, int H, const float *__restrict__ scale2,
+                         uint8_t *__restrict__ w2f8) {
+    const ScreenOff o = screen_off(N, H);
+    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;  // four k of one n
+    if (e >= (int64_t)H * H) return;
+    const int nn = (int)(e / H), k = (int)(e % H);
+    const float s = scale2[0];
+    float v[4];
+    for (int u = 0; u < 4; u++) v[u] = (float)w[o.W2 + (int64_t)(k + u) * H + nn] * s;
+    *reinterpret_cast<uint32_t *>(w2f8 + e) = fp8x4(v[0], v[1], v[2], v[3]);
 }
 
 static unsigned gridfor(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
@@ -467,22 +590,31 @@ nnqs_status screen_refresh(nnqs_screen *s, hipStream_t st) {
     if (!s->infer_dirty) return NNQS_OK;
     const ScreenOff o = screen_off(s->N, s->H);
     hipLaunchKernelGGL(k_refresh_infer, dim3(gridfor(o.total)), dim3(256), 0, st, s->w, s->N, s->H, s->w32, s->w2t);
+    hipLaunchKernelGGL(k_refresh_combined, dim3(gridfor((int64_t)4 * s->N * s->H)), dim3(256), 0, st, s->w, s->N, s->H,
+                       s->cw1);
+    hipLaunchKernelGGL(k_w2_scale, dim3(1), dim3(256), 0, st, s->w, s->N, s->H, s->w2scale);
+    hipLaunchKernelGGL(k_w2_fp8, dim3(gridfor((int64_t)s->H * s->H / 4)), dim3(256), 0, st, s->w, s->N, s->H,
+                       (const float *)s->w2scale, s->w2f8);
     NNQS_HIP_CHECK(hipGetLastError());
     s->infer_dirty = false;
     return NNQS_OK;
 }
 
-// BF16 inference into FP32 predictions (used by the full local energy).
+// BF16 (or FP8) inference into FP32 predictions (used by the full local energy).
 nnqs_status screen_infer(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, int64_t n, float *pred,
-                         hipStream_t st) {
-    if (s->H != kScreenH) return fail(NNQS_EUNSUPPORTED, "BF16 screen inference needs hidden = 256");
+                         hipStream_t st, bool fp8) {
+    if (s->H != kScreenH) return fail(NNQS_EUNSUPPORTED, "BF16 / FP8 screen inference needs hidden = 256");
     nnqs_status r = screen_refresh(s, st);
     if (r != NNQS_OK) return r;
-    int64_t blocks = (n + 63) / 64;
+    int64_t blocks = (n + 127) / 128;
     if (blocks > 4096) blocks = 4096;
     TimedRegion tr("k_screen_infer", st);
-    hipLaunchKernelGGL(k_screen_infer, dim3((unsigned)blocks), dim3(256), 0, st, s->N, s->w32, s->w2t, keys, exc, n,
-                       pred);
+    if (fp8)
+        hipLaunchKernelGGL(k_screen_infer<true>, dim3((unsigned)blocks), dim3(256), 0, st, s->N, s->w32, s->cw1,
+                           s->w2t, s->w2f8, (const float *)s->w2scale + 1, s->gelu_tab, keys, exc, n, pred);
+    else
+        hipLaunchKernelGGL(k_screen_infer<false>, dim3((unsigned)blocks), dim3(256), 0, st, s->N, s->w32, s->cw1,
+                           s->w2t, s->w2f8, (const float *)s->w2scale + 1, s->gelu_tab, keys, exc, n, pred);
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
 }
@@ -610,11 +742,22 @@ nnqs_status nnqs_screen_create(nnqs_screen **out, int32_t n_spin_orb, int32_t hi
     s->count = cnt;
     if (hipMalloc(&s->w, cnt * 8) != hipSuccess || hipMalloc(&s->m, cnt * 8) != hipSuccess ||
         hipMalloc(&s->v, cnt * 8) != hipSuccess || hipMalloc(&s->w32, cnt * 4) != hipSuccess ||
-        hipMalloc(&s->w2t, (size_t)hidden * hidden * 2) != hipSuccess) {
+        hipMalloc(&s->w2t, (size_t)hidden * hidden * 2) != hipSuccess ||
+        hipMalloc(&s->cw1, (size_t)4 * n_spin_orb * hidden * 4) != hipSuccess ||
+        hipMalloc(&s->w2f8, (size_t)hidden * hidden) != hipSuccess || hipMalloc(&s->w2scale, 2 * 4) != hipSuccess ||
+        hipMalloc(&s->gelu_tab, 2 * kSGeluN * 4) != hipSuccess) {
         nnqs_screen_destroy(s);
         return fail(NNQS_ENOMEM, "screen allocation failed");
     }
-    if (hipMemcpy(s->w, weights, cnt * 8, hipMemcpyHostToDevice) != hipSuccess ||
+    std::vector<float> gt(2 * kSGeluN);
+    for (int i = 0; i < kSGeluN; i++) {  // Phi at the knots, in FP64
+        const double v0 = (i - (double)kSGeluOff) / kSGeluScale, v1 = v0 + 1.0 / kSGeluScale;
+        const double p0 = 0.5 * std::erfc(-v0 / std::sqrt(2.0)), p1 = 0.5 * std::erfc(-v1 / std::sqrt(2.0));
+        gt[2 * i] = (float)p0;
+        gt[2 * i + 1] = (float)(p1 - p0);
+    }
+    if (hipMemcpy(s->gelu_tab, gt.data(), gt.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->w, weights, cnt * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(s->m, 0, cnt * 8) != hipSuccess || hipMemset(s->v, 0, cnt * 8) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         nnqs_screen_destroy(s);
@@ -631,6 +774,10 @@ nnqs_status nnqs_screen_destroy(nnqs_screen *s) {
     hipFree(s->v);
     hipFree(s->w32);
     hipFree(s->w2t);
+    hipFree(s->cw1);
+    hipFree(s->w2f8);
+    hipFree(s->w2scale);
+    hipFree(s->gelu_tab);
     hipFree(s->scratch);
     hipFree(s->jscratch);
     delete s;
@@ -654,11 +801,11 @@ nnqs_status nnqs_screen_forward(nnqs_screen *s, const uint64_t *keys, const uint
     hipStream_t st = as_stream(stream);
     if (precision == NNQS_FP64) return screen_fwd_bwd<double>(s, keys, exc, nullptr, n, pred, nullptr, nullptr, st);
     if (precision == NNQS_FP32) return screen_fwd_bwd<float>(s, keys, exc, nullptr, n, pred, nullptr, nullptr, st);
-    if (precision == NNQS_BF16) {
+    if (precision == NNQS_BF16 || precision == NNQS_FP8) {
         nnqs_status r = ensure_scratch(s, (size_t)n * 4 + 256, st);
         if (r != NNQS_OK) return r;
         float *p32 = static_cast<float *>(s->scratch);
-        r = screen_infer(s, keys, exc, n, p32, st);
+        r = screen_infer(s, keys, exc, n, p32, st, precision == NNQS_FP8);
         if (r != NNQS_OK) return r;
         hipLaunchKernelGGL(k_to_double<float>, dim3(gridfor(n)), dim3(256), 0, st, p32, pred, n);
         NNQS_HIP_CHECK(hipGetLastError());

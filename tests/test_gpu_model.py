@@ -162,10 +162,11 @@ def test_eloc_model_refinement_shrinks_bf16_error(nn):
     assert frac < 1.0
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
 @pytest.mark.parametrize("kw,take", [(dict(cfg=2, K=16, n_up=4, n_dn=4, n_unique=20, model=True), 6),
                                      (dict(cfg=2, K=64, n_up=8, n_dn=8, n_unique=4, model=True), 1),
                                      (dict(cfg=3, n_unique=2), 1)])
-def test_bf16_prefix_reuse_equals_whole_forward(nn, kw, take):
+def test_bf16_prefix_reuse_equals_whole_forward(nn, kw, take, prec):
     """The BF16 full path evaluates each x' from its first changed position on,
     with the sample's cached keys and values for the rows before; by causality
     that is the same computation as the whole forward of x'.  E_loc from
@@ -176,16 +177,17 @@ def test_bf16_prefix_reuse_equals_whole_forward(nn, kw, take):
     kw = dict(kw)
     cfg = kw.pop("cfg")
     d = synth.config_inputs(cfg, **kw)
-    _print_case("bf16_prefix_vs_whole", K=d["K"], take=take)
+    P = nn.NNQS_BF16 if prec == "bf16" else nn.NNQS_FP8
+    _print_case("prefix_vs_whole", K=d["K"], take=take, prec=prec)
     S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
     M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
     keys = dev(d["keys"][:take])
     cnt = dev(d["counts"][:take], torch.int32)
-    e, _, st = nn.eloc_model(S, M, keys, cnt, nn.NNQS_BF16, with_stats=True)
+    e, _, st = nn.eloc_model(S, M, keys, cnt, P, with_stats=True)
     con = nn.connections(S, keys)
     C = S.connection_count
-    xla, xph = nn.model_logpsi(M, con["xprime"].reshape(-1, 2), nn.NNQS_BF16)
-    sla, sph = nn.model_logpsi(M, keys, nn.NNQS_BF16)
+    xla, xph = nn.model_logpsi(M, con["xprime"].reshape(-1, 2), P)
+    sla, sph = nn.model_logpsi(M, keys, P)
     torch.cuda.synchronize()
     hv = con["hxx"].cpu().numpy()
     xla, xph = xla.cpu().numpy().reshape(take, C), xph.cpu().numpy().reshape(take, C)
@@ -196,7 +198,7 @@ def test_bf16_prefix_reuse_equals_whole_forward(nn, kw, take):
     g = eloc_complex(e)
     assert st["evaluated"] == take * C
     err = np.abs(g - ref) / absum
-    print(f"prefix vs whole-forward BF16 K={d['K']}: max |dE|/A = {err.max():.3e}")
+    print(f"prefix vs whole-forward {prec} K={d['K']}: max |dE|/A = {err.max():.3e}")
     assert err.max() <= 1e-12
 
 
@@ -222,3 +224,26 @@ def test_bf16_eloc_model_chunks_and_tail(nn):
     for i, kk in enumerate(idx):
         assert g[i] == g[first[int(kk)]], i
     assert np.allclose(g[:7], eloc_complex(ref), rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("kw", [dict(cfg=3, n_unique=16), dict(cfg=2, K=16, n_up=3, n_dn=5, n_unique=37, model=True)])
+def test_logpsi_fp8_error_vs_oracle(nn, kw):
+    """FP8 rung of the network: the four weight products on
+    v_mfma_f32_16x16x32_fp8_fp8 (OCP E4M3, power-of-two weight scales), the
+    attention and the phase MLP as in BF16.  The error against the FP64
+    oracle is stated and bounded by 0.5 + 0.02 |log|psi|| nats."""
+    kw = dict(kw)
+    cfg = kw.pop("cfg")
+    d = synth.config_inputs(cfg, **kw)
+    _print_case("logpsi_fp8", K=d["K"])
+    shape, w = d["model_shape"], d["weights"]
+    M = nn.Model(shape, d["n_up"], d["n_dn"], w)
+    keys = d["keys"] if d["K"] < 60 else np.concatenate([d["keys"], _random_connected(d, 2, 500, 9)])
+    la8, _ = nn.model_logpsi(M, dev(keys), nn.NNQS_FP8)
+    la16, _ = nn.model_logpsi(M, dev(keys), nn.NNQS_BF16)
+    torch.cuda.synchronize()
+    ola, _ = oracle.net_logpsi(w, shape, d["n_up"], d["n_dn"], keys)
+    d8, d16 = np.abs(la8.cpu().numpy() - ola), np.abs(la16.cpu().numpy() - ola)
+    print(f"FP8 vs FP64 oracle K={d['K']}: max |dlogabs| {d8.max():.3e} (mean {d8.mean():.3e}); "
+          f"BF16 max {d16.max():.3e} (mean {d16.mean():.3e}); n={len(keys)}")
+    assert np.all(d8 <= 0.5 + 0.02 * np.abs(ola))

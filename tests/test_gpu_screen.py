@@ -246,3 +246,24 @@ def test_kernel_timing_records_launches(nn):
     nn.timing_enable(False)
     assert cnt == 2 and ms > 0.0
     assert nn.timing_read("k_transformer_bf16") == (0.0, 0)
+
+
+@pytest.mark.parametrize("n", [64, 1000])
+def test_fp8_inference_error_vs_oracle(nn, n):
+    """FP8 rung of the screen: the hidden layer on v_mfma_f32_16x16x32_fp8_fp8
+    (OCP E4M3 activations, W2 with a power-of-two scale), the rest as BF16.
+    The error against the FP64 oracle is stated and bounded by
+    0.25 + 0.03 |y| nats (E4M3 keeps 3 mantissa bits)."""
+    K, H = 60, 256
+    N = 2 * K
+    _print_case("screen_fp8", N=N, H=H, n=n)
+    keys, exc, _ = _connection_inputs(K, n, seed=n)
+    w = _weights(N, H, seed=n + 1)
+    S = nn.Screen(N, H, w)
+    pred = S.forward(dev(keys), dev(exc), nn.NNQS_FP8).cpu().numpy()
+    p16 = S.forward(dev(keys), dev(exc), nn.NNQS_BF16).cpu().numpy()
+    ref = oracle.screen_forward(N, H, w, keys, exc)
+    err, e16 = np.abs(pred - ref), np.abs(p16 - ref)
+    print(f"FP8 screen n={n}: max err {err.max():.3e} (BF16 {e16.max():.3e}), RMS {np.sqrt(np.mean(err ** 2)):.3e} "
+          f"over y range [{ref.min():.3f}, {ref.max():.3f}]")
+    assert np.all(err <= 0.25 + 0.03 * np.abs(ref))
