@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--sa", type=int, default=1, help="also time the sample-aware N=48 path (0 = skip)")
     ap.add_argument("--batch-systems", type=int, default=32, help="systems of the batched launch (0 = skip)")
     ap.add_argument("--pauli", type=int, default=1, help="also time the Pauli-string backend (0 = skip)")
+    ap.add_argument("--batch-model-samples", type=int, default=8,
+                    help="samples per system of the batched transformer mode over the batch recipe (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
@@ -312,6 +314,8 @@ def main():
 
     sa = sample_aware_leg(args, nn, synth, np, torch) if args.sa else None
     batch = batch_leg(args, nn, synth, np, torch) if args.batch_systems > 0 else None
+    batch_model = (batch_model_leg(args, nn, synth, np, torch)
+                   if args.batch_systems > 0 and args.batch_model_samples > 0 else None)
 
     out = {
         "metric": METRIC,
@@ -372,6 +376,7 @@ def main():
                    "used": scr_used is not None},
         "sample_aware_n48": sa,
         "batch_path": batch,
+        "batch_model_path": batch_model,
     }
     if args.pauli and sa is not None:
         out["pauli_path"] = sa.pop("pauli", None)
@@ -498,6 +503,43 @@ def batch_leg(args, nn, synth, np, torch):
     log(f"batch: {med * 1e3:.1f} ms per graph step, {tot_s / med:.4g} samples/s")
     return {"systems": args.batch_systems, "samples": tot_s, "connections": tot_c, "schedule": tune,
             "ms_per_graph_step": med * 1e3, "samples_per_s": tot_s / med, "connections_per_s": tot_c / med}
+
+
+def batch_model_leg(args, nn, synth, np, torch):
+    """The batch recipe's systems in transformer mode: full E_loc in BF16 of
+    the first `--batch-model-samples` samples of each system, every
+    connection of every system through one persistent launch of the
+    prefix-reusing forward, the step captured in a hipGraph and replayed."""
+    m = args.batch_model_samples
+    log(f"batched transformer mode: {args.batch_systems} systems x {m} samples")
+    items, tot_c, tot_s = [], 0, 0
+    for k in range(args.batch_systems):
+        d = synth.config_inputs(4, k)
+        keys = torch.from_numpy(d["keys"][:m].view(np.int64).copy()).cuda()
+        S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+        items.append(dict(system=S, model=nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"]), keys=keys,
+                          counts=torch.from_numpy(d["counts"][:m].astype(np.int32)).cuda(),
+                          eloc=torch.empty((keys.shape[0], 2), dtype=torch.float64, device="cuda"),
+                          energy=torch.empty(4, dtype=torch.float64, device="cuda")))
+        tot_s += keys.shape[0]
+        tot_c += keys.shape[0] * S.connection_count
+    B = nn.BatchModel(items)
+    st = torch.cuda.Stream()
+    B.capture(st)
+    B.launch(st)
+    st.synchronize()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        B.launch(st)
+        st.synchronize()
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    log(f"batched transformer mode: {med * 1e3:.1f} ms per graph step, {tot_s / med:.4g} samples/s, "
+        f"{tot_c / med:.4g} connections/s")
+    return {"systems": args.batch_systems, "samples_per_system": m, "samples": tot_s, "connections": tot_c,
+            "ms_per_graph_step": med * 1e3, "samples_per_s": tot_s / med, "connections_per_s": tot_c / med,
+            "precision": "bf16", "note": "full E_loc, every x' from each system's own transformer"}
 
 
 if __name__ == "__main__":

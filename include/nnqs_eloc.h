@@ -509,6 +509,47 @@ nnqs_status nnqs_batch_get_tune(const nnqs_batch *batch, nnqs_tune *tune);
  * steps on `stream` and synchronises it; drops a captured graph. */
 nnqs_status nnqs_batch_autotune(nnqs_batch *batch, int32_t reps, nnqs_tune *best, double *best_ms, void *stream);
 
+/* ------------------------------------------- batched transformer mode */
+/* Full local energies (nnqs_eloc_model in BF16, no screen) of many systems
+ * of uneven N, electron and sample counts in one step: per item its
+ * connections are enumerated, its samples run once through its network
+ * (keys and values cached) and its connections are sorted into prefix
+ * classes; one persistent launch of the prefix-reusing forward then covers
+ * the connections of every item (each tile evaluated with its item's
+ * model); then per item the FP64 sums and the energy (Eq. 6).  A step
+ * neither synchronises nor allocates, so it can be captured into a
+ * hipGraph and replayed. */
+typedef struct nnqs_batch_model nnqs_batch_model;
+
+typedef struct {
+    const nnqs_system *system;
+    nnqs_model *model;        /* of `system`, BF16-capable; one item per model */
+    const uint64_t *keys;     /* device [n][2], unique samples */
+    const uint32_t *counts;   /* device [n], may be NULL when energy is NULL */
+    int64_t n;                /* 1..4096 samples, n * C < 2^31 */
+    double *eloc;             /* device [n][2] output */
+    double *energy;           /* device [4] output (layout as nnqs_eloc_table), may be NULL */
+} nnqs_batch_model_item;
+
+/* Plans a batch of 1..64 items (device buffers stay owned by the caller and
+ * must outlive the batch) and allocates its scratch (per item about
+ * 40 n C bytes plus 64 KiB per sample).  Synchronous.
+ * Errors: EINVAL, ERANGE, ENOMEM, EUNSUPPORTED, EHIP. */
+nnqs_status nnqs_batch_model_create(nnqs_batch_model **out, const nnqs_batch_model_item *items, int32_t n_items);
+
+/* Releases the batch, its scratch and its graph.  NULL is accepted. */
+nnqs_status nnqs_batch_model_destroy(nnqs_batch_model *batch);
+
+/* Enqueues one step on `stream`.  Errors: EHIP. */
+nnqs_status nnqs_batch_model_run(nnqs_batch_model *batch, void *stream);
+
+/* Records one step on `stream` (a created stream) into a hipGraph owned by
+ * the batch, replacing any earlier one.  Nothing runs. */
+nnqs_status nnqs_batch_model_capture(nnqs_batch_model *batch, void *stream);
+
+/* Replays the captured step.  Errors: EINVAL (nothing captured), EHIP. */
+nnqs_status nnqs_batch_model_launch(nnqs_batch_model *batch, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,6 +7,7 @@ fallback path.
 """
 from .api import (  # noqa: F401
     Batch,
+    BatchModel,
     NNQSError,
     NNQS_BF16,
     NNQS_FP32,

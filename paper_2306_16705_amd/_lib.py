@@ -37,6 +37,11 @@ SIGNATURES = {
     "nnqs_screen_judge": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _i32, _f64,
                                  ctypes.POINTER(_f64), ctypes.POINTER(_i32), _c_void_p]),
     "nnqs_timing_enable": (_i32, [_i32]),
+    "nnqs_batch_model_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p, _i32]),
+    "nnqs_batch_model_destroy": (_i32, [_c_void_p]),
+    "nnqs_batch_model_run": (_i32, [_c_void_p, _c_void_p]),
+    "nnqs_batch_model_capture": (_i32, [_c_void_p, _c_void_p]),
+    "nnqs_batch_model_launch": (_i32, [_c_void_p, _c_void_p]),
     "nnqs_timing_read": (_i32, [ctypes.c_char_p, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]),
     "nnqs_table_set_tune": (_i32, [_c_void_p, _c_void_p]),
     "nnqs_table_get_tune": (_i32, [_c_void_p, _c_void_p]),
@@ -93,6 +98,11 @@ class BatchItem(ctypes.Structure):
     _fields_ = [("system", _c_void_p), ("table", _c_void_p), ("model", _c_void_p), ("keys", _c_void_p),
                 ("counts", _c_void_p), ("logabs", _c_void_p), ("phase", _c_void_p), ("n", _i64),
                 ("eloc", _c_void_p), ("energy", _c_void_p)]
+
+
+class BatchModelItem(ctypes.Structure):
+    _fields_ = [("system", _c_void_p), ("model", _c_void_p), ("keys", _c_void_p), ("counts", _c_void_p),
+                ("n", _i64), ("eloc", _c_void_p), ("energy", _c_void_p)]
 
 
 class ModelDesc(ctypes.Structure):

@@ -519,3 +519,50 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class BatchModel:
+    """Full local energies of many systems in one step (``nnqs_batch_model_*``):
+    BF16 network, one persistent launch of the prefix-reusing forward over the
+    connections of every item.  ``items``: dicts with ``system``, ``model``,
+    ``keys``, ``eloc`` and optionally ``counts``, ``energy`` (device tensors
+    that must stay alive as long as the batch)."""
+
+    def __init__(self, items):
+        self._lib = L.load()
+        arr = (L.BatchModelItem * len(items))()
+        self._keep = []
+        for k, it in enumerate(items):
+            n = it["keys"].shape[0]
+            _need(it["keys"], "keys", _KEY_DTYPES, (n, 2))
+            _need(it["eloc"], "eloc", (torch.float64,), (n, 2))
+            if it.get("counts") is not None:
+                _need(it["counts"], "counts", (torch.int32, torch.uint32), (n,))
+            if it.get("energy") is not None:
+                _need(it["energy"], "energy", (torch.float64,), (4,))
+            arr[k] = L.BatchModelItem(it["system"].handle, it["model"].handle, _ptr(it["keys"]),
+                                      _ptr(it.get("counts")), n, _ptr(it["eloc"]), _ptr(it.get("energy")))
+            self._keep.append(it)
+        out = ctypes.c_void_p()
+        L.check(self._lib.nnqs_batch_model_create(ctypes.byref(out), arr, len(items)))
+        self.handle = out
+
+    def run(self, stream=None):
+        L.check(self._lib.nnqs_batch_model_run(self.handle, _stream(stream)))
+
+    def capture(self, stream):
+        L.check(self._lib.nnqs_batch_model_capture(self.handle, _stream(stream)))
+
+    def launch(self, stream):
+        L.check(self._lib.nnqs_batch_model_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.nnqs_batch_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

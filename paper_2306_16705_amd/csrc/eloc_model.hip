@@ -11,6 +11,7 @@
 // precision, so the ratio psi(x')/psi(x) is taken between like numbers.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "enumerate.hpp"
 #include "model.hpp"
@@ -610,3 +611,209 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
     }
     return NNQS_OK;
 }
+
+// ------------------------------------------------ batched transformer mode
+// Full local energies of many systems (uneven N, electron and sample
+// counts), the network in BF16: every item's connections are enumerated,
+// its samples run once through the network (keys / values cached) and its
+// connections sorted into prefix classes; then ONE persistent launch of the
+// prefix-reusing forward covers the connections of all items, each tile
+// with its item's model; then every item's sums and energy.  A step neither
+// synchronises nor allocates, so it can be captured into a hipGraph.
+struct BmItem {
+    nnqs_batch_model_item in;
+    int64_t C, total, bps;
+    int nb;  // selection blocks
+    double *sla = nullptr, *sph = nullptr, *xla = nullptr, *xph = nullptr, *partials = nullptr, *pre = nullptr,
+           *csla = nullptr;
+    uint64_t *xkeys = nullptr;
+    int32_t *list = nullptr, *blockcnt = nullptr;
+    int64_t *hdr = nullptr;  // {count[4], offset[4], evaluated, per-class evaluated[4]}
+    __bf16 *kv = nullptr;
+};
+
+struct nnqs_batch_model {
+    std::vector<BmItem> items;
+    void *d_items = nullptr;  // device array of list-mode launch descriptors (model_bf16.hip)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace nnqs {
+
+static void bm_free(nnqs_batch_model *b) {
+    for (auto &it : b->items) {
+        hipFree(it.sla);
+        hipFree(it.sph);
+        hipFree(it.xla);
+        hipFree(it.xph);
+        hipFree(it.partials);
+        hipFree(it.pre);
+        hipFree(it.csla);
+        hipFree(it.xkeys);
+        hipFree(it.list);
+        hipFree(it.blockcnt);
+        hipFree(it.hdr);
+        hipFree(it.kv);
+    }
+    hipFree(b->d_items);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+}
+
+static nnqs_status bm_step(nnqs_batch_model *b, hipStream_t st) {
+    for (auto &it : b->items) {
+        const nnqs_batch_model_item &in = it.in;
+        nnqs_status s = enqueue_logpsi(in.model, in.keys, in.n, NNQS_BF16, it.sla, it.sph, st);
+        if (s != NNQS_OK) return s;
+        hipLaunchKernelGGL(k_enum_keys, dim3((unsigned)(in.n * it.bps)), dim3(256), 0, st, in.system->view, in.keys,
+                           in.n, it.bps, it.xkeys, (uint8_t *)nullptr, (float *)nullptr);
+        s = enqueue_bf16_cached(in.model, in.keys, in.n, it.csla, it.kv, it.pre, st, false);
+        if (s != NNQS_OK) return s;
+        ClsArgs ca{};
+        ca.R = SelRule{nullptr, nullptr, nullptr, it.sla, it.C, 0.0};
+        ca.rule = false;
+        ca.keys = in.keys;
+        ca.xkeys = it.xkeys;
+        ca.total = it.total;
+        ca.K = in.system->view.K;
+        hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, it.hdr + 8, 5);
+        hipLaunchKernelGGL(k_cls_count, dim3(it.nb), dim3(256), 0, st, ca, it.blockcnt);
+        hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, it.blockcnt, it.nb, it.hdr, it.hdr + 8);
+        hipLaunchKernelGGL(k_cls_write, dim3(it.nb), dim3(64), 0, st, ca, it.blockcnt, it.list, false, it.xla, it.xph);
+        s = enqueue_bf16_phase_list(in.model, it.xkeys, it.list, it.hdr, it.total, it.xph, st);
+        if (s != NNQS_OK) return s;
+    }
+    nnqs_status s = enqueue_bf16_batch(b->items.front().in.model, b->d_items, (int)b->items.size(), st);
+    if (s != NNQS_OK) return s;
+    for (auto &it : b->items) {
+        const nnqs_batch_model_item &in = it.in;
+        const unsigned grid = (unsigned)(in.n * it.bps);
+        hipLaunchKernelGGL(k_eloc_partial, dim3(grid), dim3(256), 0, st, in.system->view, in.keys, it.sla, it.sph, in.n,
+                           it.bps, it.xla, it.xph, it.partials);
+        hipLaunchKernelGGL(k_eloc_finish, dim3((unsigned)((in.n + 255) / 256)), dim3(256), 0, st, it.partials, in.n,
+                           it.bps, in.eloc);
+        if (in.energy) {
+            s = enqueue_energy_partials(it.partials, in.counts, in.eloc, in.n, in.energy, st);
+            if (s != NNQS_OK) return s;
+        }
+    }
+    NNQS_HIP_CHECK(hipGetLastError());
+    return NNQS_OK;
+}
+
+}  // namespace nnqs
+
+extern "C" {
+
+nnqs_status nnqs_batch_model_create(nnqs_batch_model **out, const nnqs_batch_model_item *items, int32_t n_items) {
+    clear_error();
+    if (!out || !items) return fail(NNQS_EINVAL, "null pointer argument");
+    *out = nullptr;
+    if (n_items < 1 || n_items > bf16_batch_max_items())
+        return fail(NNQS_EINVAL, "n_items=%d outside [1, %d]", n_items, bf16_batch_max_items());
+    for (int i = 0; i < n_items; i++) {
+        const nnqs_batch_model_item &in = items[i];
+        if (!in.system || !in.model || !in.keys || !in.eloc) return fail(NNQS_EINVAL, "item %d: null pointer", i);
+        if (in.energy && !in.counts) return fail(NNQS_EINVAL, "item %d: energy requested without counts", i);
+        if (in.n <= 0 || in.n > kMaxChunkSamplesBf16)
+            return fail(NNQS_EINVAL, "item %d: n=%lld outside [1, %lld]", i, (long long)in.n,
+                        (long long)kMaxChunkSamplesBf16);
+        if (!in.model->bf16_ok) return fail(NNQS_EUNSUPPORTED, "item %d: model shape has no BF16 path", i);
+        const nnqs_model_desc &d = in.model->desc;
+        if (d.n_orb != in.system->view.K || d.n_up != in.system->view.n_up || d.n_dn != in.system->view.n_dn)
+            return fail(NNQS_EINVAL, "item %d: model and system disagree", i);
+        if (in.n * in.system->view.C > (int64_t)INT32_MAX)
+            return fail(NNQS_ERANGE, "item %d: %lld connections exceed 2^31 - 1", i,
+                        (long long)(in.n * in.system->view.C));
+        for (int j = 0; j < i; j++)
+            if (items[j].model == in.model) return fail(NNQS_EINVAL, "items %d and %d share a model", j, i);
+    }
+    nnqs_batch_model *b = new nnqs_batch_model();
+    b->items.resize(n_items);
+    const size_t isz = bf16_item_bytes();
+    std::vector<unsigned char> host(n_items * isz);
+    bool ok = true;
+    for (int i = 0; i < n_items && ok; i++) {
+        BmItem &it = b->items[i];
+        it.in = items[i];
+        it.C = items[i].system->view.C;
+        it.total = items[i].n * it.C;
+        it.bps = (it.C + kConnPerBlock - 1) / kConnPerBlock;
+        it.nb = (int)((it.total + kSelBlock - 1) / kSelBlock);
+        const size_t n = (size_t)items[i].n, tot = (size_t)it.total;
+        ok = hipMalloc(&it.sla, n * 8) == hipSuccess && hipMalloc(&it.sph, n * 8) == hipSuccess &&
+             hipMalloc(&it.xla, tot * 8) == hipSuccess && hipMalloc(&it.xph, tot * 8) == hipSuccess &&
+             hipMalloc(&it.partials, std::max<size_t>(n * it.bps * 4, kPartialBlocks * 8) * 8) == hipSuccess &&
+             hipMalloc(&it.pre, n * 4 * 8) == hipSuccess && hipMalloc(&it.csla, n * 8) == hipSuccess &&
+             hipMalloc(&it.xkeys, tot * 16) == hipSuccess && hipMalloc(&it.list, tot * 4) == hipSuccess &&
+             hipMalloc(&it.blockcnt, ((size_t)it.nb + 2) * 16) == hipSuccess &&
+             hipMalloc(&it.hdr, 16 * 8) == hipSuccess &&
+             hipMalloc(&it.kv, n * bf16_cache_elems(items[i].model) * sizeof(__bf16)) == hipSuccess;
+        if (ok) bf16_list_item(items[i].model, it.xkeys, it.C, it.list, it.hdr, it.kv, it.pre, it.xla, host.data() + i * isz);
+    }
+    if (ok) ok = hipMalloc(&b->d_items, n_items * isz) == hipSuccess;
+    if (!ok) {
+        bm_free(b);
+        delete b;
+        return fail(NNQS_ENOMEM, "batch scratch allocation failed");
+    }
+    if (hipMemcpy(b->d_items, host.data(), n_items * isz, hipMemcpyHostToDevice) != hipSuccess) {
+        bm_free(b);
+        delete b;
+        return fail(NNQS_EHIP, "batch descriptor upload failed");
+    }
+    *out = b;
+    return NNQS_OK;
+}
+
+nnqs_status nnqs_batch_model_destroy(nnqs_batch_model *b) {
+    if (!b) return NNQS_OK;
+    bm_free(b);
+    delete b;
+    return NNQS_OK;
+}
+
+nnqs_status nnqs_batch_model_run(nnqs_batch_model *b, void *stream) {
+    clear_error();
+    if (!b) return fail(NNQS_EINVAL, "null batch");
+    return bm_step(b, as_stream(stream));
+}
+
+nnqs_status nnqs_batch_model_capture(nnqs_batch_model *b, void *stream) {
+    clear_error();
+    if (!b) return fail(NNQS_EINVAL, "null batch");
+    if (!stream) return fail(NNQS_EINVAL, "graph capture needs a created (non-null) stream");
+    hipStream_t st = as_stream(stream);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    NNQS_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const nnqs_status s = bm_step(b, st);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (s != NNQS_OK) {
+        if (g) hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess) return fail(NNQS_EHIP, "stream capture failed: %s", hipGetErrorString(e));
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        b->graph = nullptr;
+        b->exec = nullptr;
+        return fail(NNQS_EHIP, "graph instantiation failed");
+    }
+    return NNQS_OK;
+}
+
+nnqs_status nnqs_batch_model_launch(nnqs_batch_model *b, void *stream) {
+    clear_error();
+    if (!b) return fail(NNQS_EINVAL, "null batch");
+    if (!b->exec) return fail(NNQS_EINVAL, "no captured graph (call nnqs_batch_model_capture first)");
+    NNQS_HIP_CHECK(hipGraphLaunch(b->exec, as_stream(stream)));
+    return NNQS_OK;
+}
+
+}  // extern "C"

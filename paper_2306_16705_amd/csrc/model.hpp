@@ -98,6 +98,17 @@ nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64
 int64_t bf16_cache_elems(const nnqs_model *m);
 nnqs_status enqueue_bf16_cached(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, __bf16 *kv,
                                 double *pre, hipStream_t st, bool fp8);
+// Batched list mode (one persistent launch over many systems): bytes of one
+// device launch descriptor, the largest item count, the descriptor of one
+// item written to host memory `dst`, the phase MLP of one item's lists, and
+// the launch over a device array of descriptors (models must all be BF16-capable).
+size_t bf16_item_bytes();
+int bf16_batch_max_items();
+void bf16_list_item(const nnqs_model *m, const uint64_t *xkeys, int64_t C, const int32_t *list, const int64_t *hdr,
+                    const __bf16 *kv, const double *pre, double *xla, void *dst);
+nnqs_status enqueue_bf16_phase_list(const nnqs_model *m, const uint64_t *xkeys, const int32_t *list, const int64_t *hdr,
+                                    int64_t max_entries, double *xph, hipStream_t st);
+nnqs_status enqueue_bf16_batch(const nnqs_model *m0, const void *d_items, int n_items, hipStream_t st);
 // log|psi| and phase of the connections listed by class (hdr on the device:
 // count[4], offset[4]; at most max_entries in total) into xla / xph.
 nnqs_status enqueue_bf16_list(const nnqs_model *m, const uint64_t *xkeys, int64_t C, const int32_t *list,

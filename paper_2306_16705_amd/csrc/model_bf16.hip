@@ -424,8 +424,16 @@ __device__ __forceinline__ void attend(int QB, const __bf16 *Qq, const KvSrc &S,
     }
 }
 
-template <bool kList, bool kF8>
-__device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs &A) {
+// One item of a batched list-mode launch: a system's model and work.
+struct TfItem {
+    Bf16View M;
+    TfArgs A;
+};
+constexpr int kMaxTfItems = 64;
+
+template <bool kList, bool kF8, bool kBatch>
+__device__ __forceinline__ void transformer_bf16(const Bf16View &M0, const TfArgs &A0, const TfItem *items,
+                                                 int n_items) {
     typedef Op<kF8> OP;
     typedef typename OP::T AT;
     constexpr int kLdA = OP::ld;
@@ -439,39 +447,58 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs
     __shared__ __align__(16) __bf16 ps[8][16 * kLd];
     __shared__ double slot_lp[kSlots];
     __shared__ int64_t sh_hdr[8];
+    // batched launch: first global tile of every (item, class), in item-major order
+    __shared__ int64_t sh_tile0[kBatch ? 4 * kMaxTfItems + 1 : 1];
 
     const int l = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c16 = l & 15, r0 = 4 * (l >> 4), kq = 8 * (l >> 4);
-    const int K = M.K;
-    const float *wf = M.wf;
     __bf16 *Pb = ps[w];
-    for (int i = threadIdx.x; i < kGeluN; i += blockDim.x)
-        gtab[i] = make_float2(wf[M.fl.gelu + 2 * i], wf[M.fl.gelu + 2 * i + 1]);
-    if (kList && threadIdx.x < 8) sh_hdr[threadIdx.x] = A.hdr[threadIdx.x];
+    for (int i = threadIdx.x; i < kGeluN; i += blockDim.x)  // the same table in every model
+        gtab[i] = make_float2(M0.wf[M0.fl.gelu + 2 * i], M0.wf[M0.fl.gelu + 2 * i + 1]);
+    if (!kBatch && kList && threadIdx.x < 8) sh_hdr[threadIdx.x] = A0.hdr[threadIdx.x];
+    if constexpr (kBatch) {
+        if (threadIdx.x == 0) {
+            int64_t acc = 0;
+            for (int it = 0; it < n_items; it++)
+                for (int c = 0; c < 4; c++) {
+                    sh_tile0[4 * it + c] = acc;
+                    acc += (items[it].A.hdr[c] + cls_cpt(c) - 1) / cls_cpt(c);
+                }
+            sh_tile0[4 * n_items] = acc;
+        }
+    }
     __syncthreads();
     int64_t tiles[4] = {0, 0, 0, 0}, T;
-    if (kList) {
+    if (kBatch) {
+        T = sh_tile0[4 * n_items];
+    } else if (kList) {
         T = 0;
         for (int c = 0; c < 4; c++) {
             tiles[c] = (sh_hdr[c] + cls_cpt(c) - 1) / cls_cpt(c);
             T += tiles[c];
         }
     } else {
-        T = (A.n + 3) / 4;
+        T = (A0.n + 3) / 4;
     }
-    const int64_t kv_cfg = (int64_t)M.L * kH * kKvPerHead;  // cache elements per configuration
-    // head weights (the final LayerNorm's scale folded in) held in registers
-    float hw[4][4];
-#pragma unroll
-    for (int cb = 0; cb < 4; cb++)
-#pragma unroll
-        for (int t = 0; t < 4; t++) hw[cb][t] = wf[M.fl.head_w + (cb * 16 + c16) * 4 + t];
 
     for (int64_t tile = blockIdx.x; tile < T; tile += gridDim.x) {
         int cls = 0;
-        int64_t tb = tile * 4, cnt = A.n, lbase = 0;
-        if (kList) {
+        int64_t tb = tile * 4, cnt = A0.n, lbase = 0;
+        Bf16View M = M0;
+        TfArgs A = A0;
+        if constexpr (kBatch) {
+            int q = 0;  // the last (item, class) whose first tile is at or before `tile`
+            for (int step = 4 * kMaxTfItems; step >= 1; step >>= 1)
+                if (q + step < 4 * n_items && sh_tile0[q + step] <= tile) q += step;
+            const int it = q >> 2;
+            cls = q & 3;
+            M = items[it].M;
+            A = items[it].A;
+            tb = (tile - sh_tile0[q]) * cls_cpt(cls);
+            cnt = A.hdr[cls];
+            lbase = A.hdr[4 + cls];
+        } else if (kList) {
             int64_t tt = tile;
             cls = 3;
             for (int c = 0; c < 3; c++) {
@@ -485,6 +512,15 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs
             cnt = sh_hdr[cls];
             lbase = sh_hdr[4 + cls];
         }
+        const int K = M.K;
+        const float *wf = M.wf;
+        const int64_t kv_cfg = (int64_t)M.L * kH * kKvPerHead;  // cache elements per configuration
+        // head weights (the final LayerNorm's scale folded in) held in registers
+        float hw[4][4];
+#pragma unroll
+        for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+            for (int t = 0; t < 4; t++) hw[cb][t] = wf[M.fl.head_w + (cb * 16 + c16) * 4 + t];
         const int cpt = cls_cpt(cls);
         // the wave's two slots: configuration, row block, key, sample
         int sc[2], srb[2];
@@ -749,15 +785,28 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M, const TfArgs
 }
 
 // Phase MLP: 16 configurations per wave, B tiles from global (L2) memory.
-__global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) { transformer_bf16<false, false>(M, A); }
-
-__global__ void __launch_bounds__(512) k_transformer_bf16_list(Bf16View M, TfArgs A) {
-    transformer_bf16<true, false>(M, A);
+__global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) {
+    transformer_bf16<false, false, false>(M, A, nullptr, 0);
 }
 
-__global__ void __launch_bounds__(512) k_transformer_fp8(Bf16View M, TfArgs A) { transformer_bf16<false, true>(M, A); }
+__global__ void __launch_bounds__(512) k_transformer_bf16_list(Bf16View M, TfArgs A) {
+    transformer_bf16<true, false, false>(M, A, nullptr, 0);
+}
 
-__global__ void __launch_bounds__(512) k_transformer_fp8_list(Bf16View M, TfArgs A) { transformer_bf16<true, true>(M, A); }
+__global__ void __launch_bounds__(512) k_transformer_fp8(Bf16View M, TfArgs A) {
+    transformer_bf16<false, true, false>(M, A, nullptr, 0);
+}
+
+__global__ void __launch_bounds__(512) k_transformer_fp8_list(Bf16View M, TfArgs A) {
+    transformer_bf16<true, true, false>(M, A, nullptr, 0);
+}
+
+// Many systems in one persistent launch: the list-mode work of every item
+// (its four class lists, hdr on the device) as one tile space; each block
+// takes tiles in turn and runs them with that item's model.
+__global__ void __launch_bounds__(512) k_transformer_bf16_batch(Bf16View M0, const TfItem *items, int n_items) {
+    transformer_bf16<true, false, true>(M0, items[0].A, items, n_items);
+}
 
 // In list mode (see TfArgs) the configurations are xkeys[list[k]] for k
 // below the total of the four class counts, and phase[list[k]] receives them.
@@ -1100,6 +1149,46 @@ nnqs_status enqueue_bf16_list(const nnqs_model *m, const uint64_t *xkeys, int64_
         TimedRegion tr("k_phase_bf16", st);
         hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(max_entries)), dim3(kWaves * 64), 0, st, v, A, xph);
     }
+    NNQS_HIP_CHECK(hipGetLastError());
+    return NNQS_OK;
+}
+
+size_t bf16_item_bytes() { return sizeof(TfItem); }
+
+int bf16_batch_max_items() { return kMaxTfItems; }
+
+void bf16_list_item(const nnqs_model *m, const uint64_t *xkeys, int64_t C, const int32_t *list, const int64_t *hdr,
+                    const __bf16 *kv, const double *pre, double *xla, void *dst) {
+    TfItem it{};
+    it.M = bf16_view(m);
+    it.A.kv_in = kv;
+    it.A.pre_in = pre;
+    it.A.list = list;
+    it.A.hdr = hdr;
+    it.A.xkeys = xkeys;
+    it.A.C = C;
+    it.A.xla = xla;
+    it.A.list_mode = 1;
+    std::memcpy(dst, &it, sizeof(it));
+}
+
+nnqs_status enqueue_bf16_phase_list(const nnqs_model *m, const uint64_t *xkeys, const int32_t *list, const int64_t *hdr,
+                                    int64_t max_entries, double *xph, hipStream_t st) {
+    TfArgs A{};
+    A.list = list;
+    A.hdr = hdr;
+    A.xkeys = xkeys;
+    A.list_mode = 1;
+    TimedRegion tr("k_phase_bf16", st);
+    hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(max_entries)), dim3(kWaves * 64), 0, st, bf16_view(m), A, xph);
+    NNQS_HIP_CHECK(hipGetLastError());
+    return NNQS_OK;
+}
+
+nnqs_status enqueue_bf16_batch(const nnqs_model *m0, const void *d_items, int n_items, hipStream_t st) {
+    TimedRegion tr("k_transformer_bf16_batch", st);
+    hipLaunchKernelGGL(k_transformer_bf16_batch, dim3((unsigned)cu_count()), dim3(512), 0, st, bf16_view(m0),
+                       static_cast<const TfItem *>(d_items), n_items);
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
 }

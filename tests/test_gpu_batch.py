@@ -146,3 +146,56 @@ def test_batch_rejects_bad_items(nn):
         B.launch(torch.cuda.Stream())
     with pytest.raises(nn.NNQSError):
         B.set_tune(search=3)
+
+
+MODEL_SYSTEMS = [dict(K=4, n_up=2, n_dn=2, n_unique=30), dict(K=8, n_up=2, n_dn=2, n_unique=50),
+                 dict(K=12, n_up=4, n_dn=3, n_unique=40), dict(K=20, n_up=7, n_dn=7, n_unique=6),
+                 dict(K=33, n_up=5, n_dn=6, n_unique=3)]
+
+
+def test_batch_model_matches_single_system_and_oracle(nn):
+    """Batched transformer mode: five systems (N = 8 .. 66, one- and two-word
+    keys) whose connections go through one persistent launch of the
+    prefix-reusing BF16 forward.  Each item equals the single-system BF16
+    full path exactly (same kernels per configuration), graph replays are
+    checked against the eager step, and the two smallest systems are within
+    the BF16 error of the FP64 oracle."""
+    _print_case("batch_model", systems=len(MODEL_SYSTEMS))
+    items = []
+    for k, kw in enumerate(MODEL_SYSTEMS):
+        d = synth.config_inputs(2, sys=10 + k, model=True, **kw)
+        n = d["keys"].shape[0]
+        S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+        items.append(dict(d=d, system=S, model=nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"]),
+                          keys=dev(d["keys"]), counts=dev(d["counts"], torch.int32),
+                          eloc=torch.full((n, 2), np.nan, dtype=torch.float64, device="cuda"),
+                          energy=torch.zeros(4, dtype=torch.float64, device="cuda")))
+    B = nn.BatchModel(items)
+    B.run()
+    torch.cuda.synchronize()
+    eager = [(it["eloc"].clone(), it["energy"].clone()) for it in items]
+    for it, (e, en) in zip(items, eager):
+        e1, en1, _ = nn.eloc_model(it["system"], it["model"], it["keys"], it["counts"], nn.NNQS_BF16)
+        torch.cuda.synchronize()
+        assert torch.equal(e, e1), it["d"]["K"]
+        assert torch.equal(en, en1), it["d"]["K"]
+    st = torch.cuda.Stream()
+    B.capture(st)
+    for rep in range(3):
+        for it in items:
+            it["eloc"].fill_(np.nan)
+        torch.cuda.synchronize()
+        B.launch(st)
+        st.synchronize()
+        for it, (e, en) in zip(items, eager):
+            assert torch.equal(it["eloc"], e), (rep, it["d"]["K"])
+            assert torch.equal(it["energy"], en), (rep, it["d"]["K"])
+        torch.zeros(1024, device="cuda").sum().item()  # eager work between replays
+    for it in items[:2]:
+        d = it["d"]
+        ora, absum = oracle.eloc_model(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"], d["weights"],
+                                       d["model_shape"], d["keys"], with_absum=True)
+        g = eloc_complex(it["eloc"])
+        rel = np.abs(g - ora) / absum
+        print(f"batch model K={d['K']}: BF16 vs FP64 oracle max |dE|/A {rel.max():.3e}")
+        assert rel.max() <= 0.05
