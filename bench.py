@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--sa", type=int, default=1, help="also time the sample-aware N=48 path (0 = skip)")
     ap.add_argument("--batch-systems", type=int, default=32, help="systems of the batched launch (0 = skip)")
     ap.add_argument("--pauli", type=int, default=1, help="also time the Pauli-string backend (0 = skip)")
+    ap.add_argument("--bas-samples", type=int, default=100000,
+                    help="samples drawn by batch autoregressive sampling from the N=120 network (0 = skip)")
     ap.add_argument("--batch-model-samples", type=int, default=8,
                     help="samples per system of the batched transformer mode over the batch recipe (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -312,6 +314,19 @@ def main():
                "connections_per_s": C / t_sample}
         log(f"oracle: {t_sample:.1f} s per sample on {nthr} threads")
 
+    bas = None
+    if args.bas_samples > 0:
+        nn.bas(M, 1000, 1, nn.NNQS_BF16, capacity=1 << 16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bk, bc, _, _ = nn.bas(M, args.bas_samples, 2, nn.NNQS_BF16, capacity=1 << 20)
+        torch.cuda.synchronize()
+        dt_bas = time.perf_counter() - t0
+        bas = {"n_samples": args.bas_samples, "unique": int(bk.shape[0]), "seconds": dt_bas,
+               "samples_per_s": args.bas_samples / dt_bas, "unique_per_s": bk.shape[0] / dt_bas, "precision": "bf16",
+               "note": "batch autoregressive sampling from the N=120 network (60 positions, one forward of every "
+                       "unique prefix per position)"}
+        log(f"BAS: {args.bas_samples} samples -> {bk.shape[0]} unique in {dt_bas:.2f} s")
     sa = sample_aware_leg(args, nn, synth, np, torch) if args.sa else None
     batch = batch_leg(args, nn, synth, np, torch) if args.batch_systems > 0 else None
     batch_model = (batch_model_leg(args, nn, synth, np, torch)
@@ -374,6 +389,7 @@ def main():
         "screen": {"pairs": n_pairs, "labels": "BF16 network log|psi(x')|", "data_s": t_data,
                    "training_s": t_train, "adam_steps": args.screen_steps, "held_out_rmse_nats": rmse,
                    "used": scr_used is not None},
+        "batch_autoregressive_sampling": bas,
         "sample_aware_n48": sa,
         "batch_path": batch,
         "batch_model_path": batch_model,

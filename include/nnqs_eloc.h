@@ -251,6 +251,24 @@ nnqs_status nnqs_model_destroy(nnqs_model *model);
 nnqs_status nnqs_model_logpsi(const nnqs_model *model, const uint64_t *keys, int64_t n, int32_t precision,
                               double *logabs, double *phase, void *stream);
 
+/* Batch autoregressive sampling (Section 3.1) of n_samples samples from the
+ * model, the network in `precision` (NNQS_FP64 or NNQS_BF16).  At sequence
+ * position s every unique prefix u of weight c_u gets its conditional
+ * pi(t | prefix) (the Eq. 12 mask included); its c_u sample slots (numbered
+ * in prefix order) each draw a token with the uniform of Philox4x32-10
+ * (Salmon et al., SC 2011) at counter (slot mod 2^32, slot / 2^32, s,
+ * 0x42415300) and key `seed` (top 53 bits of the first two output words),
+ * splitting c_u multinomially among the four children; children of zero
+ * weight are dropped and the rest kept in (parent, token) order.  Outputs
+ * (device, `capacity` entries): keys_out [m][2] the unique samples,
+ * counts_out [m] their counts (sum n_samples), logabs_out [m] = 1/2 sum of
+ * log pi along the path, phase_out [m] (may be NULL) the phase MLP; *n_unique
+ * (host) = m.  Synchronises `stream` once per position.  Errors: EINVAL,
+ * ERANGE (more than `capacity` prefixes), ENOMEM, EUNSUPPORTED, EHIP. */
+nnqs_status nnqs_bas(nnqs_model *model, int32_t precision, uint64_t seed, uint64_t n_samples, int64_t capacity,
+                     uint64_t *keys_out, uint32_t *counts_out, double *logabs_out, double *phase_out,
+                     int64_t *n_unique, void *stream);
+
 /* ----------------------------------------------------------------- screen */
 /* Learned screen (an addition to the paper, whose only filter is the
  * sample-aware restriction of Section 3.4 item 4): an MLP that predicts

@@ -21,4 +21,7 @@ from .oracle import (  # noqa: F401
     screen_forward,
     screen_loss_grad,
     adam_step,
+    philox4x32_10,
+    bas_uniform,
+    bas,
 )

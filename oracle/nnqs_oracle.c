@@ -738,3 +738,119 @@ void ora_adam_step(double *w, const double *grad, double *m, double *v, int64_t 
         w[q] -= lr * (m[q] / c1) / (sqrt(v[q] / c2) + eps);
     }
 }
+
+/* ------------------------------------------- batch autoregressive sampling */
+/* Counter-based generator Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC 2011): ten rounds of
+ * two 32x32 -> 64-bit multiplications, the key bumped by the Weyl constants
+ * between rounds. */
+void ora_philox4x32_10(const uint32_t *ctr_in, const uint32_t *key_in, uint32_t *out) {
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; r++) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, n1 = (uint32_t)p1;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1, n3 = (uint32_t)p0;
+        c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    for (int i = 0; i < 4; i++) out[i] = c[i];
+}
+
+/* Uniform draw in [0, 1) of sample slot i at sequence position s: counter
+ * (i mod 2^32, i / 2^32, s, 0x42415300), key the seed's two halves; the top
+ * 53 bits of the first two output words. */
+double ora_bas_uniform(uint64_t seed, int s, uint64_t i) {
+    const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)s, 0x42415300u};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t o[4];
+    ora_philox4x32_10(ctr, key, o);
+    const uint64_t x = ((uint64_t)o[0] << 32) | o[1];
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* Token of one sample slot from its uniform u and the prefix's masked
+ * conditional log-probabilities: walk the allowed tokens in order 0..3,
+ * adding their probabilities, and take the first whose running sum exceeds
+ * u (the last allowed token if rounding leaves u above the total). */
+static int bas_token(const double *logp, double u) {
+    double acc = 0.0;
+    int last = -1;
+    for (int t = 0; t < 4; t++) {
+        if (!(logp[t] > -INFINITY)) continue;
+        last = t;
+        acc += exp(logp[t]);
+        if (u < acc) return t;
+    }
+    return last;
+}
+
+/* Batch autoregressive sampling (Section 3.1): n_samples samples drawn at
+ * once by following unique prefixes with their weights.  At position s every
+ * unique prefix u (weight c_u) gets its conditional distribution
+ * pi(t | prefix) from the network (the Eq. 12 mask included); the c_u sample
+ * slots of u (slots numbered in prefix order) each draw one token, which
+ * splits c_u multinomially among the four children; children with zero
+ * weight are dropped.  After K positions the prefixes are the unique samples
+ * and their weights the occurrence counts; logabs = 1/2 sum log pi along the
+ * path.  Returns the number of unique samples, or -1 when more than
+ * `capacity` prefixes would be needed. */
+int64_t ora_bas(int K, int d, int L, int H, int F, int P, int n_up, int n_dn, const double *w, uint64_t n_samples,
+                uint64_t seed, int64_t capacity, uint64_t *keys_out, uint32_t *counts_out, double *logabs_out) {
+    ora_net net = {K, d, L, H, F, P, n_up, n_dn};
+    uint64_t *pk = (uint64_t *)calloc((size_t)capacity * 2, sizeof(uint64_t));
+    uint64_t *nk = (uint64_t *)calloc((size_t)capacity * 2, sizeof(uint64_t));
+    uint64_t *pc = (uint64_t *)calloc((size_t)capacity, sizeof(uint64_t));
+    uint64_t *nc = (uint64_t *)calloc((size_t)capacity, sizeof(uint64_t));
+    double *pl = (double *)calloc((size_t)capacity, sizeof(double));
+    double *nl = (double *)calloc((size_t)capacity, sizeof(double));
+    double *cond = (double *)calloc((size_t)capacity * 4, sizeof(double));
+    uint64_t *child = (uint64_t *)calloc((size_t)capacity * 4, sizeof(uint64_t));
+    int64_t n = 1, result = -1;
+    pc[0] = n_samples;
+    for (int s = 0; s < K; s++) {
+        #pragma omp parallel for schedule(dynamic)
+        for (int64_t u = 0; u < n; u++) {
+            double *lp = (double *)malloc(sizeof(double) * K * 4);
+            transformer_conditionals(&net, w, pk + 2 * u, lp);
+            for (int t = 0; t < 4; t++) cond[u * 4 + t] = lp[s * 4 + t];
+            free(lp);
+        }
+        memset(child, 0, sizeof(uint64_t) * 4 * (size_t)n);
+        uint64_t slot = 0;
+        for (int64_t u = 0; u < n; u++)
+            for (uint64_t j = 0; j < pc[u]; j++, slot++) {
+                const int t = bas_token(cond + 4 * u, ora_bas_uniform(seed, s, slot));
+                child[u * 4 + t]++;
+            }
+        int64_t m = 0;
+        const int i = K - 1 - s;  /* position s holds spatial orbital K-1-s */
+        for (int64_t u = 0; u < n; u++)
+            for (int t = 0; t < 4; t++) {
+                if (!child[u * 4 + t]) continue;
+                if (m >= capacity) goto done;
+                nk[2 * m] = pk[2 * u];
+                nk[2 * m + 1] = pk[2 * u + 1];
+                if (t & 1) flip_bit(nk + 2 * m, 2 * i);
+                if (t & 2) flip_bit(nk + 2 * m, 2 * i + 1);
+                nc[m] = child[u * 4 + t];
+                nl[m] = pl[u] + cond[u * 4 + t];
+                m++;
+            }
+        { uint64_t *tk = pk; pk = nk; nk = tk; }
+        { uint64_t *tc = pc; pc = nc; nc = tc; }
+        { double *tl = pl; pl = nl; nl = tl; }
+        n = m;
+    }
+    for (int64_t u = 0; u < n; u++) {
+        keys_out[2 * u] = pk[2 * u];
+        keys_out[2 * u + 1] = pk[2 * u + 1];
+        counts_out[u] = (uint32_t)pc[u];
+        logabs_out[u] = 0.5 * pl[u];
+    }
+    result = n;
+done:
+    free(pk); free(nk); free(pc); free(nc); free(pl); free(nl); free(cond); free(child);
+    return result;
+}

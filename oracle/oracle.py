@@ -81,6 +81,12 @@ def _load():
     lib.ora_adam_step.restype = None
     lib.ora_adam_step.argtypes = [_f64p, _f64p, _f64p, _f64p, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, _i]
+    lib.ora_philox4x32_10.restype = None
+    lib.ora_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    lib.ora_bas_uniform.restype = ctypes.c_double
+    lib.ora_bas_uniform.argtypes = [ctypes.c_uint64, _i, ctypes.c_uint64]
+    lib.ora_bas.restype = ctypes.c_int64
+    lib.ora_bas.argtypes = [_i] * 8 + [_f64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, _u64p, _u32p, _f64p]
     _lib = lib
     return lib
 
@@ -261,3 +267,32 @@ def adam_step(w, grad, m, v, lr, beta1, beta2, eps, t):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     _load().ora_adam_step(_p(w, _f64p), _p(grad, _f64p), _p(m, _f64p), _p(v, _f64p), w.size, lr, beta1, beta2,
                           eps, int(t))
+
+
+# ------------------------------------------- batch autoregressive sampling
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 of a 4-word counter and a 2-word key (four uint32 words)."""
+    c = _c(ctr, np.uint32)
+    k = _c(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    _load().ora_philox4x32_10(_p(c, _u32p), _p(k, _u32p), _p(out, _u32p))
+    return out
+
+
+def bas_uniform(seed: int, s: int, i: int) -> float:
+    return float(_load().ora_bas_uniform(int(seed), int(s), int(i)))
+
+
+def bas(weights, shape, n_up, n_dn, n_samples: int, seed: int, capacity: int = 1 << 20):
+    """Batch autoregressive sampling (Section 3.1) with the FP64 network:
+    ``(keys [m, 2], counts [m] uint32, logabs [m])`` of the unique samples in
+    generation order."""
+    w = pack_net(weights, shape)
+    keys = np.zeros((capacity, 2), np.uint64)
+    counts = np.zeros(capacity, np.uint32)
+    la = np.zeros(capacity, np.float64)
+    m = _load().ora_bas(*_dims(shape), n_up, n_dn, _p(w, _f64p), int(n_samples), int(seed), int(capacity),
+                        _p(keys, _u64p), _p(counts, _u32p), _p(la, _f64p))
+    if m < 0:
+        raise ValueError("capacity exceeded")
+    return keys[:m].copy(), counts[:m].copy(), la[:m].copy()

@@ -21,6 +21,7 @@ from .api import (  # noqa: F401
     Screen,
     System,
     Table,
+    bas,
     connections,
     eloc_model,
     eloc_pauli,

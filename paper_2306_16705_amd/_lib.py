@@ -37,6 +37,8 @@ SIGNATURES = {
     "nnqs_screen_judge": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _i32, _f64,
                                  ctypes.POINTER(_f64), ctypes.POINTER(_i32), _c_void_p]),
     "nnqs_timing_enable": (_i32, [_i32]),
+    "nnqs_bas": (_i32, [_c_void_p, _i32, ctypes.c_uint64, ctypes.c_uint64, _i64, _c_void_p, _c_void_p, _c_void_p,
+                        _c_void_p, ctypes.POINTER(_i64), _c_void_p]),
     "nnqs_batch_model_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p, _i32]),
     "nnqs_batch_model_destroy": (_i32, [_c_void_p]),
     "nnqs_batch_model_run": (_i32, [_c_void_p, _c_void_p]),

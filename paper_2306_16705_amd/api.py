@@ -252,6 +252,23 @@ class Model:
             pass
 
 
+def bas(model: Model, n_samples: int, seed: int, precision: int = NNQS_BF16, capacity: int = 1 << 20,
+        with_phase: bool = True, stream=None):
+    """Batch autoregressive sampling (``nnqs_bas``): ``(keys [m, 2] int64,
+    counts [m] int32 (uint32 values), logabs [m], phase [m] or None)`` of the
+    unique samples on the current device."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    keys = torch.empty((capacity, 2), dtype=torch.int64, device=dev)
+    counts = torch.empty(capacity, dtype=torch.int32, device=dev)
+    la = torch.empty(capacity, dtype=torch.float64, device=dev)
+    ph = torch.empty(capacity, dtype=torch.float64, device=dev) if with_phase else None
+    m = ctypes.c_int64()
+    L.check(L.load().nnqs_bas(model.handle, int(precision), int(seed), int(n_samples), int(capacity), _ptr(keys),
+                              _ptr(counts), _ptr(la), _ptr(ph), ctypes.byref(m), _stream(stream)))
+    k = m.value
+    return keys[:k], counts[:k], la[:k], (ph[:k] if ph is not None else None)
+
+
 def model_logpsi(model: Model, keys, precision: int = NNQS_FP64, logabs=None, phase=None, stream=None):
     """``(log|psi|, phase)`` device tensors for ``keys [n, 2]`` (``nnqs_model_logpsi``)."""
     n = keys.shape[0]

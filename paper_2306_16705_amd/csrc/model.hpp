@@ -98,6 +98,10 @@ nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64
 int64_t bf16_cache_elems(const nnqs_model *m);
 nnqs_status enqueue_bf16_cached(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, __bf16 *kv,
                                 double *pre, hipStream_t st, bool fp8);
+// BF16 forward of n configurations writing only the masked conditionals of
+// position cpos into cond[n][4] (batch sampling; logabs is scratch).
+nnqs_status enqueue_bf16_cond(const nnqs_model *m, const uint64_t *keys, int64_t n, int cpos, double *cond,
+                              double *logabs, hipStream_t st);
 // Batched list mode (one persistent launch over many systems): bytes of one
 // device launch descriptor, the largest item count, the descriptor of one
 // item written to host memory `dst`, the phase MLP of one item's lists, and
@@ -116,8 +120,10 @@ nnqs_status enqueue_bf16_list(const nnqs_model *m, const uint64_t *xkeys, int64_
                               double *xla, double *xph, hipStream_t st, bool fp8);
 void eloc_model_free(nnqs_model *m);
 bool f64_shape_ok(const nnqs_model_desc &m);
+// FP64 forward; with cond, also the masked conditionals of position cpos
+// into cond[n][4] (batch sampling).
 nnqs_status enqueue_logpsi_f64(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, double *phase,
-                               hipStream_t st);
+                               hipStream_t st, int cpos = -1, double *cond = nullptr);
 nnqs_status screen_infer(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, int64_t n, float *pred,
                          hipStream_t st, bool fp8);
 }  // namespace nnqs

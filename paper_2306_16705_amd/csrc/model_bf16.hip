@@ -232,6 +232,8 @@ struct TfArgs {
     int64_t C;
     double *xla;
     int list_mode;
+    int cond_pos;      // sample mode, batch sampling: position whose conditionals are written
+    double *cond_out;  // [n][4] masked log-probabilities of the four tokens there (may be null)
 };
 
 // A block evaluates one tile of 16 row-block slots (16 rows each), two per
@@ -754,7 +756,12 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M0, const TfArg
                     for (int t = 0; t < 4; t++)
                         if (ok[t]) den += __expf(z[t] - mx);
                     const int ts = token(j, s);
-                    lsum += ok[ts] ? (z[ts] - mx) - __logf(den) : -INFINITY;
+                    const float lden = __logf(den);
+                    lsum += ok[ts] ? (z[ts] - mx) - lden : -INFINITY;
+                    if (!kList && A.cond_out && s == A.cond_pos && sc[j] < cpt && tb + sc[j] < cnt)
+#pragma unroll
+                        for (int t = 0; t < 4; t++)
+                            A.cond_out[(tb + sc[j]) * 4 + t] = ok[t] ? (double)((z[t] - mx) - lden) : -INFINITY;
                 }
             }
             // rows live in lanes 0, 16, 32, 48
@@ -1098,6 +1105,21 @@ nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64
         TimedRegion tr("k_phase_bf16", st);
         hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(n)), dim3(kWaves * 64), 0, st, v, A, phase);
     }
+    NNQS_HIP_CHECK(hipGetLastError());
+    return NNQS_OK;
+}
+
+nnqs_status enqueue_bf16_cond(const nnqs_model *m, const uint64_t *keys, int64_t n, int cpos, double *cond,
+                              double *logabs, hipStream_t st) {
+    if (!m->bf16_ok) return fail(NNQS_EUNSUPPORTED, "BF16 forward needs d_model 64, 4 heads, FFN 256, P 512, K <= 64");
+    TfArgs A{};
+    A.keys = keys;
+    A.n = n;
+    A.logabs = logabs;
+    A.cond_pos = cpos;
+    A.cond_out = cond;
+    TimedRegion tr("k_transformer_bf16", st);
+    hipLaunchKernelGGL(k_transformer_bf16, dim3(tf_grid((n + 3) / 4)), dim3(512), 0, st, bf16_view(m), A);
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
 }

@@ -220,8 +220,11 @@ __global__ void __launch_bounds__(256) k64_attention(const double *__restrict__ 
 // Output head with the logit bias, the mask (Eq. 12, read with the lower
 // bound too) and the log-probability of the actual token: one wave per
 // (config, position).
+// With `cond`, the masked conditional log-probabilities of all four tokens at
+// position cpos are also written to cond[b][4] (batch sampling).
 __global__ void __launch_bounds__(256) k64_head(ModelView M, const double *__restrict__ a,
-                                                const int8_t *__restrict__ tok, int64_t B, double *__restrict__ lp) {
+                                                const int8_t *__restrict__ tok, int64_t B, double *__restrict__ lp,
+                                                int cpos, double *__restrict__ cond) {
     // lane = model column (d = 64)
     const int K = M.K;
     const int lane = threadIdx.x & 63;
@@ -258,7 +261,11 @@ __global__ void __launch_bounds__(256) k64_head(ModelView M, const double *__res
     for (int t = 0; t < 4; t++)
         if (ok[t]) den += exp(z[t] - mx);
     const int ts = tok[row];
-    lp[row] = ok[ts] ? (z[ts] - mx) - log(den) : -INFINITY;
+    const double lden = log(den);
+    lp[row] = ok[ts] ? (z[ts] - mx) - lden : -INFINITY;
+    if (cond && s == cpos)
+#pragma unroll
+        for (int t = 0; t < 4; t++) cond[b * 4 + t] = ok[t] ? (z[t] - mx) - lden : -INFINITY;
 }
 
 // First phase layer from the occupation bits: z1[b][j] = GELU(b1[j] + sum
@@ -306,7 +313,7 @@ static unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 
 bool f64_shape_ok(const nnqs_model_desc &m) { return m.d_model == 64 && m.n_heads == 4 && m.d_ff % 64 == 0; }
 
 nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64_t n, double *logabs,
-                               double *phase, hipStream_t st) {
+                               double *phase, hipStream_t st, int cpos, double *cond) {
     nnqs_model *m = const_cast<nnqs_model *>(cm);  // owns its scratch (one call at a time per model)
     const ModelView M = model_view(m);
     const int K = M.K, d = M.d, F = M.F, P = M.P;
@@ -358,7 +365,8 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
         }
         hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, W + M.off.lnf_g,
                            W + M.off.lnf_b, R, a);
-        hipLaunchKernelGGL(k64_head, dim3(blocks_for(R, 4)), dim3(256), 0, st, M, a, tok, B, lp);
+        hipLaunchKernelGGL(k64_head, dim3(blocks_for(R, 4)), dim3(256), 0, st, M, a, tok, B, lp, cpos,
+                           cond ? cond + 4 * b0 : (double *)nullptr);
         double *z1 = f, *z2 = f + (size_t)B * P;
         hipLaunchKernelGGL(k64_phase1, dim3(blocks_for(B * P)), dim3(256), 0, st, M, keys + 2 * b0, B, z1);
         hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((P + 63) / 64), (unsigned)((B + 63) / 64)), dim3(256), 0, st,
