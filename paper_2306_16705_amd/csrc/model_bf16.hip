@@ -319,6 +319,100 @@ __device__ __forceinline__ void normalize_rows(const Tile32 &h, typename Op<kF8>
     }
 }
 
+// The residual stream is kept transposed: tile t[j * 4 + db] of slot j holds,
+// in lane l, sequence row (l & 15) of the slot and model columns
+// 16 db + 4 (l >> 4) + i, i = 0..3.  Products that feed it are computed as
+// C^T = W^T A^T (weights as the A operand, activations as the B operand), so
+// each lane's four outputs are consecutive columns of one row: LDS stores of
+// normalised rows and GELU outputs are one 8-byte write per four values.
+// acc^T += W^T X_j^T for both own slots; Wt[n][k] in LDS, X_j row-major.
+template <bool kF8>
+__device__ __forceinline__ void gemm_slots_t(Tile32 &acc, const typename Op<kF8>::T *X0, const typename Op<kF8>::T *X1,
+                                             const typename Op<kF8>::T *Wt, int k_len) {
+    typedef Op<kF8> OP;
+    const int l = threadIdx.x & 63;
+    const int r = l & 15, kq = 8 * (l >> 4);
+    for (int ks = 0; ks < k_len; ks += 32) {
+        typename OP::Frag a[4], b[2];
+        b[0] = OP::frag(X0, r, ks + kq);
+        b[1] = OP::frag(X1, r, ks + kq);
+#pragma unroll
+        for (int db = 0; db < 4; db++) a[db] = OP::frag(Wt, db * 16 + r, ks + kq);
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int db = 0; db < 4; db++) acc.t[j * 4 + db] = OP::mma(a[db], b[j], acc.t[j * 4 + db]);
+    }
+}
+
+// Four consecutive values of one row into LDS (BF16, or FP8 E4M3).
+template <bool kF8>
+__device__ __forceinline__ void store4(typename Op<kF8>::T *dst, const f32x4 &v);
+template <>
+__device__ __forceinline__ void store4<false>(__bf16 *dst, const f32x4 &v) {
+    bf16x4 o;
+#pragma unroll
+    for (int i = 0; i < 4; i++) o[i] = (__bf16)v[i];
+    *reinterpret_cast<bf16x4 *>(dst) = o;
+}
+template <>
+__device__ __forceinline__ void store4<true>(uint8_t *dst, const f32x4 &v) {
+    int r = 0;
+    r = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(v[0], -448.f, 448.f),
+                                        __builtin_amdgcn_fmed3f(v[1], -448.f, 448.f), r, false);
+    r = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(v[2], -448.f, 448.f),
+                                        __builtin_amdgcn_fmed3f(v[3], -448.f, 448.f), r, true);
+    *reinterpret_cast<int *>(dst) = r;
+}
+
+// Mean and 1/sqrt(var + eps) of the row of slot j held by this lane's group
+// of four lanes (l, l ^ 16, l ^ 32, l ^ 48), one-pass statistics.
+__device__ __forceinline__ void row_stats_t(const Tile32 &h, int j, float &rstd, float &shift) {
+    float s = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int db = 0; db < 4; db++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const float v = h.t[j * 4 + db][i];
+            s += v;
+            s2 = fmaf(v, v, s2);
+        }
+    s += __shfl_xor(s, 16, 64);
+    s2 += __shfl_xor(s2, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    s2 += __shfl_xor(s2, 32, 64);
+    const float mean = s * (1.0f / kD);
+    const float var = fmaxf(s2 * (1.0f / kD) - mean * mean, 0.0f);
+    rstd = rsqrtf(var + 1e-5f);
+    shift = -mean * rstd;
+}
+
+// Normalised rows of both own slots into X_j (LDS, row-major); the
+// LayerNorm's scale and shift are folded into the next product's weights.
+template <bool kF8>
+__device__ __forceinline__ void normalize_rows_t(const Tile32 &h, typename Op<kF8>::T *X0, typename Op<kF8>::T *X1) {
+    const int l = threadIdx.x & 63;
+    const int c16 = l & 15, r0 = 4 * (l >> 4);
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        float rstd, sh;
+        row_stats_t(h, j, rstd, sh);
+        typename Op<kF8>::T *X = (j ? X1 : X0) + c16 * Op<kF8>::ld + r0;
+#pragma unroll
+        for (int db = 0; db < 4; db++) {
+            f32x4 y;
+#pragma unroll
+            for (int i = 0; i < 4; i++) y[i] = fmaf(h.t[j * 4 + db][i], rstd, sh);
+            store4<kF8>(X + db * 16, y);
+        }
+    }
+}
+
+__device__ __forceinline__ f32x4 ld4(const float *p) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    return f32x4{v.x, v.y, v.z, v.w};
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -517,12 +611,6 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M0, const TfArg
         const int K = M.K;
         const float *wf = M.wf;
         const int64_t kv_cfg = (int64_t)M.L * kH * kKvPerHead;  // cache elements per configuration
-        // head weights (the final LayerNorm's scale folded in) held in registers
-        float hw[4][4];
-#pragma unroll
-        for (int cb = 0; cb < 4; cb++)
-#pragma unroll
-            for (int t = 0; t < 4; t++) hw[cb][t] = wf[M.fl.head_w + (cb * 16 + c16) * 4 + t];
         const int cpt = cls_cpt(cls);
         // the wave's two slots: configuration, row block, key, sample
         int sc[2], srb[2];
@@ -555,20 +643,20 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M0, const TfArg
             return (int)((upm[j] >> q) & 1ull) | ((int)((dnm[j] >> q) & 1ull) << 1);
         };
         AT *X0 = xs[2 * w], *X1 = xs[2 * w + 1], *O0 = os[2 * w], *O1 = os[2 * w + 1];
-        // embeddings of the own rows: h[s][c] = tok_emb[prev token][c] + pos_emb[s][c], padding rows 0
+        // embeddings of the own rows (transposed layout): h[s][c] = tok_emb[prev token][c] +
+        // pos_emb[s][c], padding rows 0
         Tile32 h;
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int j = 0; j < 2; j++) {
+            const int s = srb[j] * 16 + c16;
+            const int prev = s == 0 ? 4 : (s < K ? token(j, s - 1) : 0);
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int s = srb[j] * 16 + r0 + i;
-                const int prev = s == 0 ? 4 : (s < K ? token(j, s - 1) : 0);
-#pragma unroll
-                for (int cb = 0; cb < 4; cb++) {
-                    const int c = cb * 16 + c16;
-                    h.t[j * 4 + cb][i] = s < K ? wf[M.fl.tok_emb + prev * kD + c] + wf[M.fl.pos_emb + s * kD + c] : 0.f;
-                }
+            for (int db = 0; db < 4; db++) {
+                const int c = db * 16 + r0;
+                h.t[j * 4 + db] = s < K ? ld4(wf + M.fl.tok_emb + prev * kD + c) + ld4(wf + M.fl.pos_emb + s * kD + c)
+                                        : f32x4{0.f, 0.f, 0.f, 0.f};
             }
+        }
 
         for (int layer = 0; layer < M.L; layer++) {
             const float *lv = wf + M.fl.layer0 + layer * M.fl.layer_stride;
@@ -576,7 +664,7 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M0, const TfArg
                            M.bl.layer0 + layer * M.bl.layer_stride;
             // FP8: power-of-two scale s of each weight matrix and 1/s
             const float *f8 = lv + kV_f8;
-            normalize_rows<kF8>(h, X0, X1);
+            normalize_rows_t<kF8>(h, X0, X1);
             __syncthreads();  // previous users of wbuf are done
             stage_rows_t(wbuf, kLdA, lw, 64, 192, 64);
             __syncthreads();
@@ -650,10 +738,10 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M0, const TfArg
             stage_rows_t(wbuf, kLdA, lw + 192 * 64, 64, 64, 64);
             __syncthreads();
 #pragma unroll
-            for (int cb = 0; cb < 4; cb++) {
-                const float bo = lv[kV_bo + cb * 16 + c16];
+            for (int db = 0; db < 4; db++) {
+                const f32x4 bo = ld4(lv + kV_bo + db * 16 + r0);
 #pragma unroll
-                for (int j = 0; j < 2; j++) h.t[j * 4 + cb] += bo;
+                for (int j = 0; j < 2; j++) h.t[j * 4 + db] += bo;
             }
             // FP8: the products come out scaled by the matrix's power of two s;
             // the residual is scaled by s around them (exact)
@@ -661,12 +749,12 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M0, const TfArg
 #pragma unroll
                 for (int q = 0; q < 8; q++) h.t[q] *= f8[6];
             }
-            gemm_slots<kF8>(h, O0, O1, wbuf, 64);
+            gemm_slots_t<kF8>(h, O0, O1, wbuf, 64);
             if constexpr (kF8) {
 #pragma unroll
                 for (int q = 0; q < 8; q++) h.t[q] *= f8[7];
             }
-            normalize_rows<kF8>(h, X0, X1);
+            normalize_rows_t<kF8>(h, X0, X1);
             if constexpr (kF8) {
 #pragma unroll
                 for (int q = 0; q < 8; q++) h.t[q] *= f8[10];
@@ -677,96 +765,93 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M0, const TfArg
                 stage_rows_t(wbuf, kLdA, lw + 192 * 64 + 64 * 64 + chunk * 64 * 64, 64, 64, 64);  // w1T rows
                 stage_rows_t(wbuf + 64 * kLdA, kLdA, lw + 192 * 64 + 64 * 64 + 256 * 64 + chunk * 64, 256, 64, 64);
                 __syncthreads();
+                // f^T: lane (row c16, hidden units 16 hb + r0 + i) of the chunk
                 Tile32 f;
 #pragma unroll
-                for (int cb = 0; cb < 4; cb++) {
-                    const float b1 = lv[kV_b1 + chunk * 64 + cb * 16 + c16] * (kF8 ? f8[8] : 1.0f);
+                for (int hb = 0; hb < 4; hb++) {
+                    f32x4 b1 = ld4(lv + kV_b1 + chunk * 64 + hb * 16 + r0);
+                    if constexpr (kF8) b1 *= f8[8];
 #pragma unroll
-                    for (int j = 0; j < 2; j++) f.t[j * 4 + cb] = f32x4{b1, b1, b1, b1};
+                    for (int j = 0; j < 2; j++) f.t[j * 4 + hb] = b1;
                 }
-                gemm_slots<kF8>(f, X0, X1, wbuf, 64);
+                gemm_slots_t<kF8>(f, X0, X1, wbuf, 64);
 #pragma unroll
                 for (int j = 0; j < 2; j++) {
-                    AT *O = j ? O1 : O0;
+                    AT *O = (j ? O1 : O0) + c16 * kLdA + r0;
 #pragma unroll
-                    for (int cb = 0; cb < 4; cb++)
+                    for (int hb = 0; hb < 4; hb++) {
+                        f32x4 g;
 #pragma unroll
-                        for (int i = 0; i < 4; i++)
-                            O[(r0 + i) * kLdA + cb * 16 + c16] =
-                                OP::cvt(gelu_tab(gtab, kF8 ? f.t[j * 4 + cb][i] * f8[9] : f.t[j * 4 + cb][i]));
+                        for (int i = 0; i < 4; i++) g[i] = gelu_tab(gtab, kF8 ? f.t[j * 4 + hb][i] * f8[9] : f.t[j * 4 + hb][i]);
+                        store4<kF8>(O + hb * 16, g);
+                    }
                 }
                 wave_lds_sync();
-                gemm_slots<kF8>(h, O0, O1, wbuf + 64 * kLdA, 64);
+                gemm_slots_t<kF8>(h, O0, O1, wbuf + 64 * kLdA, 64);
             }
             if constexpr (kF8) {
 #pragma unroll
                 for (int q = 0; q < 8; q++) h.t[q] *= f8[11];
             }
 #pragma unroll
-            for (int cb = 0; cb < 4; cb++) {
-                const float b2 = lv[kV_b2 + cb * 16 + c16];
+            for (int db = 0; db < 4; db++) {
+                const f32x4 b2 = ld4(lv + kV_b2 + db * 16 + r0);
 #pragma unroll
-                for (int j = 0; j < 2; j++) h.t[j * 4 + cb] += b2;
+                for (int j = 0; j < 2; j++) h.t[j * 4 + db] += b2;
             }
         }
         // final LayerNorm (scale folded into the head), head, mask and the
-        // log-probability of the actual token, per own slot
+        // log-probability of the actual token, per own slot: lane l's group of
+        // four lanes holds row c16; lanes 0..15 finish it
 #pragma unroll
         for (int j = 0; j < 2; j++) {
+            float rstd, sh;
+            row_stats_t(h, j, rstd, sh);
+            float z[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int db = 0; db < 4; db++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const float y = fmaf(h.t[j * 4 + db][i], rstd, sh);
+                    const f32x4 hw4 = ld4(wf + M.fl.head_w + (db * 16 + r0 + i) * 4);
+#pragma unroll
+                    for (int t = 0; t < 4; t++) z[t] = fmaf(y, hw4[t], z[t]);
+                }
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                z[t] += __shfl_xor(z[t], 16, 64);
+                z[t] += __shfl_xor(z[t], 32, 64);
+            }
             float lsum = 0.f;
+            const int s = srb[j] * 16 + c16;
+            if (l < 16 && s < K) {
+                const uint64_t below = (1ull << s) - 1ull;  // s < K <= 64
+                const int up = __popcll(upm[j] & below), dn = __popcll(dnm[j] & below);
+                const int rem = K - 1 - s, orb = K - 1 - s;
+                float mx = -INFINITY;
+                bool ok[4];
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                float rs = 0.f, rs2 = 0.f;
-#pragma unroll
-                for (int cb = 0; cb < 4; cb++) {
-                    const float v = h.t[j * 4 + cb][i];
-                    rs += v;
-                    rs2 = fmaf(v, v, rs2);
+                for (int t = 0; t < 4; t++) {
+                    z[t] += wf[M.fl.head_b + t] + wf[M.fl.bias + orb * 4 + t];
+                    const int bu = t & 1, bd = t >> 1;
+                    ok[t] = (up + bu <= M.n_up) && (dn + bd <= M.n_dn) && (M.n_up - up - bu <= rem) &&
+                            (M.n_dn - dn - bd <= rem);
+                    if (ok[t]) mx = fmaxf(mx, z[t]);
                 }
-                const float mean = dpp_row_sum(rs) * (1.0f / kD);
-                const float var = fmaxf(dpp_row_sum(rs2) * (1.0f / kD) - mean * mean, 0.0f);
-                const float rstd = rsqrtf(var + 1e-5f);
-                const float sh = -mean * rstd;
-                float z[4] = {0.f, 0.f, 0.f, 0.f};
+                float den = 0.f;
 #pragma unroll
-                for (int cb = 0; cb < 4; cb++) {
-                    const float y = fmaf(h.t[j * 4 + cb][i], rstd, sh);
-#pragma unroll
-                    for (int t = 0; t < 4; t++) z[t] = fmaf(y, hw[cb][t], z[t]);
-                }
-#pragma unroll
-                for (int t = 0; t < 4; t++) z[t] = dpp_row_sum(z[t]);
-                const int s = srb[j] * 16 + r0 + i;
-                if (c16 == 0 && s < K) {
-                    const uint64_t below = (1ull << s) - 1ull;  // s < K <= 64
-                    const int up = __popcll(upm[j] & below), dn = __popcll(dnm[j] & below);
-                    const int rem = K - 1 - s, orb = K - 1 - s;
-                    float mx = -INFINITY;
-                    bool ok[4];
-#pragma unroll
-                    for (int t = 0; t < 4; t++) {
-                        z[t] += wf[M.fl.head_b + t] + wf[M.fl.bias + orb * 4 + t];
-                        const int bu = t & 1, bd = t >> 1;
-                        ok[t] = (up + bu <= M.n_up) && (dn + bd <= M.n_dn) && (M.n_up - up - bu <= rem) &&
-                                (M.n_dn - dn - bd <= rem);
-                        if (ok[t]) mx = fmaxf(mx, z[t]);
-                    }
-                    float den = 0.f;
+                for (int t = 0; t < 4; t++)
+                    if (ok[t]) den += __expf(z[t] - mx);
+                const int ts = token(j, s);
+                const float lden = __logf(den);
+                lsum = ok[ts] ? (z[ts] - mx) - lden : -INFINITY;
+                if (!kList && A.cond_out && s == A.cond_pos && sc[j] < cpt && tb + sc[j] < cnt)
 #pragma unroll
                     for (int t = 0; t < 4; t++)
-                        if (ok[t]) den += __expf(z[t] - mx);
-                    const int ts = token(j, s);
-                    const float lden = __logf(den);
-                    lsum += ok[ts] ? (z[ts] - mx) - lden : -INFINITY;
-                    if (!kList && A.cond_out && s == A.cond_pos && sc[j] < cpt && tb + sc[j] < cnt)
-#pragma unroll
-                        for (int t = 0; t < 4; t++)
-                            A.cond_out[(tb + sc[j]) * 4 + t] = ok[t] ? (double)((z[t] - mx) - lden) : -INFINITY;
-                }
+                        A.cond_out[(tb + sc[j]) * 4 + t] = ok[t] ? (double)((z[t] - mx) - lden) : -INFINITY;
             }
-            // rows live in lanes 0, 16, 32, 48
-            lsum += __shfl_xor(lsum, 16, 64);
-            lsum += __shfl_xor(lsum, 32, 64);
+            // the slot's rows live in lanes 0..15
+            lsum = dpp_row_sum(lsum);
             if (l == 0) slot_lp[2 * w + j] = (double)lsum;
         }
         __syncthreads();
