@@ -269,6 +269,55 @@ nnqs_status nnqs_bas(nnqs_model *model, int32_t precision, uint64_t seed, uint64
                      uint64_t *keys_out, uint32_t *counts_out, double *logabs_out, double *phase_out,
                      int64_t *n_unique, void *stream);
 
+/* ------------------------------------------------------- VMC gradient step */
+/* Weighted parameter gradient of the ansatz in FP64 (the derivative that
+ * Eq. 7 of Section 2.1 contracts): for device keys [n][2] and cotangents
+ * c_logabs [n], c_phase [n],
+ *   grad[w] = sum_b c_logabs[b] d log|psi(x_b)|/dw + c_phase[b] d phi(x_b)/dw
+ * over every weight of the layout of nnqs_model_create (device grad
+ * [nnqs_model_weight_count], overwritten).  The logit-bias table is a fixed
+ * part of the ansatz: its entries are zero.  With logabs / phase (device [n],
+ * both or neither) the forward values of the same pass are written too.
+ * Needs d_model 64, 4 heads, d_ff a multiple of 64 (the FP64 batched
+ * forward).  Grows model-owned scratch (about 33 KB per sequence row of a
+ * 256-configuration pass); calls on one model must not overlap.
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EHIP. */
+nnqs_status nnqs_model_grad(nnqs_model *model, const uint64_t *keys, int64_t n, const double *c_logabs,
+                            const double *c_phase, double *grad, double *logabs, double *phase, void *stream);
+
+/* The VMC energy gradient of Eq. 7 (Section 2.1) over unique samples with
+ * the weights of Eq. 6: with p_b = counts[b] / sum counts and
+ * E = sum_b p_b E_loc(b) (complex),
+ *   grad = 2 Re sum_b p_b (E_loc(b) - E) d ln psi*(x_b)
+ *        = sum_b 2 p_b [Re(E_loc(b) - E) d log|psi(x_b)| + Im(E_loc(b) - E) d phi(x_b)].
+ * Inputs (device): keys [n][2], counts [n], eloc [n][2] (re, im); outputs
+ * (device): grad [nnqs_model_weight_count]; energy [4] as in nnqs_eloc_table
+ * (may be NULL).  Errors: as nnqs_model_grad. */
+nnqs_status nnqs_vmc_gradient(nnqs_model *model, const uint64_t *keys, const uint32_t *counts, const double *eloc,
+                              int64_t n, double *grad, double *energy, void *stream);
+
+/* Learning rate of Eq. 13 (Section 4.1) at iteration step >= 1:
+ * d_model^-1/2 min(step^-1/2, step warmup^-3/2); 0 for invalid arguments. */
+double nnqs_lr_schedule(int64_t step, int32_t d_model, int32_t warmup);
+
+/* One AdamW step (decoupled weight decay; Section 4.1 names the optimizer,
+ * hyper-parameters are the caller's) of the model's FP64 weights with device
+ * grad and moments mom1, mom2 [nnqs_model_weight_count] (zero before step 1,
+ * updated in place): w <- w (1 - lr wd) - lr mh / (sqrt(vh) + eps) with
+ * mh = mom1 / (1 - beta1^step), vh = mom2 / (1 - beta2^step).  The fixed
+ * logit-bias table is left unchanged (its moments stay zero).  Afterwards the
+ * BF16 / FP8 copies of the weights are rebuilt from the FP64 ones
+ * (synchronises `stream`); batched-model objects made from the model must be
+ * made again.  Errors: EINVAL (step < 1, beta outside [0, 1), eps <= 0,
+ * lr < 0, weight_decay < 0), ENOMEM, EHIP. */
+nnqs_status nnqs_model_adamw_step(nnqs_model *model, const double *grad, int64_t step, double lr, double beta1,
+                                  double beta2, double eps, double weight_decay, double *mom1, double *mom2,
+                                  void *stream);
+
+/* Copies the model's FP64 weights (layout of nnqs_model_create) to device
+ * out [nnqs_model_weight_count].  Errors: EINVAL, EHIP. */
+nnqs_status nnqs_model_get_weights(const nnqs_model *model, double *out, void *stream);
+
 /* ----------------------------------------------------------------- screen */
 /* Learned screen (an addition to the paper, whose only filter is the
  * sample-aware restriction of Section 3.4 item 4): an MLP that predicts
@@ -429,6 +478,21 @@ nnqs_status nnqs_table_get_tune(const nnqs_table *tab, nnqs_tune *tune);
 nnqs_status nnqs_table_autotune(const nnqs_system *sys, nnqs_table *tab, const uint64_t *keys, const double *logabs,
                                 const double *phase, int64_t n, double *eloc, int32_t reps, nnqs_tune *best,
                                 double *best_ms, void *stream);
+
+/* Autotuner cache (host file, no GPU work).  nnqs_tune_key writes the key of
+ * a sample-aware workload, "<arch>:cu<CUs>:K<K>:u<n_up>:d<n_dn>:n<samples>",
+ * into out[cap] (ERANGE when it does not fit).  The cache is a text file of
+ * lines "<key> <waves_per_block> <blocks_per_cu> <filter_log2_bits>
+ * <splitter_levels> <search> <tile_samples> <ms>".  nnqs_tune_cache_lookup
+ * sets *found = 1 and fills tune (and *ms, may be NULL) from the last valid
+ * line of `key`, else *found = 0 (also when the file does not exist).
+ * nnqs_tune_cache_store replaces the line of `key` (or appends one),
+ * writing a temporary file next to `path` and renaming it over `path`.
+ * Keys hold no white space.  Errors: EINVAL (null, bad key, tune out of
+ * range, file not writable), ERANGE, EHIP. */
+nnqs_status nnqs_tune_key(const nnqs_system *sys, int64_t n, char *out, int64_t cap);
+nnqs_status nnqs_tune_cache_lookup(const char *path, const char *key, nnqs_tune *tune, double *ms, int32_t *found);
+nnqs_status nnqs_tune_cache_store(const char *path, const char *key, const nnqs_tune *tune, double ms);
 
 /* ------------------------------------------------- Pauli-string backend */
 /* The paper's own formulation of the sample-aware local energy (Section 3.4

@@ -28,9 +28,17 @@ from .api import (  # noqa: F401
     eloc_table,
     energy,
     energy_noalloc,
+    lr_schedule,
+    model_adamw_step,
+    model_get_weights,
+    model_grad,
     model_logpsi,
     pauli_build_host,
     timing_enable,
     timing_read,
+    tune_cache_lookup,
+    tune_cache_store,
+    tune_key,
     version,
+    vmc_gradient,
 )

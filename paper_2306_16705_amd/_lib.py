@@ -39,6 +39,18 @@ SIGNATURES = {
     "nnqs_timing_enable": (_i32, [_i32]),
     "nnqs_bas": (_i32, [_c_void_p, _i32, ctypes.c_uint64, ctypes.c_uint64, _i64, _c_void_p, _c_void_p, _c_void_p,
                         _c_void_p, ctypes.POINTER(_i64), _c_void_p]),
+    "nnqs_tune_key": (_i32, [_c_void_p, _i64, ctypes.c_char_p, _i64]),
+    "nnqs_tune_cache_lookup": (_i32, [ctypes.c_char_p, ctypes.c_char_p, _c_void_p, ctypes.POINTER(_f64),
+                                      ctypes.POINTER(_i32)]),
+    "nnqs_tune_cache_store": (_i32, [ctypes.c_char_p, ctypes.c_char_p, _c_void_p, _f64]),
+    "nnqs_model_grad": (_i32, [_c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                               _c_void_p]),
+    "nnqs_vmc_gradient": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p,
+                                 _c_void_p]),
+    "nnqs_lr_schedule": (_f64, [_i64, _i32, _i32]),
+    "nnqs_model_adamw_step": (_i32, [_c_void_p, _c_void_p, _i64, _f64, _f64, _f64, _f64, _f64, _c_void_p,
+                                     _c_void_p, _c_void_p]),
+    "nnqs_model_get_weights": (_i32, [_c_void_p, _c_void_p, _c_void_p]),
     "nnqs_batch_model_create": (_i32, [ctypes.POINTER(_c_void_p), _c_void_p, _i32]),
     "nnqs_batch_model_destroy": (_i32, [_c_void_p]),
     "nnqs_batch_model_run": (_i32, [_c_void_p, _c_void_p]),

@@ -117,21 +117,35 @@ class Table:
         L.check(self._lib.nnqs_table_get_tune(self.handle, ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in Tune._fields_}
 
-    def autotune(self, keys, logabs, phase, reps: int = 2, eloc=None, stream=None):
+    def autotune(self, keys, logabs, phase, reps: int = 2, eloc=None, cache_path: str | None = None, stream=None):
         """Times the candidate schedules of ``nnqs_eloc_table`` on these
         samples, keeps the fastest (the table is left built from them) and
-        returns ``(tune dict, best ms)``."""
+        returns ``(tune dict, best ms)``.  With ``cache_path`` a schedule
+        stored there for this workload's key is used without timing, and a
+        newly timed one is stored (``nnqs_tune_cache_*``)."""
         n = keys.shape[0]
         _need(keys, "keys", _KEY_DTYPES, (n, 2))
         _need(logabs, "logabs", (torch.float64,), (n,))
         _need(phase, "phase", (torch.float64,), (n,))
-        if eloc is None:
-            eloc = torch.empty((n, 2), dtype=torch.float64, device=keys.device)
         t = Tune()
         ms = ctypes.c_double()
+        key = None
+        if cache_path is not None:
+            key = tune_key(self.system, n)
+            found = ctypes.c_int32(0)
+            L.check(self._lib.nnqs_tune_cache_lookup(cache_path.encode(), key.encode(), ctypes.byref(t),
+                                                     ctypes.byref(ms), ctypes.byref(found)))
+            if found.value:
+                L.check(self._lib.nnqs_table_set_tune(self.handle, ctypes.byref(t)))
+                self.build(keys, logabs, phase, stream=stream)
+                return {f: getattr(t, f) for f, _ in Tune._fields_}, ms.value
+        if eloc is None:
+            eloc = torch.empty((n, 2), dtype=torch.float64, device=keys.device)
         L.check(self._lib.nnqs_table_autotune(self.system.handle, self.handle, _ptr(keys), _ptr(logabs), _ptr(phase),
                                               n, _ptr(eloc), int(reps), ctypes.byref(t), ctypes.byref(ms),
                                               _stream(stream)))
+        if key is not None:
+            L.check(self._lib.nnqs_tune_cache_store(cache_path.encode(), key.encode(), ctypes.byref(t), ms.value))
         return {f: getattr(t, f) for f, _ in Tune._fields_}, ms.value
 
     def close(self):
@@ -269,6 +283,90 @@ def bas(model: Model, n_samples: int, seed: int, precision: int = NNQS_BF16, cap
     return keys[:k], counts[:k], la[:k], (ph[:k] if ph is not None else None)
 
 
+def tune_key(system: System, n: int) -> str:
+    """Autotuner cache key of a sample-aware workload (``nnqs_tune_key``)."""
+    buf = ctypes.create_string_buffer(256)
+    L.check(L.load().nnqs_tune_key(system.handle, int(n), buf, 256))
+    return buf.value.decode()
+
+
+def tune_cache_lookup(path: str, key: str):
+    """``(tune dict, ms)`` stored for ``key`` in the cache file, or None."""
+    t = Tune()
+    ms = ctypes.c_double()
+    found = ctypes.c_int32(0)
+    L.check(L.load().nnqs_tune_cache_lookup(path.encode(), key.encode(), ctypes.byref(t), ctypes.byref(ms),
+                                            ctypes.byref(found)))
+    return ({f: getattr(t, f) for f, _ in Tune._fields_}, ms.value) if found.value else None
+
+
+def tune_cache_store(path: str, key: str, tune: dict, ms: float) -> None:
+    """Stores a schedule for ``key`` in the cache file (``nnqs_tune_cache_store``)."""
+    t = Tune(*(int(tune[f]) for f, _ in Tune._fields_))
+    L.check(L.load().nnqs_tune_cache_store(path.encode(), key.encode(), ctypes.byref(t), float(ms)))
+
+
+def model_grad(model: Model, keys, c_logabs, c_phase, grad=None, with_values: bool = False, stream=None):
+    """FP64 weighted parameter gradient (``nnqs_model_grad``): device tensor
+    ``grad [weight_count]`` (and ``(logabs, phase)`` of the same pass with
+    ``with_values``)."""
+    n = keys.shape[0]
+    _need(keys, "keys", _KEY_DTYPES, (n, 2))
+    _need(c_logabs, "c_logabs", (torch.float64,), (n,))
+    _need(c_phase, "c_phase", (torch.float64,), (n,))
+    nw = L.load().nnqs_model_weight_count(ctypes.byref(model.desc))
+    if grad is None:
+        grad = torch.empty(nw, dtype=torch.float64, device=keys.device)
+    la = torch.empty(n, dtype=torch.float64, device=keys.device) if with_values else None
+    ph = torch.empty(n, dtype=torch.float64, device=keys.device) if with_values else None
+    L.check(L.load().nnqs_model_grad(model.handle, _ptr(keys), n, _ptr(c_logabs), _ptr(c_phase), _ptr(grad),
+                                     _ptr(la), _ptr(ph), _stream(stream)))
+    return (grad, la, ph) if with_values else grad
+
+
+def vmc_gradient(model: Model, keys, counts, eloc, grad=None, energy=None, stream=None):
+    """Eq. 7 gradient (``nnqs_vmc_gradient``): ``(grad [weight_count],
+    energy [4])`` device tensors."""
+    n = keys.shape[0]
+    _need(keys, "keys", _KEY_DTYPES, (n, 2))
+    _need(counts, "counts", (torch.int32,), (n,))
+    _need(eloc, "eloc", (torch.float64,), (n, 2))
+    nw = L.load().nnqs_model_weight_count(ctypes.byref(model.desc))
+    if grad is None:
+        grad = torch.empty(nw, dtype=torch.float64, device=keys.device)
+    if energy is None:
+        energy = torch.empty(4, dtype=torch.float64, device=keys.device)
+    L.check(L.load().nnqs_vmc_gradient(model.handle, _ptr(keys), _ptr(counts), _ptr(eloc), n, _ptr(grad),
+                                       _ptr(energy), _stream(stream)))
+    return grad, energy
+
+
+def lr_schedule(step: int, d_model: int, warmup: int = 4000) -> float:
+    """Eq. 13 learning rate (``nnqs_lr_schedule``)."""
+    return float(L.load().nnqs_lr_schedule(int(step), int(d_model), int(warmup)))
+
+
+def model_adamw_step(model: Model, grad, step: int, lr: float, mom1, mom2, beta1: float = 0.9,
+                     beta2: float = 0.999, eps: float = 1e-8, weight_decay: float = 0.01, stream=None):
+    """One AdamW step of the model's FP64 weights (``nnqs_model_adamw_step``)."""
+    nw = L.load().nnqs_model_weight_count(ctypes.byref(model.desc))
+    for t, name in ((grad, "grad"), (mom1, "mom1"), (mom2, "mom2")):
+        _need(t, name, (torch.float64,), (nw,))
+    L.check(L.load().nnqs_model_adamw_step(model.handle, _ptr(grad), int(step), float(lr), float(beta1),
+                                           float(beta2), float(eps), float(weight_decay), _ptr(mom1), _ptr(mom2),
+                                           _stream(stream)))
+
+
+def model_get_weights(model: Model, out=None, stream=None):
+    """The model's FP64 weights as a device tensor (``nnqs_model_get_weights``)."""
+    nw = L.load().nnqs_model_weight_count(ctypes.byref(model.desc))
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = torch.empty(nw, dtype=torch.float64, device=dev)
+    L.check(L.load().nnqs_model_get_weights(model.handle, _ptr(out), _stream(stream)))
+    return out
+
+
 def model_logpsi(model: Model, keys, precision: int = NNQS_FP64, logabs=None, phase=None, stream=None):
     """``(log|psi|, phase)`` device tensors for ``keys [n, 2]`` (``nnqs_model_logpsi``)."""
     n = keys.shape[0]
@@ -345,6 +443,21 @@ class Screen:
         out = np.empty(self.count, np.float64)
         L.check(self._lib.nnqs_screen_get_weights(self.handle, out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return out
+
+    def save(self, path: str, stream=None) -> None:
+        """Writes the FP64 master weights and the shape to ``path`` (a
+        safetensors file: no code runs when it is read back)."""
+        from safetensors.numpy import save_file
+        save_file({"weights": self.weights(stream),
+                   "shape": np.array([self.n_spin_orb, self.hidden], dtype=np.int64)}, path)
+
+    @classmethod
+    def load(cls, path: str) -> "Screen":
+        """A screen with the weights and shape stored by :meth:`save`."""
+        from safetensors.numpy import load_file
+        d = load_file(path)
+        n_spin_orb, hidden = (int(v) for v in d["shape"])
+        return cls(n_spin_orb, hidden, d["weights"])
 
     def forward(self, xkeys, exc, precision: int = NNQS_FP64, out=None, stream=None):
         n = xkeys.shape[0]

@@ -273,6 +273,7 @@ nnqs_status nnqs_model_destroy(nnqs_model *m) {
     if (!m) return NNQS_OK;
     hipFree(m->d_w64);
     hipFree(m->d_f64s);
+    hipFree(m->d_grads);
     bf16_model_free(m);
     eloc_model_free(m);
     delete m;

@@ -56,6 +56,10 @@ struct nnqs_model {
     // scratch of the layer-batched FP64 forward (model_f64.hip), grown on demand
     void *d_f64s = nullptr;
     size_t f64cap = 0;
+    // scratch of the FP64 backward (grad_f64.hip): saved activations of one
+    // pass, their gradients and the weight-gradient partials
+    void *d_grads = nullptr;
+    size_t gradcap = 0;
     // BF16 path: transposed BF16 matrices and FP32 vectors (model_bf16.hip)
     void *d_bf16 = nullptr;
     float *d_f32 = nullptr;

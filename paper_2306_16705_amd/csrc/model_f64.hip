@@ -9,13 +9,11 @@
 // order differs from a one-configuration-at-a-time evaluation.
 #include <cmath>
 
-#include "model.hpp"
+#include "f64_kernels.hpp"
 
 namespace nnqs {
 
 constexpr int64_t kF64Batch = 4096;  // configurations per pass
-
-__device__ __forceinline__ double gelu_f64(double v) { return 0.5 * v * (1.0 + erf(v * 0.70710678118654752440)); }
 
 // Tokens (previous-token input) and embeddings: h[b*K + s][c].
 __global__ void k64_embed(ModelView M, const uint64_t *__restrict__ keys, int64_t B, int8_t *__restrict__ tok,
@@ -58,17 +56,16 @@ __global__ void __launch_bounds__(256) k64_layernorm(const double *__restrict__ 
     out[row * 64 + lane] = (v - mean) * r * g[lane] + b[lane];
 }
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-// C[r][j] = epi(bias[j] + sum_k A[r][k] W[k][j]) for r < M, j < N; EPI 0
-// stores, 1 adds to C (residual), 2 stores GELU.  Block: 64 x 64 tile of C,
+// C[r][j] = epi(bias[j] + sum_k A[r][k] B[k][j]) for r < M, j < N, with
+// B[k][j] = W[k][j], or W[j][k] with TB (products with a transposed weight in
+// the backward); EPI 0 stores, 1 adds to C (residual), 2 stores GELU.  Block: 64 x 64 tile of C,
 // four waves of 16 rows each, on v_mfma_f64_16x16x4_f64 (lane l holds
 // A[l & 15][l >> 4] and B[l >> 4][l & 15]; accumulator register i of lane l
 // holds row (l >> 4) + 4 i, column l & 15, unlike the BF16 16x16 variants);
 // k in slices of 32 through LDS, the next slice's global loads in flight
 // during the current slice's products.  FP64 throughout: only the summation order differs from a plain dot
 // product.
-template <int EPI>
+template <int EPI, bool TB>
 __global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, int lda, const double *__restrict__ W,
                                                 int ldw, const double *__restrict__ bias, int64_t M, int N, int Kd,
                                                 double *__restrict__ C, int ldc) {
@@ -80,7 +77,8 @@ __global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, in
     const int64_t r0 = (int64_t)blockIdx.y * 64;
     const int c0 = blockIdx.x * 64;
     // slice loads: thread t takes A[r0 + (t >> 5) + 8 e][k0 + (t & 31)] and
-    // W[k0 + (t >> 6) + 4 e][c0 + (t & 63)], e = 0..7 (coalesced rows)
+    // W[k0 + (t >> 6) + 4 e][c0 + (t & 63)], e = 0..7 (coalesced rows); with
+    // TB, W[c0 + (t >> 5) + 8 e][k0 + (t & 31)] into the slice's column
     const int at = threadIdx.x & 31, ar = threadIdx.x >> 5, wc = threadIdx.x & 63, wr = threadIdx.x >> 6;
     double pa[8], pw[8];
     auto load = [&](int k0) {
@@ -88,8 +86,13 @@ __global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, in
         for (int e = 0; e < 8; e++) {
             const int64_t r = r0 + ar + 8 * e;
             pa[e] = (r < M && k0 + at < Kd) ? A[r * lda + k0 + at] : 0.0;
-            const int kw = k0 + wr + 4 * e;
-            pw[e] = (kw < Kd && c0 + wc < N) ? W[(int64_t)kw * ldw + c0 + wc] : 0.0;
+            if (TB) {
+                const int cw = c0 + ar + 8 * e;
+                pw[e] = (cw < N && k0 + at < Kd) ? W[(int64_t)cw * ldw + k0 + at] : 0.0;
+            } else {
+                const int kw = k0 + wr + 4 * e;
+                pw[e] = (kw < Kd && c0 + wc < N) ? W[(int64_t)kw * ldw + c0 + wc] : 0.0;
+            }
         }
     };
     f64x4 acc[4];
@@ -101,7 +104,8 @@ __global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, in
 #pragma unroll
         for (int e = 0; e < 8; e++) {
             As[ar + 8 * e][at] = pa[e];
-            Ws[wr + 4 * e][wc] = pw[e];
+            if (TB) Ws[at][ar + 8 * e] = pw[e];
+            else Ws[wr + 4 * e][wc] = pw[e];
         }
         __syncthreads();
         if (k0 + KS < Kd) load(k0 + KS);  // the next slice's loads overlap this slice's products
@@ -377,5 +381,15 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
     }
     return NNQS_OK;
 }
+
+// Instances launched from other files (the FP64 backward).
+template __global__ void k64_gemm<0, false>(const double *, int, const double *, int, const double *, int64_t, int,
+                                            int, double *, int);
+template __global__ void k64_gemm<1, false>(const double *, int, const double *, int, const double *, int64_t, int,
+                                            int, double *, int);
+template __global__ void k64_gemm<0, true>(const double *, int, const double *, int, const double *, int64_t, int,
+                                           int, double *, int);
+template __global__ void k64_gemm<1, true>(const double *, int, const double *, int, const double *, int64_t, int,
+                                           int, double *, int);
 
 }  // namespace nnqs
