@@ -14,6 +14,10 @@
 // the accumulation as in Section 3.4 item 2).  The filter has no false
 // negatives, so every table member connected to x is found.
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
 
 #include "enumerate.hpp"
 
@@ -853,6 +857,79 @@ done:
         if (best_ms) *best_ms = best_t;
     }
     return s;
+}
+
+// Autotuner cache: a text file of lines
+//   <key> <waves_per_block> <blocks_per_cu> <filter_log2_bits> <splitter_levels> <search> <tile_samples> <ms>
+// written whole to a temporary file and renamed over the old one.
+nnqs_status nnqs_tune_key(const nnqs_system *sys, int64_t n, char *out, int64_t cap) {
+    clear_error();
+    if (!sys || !out) return fail(NNQS_EINVAL, "null pointer argument");
+    hipDeviceProp_t prop{};
+    NNQS_HIP_CHECK(hipGetDeviceProperties(&prop, sys->device));
+    char arch[64];
+    int a = 0;
+    for (const char *c = prop.gcnArchName; *c && *c != ':' && a < 63; c++) arch[a++] = *c;  // drop feature flags
+    arch[a] = 0;
+    const int w = std::snprintf(out, (size_t)(cap > 0 ? cap : 0), "%s:cu%d:K%d:u%d:d%d:n%lld", arch, sys->cu_count,
+                                sys->view.K, sys->view.n_up, sys->view.n_dn, (long long)n);
+    if (w < 0 || w >= cap) return fail(NNQS_ERANGE, "key needs %d bytes", w + 1);
+    return NNQS_OK;
+}
+
+static bool key_ok(const char *key) {
+    if (!key || !*key) return false;
+    for (const char *c = key; *c; c++)
+        if (*c == ' ' || *c == '\t' || *c == '\n' || *c == '\r') return false;
+    return true;
+}
+
+nnqs_status nnqs_tune_cache_lookup(const char *path, const char *key, nnqs_tune *tune, double *ms, int32_t *found) {
+    clear_error();
+    if (!path || !tune || !found) return fail(NNQS_EINVAL, "null pointer argument");
+    if (!key_ok(key)) return fail(NNQS_EINVAL, "key must be non-empty without white space");
+    *found = 0;
+    std::FILE *f = std::fopen(path, "r");
+    if (!f) return NNQS_OK;  // no cache yet
+    char line[512], k[256];
+    while (std::fgets(line, sizeof line, f)) {
+        nnqs_tune t{};
+        double v = 0.0;
+        if (std::sscanf(line, "%255s %d %d %d %d %d %d %lf", k, &t.waves_per_block, &t.blocks_per_cu,
+                        &t.filter_log2_bits, &t.splitter_levels, &t.search, &t.tile_samples, &v) != 8)
+            continue;  // not an entry
+        if (std::strcmp(k, key) != 0 || !tune_valid(t)) continue;
+        *tune = t;
+        if (ms) *ms = v;
+        *found = 1;  // the last valid entry of the key wins
+    }
+    std::fclose(f);
+    return NNQS_OK;
+}
+
+nnqs_status nnqs_tune_cache_store(const char *path, const char *key, const nnqs_tune *tune, double ms) {
+    clear_error();
+    if (!path || !tune) return fail(NNQS_EINVAL, "null pointer argument");
+    if (!key_ok(key)) return fail(NNQS_EINVAL, "key must be non-empty without white space");
+    if (!tune_valid(*tune)) return fail(NNQS_EINVAL, "tuning parameters out of range");
+    std::vector<std::string> keep;
+    if (std::FILE *f = std::fopen(path, "r")) {
+        char line[512], k[256];
+        while (std::fgets(line, sizeof line, f)) {
+            if (std::sscanf(line, "%255s", k) == 1 && std::strcmp(k, key) == 0) continue;  // replaced below
+            keep.emplace_back(line);
+        }
+        std::fclose(f);
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    std::FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return fail(NNQS_EINVAL, "cannot write %s", tmp.c_str());
+    for (const std::string &l : keep) std::fputs(l.c_str(), f);
+    std::fprintf(f, "%s %d %d %d %d %d %d %.6f\n", key, tune->waves_per_block, tune->blocks_per_cu,
+                 tune->filter_log2_bits, tune->splitter_levels, tune->search, tune->tile_samples, ms);
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) return fail(NNQS_EINVAL, "cannot replace %s", path);
+    return NNQS_OK;
 }
 
 }  // extern "C"

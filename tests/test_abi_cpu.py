@@ -82,3 +82,25 @@ def test_null_pointers_rejected_on_host(lib):
     assert lib.nnqs_connection_count(None) == -1
     assert lib.nnqs_system_destroy(None) == 0
     assert lib.nnqs_table_destroy(None) == 0
+
+
+def test_tune_cache_on_host(lib, tmp_path):
+    """The autotuner cache is plain host file work: store, replace, look up."""
+    import paper_2306_16705_amd as nn
+    path = str(tmp_path / "tune.txt")
+    assert nn.tune_cache_lookup(path, "gfx950:cu256:K24:u6:d6:n65536") is None  # no file yet
+    t1 = dict(waves_per_block=16, blocks_per_cu=1, filter_log2_bits=20, splitter_levels=10, search=1,
+              tile_samples=256)
+    nn.tune_cache_store(path, "gfx950:cu256:K24:u6:d6:n65536", t1, 1.99)
+    nn.tune_cache_store(path, "gfx950:cu256:K60:u20:d20:n128", dict(t1, search=2), 7.5)
+    t2 = dict(t1, waves_per_block=12)
+    nn.tune_cache_store(path, "gfx950:cu256:K24:u6:d6:n65536", t2, 1.80)
+    got = nn.tune_cache_lookup(path, "gfx950:cu256:K24:u6:d6:n65536")
+    assert got[0] == t2 and abs(got[1] - 1.80) < 1e-9
+    assert nn.tune_cache_lookup(path, "gfx950:cu256:K60:u20:d20:n128")[0]["search"] == 2
+    with open(path) as f:
+        assert len(f.read().splitlines()) == 2
+    with pytest.raises(nn.NNQSError):
+        nn.tune_cache_store(path, "bad key", t1, 1.0)
+    with pytest.raises(nn.NNQSError):
+        nn.tune_cache_store(path, "k", dict(t1, search=3), 1.0)

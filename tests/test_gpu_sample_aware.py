@@ -212,6 +212,28 @@ def test_autotune_picks_a_schedule_and_keeps_results(nn):
     assert np.all(np.abs(g - base) <= 1e-12 * np.maximum(1.0, np.abs(base)))
 
 
+def test_autotune_cache_round_trip(nn, tmp_path):
+    """A schedule timed once is stored under the workload's key and used
+    again without timing; results stay those of the default schedule."""
+    d = synth.config_inputs(2, n_unique=2048)
+    _print_case("autotune cache")
+    S = _system(nn, d)
+    args = (dev(d["keys"]), dev(d["counts"], torch.int32), dev(d["logabs"]), dev(d["phase"]))
+    key = nn.tune_key(S, 2048)
+    assert ":K24:u6:d6:n2048" in key and key.startswith("gfx")
+    path = str(tmp_path / "tune.txt")
+    T = nn.Table(S, capacity=2048)
+    tune, ms = T.autotune(args[0], args[2], args[3], reps=1, cache_path=path)
+    assert nn.tune_cache_lookup(path, key) == (tune, pytest.approx(ms))
+    T2 = nn.Table(S, capacity=2048)
+    tune2, ms2 = T2.autotune(args[0], args[2], args[3], reps=1, cache_path=path)
+    assert tune2 == tune and ms2 == pytest.approx(ms) and T2.get_tune() == tune
+    e1, _ = nn.eloc_table(S, T, *args)
+    e2, _ = nn.eloc_table(S, T2, *args)
+    torch.cuda.synchronize()
+    assert torch.equal(e1, e2)
+
+
 # ---------------------------------------------------------- error model
 def test_error_codes(nn):
     d = synth.config_inputs(2, n_unique=64)

@@ -267,3 +267,16 @@ def test_fp8_inference_error_vs_oracle(nn, n):
     print(f"FP8 screen n={n}: max err {err.max():.3e} (BF16 {e16.max():.3e}), RMS {np.sqrt(np.mean(err ** 2)):.3e} "
           f"over y range [{ref.min():.3f}, {ref.max():.3f}]")
     assert np.all(err <= 0.25 + 0.03 * np.abs(ref))
+
+
+def test_screen_save_load_round_trip(nn, tmp_path):
+    """Screen weights persist through a safetensors file bit for bit."""
+    N, H = 48, 32
+    rng = np.random.default_rng(12)
+    w = rng.normal(0.0, 0.1, size=int(oracle.screen_size(N, H)))
+    s1 = nn.Screen(N, H, w)
+    path = str(tmp_path / "screen.safetensors")
+    s1.save(path)
+    s2 = nn.Screen.load(path)
+    assert (s2.n_spin_orb, s2.hidden) == (N, H)
+    assert np.array_equal(s2.weights(), s1.weights())
