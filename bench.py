@@ -115,6 +115,8 @@ def main():
                     help="samples drawn by batch autoregressive sampling from the N=120 network (0 = skip)")
     ap.add_argument("--batch-model-samples", type=int, default=8,
                     help="samples per system of the batched transformer mode over the batch recipe (0 = skip)")
+    ap.add_argument("--vmc-reps", type=int, default=3,
+                    help="timed FP64 VMC gradient passes (Eq. 7) on the headline samples (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
@@ -327,6 +329,24 @@ def main():
                "note": "batch autoregressive sampling from the N=120 network (60 positions, one forward of every "
                        "unique prefix per position)"}
         log(f"BAS: {args.bas_samples} samples -> {bk.shape[0]} unique in {dt_bas:.2f} s")
+    vmc = None
+    if args.vmc_reps > 0:
+        # Eq. 7 on the headline samples with their screened local energies:
+        # the FP64 forward with saved activations, the backward, the weighted sum
+        e_dev = torch.from_numpy(e_scr).cuda()
+        nn.vmc_gradient(M, keys, cnt, e_dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.vmc_reps):
+            g, _ = nn.vmc_gradient(M, keys, cnt, e_dev)
+        torch.cuda.synchronize()
+        dt_vmc = (time.perf_counter() - t0) / args.vmc_reps
+        vmc = {"samples": S_n, "ms": dt_vmc * 1e3, "samples_per_s": S_n / dt_vmc, "weights": int(g.numel()),
+               "grad_norm": float(g.norm()), "precision": "fp64",
+               "note": "FP64 parameter gradient of Eq. 7 (forward with saved activations + backward) for the "
+                       "headline's samples and their screened local energies"}
+        log(f"VMC gradient: {S_n} samples in {dt_vmc * 1e3:.1f} ms ({S_n / dt_vmc:.0f} samples/s), "
+            f"{g.numel()} weights")
     sa = sample_aware_leg(args, nn, synth, np, torch) if args.sa else None
     batch = batch_leg(args, nn, synth, np, torch) if args.batch_systems > 0 else None
     batch_model = (batch_model_leg(args, nn, synth, np, torch)
@@ -390,6 +410,7 @@ def main():
                    "training_s": t_train, "adam_steps": args.screen_steps, "held_out_rmse_nats": rmse,
                    "used": scr_used is not None},
         "batch_autoregressive_sampling": bas,
+        "vmc_gradient": vmc,
         "sample_aware_n48": sa,
         "batch_path": batch,
         "batch_model_path": batch_model,
