@@ -392,6 +392,10 @@ void eloc_model_free(nnqs_model *m) {
     hipFree(m->d_pre);
     hipFree(m->d_csla);
     hipFree(m->d_hdr);
+    hipFree(m->d_kv64);
+    hipFree(m->d_pre64);
+    m->d_kv64 = m->d_pre64 = nullptr;
+    m->kv64cap = 0;
     m->d_kv = nullptr;
     m->d_pre = m->d_csla = nullptr;
     m->d_hdr = nullptr;
@@ -496,7 +500,7 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cla), cc * 8);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cph), cc * 8);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_nsel), 8);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_hdr), 16 * 8);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_hdr), 24 * 8);
         if (s1 != NNQS_OK) {
             eloc_model_free(model);
             return s1;
@@ -515,6 +519,18 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         }
         model->kvcap = chunk;
     }
+    const bool refine64 = refine && bf16;  // FP64 refinement with the samples' FP64 prefix cache
+    if (refine64 && model->kv64cap < chunk) {
+        NNQS_HIP_CHECK(hipStreamSynchronize(st));
+        nnqs_status s1 =
+            grow(reinterpret_cast<void **>(&model->d_kv64), (size_t)chunk * f64_cache_doubles(model) * sizeof(double));
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_pre64), (size_t)chunk * 4 * sizeof(double));
+        if (s1 != NNQS_OK) {
+            eloc_model_free(model);
+            return s1;
+        }
+        model->kv64cap = chunk;
+    }
     if (model->scap < n) {
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
         nnqs_status s1 = grow(reinterpret_cast<void **>(&model->d_sla), (size_t)n * 8);
@@ -526,9 +542,13 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         model->scap = n;
     }
     // the samples' own amplitudes: in the top precision of the evaluation
-    nnqs_status s1 =
-        enqueue_logpsi(model, keys, n, refine ? NNQS_FP64 : precision, model->d_sla, model->d_sph, st);
-    if (s1 != NNQS_OK) return s1;
+    // (with FP64 refinement of the BF16 / FP8 path, chunk by chunk below,
+    // together with their FP64 prefix cache)
+    nnqs_status s1 = NNQS_OK;
+    if (!refine64) {
+        s1 = enqueue_logpsi(model, keys, n, refine ? NNQS_FP64 : precision, model->d_sla, model->d_sph, st);
+        if (s1 != NNQS_OK) return s1;
+    }
     int64_t evaluated = 0, refined = 0;
     int64_t *d_evalcnt = model->d_hdr + 8;
     if (bf16) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, d_evalcnt, 5);
@@ -539,6 +559,11 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         hipLaunchKernelGGL(k_enum_keys, dim3(grid), dim3(256), 0, st, sys->view, keys + 2 * s0, m, bps,
                            model->d_xkeys, screen ? model->d_xexc : (uint8_t *)nullptr,
                            need_lh ? model->d_loghx : (float *)nullptr);
+        if (refine64) {
+            s1 = enqueue_logpsi_f64(model, keys + 2 * s0, m, model->d_sla + s0, model->d_sph + s0, st, -1, nullptr,
+                                    model->d_kv64, model->d_pre64);
+            if (s1 != NNQS_OK) return s1;
+        }
         if (bf16) {
             // the chunk's samples once through the forward, keeping their keys,
             // values and log-probability prefix sums; then every kept x'
@@ -581,7 +606,32 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
             if (s1 != NNQS_OK) return s1;
             evaluated += k;
         }
-        if (refine) {  // FP64 for every connection whose first-pass contribution is not negligible
+        if (refine64) {
+            // FP64 for every connection whose first-pass contribution is not
+            // negligible, by prefix class from the samples' FP64 cache
+            ClsArgs ra{};
+            ra.R = SelRule{nullptr, model->d_xla, model->d_loghx, model->d_sla + s0, C, o.refine_nats};
+            ra.rule = true;
+            ra.keys = keys + 2 * s0;
+            ra.xkeys = model->d_xkeys;
+            ra.total = total;
+            ra.K = sys->view.K;
+            const int nb = (int)((total + kSelBlock - 1) / kSelBlock);
+            int64_t *d_rhdr = model->d_hdr + 16;
+            hipLaunchKernelGGL(k_cls_count, dim3(nb), dim3(256), 0, st, ra, model->d_blockcnt);
+            hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, model->d_blockcnt, nb, d_rhdr,
+                               (int64_t *)nullptr);
+            hipLaunchKernelGGL(k_cls_write, dim3(nb), dim3(64), 0, st, ra, model->d_blockcnt, model->d_sel, false,
+                               (double *)nullptr, (double *)nullptr);
+            NNQS_HIP_CHECK(hipGetLastError());
+            int64_t rh[8];
+            NNQS_HIP_CHECK(hipMemcpyAsync(rh, d_rhdr, sizeof(rh), hipMemcpyDeviceToHost, st));
+            NNQS_HIP_CHECK(hipStreamSynchronize(st));
+            refined += rh[0] + rh[1] + rh[2] + rh[3];
+            s1 = enqueue_f64_list(model, model->d_xkeys, C, model->d_sel, rh, model->d_kv64, model->d_pre64,
+                                  model->d_xla, model->d_xph, st);
+            if (s1 != NNQS_OK) return s1;
+        } else if (refine) {  // FP64 for every connection whose first-pass contribution is not negligible
             SelRule R{nullptr, model->d_xla, model->d_loghx, model->d_sla + s0, C, o.refine_nats};
             int64_t k = 0;
             s1 = select_and_evaluate(model, R, total, false, NNQS_FP64, st, &k);

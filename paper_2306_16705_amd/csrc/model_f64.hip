@@ -312,12 +312,237 @@ __global__ void __launch_bounds__(256) k64_finish(ModelView M, const double *__r
     }
 }
 
+// ------------------------------------------------ prefix reuse in FP64
+// Cache of a configuration's forward for the prefix-reusing evaluation of its
+// connections: per configuration [L][2][K][64] doubles, every layer's keys
+// then values (all heads, as the attention used them), and pre[4] with
+// pre[q] = sum_{s < 16 q} log pi_s.  By causality of the attention and of the
+// autoregressive product of Eq. 8, a connected x' whose first changed
+// position is s0 has the same rows s <= s0 as its sample, so its forward can
+// start at row 16 floor(s0 / 16) from the cache.
+__global__ void k64_cache_kv(const double *__restrict__ kk, const double *__restrict__ v, int64_t B, int K, int l,
+                             int L, double *__restrict__ kvc) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)K * 64;
+    if (e >= B * per) return;
+    const int64_t b = e / per, r = e - b * per;
+    double *dst = kvc + ((b * L + l) * 2) * per + r;
+    dst[0] = kk[e];
+    dst[per] = v[e];
+}
+
+__global__ void k64_prefix(const double *__restrict__ lp, int64_t B, int K, double *__restrict__ pre) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double s = 0.0;
+    for (int q = 0; q < 4; q++) {
+        pre[4 * b + q] = s;
+        for (int t = 16 * q; t < 16 * q + 16 && t < K; t++) s += lp[b * K + t];
+    }
+}
+
+// Rows s = 16 sb .. K-1 of listed connections x' = xkeys[list[i]]: row
+// r = i Rb + s - 16 sb (Rb = K - 16 sb).  Embeddings, and the keys of the
+// batch gathered into ckeys (phase MLP, head).
+__global__ void k64r_embed(ModelView M, const uint64_t *__restrict__ xkeys, const int32_t *__restrict__ list,
+                           int64_t B, int sb, double *__restrict__ h, uint64_t *__restrict__ ckeys) {
+    const int K = M.K, d = M.d, Rb = K - 16 * sb;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= B * Rb * d) return;
+    const int64_t row = e / d;
+    const int c = (int)(e - row * d);
+    const int64_t i = row / Rb;
+    const int s = 16 * sb + (int)(row - i * Rb);
+    const int64_t src = list[i];
+    Key x;
+    x.lo = xkeys[2 * src];
+    x.hi = xkeys[2 * src + 1];
+    if (c == 0 && s == 16 * sb) {
+        ckeys[2 * i] = x.lo;
+        ckeys[2 * i + 1] = x.hi;
+    }
+    int prev = 4;
+    if (s > 0) {
+        const int o = K - s;  // orbital of position s - 1
+        prev = key_bit(x, 2 * o) + 2 * key_bit(x, 2 * o + 1);
+    }
+    h[e] = M.w64[M.off.tok_emb + prev * d + c] + M.w64[M.off.pos_emb + (int64_t)s * d + c];
+}
+
+// Causal attention of the listed rows on FP64 MFMA (the tiling of
+// k64_attention): one wave per (configuration, head); keys and values of rows
+// below 16 sb come from the cache of the connection's sample (list[i] / C in
+// the chunk), the rest from this pass.
+__global__ void __launch_bounds__(256) k64r_attention(const double *__restrict__ q, const double *__restrict__ k,
+                                                      const double *__restrict__ v, const double *__restrict__ kvc,
+                                                      const int32_t *__restrict__ list, int64_t C, int64_t B, int K,
+                                                      int L, int l, int sb, double scale, double *__restrict__ o) {
+    __shared__ double Ps[4][16][64 + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t g = (int64_t)blockIdx.x * 4 + w;
+    if (g >= B * 4) return;  // wave-uniform; the kernel has no block barrier
+    const int64_t i = g >> 2;
+    const int hh = (int)(g & 3);
+    const int Rb = K - 16 * sb, s0 = 16 * sb;
+    const int64_t smp = list[i] / C;
+    const int64_t per = (int64_t)K * 64;
+    const double *kc = kvc + ((smp * L + l) * 2) * per + hh * 16, *vc = kc + per;
+    const int64_t rb = i * Rb * 64 + hh * 16;
+    const double *qh = q + rb, *kh = k + rb, *vh = v + rb;
+    auto ldk = [&](int s, int c) { return s >= K ? 0.0 : s < s0 ? kc[(int64_t)s * 64 + c] : kh[(int64_t)(s - s0) * 64 + c]; };
+    auto ldv = [&](int s, int c) { return s >= K ? 0.0 : s < s0 ? vc[(int64_t)s * 64 + c] : vh[(int64_t)(s - s0) * 64 + c]; };
+    double kf[4][4], vf[16];
+#pragma unroll
+    for (int kb = 0; kb < 4; kb++)
+#pragma unroll
+        for (int k4 = 0; k4 < 4; k4++) kf[kb][k4] = ldk(kb * 16 + lr, 4 * k4 + lk);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) vf[kk] = ldv(4 * kk + lk, lr);
+    double(*P)[64 + 1] = Ps[w];
+#pragma unroll
+    for (int qb = 0; qb < 4; qb++) {
+        if (qb < sb || 16 * qb >= K) continue;  // wave-uniform
+        double qf[4];
+#pragma unroll
+        for (int k4 = 0; k4 < 4; k4++) {
+            const int s = qb * 16 + lr;
+            qf[k4] = s < K ? qh[(int64_t)(s - s0) * 64 + 4 * k4 + lk] : 0.0;
+        }
+        f64x4 st[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++) {
+            st[kb] = f64x4{0.0, 0.0, 0.0, 0.0};
+            if (kb <= qb)
+#pragma unroll
+                for (int k4 = 0; k4 < 4; k4++)
+                    st[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(qf[k4], kf[kb][k4], st[kb], 0, 0, 0);
+        }
+        double mx[4], den[4];
+#pragma unroll
+        for (int ii = 0; ii < 4; ii++) {
+            mx[ii] = -INFINITY;
+#pragma unroll
+            for (int kb = 0; kb <= qb; kb++)
+                if (kb < qb || lr <= lk + 4 * ii) mx[ii] = fmax(mx[ii], st[kb][ii]);
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) mx[ii] = fmax(mx[ii], __shfl_xor(mx[ii], off, 16));
+            den[ii] = 0.0;
+#pragma unroll
+            for (int kb = 0; kb < 4; kb++) {
+                const double p =
+                    (kb < qb || (kb == qb && lr <= lk + 4 * ii)) ? exp((st[kb][ii] - mx[ii]) * scale) : 0.0;
+                st[kb][ii] = p;
+                den[ii] += p;
+            }
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) den[ii] += __shfl_xor(den[ii], off, 16);
+        }
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++)
+#pragma unroll
+            for (int ii = 0; ii < 4; ii++) P[lk + 4 * ii][kb * 16 + lr] = st[kb][ii] / den[ii];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        f64x4 ot = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4 * (qb + 1); kk++)
+            ot = __builtin_amdgcn_mfma_f64_16x16x4f64(P[lr][4 * kk + lk], vf[kk], ot, 0, 0, 0);
+#pragma unroll
+        for (int ii = 0; ii < 4; ii++) {
+            const int s = qb * 16 + lk + 4 * ii;
+            if (s < K) o[(i * Rb + s - s0) * 64 + hh * 16 + lr] = ot[ii];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Output head of the listed rows (as k64_head): one wave per row; the
+// electrons placed before position s are counted from the key.
+__global__ void __launch_bounds__(256) k64r_head(ModelView M, const double *__restrict__ a,
+                                                 const uint64_t *__restrict__ ckeys, int64_t B, int sb,
+                                                 double *__restrict__ lp) {
+    const int K = M.K, Rb = K - 16 * sb;
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= B * Rb) return;  // wave-uniform
+    const int64_t i = row / Rb;
+    const int s = 16 * sb + (int)(row - i * Rb);
+    Key x;
+    x.lo = ckeys[2 * i];
+    x.hi = ckeys[2 * i + 1];
+    auto token = [&](int pos) {
+        const int o = K - 1 - pos;
+        return key_bit(x, 2 * o) + 2 * key_bit(x, 2 * o + 1);
+    };
+    const int tr = lane < s ? token(lane) : 0;
+    const int up = __popcll(__ballot(tr & 1)), dn = __popcll(__ballot(tr >> 1));
+    const double *W = M.w64;
+    const double av = a[row * 64 + lane];
+    double z[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        double vv = av * W[M.off.head_w + lane * 4 + t];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) vv += __shfl_xor(vv, off, 64);
+        z[t] = vv;
+    }
+    if (lane != 0) return;
+    const int rem = K - 1 - s, orb = K - 1 - s;
+    bool ok[4];
+    double mx = -INFINITY;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        z[t] += W[M.off.head_b + t] + W[M.off.bias + orb * 4 + t];
+        const int bu = t & 1, bd = t >> 1;
+        ok[t] = (up + bu <= M.n_up) && (dn + bd <= M.n_dn) && (M.n_up - up - bu <= rem) && (M.n_dn - dn - bd <= rem);
+        if (ok[t] && z[t] > mx) mx = z[t];
+    }
+    double den = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+        if (ok[t]) den += exp(z[t] - mx);
+    const int ts = token(s);
+    lp[row] = ok[ts] ? (z[ts] - mx) - log(den) : -INFINITY;
+}
+
+// Per listed connection: log|psi| = 1/2 (pre[sample][sb] + sum of its rows'
+// log pi), phase = b3 + z2 . w3, written to xla / xph at list[i] (one wave each).
+__global__ void __launch_bounds__(256) k64r_finish(ModelView M, const double *__restrict__ lp,
+                                                   const double *__restrict__ z2, const double *__restrict__ pre,
+                                                   const int32_t *__restrict__ list, int64_t C, int64_t B, int sb,
+                                                   double *__restrict__ xla, double *__restrict__ xph) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (i >= B) return;
+    const int Rb = M.K - 16 * sb;
+    double s = 0.0;
+    for (int t = lane; t < Rb; t += 64) s += lp[i * Rb + t];
+    double ph = 0.0;
+    for (int j = lane; j < M.P; j += 64) ph += z2[i * M.P + j] * M.w64[M.off.ph_w3 + j];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        ph += __shfl_xor(ph, off, 64);
+    }
+    if (lane == 0) {
+        const int64_t e = list[i];
+        xla[e] = 0.5 * (pre[4 * (e / C) + sb] + s);
+        xph[e] = M.w64[M.off.ph_b3] + ph;
+    }
+}
+
 static unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+int64_t f64_cache_doubles(const nnqs_model *m) { return (int64_t)m->desc.n_layers * 2 * m->desc.n_orb * 64; }
 
 bool f64_shape_ok(const nnqs_model_desc &m) { return m.d_model == 64 && m.n_heads == 4 && m.d_ff % 64 == 0; }
 
 nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64_t n, double *logabs,
-                               double *phase, hipStream_t st, int cpos, double *cond) {
+                               double *phase, hipStream_t st, int cpos, double *cond, double *kvc, double *pre) {
     nnqs_model *m = const_cast<nnqs_model *>(cm);  // owns its scratch (one call at a time per model)
     const ModelView M = model_view(m);
     const int K = M.K, d = M.d, F = M.F, P = M.P;
@@ -357,6 +582,9 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
                                kk, d);
             hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wv, d, Lw + LO.bv, R, d, d,
                                v, d);
+            if (kvc)
+                hipLaunchKernelGGL(k64_cache_kv, dim3(blocks_for(R * 64)), dim3(256), 0, st, kk, v, B, K, l, M.L,
+                                   kvc + b0 * M.L * 2 * K * 64);
             hipLaunchKernelGGL(k64_attention, dim3((unsigned)B), dim3(256), 0, st, q, kk, v, B, K, scale, a);
             hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wo, d, Lw + LO.bo, R, d, d,
                                h, d);
@@ -371,6 +599,7 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
                            W + M.off.lnf_b, R, a);
         hipLaunchKernelGGL(k64_head, dim3(blocks_for(R, 4)), dim3(256), 0, st, M, a, tok, B, lp, cpos,
                            cond ? cond + 4 * b0 : (double *)nullptr);
+        if (pre) hipLaunchKernelGGL(k64_prefix, dim3(blocks_for(B)), dim3(256), 0, st, lp, B, K, pre + 4 * b0);
         double *z1 = f, *z2 = f + (size_t)B * P;
         hipLaunchKernelGGL(k64_phase1, dim3(blocks_for(B * P)), dim3(256), 0, st, M, keys + 2 * b0, B, z1);
         hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((P + 63) / 64), (unsigned)((B + 63) / 64)), dim3(256), 0, st,
@@ -378,6 +607,85 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
         hipLaunchKernelGGL(k64_finish, dim3(blocks_for(B, 4)), dim3(256), 0, st, M, lp, z2, B, logabs + b0,
                            phase + b0);
         NNQS_HIP_CHECK(hipGetLastError());
+    }
+    return NNQS_OK;
+}
+
+// FP64 forward of listed connections with prefix reuse (see k64_cache_kv):
+// class q of hdr (count hdr[q], list offset hdr[4 + q], host copies) holds
+// connections whose first changed position lies in row block q; they are
+// evaluated from row 16 min(q, (K - 1) / 16) on (a later start than K - 1 has
+// no rows left, so the last block is recomputed).  kvc / pre: the cache of
+// the chunk's samples, indexed by list entry / C.  Results go to xla / xph.
+nnqs_status enqueue_f64_list(const nnqs_model *cm, const uint64_t *xkeys, int64_t C, const int32_t *list,
+                             const int64_t *hdr, const double *kvc, const double *pre, double *xla, double *xph,
+                             hipStream_t st) {
+    nnqs_model *m = const_cast<nnqs_model *>(cm);
+    const ModelView M = model_view(m);
+    const int K = M.K, d = M.d, F = M.F, P = M.P;
+    int64_t nmax = 0;
+    for (int q = 0; q < 4; q++) nmax = hdr[q] > nmax ? hdr[q] : nmax;
+    if (nmax == 0) return NNQS_OK;
+    const int64_t Bmax = nmax < kF64Batch ? nmax : kF64Batch;
+    const int64_t Rmax = Bmax * K;
+    // h, a, q, k, v [rows][64]; f [rows][F]; z1, z2 [B][P]; lp [rows]; ckeys [B][2]
+    const size_t need = ((size_t)Rmax * (5 * d + F + 1) + (size_t)Bmax * (2 * P + 2)) * 8 + 256;
+    if (m->f64cap < need) {
+        NNQS_HIP_CHECK(hipStreamSynchronize(st));
+        hipFree(m->d_f64s);
+        m->d_f64s = nullptr;
+        m->f64cap = 0;
+        if (hipMalloc(&m->d_f64s, need) != hipSuccess) return fail(NNQS_ENOMEM, "FP64 forward scratch (%zu bytes)", need);
+        m->f64cap = need;
+    }
+    double *h = reinterpret_cast<double *>(m->d_f64s);
+    double *a = h + Rmax * d, *qb = a + Rmax * d, *kk = qb + Rmax * d, *v = kk + Rmax * d;
+    double *f = v + Rmax * d, *z1 = f + Rmax * F, *z2 = z1 + Bmax * P, *lp = z2 + Bmax * P;
+    uint64_t *ckeys = reinterpret_cast<uint64_t *>(lp + Rmax);
+    const LayerOffsets LO = layer_offsets(d, F);
+    const double *W = m->d_w64;
+    const double scale = 1.0 / sqrt((double)(d / M.H));
+    for (int q = 0; q < 4; q++) {
+        const int sb = q < (K - 1) / 16 ? q : (K - 1) / 16;
+        const int Rb = K - 16 * sb;
+        const int32_t *lq = list + hdr[4 + q];
+        for (int64_t b0 = 0; b0 < hdr[q]; b0 += kF64Batch) {
+            const int64_t B = hdr[q] - b0 < kF64Batch ? hdr[q] - b0 : kF64Batch;
+            const int64_t R = B * Rb;
+            const unsigned gy = (unsigned)((R + 63) / 64);
+            hipLaunchKernelGGL(k64r_embed, dim3(blocks_for(R * d)), dim3(256), 0, st, M, xkeys, lq + b0, B, sb, h,
+                               ckeys);
+            for (int l = 0; l < M.L; l++) {
+                const double *Lw = W + M.off.layer0 + (int64_t)l * M.off.layer_stride;
+                hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln1_g,
+                                   Lw + LO.ln1_b, R, a);
+                hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wq, d, Lw + LO.bq, R, d,
+                                   d, qb, d);
+                hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wk, d, Lw + LO.bk, R, d,
+                                   d, kk, d);
+                hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wv, d, Lw + LO.bv, R, d,
+                                   d, v, d);
+                hipLaunchKernelGGL(k64r_attention, dim3((unsigned)B), dim3(256), 0, st, qb, kk, v, kvc, lq + b0, C, B,
+                                   K, M.L, l, sb, scale, a);
+                hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wo, d, Lw + LO.bo, R, d,
+                                   d, h, d);
+                hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,
+                                   Lw + LO.ln2_b, R, a);
+                hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, d,
+                                   Lw + LO.w1, F, Lw + LO.b1, R, F, d, f, F);
+                hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, f, F, Lw + LO.w2, d, Lw + LO.b2, R, d,
+                                   F, h, d);
+            }
+            hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, W + M.off.lnf_g,
+                               W + M.off.lnf_b, R, a);
+            hipLaunchKernelGGL(k64r_head, dim3(blocks_for(R, 4)), dim3(256), 0, st, M, a, ckeys, B, sb, lp);
+            hipLaunchKernelGGL(k64_phase1, dim3(blocks_for(B * P)), dim3(256), 0, st, M, ckeys, B, z1);
+            hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((P + 63) / 64), (unsigned)((B + 63) / 64)), dim3(256), 0,
+                               st, z1, P, W + M.off.ph_w2, P, W + M.off.ph_b2, B, P, P, z2, P);
+            hipLaunchKernelGGL(k64r_finish, dim3(blocks_for(B, 4)), dim3(256), 0, st, M, lp, z2, pre, lq + b0, C, B,
+                               sb, xla, xph);
+            NNQS_HIP_CHECK(hipGetLastError());
+        }
     }
     return NNQS_OK;
 }

@@ -118,13 +118,21 @@ def test_logpsi_bf16_error_vs_oracle(nn, kw):
     assert np.all(dph <= 0.02)
 
 
-def test_eloc_model_refined_bf16_equals_fp64_when_all_terms_refined(nn):
+@pytest.mark.parametrize("cfg,kw", [(1, dict(K=6, n_up=2, n_dn=3, model=True)),
+                                    (2, dict(K=40, n_up=3, n_dn=3, n_unique=3, model=True)),
+                                    (2, dict(K=48, n_up=3, n_dn=2, n_unique=2, model=True)),
+                                    (2, dict(K=64, n_up=4, n_dn=4, n_unique=2, model=True)),
+                                    (3, dict(n_unique=2))])
+def test_eloc_model_refined_bf16_equals_fp64_when_all_terms_refined(nn, cfg, kw):
     """Precision ladder: with a refinement threshold far below every term
     (exp(-60) Ha), the BF16 pass only decides what to refine, every term and
     the samples' own amplitudes come from the FP64 network, and the result is
-    the FP64 path's."""
-    d = synth.config_inputs(1, K=6, n_up=2, n_dn=3, model=True)
-    _print_case("eloc_model_refine_all")
+    the FP64 path's.  The refinement evaluates each x' from the row block of
+    its first changed position on, with the sample's FP64 keys and values
+    below it: K = 40, 48, 60 and 64 cover every start block, the diagonal's
+    start past the last row (K = 48) and a ragged last block (K = 40, 60)."""
+    d = synth.config_inputs(cfg, **kw)
+    _print_case("eloc_model_refine_all", K=d["K"])
     S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
     M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
     keys, cnt = dev(d["keys"]), dev(d["counts"], torch.int32)
