@@ -321,6 +321,13 @@ __device__ __forceinline__ float sgelu(const float2 *tab, float v) {
     return v * fmaf(__builtin_amdgcn_fractf(u), e.y, e.x);
 }
 
+// Lane 0's value of a 64-bit word, for every lane.
+__device__ __forceinline__ uint64_t lane0_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 0);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 0);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) {  // OCP E4M3, saturated
     a = __builtin_amdgcn_fmed3f(a, -448.f, 448.f);
     b = __builtin_amdgcn_fmed3f(b, -448.f, 448.f);
@@ -332,198 +339,191 @@ __device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) { 
     return (uint32_t)v;
 }
 
-// Inference: each wave takes one contiguous run of connections, 32 at a
+// Inference: each wave takes one contiguous run of connections, 16 at a
 // time.  The connections of one sample x are contiguous and x' differs from
 // x only in the excitation's bits, so the first layer is
 //   b1 + sum_{p in x} W1[p]   (per run sample, kept in LDS)
 //   + sum_t C_t[e_t],  C_t = W1[one-hot block t + 1] + s_t W1[bit block],
 // s_t = -1 for the annihilated i, j and +1 for the created a, b: four
-// precombined rows per connection.  GELU outputs go to LDS as BF16 (or FP8
-// E4M3); the hidden layer runs on v_mfma_f32_16x16x32_bf16 (or _fp8_fp8 with
-// a per-tensor power-of-two scale of W2), each B fragment read from L2 once
-// for 32 connections; the output dot product by DPP row sums.
+// precombined rows per connection.  Lane l computes, for connection l & 15 of
+// a group of 16, the units 32 ks + 8 (l >> 4) + j (ks < 8, j < 8): exactly the
+// A operand of the hidden layer's v_mfma_f32_16x16x32_bf16 (or _fp8_fp8), so
+// the GELU outputs stay in registers.  W2 (transposed, BF16 or FP8 with a
+// per-tensor power-of-two scale) is loaded into LDS once per block and every
+// B fragment is read from there; the output dot product by DPP row sums.
+constexpr int kScreenWaves = 12;  // waves per block (one block per CU, three waves per SIMD)
+
 template <bool kFp8>
-__global__ void __launch_bounds__(256) k_screen_infer(int N, const float *__restrict__ w32,
-                                                      const float *__restrict__ cw1, const __bf16 *__restrict__ w2t,
-                                                      const uint8_t *__restrict__ w2f8,
-                                                      const float *__restrict__ w2inv,
-                                                      const float *__restrict__ gelu_tab,
-                                                      const uint64_t *__restrict__ keys,
-                                                      const uint8_t *__restrict__ exc, int64_t n,
-                                                      float *__restrict__ pred) {
+__global__ void __launch_bounds__(64 * kScreenWaves) k_screen_infer(int N, const float *__restrict__ w32,
+                                                                    const float *__restrict__ cw1,
+                                                                    const __bf16 *__restrict__ w2t,
+                                                                    const uint8_t *__restrict__ w2f8,
+                                                                    const float *__restrict__ w2inv,
+                                                                    const float *__restrict__ gelu_tab,
+                                                                    const uint64_t *__restrict__ keys,
+                                                                    const uint8_t *__restrict__ exc, int64_t n,
+                                                                    float *__restrict__ pred) {
     constexpr int H = kScreenH;
-    constexpr int ZLD = kFp8 ? H + 16 : H + 8;  // row length (elements) of the activation tile
-    typedef typename std::conditional<kFp8, uint8_t, __bf16>::type ZT;
-    __shared__ __align__(16) ZT zs[4][32 * ZLD];
-    __shared__ __align__(16) float basev[4][H];  // per wave: b1 + W1 rows of the run's sample
+    constexpr int WLD = kFp8 ? H + 16 : H + 8;  // LDS row length (elements) of W2^T, 16 bytes of padding
+    typedef typename std::conditional<kFp8, uint8_t, __bf16>::type WT;
+    typedef typename std::conditional<kFp8, long, bf16x8>::type AF;  // one A / B fragment per lane
+    __shared__ __align__(16) WT w2s[H * WLD];
+    __shared__ __align__(16) float basev[kScreenWaves][H];  // per wave: b1 + W1 rows of the run's sample
     __shared__ __align__(16) float2 gtab[kSGeluN];
     const int l = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int c16 = l & 15, r0 = 4 * (l >> 4), kq = 8 * (l >> 4);
+    const int c16 = l & 15, q = l >> 4, r0 = 4 * q, kq = 8 * q;
     for (int i = threadIdx.x; i < kSGeluN; i += blockDim.x) gtab[i] = make_float2(gelu_tab[2 * i], gelu_tab[2 * i + 1]);
+    {  // W2^T rows (output unit, k) into LDS, 16 bytes per load
+        constexpr int per_row = H * (int)sizeof(WT) / 16;
+        const uint8_t *src = kFp8 ? w2f8 : reinterpret_cast<const uint8_t *>(w2t);
+        for (int i = threadIdx.x; i < H * per_row; i += blockDim.x) {
+            const int r = i / per_row, c = i - r * per_row;
+            *reinterpret_cast<uint4 *>(reinterpret_cast<uint8_t *>(w2s + r * WLD) + 16 * c) =
+                *reinterpret_cast<const uint4 *>(src + (int64_t)r * H * sizeof(WT) + 16 * c);
+        }
+    }
     __syncthreads();
-    ZT *Z = zs[w];
     float *bv = basev[w];
     const ScreenOff o = screen_off(N, H);
     const float inv2 = kFp8 ? w2inv[0] : 1.0f;
-    const int64_t nwaves = (int64_t)gridDim.x * 4, wid = (int64_t)blockIdx.x * 4 + w;
-    const int64_t per = (((n + nwaves - 1) / nwaves) + 31) & ~(int64_t)31;
+    const int64_t nwaves = (int64_t)gridDim.x * kScreenWaves, wid = (int64_t)blockIdx.x * kScreenWaves + w;
+    const int64_t per = (((n + nwaves - 1) / nwaves) + 15) & ~(int64_t)15;
     const int64_t beg = wid * per, end = beg + per < n ? beg + per : n;
     Key ref;
     ref.lo = ref.hi = 0ull;
     bool have_ref = false;
-    const int c0 = (l >> 4) * 64;  // this lane's 64 first-layer units
-    for (int64_t base = beg; base < end; base += 32) {
+    // this lane's units: 32 ks + kq + j
+    auto add_row = [&](float(&acc)[8][8], const float *row) {
 #pragma unroll
-        for (int hf = 0; hf < 2; hf++) {
-            // layer 1: lane (row = 16 hf + c16, quarter l >> 4) computes 64 of the 256 units of its row
-            const int64_t k = base + 16 * hf + c16;
-            const bool ok = k < end;
-            Key x;
-            x.lo = ok ? keys[2 * k] : 0ull;
-            x.hi = ok ? keys[2 * k + 1] : 0ull;
-            uint8_t e4[4] = {255, 255, 255, 255};
-            if (ok)
-                for (int t = 0; t < 4; t++) e4[t] = exc[4 * k + t];
-            // flipped bits (codes below N) and the sample x0 = x' ^ flips
-            Key fm;
-            fm.lo = fm.hi = 0ull;
+        for (int ks = 0; ks < 8; ks++) {
+            const float4 lo = *reinterpret_cast<const float4 *>(row + 32 * ks + kq);
+            const float4 hi = *reinterpret_cast<const float4 *>(row + 32 * ks + kq + 4);
+            acc[ks][0] += lo.x;
+            acc[ks][1] += lo.y;
+            acc[ks][2] += lo.z;
+            acc[ks][3] += lo.w;
+            acc[ks][4] += hi.x;
+            acc[ks][5] += hi.y;
+            acc[ks][6] += hi.z;
+            acc[ks][7] += hi.w;
+        }
+    };
+    for (int64_t base = beg; base < end; base += 16) {
+        // layer 1 for connection k = base + c16
+        const int64_t k = base + c16;
+        const bool ok = k < end;
+        Key x;
+        x.lo = ok ? keys[2 * k] : 0ull;
+        x.hi = ok ? keys[2 * k + 1] : 0ull;
+        uint8_t e4[4] = {255, 255, 255, 255};
+        if (ok)
+            for (int t = 0; t < 4; t++) e4[t] = exc[4 * k + t];
+        // flipped bits (codes below N) and the sample x0 = x' ^ flips
+        Key fm;
+        fm.lo = fm.hi = 0ull;
+        for (int t = 0; t < 4; t++)
+            if (e4[t] < N) key_flip(fm, e4[t]);
+        Key x0;
+        x0.lo = x.lo ^ fm.lo;
+        x0.hi = x.hi ^ fm.hi;
+        // the run's reference sample is that of the group's first row (lane 0)
+        // (the readlane builtin moves 32 bits: each word goes in two halves)
+        const uint64_t rlo = lane0_u64(x0.lo), rhi = lane0_u64(x0.hi);
+        if (!have_ref || rlo != ref.lo || rhi != ref.hi) {
+            ref.lo = rlo;
+            ref.hi = rhi;
+            have_ref = true;
+            float s4[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) s4[u] = w32[o.b1 + 4 * l + u];
+            for (int wd = 0; wd < 2; wd++) {
+                uint64_t m = wd ? ref.hi : ref.lo;
+                while (m) {
+                    const int bt = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    const int p = wd * 64 + bt;
+                    if (p >= N) break;  // bits above the spin orbitals carry no input
+                    const float *row = w32 + o.W1 + (int64_t)p * H + 4 * l;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) s4[u] += row[u];
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();  // earlier readers of bv are done
+#pragma unroll
+            for (int u = 0; u < 4; u++) bv[4 * l + u] = s4[u];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        float acc[8][8];
+        if (x0.lo == ref.lo && x0.hi == ref.hi) {
+#pragma unroll
+            for (int ks = 0; ks < 8; ks++)
+#pragma unroll
+                for (int j = 0; j < 8; j++) acc[ks][j] = bv[32 * ks + kq + j];
+#pragma unroll 1
             for (int t = 0; t < 4; t++)
-                if (e4[t] < N) key_flip(fm, e4[t]);
-            Key x0;
-            x0.lo = x.lo ^ fm.lo;
-            x0.hi = x.hi ^ fm.hi;
-            // the run's reference sample is that of the group's first row (lane 0)
-            const uint64_t rlo = __builtin_amdgcn_readlane((unsigned long long)x0.lo, 0);
-            const uint64_t rhi = __builtin_amdgcn_readlane((unsigned long long)x0.hi, 0);
-            if (!have_ref || rlo != ref.lo || rhi != ref.hi) {
-                ref.lo = rlo;
-                ref.hi = rhi;
-                have_ref = true;
-                float s4[4];
+                if (e4[t] < N) add_row(acc, cw1 + ((int64_t)t * N + e4[t]) * H);
+        } else {  // another sample inside the group: the plain sum over the bits of x' and the one-hots
 #pragma unroll
-                for (int u = 0; u < 4; u++) s4[u] = w32[o.b1 + 4 * l + u];
-                for (int wd = 0; wd < 2; wd++) {
-                    uint64_t m = wd ? ref.hi : ref.lo;
-                    while (m) {
-                        const int bt = __ffsll((unsigned long long)m) - 1;
-                        m &= m - 1;
-                        const int p = wd * 64 + bt;
-                        if (p >= N) break;  // bits above the spin orbitals carry no input
-                        const float *row = w32 + o.W1 + (int64_t)p * H + 4 * l;
+            for (int ks = 0; ks < 8; ks++)
 #pragma unroll
-                        for (int u = 0; u < 4; u++) s4[u] += row[u];
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();  // earlier readers of bv are done
-#pragma unroll
-                for (int u = 0; u < 4; u++) bv[4 * l + u] = s4[u];
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-            float acc[64];
-            if (x0.lo == ref.lo && x0.hi == ref.hi) {
-#pragma unroll
-                for (int c = 0; c < 64; c++) acc[c] = bv[c0 + c];
-                for (int t = 0; t < 4; t++) {
-                    if (e4[t] >= N) continue;  // absent
-                    const float *row = cw1 + ((int64_t)t * N + e4[t]) * H + c0;
-#pragma unroll
-                    for (int c = 0; c < 64; c += 4) {
-                        const float4 r4 = *reinterpret_cast<const float4 *>(row + c);
-                        acc[c] += r4.x;
-                        acc[c + 1] += r4.y;
-                        acc[c + 2] += r4.z;
-                        acc[c + 3] += r4.w;
-                    }
-                }
-            } else {  // another sample inside the group: the plain sum over the bits of x' and the one-hots
-#pragma unroll
-                for (int c = 0; c < 64; c++) acc[c] = w32[o.b1 + c0 + c];
-                for (int wd = 0; wd < 2; wd++) {
-                    uint64_t m = wd ? x.hi : x.lo;
-                    while (m) {
-                        const int bt = __ffsll((unsigned long long)m) - 1;
-                        m &= m - 1;
-                        const int p = wd * 64 + bt;
-                        if (p >= N) break;
-                        const float *row = w32 + o.W1 + (int64_t)p * H + c0;
-#pragma unroll
-                        for (int c = 0; c < 64; c++) acc[c] += row[c];
-                    }
-                }
-                for (int t = 0; t < 4; t++) {
-                    if (e4[t] >= N) continue;
-                    const float *row = w32 + o.W1 + (int64_t)((t + 1) * N + e4[t]) * H + c0;
-#pragma unroll
-                    for (int c = 0; c < 64; c++) acc[c] += row[c];
+                for (int j = 0; j < 8; j++) acc[ks][j] = w32[o.b1 + 32 * ks + kq + j];
+            for (int wd = 0; wd < 2; wd++) {
+                uint64_t m = wd ? x.hi : x.lo;
+                while (m) {
+                    const int bt = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    const int p = wd * 64 + bt;
+                    if (p >= N) break;
+                    add_row(acc, w32 + o.W1 + (int64_t)p * H);
                 }
             }
-            ZT *zr = Z + (16 * hf + c16) * ZLD + c0;
+#pragma unroll 1
+            for (int t = 0; t < 4; t++)
+                if (e4[t] < N) add_row(acc, w32 + o.W1 + (int64_t)((t + 1) * N + e4[t]) * H);
+        }
+        AF af[8];
+#pragma unroll
+        for (int ks = 0; ks < 8; ks++) {
             if constexpr (kFp8) {
-#pragma unroll
-                for (int c = 0; c < 64; c += 4)
-                    *reinterpret_cast<uint32_t *>(zr + c) = fp8x4(sgelu(gtab, acc[c]), sgelu(gtab, acc[c + 1]),
-                                                                  sgelu(gtab, acc[c + 2]), sgelu(gtab, acc[c + 3]));
+                const uint32_t lo = fp8x4(sgelu(gtab, acc[ks][0]), sgelu(gtab, acc[ks][1]), sgelu(gtab, acc[ks][2]),
+                                          sgelu(gtab, acc[ks][3]));
+                const uint32_t hi = fp8x4(sgelu(gtab, acc[ks][4]), sgelu(gtab, acc[ks][5]), sgelu(gtab, acc[ks][6]),
+                                          sgelu(gtab, acc[ks][7]));
+                af[ks] = (long)(((uint64_t)hi << 32) | lo);
             } else {
 #pragma unroll
-                for (int c = 0; c < 64; c += 4) {
-                    bf16x4 z4;
-#pragma unroll
-                    for (int u = 0; u < 4; u++) z4[u] = (__bf16)sgelu(gtab, acc[c + u]);
-                    *reinterpret_cast<bf16x4 *>(zr + c) = z4;
-                }
+                for (int j = 0; j < 8; j++) af[ks][j] = (__bf16)sgelu(gtab, acc[ks][j]);
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // layer 2 + output, both row blocks per B fragment
-        float part[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        // layer 2 + output
+        float part[4] = {0.f, 0.f, 0.f, 0.f};
         for (int nb = 0; nb < H / 16; nb++) {
-            f32x4 a2[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+            f32x4 a2 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int ks = 0; ks < H; ks += 32) {
-                if constexpr (kFp8) {
-                    const long b = *reinterpret_cast<const long *>(w2f8 + (int64_t)(nb * 16 + c16) * H + ks + kq);
-#pragma unroll
-                    for (int hf = 0; hf < 2; hf++) {
-                        const long a = *reinterpret_cast<const long *>(Z + (16 * hf + c16) * ZLD + ks + kq);
-                        a2[hf] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, a2[hf], 0, 0, 0);
-                    }
-                } else {
-                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(w2t + (int64_t)(nb * 16 + c16) * H + ks + kq);
-#pragma unroll
-                    for (int hf = 0; hf < 2; hf++) {
-                        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(Z + (16 * hf + c16) * ZLD + ks + kq);
-                        a2[hf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, a2[hf], 0, 0, 0);
-                    }
-                }
+            for (int ks = 0; ks < 8; ks++) {
+                const AF b = *reinterpret_cast<const AF *>(w2s + (nb * 16 + c16) * WLD + 32 * ks + kq);
+                if constexpr (kFp8)
+                    a2 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[ks], b, a2, 0, 0, 0);
+                else
+                    a2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks], b, a2, 0, 0, 0);
             }
             const float bb = w32[o.b2 + nb * 16 + c16], ww = w32[o.w3 + nb * 16 + c16];
 #pragma unroll
-            for (int hf = 0; hf < 2; hf++)
-#pragma unroll
-                for (int i = 0; i < 4; i++) part[hf][i] = fmaf(sgelu(gtab, fmaf(a2[hf][i], inv2, bb)), ww, part[hf][i]);
+            for (int i = 0; i < 4; i++) part[i] = fmaf(sgelu(gtab, fmaf(a2[i], inv2, bb)), ww, part[i]);
         }
 #pragma unroll
-        for (int hf = 0; hf < 2; hf++)
-#pragma unroll
-            for (int i = 0; i < 4; i++) part[hf][i] = dpp_sum16(part[hf][i]);
+        for (int i = 0; i < 4; i++) part[i] = dpp_sum16(part[i]);
         if (c16 == 0) {
 #pragma unroll
-            for (int hf = 0; hf < 2; hf++)
-#pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    const int64_t kk = base + 16 * hf + r0 + i;
-                    if (kk < end) pred[kk] = part[hf][i] + w32[o.b3];
-                }
+            for (int i = 0; i < 4; i++) {
+                const int64_t kk = base + r0 + i;
+                if (kk < end) pred[kk] = part[i] + w32[o.b3];
+            }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -606,15 +606,21 @@ nnqs_status screen_infer(nnqs_screen *s, const uint64_t *keys, const uint8_t *ex
     if (s->H != kScreenH) return fail(NNQS_EUNSUPPORTED, "BF16 / FP8 screen inference needs hidden = 256");
     nnqs_status r = screen_refresh(s, st);
     if (r != NNQS_OK) return r;
-    int64_t blocks = (n + 127) / 128;
-    if (blocks > 4096) blocks = 4096;
+    // one block of kScreenWaves waves per CU (W2 fills most of its LDS), each
+    // wave a contiguous run of connections
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    int64_t blocks = (n + 32 * kScreenWaves - 1) / (32 * kScreenWaves);
+    if (blocks > cus) blocks = cus;
     TimedRegion tr("k_screen_infer", st);
     if (fp8)
-        hipLaunchKernelGGL(k_screen_infer<true>, dim3((unsigned)blocks), dim3(256), 0, st, s->N, s->w32, s->cw1,
-                           s->w2t, s->w2f8, (const float *)s->w2scale + 1, s->gelu_tab, keys, exc, n, pred);
+        hipLaunchKernelGGL(k_screen_infer<true>, dim3((unsigned)blocks), dim3(64 * kScreenWaves), 0, st, s->N, s->w32,
+                           s->cw1, s->w2t, s->w2f8, (const float *)s->w2scale + 1, s->gelu_tab, keys, exc, n, pred);
     else
-        hipLaunchKernelGGL(k_screen_infer<false>, dim3((unsigned)blocks), dim3(256), 0, st, s->N, s->w32, s->cw1,
-                           s->w2t, s->w2f8, (const float *)s->w2scale + 1, s->gelu_tab, keys, exc, n, pred);
+        hipLaunchKernelGGL(k_screen_infer<false>, dim3((unsigned)blocks), dim3(64 * kScreenWaves), 0, st, s->N,
+                           s->w32, s->cw1, s->w2t, s->w2f8, (const float *)s->w2scale + 1, s->gelu_tab, keys, exc, n,
+                           pred);
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
 }

@@ -120,17 +120,21 @@ def test_bf16_inference_error_vs_oracle(nn, n):
     assert np.all(err <= 0.05 + 0.01 * np.abs(ref))
 
 
-def test_bf16_inference_on_contiguous_runs(nn):
+@pytest.mark.parametrize("K,nu,nd,cfg", [(24, 6, 6, 2), (60, 20, 20, 3)])
+def test_bf16_inference_on_contiguous_runs(nn, K, nu, nd, cfg):
     """Connections in runs of one sample (the layout of the full local
     energy), with run boundaries off the 16-row groups and a sample that
     comes back after another: the first layer is then assembled from the
     sample's sum plus signed flip rows.  The result stays within the BF16
     bound against the FP64 oracle and agrees with the same rows in shuffled
-    order (every row assembled from its own bits) to FP32 rounding."""
-    K, H = 24, 256
+    order (every row assembled from its own bits) to FP32 rounding.  At
+    N = 120 the samples' keys fill both 64-bit words (the run's sample is
+    compared word by word across the wave)."""
+    H = 256
     N = 2 * K
     _print_case("screen_bf16_runs", N=N, H=H)
-    d = synth.config_inputs(2, K=K, n_up=6, n_dn=6, n_unique=8)
+    d = (synth.config_inputs(2, K=K, n_up=nu, n_dn=nd, n_unique=8) if cfg == 2
+         else synth.config_inputs(3, n_unique=8))
     runs = []
     for k, (a, b) in ((0, (5, 700)), (1, (0, 333)), (2, (17, 420)), (1, (333, 900))):
         xp, _, exc, _ = oracle.connections(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], 0.0, d["keys"][k])
