@@ -438,8 +438,9 @@ struct KvSrc {
 // Causal attention of query block QB (a slot of configuration c) for one
 // head: S^T[key][query] = K Q^T (the lane owns query c16 + 16 QB and keys
 // 16 kb + r0 + i), softmax over keys in base 2 (scale and log2(e) are folded
-// into Q), P[query][key] -> Pb, then O^T[c][query] = V^T P^T into
-// Oq[query][16 hh + c].
+// into Q): unnormalised P[query][key] -> Pb, then O^T[c][query] = V^T P^T
+// divided by the row sums 1^T P^T (the same MFMA with an all-ones operand)
+// into Oq[query][16 hh + c].
 template <int QB, bool kF8>
 __device__ __forceinline__ void attend_block(const __bf16 *Qq, const KvSrc &S, __bf16 *Pb, typename Op<kF8>::T *Oq,
                                              int hh) {
@@ -470,27 +471,22 @@ __device__ __forceinline__ void attend_block(const __bf16 *Qq, const KvSrc &S, _
             if (kb < QB || r0 + i <= c16) mx = fmaxf(mx, st[kb][i]);
     mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
     mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-    float sum = 0.f;
-#pragma unroll
-    for (int kb = 0; kb < 4; kb++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const float p = (kb < QB || (kb == QB && r0 + i <= c16)) ? __builtin_amdgcn_exp2f(st[kb][i] - mx) : 0.f;
-            st[kb][i] = p;
-            sum += p;
-        }
-    sum += __shfl_xor(sum, 16, 64);
-    sum += __shfl_xor(sum, 32, 64);
-    const float inv = 1.0f / sum;
+    // unnormalised weights p = 2^(s - max) in BF16; the denominator of each
+    // query is the sum of the same BF16 values, taken by one more MFMA with an
+    // all-ones operand, and divides the output (four values per lane)
 #pragma unroll
     for (int kb = 0; kb < 4; kb++) {
         bf16x4 pk;
 #pragma unroll
-        for (int i = 0; i < 4; i++) pk[i] = (__bf16)(st[kb][i] * inv);
+        for (int i = 0; i < 4; i++)
+            pk[i] = (__bf16)((kb < QB || (kb == QB && r0 + i <= c16)) ? __builtin_amdgcn_exp2f(st[kb][i] - mx) : 0.f);
         *reinterpret_cast<bf16x4 *>(Pb + c16 * kLd + kb * 16 + r0) = pk;
     }
     wave_lds_sync();
-    f32x4 ot = {0.f, 0.f, 0.f, 0.f};
+    bf16x8 ones;
+#pragma unroll
+    for (int e = 0; e < 8; e++) ones[e] = (__bf16)1.0f;
+    f32x4 ot = {0.f, 0.f, 0.f, 0.f}, den = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 64; ks += 32) {
         if (ks <= QB * 16 + 15) {
@@ -500,8 +496,10 @@ __device__ __forceinline__ void attend_block(const __bf16 *Qq, const KvSrc &S, _
             else av = *reinterpret_cast<const bf16x8 *>(S.vt + slot_of(S.cls, S.c, kb) * (kDh * kVLd) + c16 * kVLd + (kq & 15));
             const bf16x8 bp = lds_frag(Pb, c16, kLd, ks + kq);
             ot = mfma16(av, bp, ot);
+            den = mfma16(ones, bp, den);
         }
     }
+    ot *= __builtin_amdgcn_rcpf(den[0]);
     if constexpr (kF8)
         *reinterpret_cast<uint32_t *>(Oq + c16 * Op<true>::ld + hh * kDh + r0) = fp8x4(ot);
     else
