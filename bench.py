@@ -41,6 +41,16 @@ ALU_PEAK_GOPS = 256 * 64 * 2.4   # 256 CUs x 64 lanes x 2.4 GHz, 32-bit integer 
 # filter word address shift and AND; third bit position shift and add; three
 # bit extracts, their two ANDs and the candidate test).
 SA_OPS_PER_CONNECTION = 11
+# Counters of the sample-aware kernel (autotuned schedule, 16 waves per block)
+# on this workload: VALU wave instructions per connection (SQ_INSTS_VALU /
+# connections) and FETCH_SIZE / WRITE_SIZE in KiB per launch with the
+# copy-calibrated scales.  Valid only for the kernel sources hashed below.
+SA_COUNTERS = {"sources_sha256_16": "4974635252aa2c66", "valu_per_connection": 0.5720,
+               "fetch_kib": 56042.6, "write_kib": 3997.3, "fetch_scale": 262144.0 / 131093.0,
+               "write_scale": 1.0}
+SA_SOURCES = ("paper_2306_16705_amd/csrc/eloc_sa.hip", "paper_2306_16705_amd/csrc/enumerate.hpp",
+              "paper_2306_16705_amd/csrc/internal.hpp")
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s: 4 SIMDs per CU, 4 cycles each
 
 # Operating point of the screened path: skip a connection when its predicted
 # contribution |H_xx' psi(x')/psi(x)| is below exp(-15) Ha, recompute in
@@ -464,12 +474,20 @@ def sample_aware_leg(args, nn, synth, np, torch):
                             d["phase"], d["keys"][:mm], d["logabs"][:mm], d["phase"][:mm], nthreads=cores())
     err = float(np.max(np.abs(g[:mm, 0] + 1j * g[:mm, 1] - ref)))
     ach = SA_OPS_PER_CONNECTION * n * C / (kms * 1e-3) / 1e9
+    sc = SA_COUNTERS if SA_COUNTERS["sources_sha256_16"] == sources_hash(SA_SOURCES) else None
+    counters = None
+    if sc is not None:
+        counters = {"valu_wave_instructions_per_connection": sc["valu_per_connection"],
+                    "valu_issue_frac": sc["valu_per_connection"] * n * C / (kms * 1e-3) / VALU_ISSUE_PEAK,
+                    "traffic": (sc["fetch_kib"] * sc["fetch_scale"] + sc["write_kib"] * sc["write_scale"]) * 1024.0,
+                    "traffic_unit": "bytes per launch", "sources_sha256_16": sc["sources_sha256_16"]}
     res = {"workload": "sample-aware E_loc, N=48 (K=24), 6 up + 6 down, 65,536 unique samples, FP64, table build + "
                        "E_loc + weighted energy per step", "samples_per_s": n / (ms * 1e-3),
            "connections_per_s": n * C / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": kms, "schedule": tune,
            "max_abs_err_vs_oracle_ha": err, "oracle_checked_samples": mm,
            "roofline": {"bound": "alu", "achieved": ach, "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
-                        "frac": ach / ALU_PEAK_GOPS, "ops_per_connection": SA_OPS_PER_CONNECTION}}
+                        "frac": ach / ALU_PEAK_GOPS, "ops_per_connection": SA_OPS_PER_CONNECTION,
+                        "counters": counters}}
     log(f"sample-aware: {ms:.3f} ms/step, {n / (ms * 1e-3):.4g} samples/s")
     if args.pauli:
         res["pauli"] = pauli_leg(nn, S, T, keys, cnt, la, ph, n, np, torch)
