@@ -14,9 +14,10 @@
 // softmax over keys is a register reduction plus two cross-lane steps;
 // O^T = V^T P^T.  LayerNorm, softmax, GELU and the output head stay FP32.
 //
-// Phase MLP: a second kernel runs 16 configurations per wave through
-// bits[16x128] @ W1 and GELU(z1)[16x512] @ W2 on the same MFMA, B tiles read
-// from the L2-resident BF16 weights.
+// Phase MLP: a second kernel runs bits[128 x 128] @ W1 and
+// GELU(z1)[128 x 512] @ W2 on the same MFMA for 128 configurations per block,
+// each wave owning 64 output columns (weight fragments from L2, read once per
+// block pass; z1 in LDS).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -33,7 +34,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kD = 64, kH = 4, kDh = 16, kF = 256, kP = 512, kRows = 64;
 constexpr int kLd = 72;        // padded LDS row length (BF16) of 64-wide tiles
 constexpr int kQLd = 24;       // padded row length of the per-head Q / K tiles
-constexpr int kWaves = 4;      // waves per block of the phase MLP
 constexpr int kPhaseBits = 128;
 
 // Device layout of the BF16 weights (element offsets into d_bf16).
@@ -874,7 +874,6 @@ __device__ __forceinline__ void transformer_bf16(const Bf16View &M0, const TfArg
     }
 }
 
-// Phase MLP: 16 configurations per wave, B tiles from global (L2) memory.
 __global__ void __launch_bounds__(512) k_transformer_bf16(Bf16View M, TfArgs A) {
     transformer_bf16<false, false, false>(M, A, nullptr, 0);
 }
@@ -898,76 +897,124 @@ __global__ void __launch_bounds__(512) k_transformer_bf16_batch(Bf16View M0, con
     transformer_bf16<true, false, true>(M0, items[0].A, items, n_items);
 }
 
+// Phase MLP (Section 4.1): phi = b3 + w3 . GELU(GELU(bits W1 + b1) W2 + b2)
+// on BF16 MFMA with FP32 accumulation.  A block of kPhWaves waves takes 128
+// configurations per pass; wave w owns output columns 64 w .. 64 w + 63 of
+// both layers, so each weight fragment is read once per 128 configurations
+// (held in registers across the eight groups of 16), the hidden layer z1
+// stays in LDS, and the four per-wave partial dot products of each
+// configuration are added in wave order at the end.
 // In list mode (see TfArgs) the configurations are xkeys[list[k]] for k
 // below the total of the four class counts, and phase[list[k]] receives them.
-__global__ void __launch_bounds__(256) k_phase_bf16(Bf16View M, TfArgs A, double *__restrict__ phase) {
-    __shared__ __align__(16) __bf16 zs[kWaves][16 * (kP + 8)];
+constexpr int kPhWaves = 8, kPhRows = 16 * kPhWaves, kZld = kP + 8;
+__global__ void __launch_bounds__(64 * kPhWaves) k_phase_bf16(Bf16View M, TfArgs A, double *__restrict__ phase) {
+    __shared__ __align__(16) __bf16 zs[kPhRows * kZld];
+    __shared__ float parts[kPhWaves][kPhRows];
     const int l = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c16 = l & 15, r0 = 4 * (l >> 4), kq = 8 * (l >> 4);
-    __bf16 *Z = zs[w];
-    const int zld = kP + 8;
+    const int col0 = 64 * w;  // this wave's output columns
     const __bf16 *w1T = M.wb + M.bl.ph_w1T, *w2T = M.wb + M.bl.ph_w2T;
     const float *b1 = M.wf + M.fl.ph_b1, *b2 = M.wf + M.fl.ph_b2, *w3 = M.wf + M.fl.ph_w3;
     const int nbits = 2 * M.K;
     const int64_t n = A.list_mode ? A.hdr[0] + A.hdr[1] + A.hdr[2] + A.hdr[3] : A.n;
-    for (int64_t base = ((int64_t)blockIdx.x * kWaves + w) * 16; base < n; base += (int64_t)gridDim.x * kWaves * 16) {
-        // A tiles of the bit matrix: row = configuration (c16), k = bit index
-        const int64_t cr = base + c16;
-        Key x{0ull, 0ull};
-        if (cr < n) {
-            const uint64_t *kp = A.list_mode ? A.xkeys + 2 * (int64_t)A.list[cr] : A.keys + 2 * cr;
-            x.lo = kp[0];
-            x.hi = kp[1];
-        }
-        bf16x8 abits[kPhaseBits / 32];
+    for (int64_t base = (int64_t)blockIdx.x * kPhRows; base < n; base += (int64_t)gridDim.x * kPhRows) {
+        // z1 = GELU(bits @ W1 + b1) for the block's 128 configurations, this wave's 64 columns;
+        // the layer-1 B fragments (W1^T rows col0 + 16 cb + c16) serve all eight groups
+        bf16x8 bw1[kPhaseBits / 32][4];
 #pragma unroll
         for (int ks = 0; ks < kPhaseBits / 32; ks++)
 #pragma unroll
-            for (int e = 0; e < 8; e++) {
-                const int p = ks * 32 + kq + e;
-                abits[ks][e] = (__bf16)((p < nbits && key_bit(x, p)) ? 1.0f : 0.0f);
+            for (int cb = 0; cb < 4; cb++)
+                bw1[ks][cb] =
+                    *reinterpret_cast<const bf16x8 *>(w1T + (int64_t)(col0 + cb * 16 + c16) * kPhaseBits + ks * 32 + kq);
+        for (int rg = 0; rg < kPhWaves; rg++) {
+            const int64_t cr = base + 16 * rg + c16;
+            Key x{0ull, 0ull};
+            if (cr < n) {
+                const uint64_t *kp = A.list_mode ? A.xkeys + 2 * (int64_t)A.list[cr] : A.keys + 2 * cr;
+                x.lo = kp[0];
+                x.hi = kp[1];
             }
-        // z1 = GELU(bits @ W1 + b1) -> Z (BF16)
-        for (int nb = 0; nb < kP / 16; nb++) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            f32x4 acc[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; cb++) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < kPhaseBits / 32; ks++) {
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(w1T + (int64_t)(nb * 16 + c16) * kPhaseBits + ks * 32 + kq);
-                acc = mfma16(abits[ks], b, acc);
-            }
-            const float bb = b1[nb * 16 + c16];
+                bf16x8 ab;
 #pragma unroll
-            for (int i = 0; i < 4; i++) Z[(r0 + i) * zld + nb * 16 + c16] = (__bf16)gelu32(acc[i] + bb);
+                for (int e = 0; e < 8; e++) {
+                    const int p = ks * 32 + kq + e;
+                    ab[e] = (__bf16)((p < nbits && key_bit(x, p)) ? 1.0f : 0.0f);
+                }
+#pragma unroll
+                for (int cb = 0; cb < 4; cb++) acc[cb] = mfma16(ab, bw1[ks][cb], acc[cb]);
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; cb++) {
+                const float bb = b1[col0 + cb * 16 + c16];
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    zs[(16 * rg + r0 + i) * kZld + col0 + cb * 16 + c16] = (__bf16)gelu32(acc[cb][i] + bb);
+            }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // phi = GELU(z1 @ W2 + b2) . w3 + b3
-        float part[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int nb = 0; nb < kP / 16; nb++) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        __syncthreads();  // z1 of every column written
+        // phi partials: w3 . GELU(z1 @ W2 + b2) over this wave's columns, in two
+        // halves of 32 columns (every W2 fragment is still read once per pass)
+        float part[kPhWaves][4];
+#pragma unroll
+        for (int rg = 0; rg < kPhWaves; rg++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) part[rg][i] = 0.f;
+#pragma unroll 1
+        for (int half = 0; half < 2; half++) {
+            f32x4 acc2[kPhWaves][2];
+#pragma unroll
+            for (int rg = 0; rg < kPhWaves; rg++)
+#pragma unroll
+                for (int cb = 0; cb < 2; cb++) acc2[rg][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
             for (int ks = 0; ks < kP; ks += 32) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(Z + c16 * zld + ks + kq);
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(w2T + (int64_t)(nb * 16 + c16) * kP + ks + kq);
-                acc = mfma16(a, b, acc);
-            }
-            const float bb = b2[nb * 16 + c16], ww = w3[nb * 16 + c16];
+                bf16x8 bw[2];
 #pragma unroll
-            for (int i = 0; i < 4; i++) part[i] += gelu32(acc[i] + bb) * ww;
+                for (int cb = 0; cb < 2; cb++)
+                    bw[cb] = *reinterpret_cast<const bf16x8 *>(w2T + (int64_t)(col0 + (2 * half + cb) * 16 + c16) * kP +
+                                                               ks + kq);
+#pragma unroll
+                for (int rg = 0; rg < kPhWaves; rg++) {
+                    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(zs + (16 * rg + c16) * kZld + ks + kq);
+#pragma unroll
+                    for (int cb = 0; cb < 2; cb++) acc2[rg][cb] = mfma16(a, bw[cb], acc2[rg][cb]);
+                }
+            }
+#pragma unroll
+            for (int cb = 0; cb < 2; cb++) {
+                const int col = col0 + (2 * half + cb) * 16 + c16;
+                const float bb = b2[col], ww = w3[col];
+#pragma unroll
+                for (int rg = 0; rg < kPhWaves; rg++)
+#pragma unroll
+                    for (int i = 0; i < 4; i++) part[rg][i] += gelu32(acc2[rg][cb][i] + bb) * ww;
+            }
         }
 #pragma unroll
-        for (int i = 0; i < 4; i++) part[i] = dpp_row_sum(part[i]);
-        if (c16 == 0) {
+        for (int rg = 0; rg < kPhWaves; rg++) {
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int64_t cfg = base + r0 + i;
-                if (cfg < n) phase[A.list_mode ? (int64_t)A.list[cfg] : cfg] = (double)(part[i] + M.wf[M.fl.ph_b3]);
+            for (int i = 0; i < 4; i++) part[rg][i] = dpp_row_sum(part[rg][i]);
+            if (c16 == 0)
+#pragma unroll
+                for (int i = 0; i < 4; i++) parts[w][16 * rg + r0 + i] = part[rg][i];
+        }
+        __syncthreads();  // every wave's partials written, z1 consumed
+        if ((int)threadIdx.x < kPhRows) {
+            const int64_t cfg = base + threadIdx.x;
+            if (cfg < n) {
+                float s = 0.f;
+                for (int q = 0; q < kPhWaves; q++) s += parts[q][threadIdx.x];
+                phase[A.list_mode ? (int64_t)A.list[cfg] : cfg] = (double)(s + M.wf[M.fl.ph_b3]);
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __syncthreads();  // parts read before the next pass rewrites them
     }
 }
 
@@ -1164,8 +1211,8 @@ static unsigned tf_grid(int64_t tiles) {
 }
 
 static unsigned phase_grid(int64_t n) {
-    const int64_t cap = (int64_t)cu_count() * 8;
-    const int64_t b = (n + kWaves * 16 - 1) / (kWaves * 16);
+    const int64_t cap = (int64_t)cu_count();  // one block per CU (z1 fills most of its LDS)
+    const int64_t b = (n + kPhRows - 1) / kPhRows;
     return (unsigned)(b < 1 ? 1 : b < cap ? b : cap);
 }
 
@@ -1186,7 +1233,7 @@ nnqs_status enqueue_logpsi_bf16(const nnqs_model *m, const uint64_t *keys, int64
     }
     {
         TimedRegion tr("k_phase_bf16", st);
-        hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(n)), dim3(kWaves * 64), 0, st, v, A, phase);
+        hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(n)), dim3(kPhWaves * 64), 0, st, v, A, phase);
     }
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
@@ -1252,7 +1299,7 @@ nnqs_status enqueue_bf16_list(const nnqs_model *m, const uint64_t *xkeys, int64_
     }
     {
         TimedRegion tr("k_phase_bf16", st);
-        hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(max_entries)), dim3(kWaves * 64), 0, st, v, A, xph);
+        hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(max_entries)), dim3(kPhWaves * 64), 0, st, v, A, xph);
     }
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
@@ -1285,7 +1332,7 @@ nnqs_status enqueue_bf16_phase_list(const nnqs_model *m, const uint64_t *xkeys, 
     A.xkeys = xkeys;
     A.list_mode = 1;
     TimedRegion tr("k_phase_bf16", st);
-    hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(max_entries)), dim3(kWaves * 64), 0, st, bf16_view(m), A, xph);
+    hipLaunchKernelGGL(k_phase_bf16, dim3(phase_grid(max_entries)), dim3(kPhWaves * 64), 0, st, bf16_view(m), A, xph);
     NNQS_HIP_CHECK(hipGetLastError());
     return NNQS_OK;
 }
