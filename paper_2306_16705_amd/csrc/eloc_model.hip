@@ -394,8 +394,11 @@ void eloc_model_free(nnqs_model *m) {
     hipFree(m->d_hdr);
     hipFree(m->d_kv64);
     hipFree(m->d_pre64);
+    hipFree(m->d_rag);
     m->d_kv64 = m->d_pre64 = nullptr;
+    m->d_rag = nullptr;
     m->kv64cap = 0;
+    m->ragcap = 0;
     m->d_kv = nullptr;
     m->d_pre = m->d_csla = nullptr;
     m->d_hdr = nullptr;
@@ -524,7 +527,9 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
         nnqs_status s1 =
             grow(reinterpret_cast<void **>(&model->d_kv64), (size_t)chunk * f64_cache_doubles(model) * sizeof(double));
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_pre64), (size_t)chunk * 4 * sizeof(double));
+        if (s1 == NNQS_OK)
+            s1 = grow(reinterpret_cast<void **>(&model->d_pre64),
+                      (size_t)chunk * (sys->view.K + 1) * sizeof(double));
         if (s1 != NNQS_OK) {
             eloc_model_free(model);
             return s1;
@@ -608,7 +613,8 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         }
         if (refine64) {
             // FP64 for every connection whose first-pass contribution is not
-            // negligible, by prefix class from the samples' FP64 cache
+            // negligible, each from its first changed position on, from the
+            // samples' FP64 cache
             ClsArgs ra{};
             ra.R = SelRule{nullptr, model->d_xla, model->d_loghx, model->d_sla + s0, C, o.refine_nats};
             ra.rule = true;
@@ -627,9 +633,10 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
             int64_t rh[8];
             NNQS_HIP_CHECK(hipMemcpyAsync(rh, d_rhdr, sizeof(rh), hipMemcpyDeviceToHost, st));
             NNQS_HIP_CHECK(hipStreamSynchronize(st));
-            refined += rh[0] + rh[1] + rh[2] + rh[3];
-            s1 = enqueue_f64_list(model, model->d_xkeys, C, model->d_sel, rh, model->d_kv64, model->d_pre64,
-                                  model->d_xla, model->d_xph, st);
+            const int64_t nref = rh[0] + rh[1] + rh[2] + rh[3];
+            refined += nref;
+            s1 = enqueue_f64_list(model, model->d_xkeys, C, model->d_sel, nref, keys + 2 * s0, model->d_kv64,
+                                  model->d_pre64, model->d_xla, model->d_xph, st);
             if (s1 != NNQS_OK) return s1;
         } else if (refine) {  // FP64 for every connection whose first-pass contribution is not negligible
             SelRule R{nullptr, model->d_xla, model->d_loghx, model->d_sla + s0, C, o.refine_nats};

@@ -90,6 +90,8 @@ struct nnqs_model {
     // values of every layer and their prefix log-probability sums
     double *d_kv64 = nullptr, *d_pre64 = nullptr;
     int64_t kv64cap = 0;
+    void *d_rag = nullptr;  // starts, row counts and row offsets of the refined connections
+    size_t ragcap = 0;
 };
 
 namespace nnqs {
@@ -133,12 +135,13 @@ bool f64_shape_ok(const nnqs_model_desc &m);
 nnqs_status enqueue_logpsi_f64(const nnqs_model *m, const uint64_t *keys, int64_t n, double *logabs, double *phase,
                                hipStream_t st, int cpos = -1, double *cond = nullptr, double *kvc = nullptr,
                                double *pre = nullptr);
-// FP64 prefix-reusing forward of class-listed connections (hdr on the host:
-// count[4], offset[4]) from a sample cache written by enqueue_logpsi_f64's kvc /
-// pre outputs (per sample [L][2][K][64] + [4] doubles); see model_f64.hip.
+// FP64 prefix-reusing forward of n listed connections from a sample cache
+// written by enqueue_logpsi_f64's kvc / pre outputs (per sample
+// [L][2][K][64] + [K + 1] doubles); each x' from its first changed position
+// on; see model_f64.hip.
 int64_t f64_cache_doubles(const nnqs_model *m);
-nnqs_status enqueue_f64_list(const nnqs_model *m, const uint64_t *xkeys, int64_t C, const int32_t *list,
-                             const int64_t *hdr, const double *kvc, const double *pre, double *xla, double *xph,
+nnqs_status enqueue_f64_list(const nnqs_model *m, const uint64_t *xkeys, int64_t C, const int32_t *list, int64_t n,
+                             const uint64_t *keys, const double *kvc, const double *pre, double *xla, double *xph,
                              hipStream_t st);
 nnqs_status screen_infer(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, int64_t n, float *pred,
                          hipStream_t st, bool fp8);

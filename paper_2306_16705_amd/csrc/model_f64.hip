@@ -8,6 +8,7 @@
 // The arithmetic is the FP64 definition of the network; only the summation
 // order differs from a one-configuration-at-a-time evaluation.
 #include <cmath>
+#include <vector>
 
 #include "f64_kernels.hpp"
 
@@ -315,11 +316,11 @@ __global__ void __launch_bounds__(256) k64_finish(ModelView M, const double *__r
 // ------------------------------------------------ prefix reuse in FP64
 // Cache of a configuration's forward for the prefix-reusing evaluation of its
 // connections: per configuration [L][2][K][64] doubles, every layer's keys
-// then values (all heads, as the attention used them), and pre[4] with
-// pre[q] = sum_{s < 16 q} log pi_s.  By causality of the attention and of the
+// then values (all heads, as the attention used them), and pre[K + 1] with
+// pre[s] = sum_{t < s} log pi_t.  By causality of the attention and of the
 // autoregressive product of Eq. 8, a connected x' whose first changed
 // position is s0 has the same rows s <= s0 as its sample, so its forward can
-// start at row 16 floor(s0 / 16) from the cache.
+// start at row s0 from the cache.
 __global__ void k64_cache_kv(const double *__restrict__ kk, const double *__restrict__ v, int64_t B, int K, int l,
                              int L, double *__restrict__ kvc) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -335,32 +336,68 @@ __global__ void k64_prefix(const double *__restrict__ lp, int64_t B, int K, doub
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     double s = 0.0;
-    for (int q = 0; q < 4; q++) {
-        pre[4 * b + q] = s;
-        for (int t = 16 * q; t < 16 * q + 16 && t < K; t++) s += lp[b * K + t];
+    for (int t = 0; t < K; t++) {
+        pre[b * (K + 1) + t] = s;
+        s += lp[b * K + t];
     }
+    pre[b * (K + 1) + K] = s;
 }
 
-// Rows s = 16 sb .. K-1 of listed connections x' = xkeys[list[i]]: row
-// r = i Rb + s - 16 sb (Rb = K - 16 sb).  Embeddings, and the keys of the
-// batch gathered into ckeys (phase MLP, head).
-__global__ void k64r_embed(ModelView M, const uint64_t *__restrict__ xkeys, const int32_t *__restrict__ list,
-                           int64_t B, int sb, double *__restrict__ h, uint64_t *__restrict__ ckeys) {
-    const int K = M.K, d = M.d, Rb = K - 16 * sb;
+// First changed sequence position of x' against its sample x (position s
+// holds orbital K-1-s); the sample itself restarts at the last position.
+__device__ __forceinline__ int first_change(int K, const uint64_t *x, const uint64_t *xp) {
+    const uint64_t d0 = x[0] ^ xp[0], d1 = x[1] ^ xp[1];
+    if (!d0 && !d1) return K - 1;
+    const int p = d1 ? 127 - __clzll(d1) : 63 - __clzll(d0);
+    return K - 1 - (p >> 1);
+}
+
+// Per listed connection i (x' = xkeys[list[i]], sample list[i] / C of the
+// chunk): its start s0 and row count K - s0.
+__global__ void k64x_count(const uint64_t *__restrict__ xkeys, const int32_t *__restrict__ list, int64_t n,
+                           const uint64_t *__restrict__ keys, int64_t C, int K, int32_t *__restrict__ s0v,
+                           int32_t *__restrict__ rows) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t e = list[i];
+    const int s0 = first_change(K, keys + 2 * (e / C), xkeys + 2 * e);
+    s0v[i] = s0;
+    rows[i] = K - s0;
+}
+
+// Row maps of one batch of B listed connections: rows off[i] - off0 ..
+// + K - s0[i] belong to connection i, position s0[i] + j; and the batch's
+// keys gathered into ckeys.
+__global__ void k64x_rowmap(const uint64_t *__restrict__ xkeys, const int32_t *__restrict__ list,
+                            const int32_t *__restrict__ s0v, const int32_t *__restrict__ off, int32_t off0, int64_t B,
+                            int K, int32_t *__restrict__ row_cfg, int32_t *__restrict__ row_pos,
+                            uint64_t *__restrict__ ckeys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    const int s0 = s0v[i];
+    const int r0 = off[i] - off0;
+    for (int j = 0; j < K - s0; j++) {
+        row_cfg[r0 + j] = (int32_t)i;
+        row_pos[r0 + j] = s0 + j;
+    }
+    const int64_t e = list[i];
+    ckeys[2 * i] = xkeys[2 * e];
+    ckeys[2 * i + 1] = xkeys[2 * e + 1];
+}
+
+// Embeddings of the mapped rows: h[r][c] = tok_emb[token at s-1][c] + pos_emb[s][c].
+__global__ void k64x_embed(ModelView M, const uint64_t *__restrict__ ckeys, const int32_t *__restrict__ row_cfg,
+                           const int32_t *__restrict__ row_pos, int64_t R, double *__restrict__ h) {
+    const int K = M.K, d = M.d;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= B * Rb * d) return;
+    if (e >= R * d) return;
     const int64_t row = e / d;
     const int c = (int)(e - row * d);
-    const int64_t i = row / Rb;
-    const int s = 16 * sb + (int)(row - i * Rb);
-    const int64_t src = list[i];
+    const int64_t i = row_cfg[row];
+    const int s = row_pos[row];
     Key x;
-    x.lo = xkeys[2 * src];
-    x.hi = xkeys[2 * src + 1];
-    if (c == 0 && s == 16 * sb) {
-        ckeys[2 * i] = x.lo;
-        ckeys[2 * i + 1] = x.hi;
-    }
+    x.lo = ckeys[2 * i];
+    x.hi = ckeys[2 * i + 1];
     int prev = 4;
     if (s > 0) {
         const int o = K - s;  // orbital of position s - 1
@@ -369,14 +406,18 @@ __global__ void k64r_embed(ModelView M, const uint64_t *__restrict__ xkeys, cons
     h[e] = M.w64[M.off.tok_emb + prev * d + c] + M.w64[M.off.pos_emb + (int64_t)s * d + c];
 }
 
-// Causal attention of the listed rows on FP64 MFMA (the tiling of
-// k64_attention): one wave per (configuration, head); keys and values of rows
-// below 16 sb come from the cache of the connection's sample (list[i] / C in
-// the chunk), the rest from this pass.
-__global__ void __launch_bounds__(256) k64r_attention(const double *__restrict__ q, const double *__restrict__ k,
+// Causal attention of the mapped rows on FP64 MFMA (the tiling of
+// k64_attention): one wave per (connection, head); query blocks from the one
+// holding s0 on, queries below s0 read as zero and are not written; keys and
+// values below s0 come from the cache of the connection's sample (list[i] / C
+// in the chunk), the rest from this pass (row off[i] - off0 + s - s0).
+__global__ void __launch_bounds__(256) k64x_attention(const double *__restrict__ q, const double *__restrict__ k,
                                                       const double *__restrict__ v, const double *__restrict__ kvc,
-                                                      const int32_t *__restrict__ list, int64_t C, int64_t B, int K,
-                                                      int L, int l, int sb, double scale, double *__restrict__ o) {
+                                                      const int32_t *__restrict__ list,
+                                                      const int32_t *__restrict__ s0v,
+                                                      const int32_t *__restrict__ off, int32_t off0, int64_t C,
+                                                      int64_t B, int K, int L, int l, double scale,
+                                                      double *__restrict__ o) {
     __shared__ double Ps[4][16][64 + 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -384,11 +425,11 @@ __global__ void __launch_bounds__(256) k64r_attention(const double *__restrict__
     if (g >= B * 4) return;  // wave-uniform; the kernel has no block barrier
     const int64_t i = g >> 2;
     const int hh = (int)(g & 3);
-    const int Rb = K - 16 * sb, s0 = 16 * sb;
+    const int s0 = s0v[i];
     const int64_t smp = list[i] / C;
     const int64_t per = (int64_t)K * 64;
     const double *kc = kvc + ((smp * L + l) * 2) * per + hh * 16, *vc = kc + per;
-    const int64_t rb = i * Rb * 64 + hh * 16;
+    const int64_t rb = (int64_t)(off[i] - off0) * 64 + hh * 16;  // row s0 of this connection, head hh
     const double *qh = q + rb, *kh = k + rb, *vh = v + rb;
     auto ldk = [&](int s, int c) { return s >= K ? 0.0 : s < s0 ? kc[(int64_t)s * 64 + c] : kh[(int64_t)(s - s0) * 64 + c]; };
     auto ldv = [&](int s, int c) { return s >= K ? 0.0 : s < s0 ? vc[(int64_t)s * 64 + c] : vh[(int64_t)(s - s0) * 64 + c]; };
@@ -400,14 +441,15 @@ __global__ void __launch_bounds__(256) k64r_attention(const double *__restrict__
 #pragma unroll
     for (int kk = 0; kk < 16; kk++) vf[kk] = ldv(4 * kk + lk, lr);
     double(*P)[64 + 1] = Ps[w];
+    const int qb0 = s0 >> 4;
 #pragma unroll
     for (int qb = 0; qb < 4; qb++) {
-        if (qb < sb || 16 * qb >= K) continue;  // wave-uniform
+        if (qb < qb0 || 16 * qb >= K) continue;  // wave-uniform
         double qf[4];
 #pragma unroll
         for (int k4 = 0; k4 < 4; k4++) {
             const int s = qb * 16 + lr;
-            qf[k4] = s < K ? qh[(int64_t)(s - s0) * 64 + 4 * k4 + lk] : 0.0;
+            qf[k4] = (s >= s0 && s < K) ? qh[(int64_t)(s - s0) * 64 + 4 * k4 + lk] : 0.0;
         }
         f64x4 st[4];
 #pragma unroll
@@ -426,7 +468,7 @@ __global__ void __launch_bounds__(256) k64r_attention(const double *__restrict__
             for (int kb = 0; kb <= qb; kb++)
                 if (kb < qb || lr <= lk + 4 * ii) mx[ii] = fmax(mx[ii], st[kb][ii]);
 #pragma unroll
-            for (int off = 8; off >= 1; off >>= 1) mx[ii] = fmax(mx[ii], __shfl_xor(mx[ii], off, 16));
+            for (int off2 = 8; off2 >= 1; off2 >>= 1) mx[ii] = fmax(mx[ii], __shfl_xor(mx[ii], off2, 16));
             den[ii] = 0.0;
 #pragma unroll
             for (int kb = 0; kb < 4; kb++) {
@@ -436,7 +478,7 @@ __global__ void __launch_bounds__(256) k64r_attention(const double *__restrict__
                 den[ii] += p;
             }
 #pragma unroll
-            for (int off = 8; off >= 1; off >>= 1) den[ii] += __shfl_xor(den[ii], off, 16);
+            for (int off2 = 8; off2 >= 1; off2 >>= 1) den[ii] += __shfl_xor(den[ii], off2, 16);
         }
 #pragma unroll
         for (int kb = 0; kb < 4; kb++)
@@ -452,7 +494,7 @@ __global__ void __launch_bounds__(256) k64r_attention(const double *__restrict__
 #pragma unroll
         for (int ii = 0; ii < 4; ii++) {
             const int s = qb * 16 + lk + 4 * ii;
-            if (s < K) o[(i * Rb + s - s0) * 64 + hh * 16 + lr] = ot[ii];
+            if (s >= s0 && s < K) o[rb + (int64_t)(s - s0) * 64 + lr] = ot[ii];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -460,23 +502,25 @@ __global__ void __launch_bounds__(256) k64r_attention(const double *__restrict__
     }
 }
 
-// Output head of the listed rows (as k64_head): one wave per row; the
+// Output head of the mapped rows (as k64_head): one wave per row; the
 // electrons placed before position s are counted from the key.
-__global__ void __launch_bounds__(256) k64r_head(ModelView M, const double *__restrict__ a,
-                                                 const uint64_t *__restrict__ ckeys, int64_t B, int sb,
+__global__ void __launch_bounds__(256) k64x_head(ModelView M, const double *__restrict__ a,
+                                                 const uint64_t *__restrict__ ckeys,
+                                                 const int32_t *__restrict__ row_cfg,
+                                                 const int32_t *__restrict__ row_pos, int64_t R,
                                                  double *__restrict__ lp) {
-    const int K = M.K, Rb = K - 16 * sb;
+    const int K = M.K;
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (row >= B * Rb) return;  // wave-uniform
-    const int64_t i = row / Rb;
-    const int s = 16 * sb + (int)(row - i * Rb);
+    if (row >= R) return;  // wave-uniform
+    const int64_t i = row_cfg[row];
+    const int s = row_pos[row];
     Key x;
     x.lo = ckeys[2 * i];
     x.hi = ckeys[2 * i + 1];
     auto token = [&](int pos) {
-        const int o = K - 1 - pos;
-        return key_bit(x, 2 * o) + 2 * key_bit(x, 2 * o + 1);
+        const int oo = K - 1 - pos;
+        return key_bit(x, 2 * oo) + 2 * key_bit(x, 2 * oo + 1);
     };
     const int tr = lane < s ? token(lane) : 0;
     const int up = __popcll(__ballot(tr & 1)), dn = __popcll(__ballot(tr >> 1));
@@ -487,7 +531,7 @@ __global__ void __launch_bounds__(256) k64r_head(ModelView M, const double *__re
     for (int t = 0; t < 4; t++) {
         double vv = av * W[M.off.head_w + lane * 4 + t];
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) vv += __shfl_xor(vv, off, 64);
+        for (int off2 = 32; off2 >= 1; off2 >>= 1) vv += __shfl_xor(vv, off2, 64);
         z[t] = vv;
     }
     if (lane != 0) return;
@@ -509,28 +553,31 @@ __global__ void __launch_bounds__(256) k64r_head(ModelView M, const double *__re
     lp[row] = ok[ts] ? (z[ts] - mx) - log(den) : -INFINITY;
 }
 
-// Per listed connection: log|psi| = 1/2 (pre[sample][sb] + sum of its rows'
+// Per listed connection: log|psi| = 1/2 (pre[sample][s0] + sum of its rows'
 // log pi), phase = b3 + z2 . w3, written to xla / xph at list[i] (one wave each).
-__global__ void __launch_bounds__(256) k64r_finish(ModelView M, const double *__restrict__ lp,
+__global__ void __launch_bounds__(256) k64x_finish(ModelView M, const double *__restrict__ lp,
                                                    const double *__restrict__ z2, const double *__restrict__ pre,
-                                                   const int32_t *__restrict__ list, int64_t C, int64_t B, int sb,
-                                                   double *__restrict__ xla, double *__restrict__ xph) {
+                                                   const int32_t *__restrict__ list,
+                                                   const int32_t *__restrict__ s0v,
+                                                   const int32_t *__restrict__ off, int32_t off0, int64_t C,
+                                                   int64_t B, double *__restrict__ xla, double *__restrict__ xph) {
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (i >= B) return;
-    const int Rb = M.K - 16 * sb;
+    const int K = M.K, s0 = s0v[i];
+    const int64_t r0 = off[i] - off0;
     double s = 0.0;
-    for (int t = lane; t < Rb; t += 64) s += lp[i * Rb + t];
+    for (int t = lane; t < K - s0; t += 64) s += lp[r0 + t];
     double ph = 0.0;
     for (int j = lane; j < M.P; j += 64) ph += z2[i * M.P + j] * M.w64[M.off.ph_w3 + j];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        s += __shfl_xor(s, off, 64);
-        ph += __shfl_xor(ph, off, 64);
+    for (int off2 = 32; off2 >= 1; off2 >>= 1) {
+        s += __shfl_xor(s, off2, 64);
+        ph += __shfl_xor(ph, off2, 64);
     }
     if (lane == 0) {
         const int64_t e = list[i];
-        xla[e] = 0.5 * (pre[4 * (e / C) + sb] + s);
+        xla[e] = 0.5 * (pre[(e / C) * (K + 1) + s0] + s);
         xph[e] = M.w64[M.off.ph_b3] + ph;
     }
 }
@@ -599,7 +646,9 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
                            W + M.off.lnf_b, R, a);
         hipLaunchKernelGGL(k64_head, dim3(blocks_for(R, 4)), dim3(256), 0, st, M, a, tok, B, lp, cpos,
                            cond ? cond + 4 * b0 : (double *)nullptr);
-        if (pre) hipLaunchKernelGGL(k64_prefix, dim3(blocks_for(B)), dim3(256), 0, st, lp, B, K, pre + 4 * b0);
+        if (pre)
+            hipLaunchKernelGGL(k64_prefix, dim3(blocks_for(B)), dim3(256), 0, st, lp, B, K,
+                               pre + (int64_t)(K + 1) * b0);
         double *z1 = f, *z2 = f + (size_t)B * P;
         hipLaunchKernelGGL(k64_phase1, dim3(blocks_for(B * P)), dim3(256), 0, st, M, keys + 2 * b0, B, z1);
         hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((P + 63) / 64), (unsigned)((B + 63) / 64)), dim3(256), 0, st,
@@ -611,25 +660,42 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
     return NNQS_OK;
 }
 
-// FP64 forward of listed connections with prefix reuse (see k64_cache_kv):
-// class q of hdr (count hdr[q], list offset hdr[4 + q], host copies) holds
-// connections whose first changed position lies in row block q; they are
-// evaluated from row 16 min(q, (K - 1) / 16) on (a later start than K - 1 has
-// no rows left, so the last block is recomputed).  kvc / pre: the cache of
-// the chunk's samples, indexed by list entry / C.  Results go to xla / xph.
-nnqs_status enqueue_f64_list(const nnqs_model *cm, const uint64_t *xkeys, int64_t C, const int32_t *list,
-                             const int64_t *hdr, const double *kvc, const double *pre, double *xla, double *xph,
+// FP64 forward of n listed connections with prefix reuse (see k64_cache_kv):
+// each x' runs only its rows from its first changed position s0 on (the
+// sample itself: the last row), in batches of up to kF64Batch connections
+// whose rows are packed one after another; kvc / pre: the cache of the
+// chunk's samples (keys [m][2]), indexed by list entry / C.  Results go to
+// xla / xph.  Synchronises `st` once (the row counts set the batches).
+nnqs_status enqueue_f64_list(const nnqs_model *cm, const uint64_t *xkeys, int64_t C, const int32_t *list, int64_t n,
+                             const uint64_t *keys, const double *kvc, const double *pre, double *xla, double *xph,
                              hipStream_t st) {
+    if (n <= 0) return NNQS_OK;
     nnqs_model *m = const_cast<nnqs_model *>(cm);
     const ModelView M = model_view(m);
     const int K = M.K, d = M.d, F = M.F, P = M.P;
-    int64_t nmax = 0;
-    for (int q = 0; q < 4; q++) nmax = hdr[q] > nmax ? hdr[q] : nmax;
-    if (nmax == 0) return NNQS_OK;
-    const int64_t Bmax = nmax < kF64Batch ? nmax : kF64Batch;
+    // per-connection starts and row counts, then their offsets (host scan)
+    const size_t rag_need = (size_t)(3 * n + 1) * sizeof(int32_t);
+    if (m->ragcap < rag_need) {
+        NNQS_HIP_CHECK(hipStreamSynchronize(st));
+        hipFree(m->d_rag);
+        m->d_rag = nullptr;
+        m->ragcap = 0;
+        if (hipMalloc(&m->d_rag, rag_need) != hipSuccess) return fail(NNQS_ENOMEM, "row maps (%zu bytes)", rag_need);
+        m->ragcap = rag_need;
+    }
+    int32_t *s0v = reinterpret_cast<int32_t *>(m->d_rag), *rows = s0v + n, *off = rows + n;
+    hipLaunchKernelGGL(k64x_count, dim3(blocks_for(n)), dim3(256), 0, st, xkeys, list, n, keys, C, K, s0v, rows);
+    NNQS_HIP_CHECK(hipGetLastError());
+    std::vector<int32_t> h_rows((size_t)n), h_off((size_t)n + 1);
+    NNQS_HIP_CHECK(hipMemcpyAsync(h_rows.data(), rows, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    NNQS_HIP_CHECK(hipStreamSynchronize(st));
+    h_off[0] = 0;
+    for (int64_t i = 0; i < n; i++) h_off[(size_t)i + 1] = h_off[(size_t)i] + h_rows[(size_t)i];
+    NNQS_HIP_CHECK(hipMemcpyAsync(off, h_off.data(), (size_t)(n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    const int64_t Bmax = n < kF64Batch ? n : kF64Batch;
     const int64_t Rmax = Bmax * K;
-    // h, a, q, k, v [rows][64]; f [rows][F]; z1, z2 [B][P]; lp [rows]; ckeys [B][2]
-    const size_t need = ((size_t)Rmax * (5 * d + F + 1) + (size_t)Bmax * (2 * P + 2)) * 8 + 256;
+    // h, a, q, k, v [rows][64]; f [rows][F]; z1, z2 [B][P]; lp [rows]; ckeys [B][2]; row maps [rows][2]
+    const size_t need = ((size_t)Rmax * (5 * d + F + 1) + (size_t)Bmax * (2 * P + 2)) * 8 + (size_t)Rmax * 8 + 256;
     if (m->f64cap < need) {
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
         hipFree(m->d_f64s);
@@ -642,50 +708,49 @@ nnqs_status enqueue_f64_list(const nnqs_model *cm, const uint64_t *xkeys, int64_
     double *a = h + Rmax * d, *qb = a + Rmax * d, *kk = qb + Rmax * d, *v = kk + Rmax * d;
     double *f = v + Rmax * d, *z1 = f + Rmax * F, *z2 = z1 + Bmax * P, *lp = z2 + Bmax * P;
     uint64_t *ckeys = reinterpret_cast<uint64_t *>(lp + Rmax);
+    int32_t *row_cfg = reinterpret_cast<int32_t *>(ckeys + 2 * Bmax), *row_pos = row_cfg + Rmax;
     const LayerOffsets LO = layer_offsets(d, F);
     const double *W = m->d_w64;
     const double scale = 1.0 / sqrt((double)(d / M.H));
-    for (int q = 0; q < 4; q++) {
-        const int sb = q < (K - 1) / 16 ? q : (K - 1) / 16;
-        const int Rb = K - 16 * sb;
-        const int32_t *lq = list + hdr[4 + q];
-        for (int64_t b0 = 0; b0 < hdr[q]; b0 += kF64Batch) {
-            const int64_t B = hdr[q] - b0 < kF64Batch ? hdr[q] - b0 : kF64Batch;
-            const int64_t R = B * Rb;
-            const unsigned gy = (unsigned)((R + 63) / 64);
-            hipLaunchKernelGGL(k64r_embed, dim3(blocks_for(R * d)), dim3(256), 0, st, M, xkeys, lq + b0, B, sb, h,
-                               ckeys);
-            for (int l = 0; l < M.L; l++) {
-                const double *Lw = W + M.off.layer0 + (int64_t)l * M.off.layer_stride;
-                hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln1_g,
-                                   Lw + LO.ln1_b, R, a);
-                hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wq, d, Lw + LO.bq, R, d,
-                                   d, qb, d);
-                hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wk, d, Lw + LO.bk, R, d,
-                                   d, kk, d);
-                hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wv, d, Lw + LO.bv, R, d,
-                                   d, v, d);
-                hipLaunchKernelGGL(k64r_attention, dim3((unsigned)B), dim3(256), 0, st, qb, kk, v, kvc, lq + b0, C, B,
-                                   K, M.L, l, sb, scale, a);
-                hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wo, d, Lw + LO.bo, R, d,
-                                   d, h, d);
-                hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,
-                                   Lw + LO.ln2_b, R, a);
-                hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, d,
-                                   Lw + LO.w1, F, Lw + LO.b1, R, F, d, f, F);
-                hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, f, F, Lw + LO.w2, d, Lw + LO.b2, R, d,
-                                   F, h, d);
-            }
-            hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, W + M.off.lnf_g,
-                               W + M.off.lnf_b, R, a);
-            hipLaunchKernelGGL(k64r_head, dim3(blocks_for(R, 4)), dim3(256), 0, st, M, a, ckeys, B, sb, lp);
-            hipLaunchKernelGGL(k64_phase1, dim3(blocks_for(B * P)), dim3(256), 0, st, M, ckeys, B, z1);
-            hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((P + 63) / 64), (unsigned)((B + 63) / 64)), dim3(256), 0,
-                               st, z1, P, W + M.off.ph_w2, P, W + M.off.ph_b2, B, P, P, z2, P);
-            hipLaunchKernelGGL(k64r_finish, dim3(blocks_for(B, 4)), dim3(256), 0, st, M, lp, z2, pre, lq + b0, C, B,
-                               sb, xla, xph);
-            NNQS_HIP_CHECK(hipGetLastError());
+    for (int64_t b0 = 0; b0 < n; b0 += kF64Batch) {
+        const int64_t B = n - b0 < kF64Batch ? n - b0 : kF64Batch;
+        const int32_t off0 = h_off[(size_t)b0];
+        const int64_t R = h_off[(size_t)(b0 + B)] - off0;
+        const unsigned gy = (unsigned)((R + 63) / 64);
+        const int32_t *lq = list + b0, *sq = s0v + b0, *oq = off + b0;
+        hipLaunchKernelGGL(k64x_rowmap, dim3(blocks_for(B)), dim3(256), 0, st, xkeys, lq, sq, oq, off0, B, K, row_cfg,
+                           row_pos, ckeys);
+        hipLaunchKernelGGL(k64x_embed, dim3(blocks_for(R * d)), dim3(256), 0, st, M, ckeys, row_cfg, row_pos, R, h);
+        for (int l = 0; l < M.L; l++) {
+            const double *Lw = W + M.off.layer0 + (int64_t)l * M.off.layer_stride;
+            hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln1_g,
+                               Lw + LO.ln1_b, R, a);
+            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wq, d, Lw + LO.bq, R, d, d,
+                               qb, d);
+            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wk, d, Lw + LO.bk, R, d, d,
+                               kk, d);
+            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wv, d, Lw + LO.bv, R, d, d,
+                               v, d);
+            hipLaunchKernelGGL(k64x_attention, dim3((unsigned)B), dim3(256), 0, st, qb, kk, v, kvc, lq, sq, oq, off0,
+                               C, B, K, M.L, l, scale, a);
+            hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wo, d, Lw + LO.bo, R, d, d,
+                               h, d);
+            hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,
+                               Lw + LO.ln2_b, R, a);
+            hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, d, Lw + LO.w1,
+                               F, Lw + LO.b1, R, F, d, f, F);
+            hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, f, F, Lw + LO.w2, d, Lw + LO.b2, R, d, F,
+                               h, d);
         }
+        hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, W + M.off.lnf_g,
+                           W + M.off.lnf_b, R, a);
+        hipLaunchKernelGGL(k64x_head, dim3(blocks_for(R, 4)), dim3(256), 0, st, M, a, ckeys, row_cfg, row_pos, R, lp);
+        hipLaunchKernelGGL(k64_phase1, dim3(blocks_for(B * P)), dim3(256), 0, st, M, ckeys, B, z1);
+        hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((P + 63) / 64), (unsigned)((B + 63) / 64)), dim3(256), 0, st,
+                           z1, P, W + M.off.ph_w2, P, W + M.off.ph_b2, B, P, P, z2, P);
+        hipLaunchKernelGGL(k64x_finish, dim3(blocks_for(B, 4)), dim3(256), 0, st, M, lp, z2, pre, lq, sq, oq, off0, C,
+                           B, xla, xph);
+        NNQS_HIP_CHECK(hipGetLastError());
     }
     return NNQS_OK;
 }

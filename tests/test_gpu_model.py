@@ -127,10 +127,11 @@ def test_eloc_model_refined_bf16_equals_fp64_when_all_terms_refined(nn, cfg, kw)
     """Precision ladder: with a refinement threshold far below every term
     (exp(-60) Ha), the BF16 pass only decides what to refine, every term and
     the samples' own amplitudes come from the FP64 network, and the result is
-    the FP64 path's.  The refinement evaluates each x' from the row block of
-    its first changed position on, with the sample's FP64 keys and values
-    below it: K = 40, 48, 60 and 64 cover every start block, the diagonal's
-    start past the last row (K = 48) and a ragged last block (K = 40, 60)."""
+    the FP64 path's.  The refinement evaluates each x' from its first changed
+    position on (the diagonal: its last row only), with the sample's FP64
+    keys and values below it, so batches pack rows of every length:
+    K = 40, 48, 60 and 64 put starts in every 16-row attention block and
+    ragged last blocks (K = 40, 60)."""
     d = synth.config_inputs(cfg, **kw)
     _print_case("eloc_model_refine_all", K=d["K"])
     S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
