@@ -63,8 +63,8 @@ REFINE_NATS = 7.0
 # dispatches of the profiled command) scaled by what the same counters read
 # for a plain device copy of known size.  Valid only for the kernel sources
 # they were taken with (hash below); otherwise the bench reports no traffic.
-TF_COUNTERS = {"sources_sha256_16": "7a6fb9688821e9d1", "fetch_kib": 41219.3, "write_kib": 14058.5,
-               "fetch_scale": 262144.0 / 131093.0, "write_scale": 1.0}
+TF_COUNTERS = {"sources_sha256_16": "ebcfe029a2e781b1", "fetch_kib": 40986.9, "write_kib": 14060.1,
+               "fetch_scale": 262144.0 / 131093.4, "write_scale": 1.0}
 TF_SOURCES = ("paper_2306_16705_amd/csrc/model_bf16.hip",)
 
 
