@@ -67,16 +67,15 @@ __global__ void __launch_bounds__(256) k64_layernorm(const double *__restrict__ 
 // during the current slice's products.  FP64 throughout: only the summation order differs from a plain dot
 // product.
 template <int EPI, bool TB>
-__global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, int lda, const double *__restrict__ W,
-                                                int ldw, const double *__restrict__ bias, int64_t M, int N, int Kd,
-                                                double *__restrict__ C, int ldc) {
+__device__ __forceinline__ void gemm64_tile(const double *__restrict__ A, int lda, const double *__restrict__ W,
+                                            int ldw, const double *__restrict__ bias, int64_t M, int N, int Kd,
+                                            double *__restrict__ C, int ldc, int c0) {
     constexpr int KS = 32;  // k per slice
     __shared__ double As[64][KS + 1];
     __shared__ double Ws[KS][64 + 1];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lr = l & 15, lk = l >> 4;
     const int64_t r0 = (int64_t)blockIdx.y * 64;
-    const int c0 = blockIdx.x * 64;
     // slice loads: thread t takes A[r0 + (t >> 5) + 8 e][k0 + (t & 31)] and
     // W[k0 + (t >> 6) + 4 e][c0 + (t & 63)], e = 0..7 (coalesced rows); with
     // TB, W[c0 + (t >> 5) + 8 e][k0 + (t & 31)] into the slice's column
@@ -136,6 +135,33 @@ __global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, in
     }
 }
 
+template <int EPI, bool TB>
+__global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, int lda, const double *__restrict__ W,
+                                                int ldw, const double *__restrict__ bias, int64_t M, int N, int Kd,
+                                                double *__restrict__ C, int ldc) {
+    gemm64_tile<EPI, TB>(A, lda, W, ldw, bias, M, N, Kd, C, ldc, blockIdx.x * 64);
+}
+
+// Products whose inner dimension is the model width 64 (output projection,
+// FFN input), with that width fixed at compile time: two k slices, no
+// run-time bounds on k.
+template <int EPI>
+__global__ void __launch_bounds__(256) k64_gemm_k64(const double *__restrict__ A, const double *__restrict__ W,
+                                                    int ldw, const double *__restrict__ bias, int64_t M, int N,
+                                                    double *__restrict__ C, int ldc) {
+    gemm64_tile<EPI, false>(A, 64, W, ldw, bias, M, N, 64, C, ldc, blockIdx.x * 64);
+}
+
+// Q, K and V of 64-wide rows in one launch: column block x = 0, 1, 2 of the
+// grid takes the weight and bias at W + x ws, bias + x ws (the layer block
+// keeps W_q, b_q, W_k, b_k, W_v, b_v at equal strides) and writes C + x cs.
+__global__ void __launch_bounds__(256) k64_gemm_qkv(const double *__restrict__ A, const double *__restrict__ W,
+                                                    const double *__restrict__ bias, int64_t ws, int64_t M,
+                                                    double *__restrict__ C, int64_t cs) {
+    const int x = blockIdx.x;
+    gemm64_tile<0, false>(A, 64, W + x * ws, 64, bias + x * ws, M, 64, 64, C + x * cs, 64, 0);
+}
+
 // Causal attention on FP64 MFMA: one wave per (configuration, head), the four
 // heads of one configuration per block; q, k, v and the output are [B*K][64]
 // with head hh in columns 16 hh .. 16 hh + 15.  Per block of 16 queries:
@@ -180,7 +206,7 @@ __global__ void __launch_bounds__(256) k64_attention(const double *__restrict__ 
                     st[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(qf[k4], kf[kb][k4], st[kb], 0, 0, 0);
         }
         // key 16 kb + lr is visible to query 16 qb + lk + 4 i when kb < qb, or kb == qb and lr <= lk + 4 i
-        double mx[4], den[4];
+        double mx[4], den[4], rden[4];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             mx[i] = -INFINITY;
@@ -199,11 +225,12 @@ __global__ void __launch_bounds__(256) k64_attention(const double *__restrict__ 
             }
 #pragma unroll
             for (int off = 8; off >= 1; off >>= 1) den[i] += __shfl_xor(den[i], off, 16);
+            rden[i] = 1.0 / den[i];
         }
 #pragma unroll
         for (int kb = 0; kb < 4; kb++)
 #pragma unroll
-            for (int i = 0; i < 4; i++) P[lk + 4 * i][kb * 16 + lr] = st[kb][i] / den[i];
+            for (int i = 0; i < 4; i++) P[lk + 4 * i][kb * 16 + lr] = st[kb][i] * rden[i];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -460,7 +487,7 @@ __global__ void __launch_bounds__(256) k64x_attention(const double *__restrict__
                 for (int k4 = 0; k4 < 4; k4++)
                     st[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(qf[k4], kf[kb][k4], st[kb], 0, 0, 0);
         }
-        double mx[4], den[4];
+        double mx[4], den[4], rden[4];
 #pragma unroll
         for (int ii = 0; ii < 4; ii++) {
             mx[ii] = -INFINITY;
@@ -479,11 +506,12 @@ __global__ void __launch_bounds__(256) k64x_attention(const double *__restrict__
             }
 #pragma unroll
             for (int off2 = 8; off2 >= 1; off2 >>= 1) den[ii] += __shfl_xor(den[ii], off2, 16);
+            rden[ii] = 1.0 / den[ii];
         }
 #pragma unroll
         for (int kb = 0; kb < 4; kb++)
 #pragma unroll
-            for (int ii = 0; ii < 4; ii++) P[lk + 4 * ii][kb * 16 + lr] = st[kb][ii] / den[ii];
+            for (int ii = 0; ii < 4; ii++) P[lk + 4 * ii][kb * 16 + lr] = st[kb][ii] * rden[ii];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -623,22 +651,18 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
             const double *Lw = W + M.off.layer0 + (int64_t)l * M.off.layer_stride;
             hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln1_g,
                                Lw + LO.ln1_b, R, a);
-            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wq, d, Lw + LO.bq, R, d, d,
-                               q, d);
-            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wk, d, Lw + LO.bk, R, d, d,
-                               kk, d);
-            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wv, d, Lw + LO.bv, R, d, d,
-                               v, d);
+            hipLaunchKernelGGL(k64_gemm_qkv, dim3(3, gy), dim3(256), 0, st, a, Lw + LO.wq, Lw + LO.bq,
+                               LO.wk - LO.wq, R, q, (int64_t)(kk - q));
             if (kvc)
                 hipLaunchKernelGGL(k64_cache_kv, dim3(blocks_for(R * 64)), dim3(256), 0, st, kk, v, B, K, l, M.L,
                                    kvc + b0 * M.L * 2 * K * 64);
             hipLaunchKernelGGL(k64_attention, dim3((unsigned)B), dim3(256), 0, st, q, kk, v, B, K, scale, a);
-            hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wo, d, Lw + LO.bo, R, d, d,
-                               h, d);
+            hipLaunchKernelGGL(k64_gemm_k64<1>, dim3(1, gy), dim3(256), 0, st, a, Lw + LO.wo, d, Lw + LO.bo, R, d, h,
+                               d);
             hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,
                                Lw + LO.ln2_b, R, a);
-            hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, d, Lw + LO.w1,
-                               F, Lw + LO.b1, R, F, d, f, (int)fcols);
+            hipLaunchKernelGGL(k64_gemm_k64<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, Lw + LO.w1,
+                               F, Lw + LO.b1, R, F, f, (int)fcols);
             hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, f, (int)fcols, Lw + LO.w2, d, Lw + LO.b2,
                                R, d, F, h, d);
         }
@@ -725,20 +749,16 @@ nnqs_status enqueue_f64_list(const nnqs_model *cm, const uint64_t *xkeys, int64_
             const double *Lw = W + M.off.layer0 + (int64_t)l * M.off.layer_stride;
             hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln1_g,
                                Lw + LO.ln1_b, R, a);
-            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wq, d, Lw + LO.bq, R, d, d,
-                               qb, d);
-            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wk, d, Lw + LO.bk, R, d, d,
-                               kk, d);
-            hipLaunchKernelGGL(k64_gemm<0>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wv, d, Lw + LO.bv, R, d, d,
-                               v, d);
+            hipLaunchKernelGGL(k64_gemm_qkv, dim3(3, gy), dim3(256), 0, st, a, Lw + LO.wq, Lw + LO.bq,
+                               LO.wk - LO.wq, R, qb, (int64_t)(kk - qb));
             hipLaunchKernelGGL(k64x_attention, dim3((unsigned)B), dim3(256), 0, st, qb, kk, v, kvc, lq, sq, oq, off0,
                                C, B, K, M.L, l, scale, a);
-            hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, a, d, Lw + LO.wo, d, Lw + LO.bo, R, d, d,
-                               h, d);
+            hipLaunchKernelGGL(k64_gemm_k64<1>, dim3(1, gy), dim3(256), 0, st, a, Lw + LO.wo, d, Lw + LO.bo, R, d, h,
+                               d);
             hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,
                                Lw + LO.ln2_b, R, a);
-            hipLaunchKernelGGL(k64_gemm<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, d, Lw + LO.w1,
-                               F, Lw + LO.b1, R, F, d, f, F);
+            hipLaunchKernelGGL(k64_gemm_k64<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, Lw + LO.w1,
+                               F, Lw + LO.b1, R, F, f, F);
             hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, f, F, Lw + LO.w2, d, Lw + LO.b2, R, d, F,
                                h, d);
         }
