@@ -286,6 +286,7 @@ def main():
     m = min(args.fp64_samples, S_n)
     err = {"screened_bf16_refined": None, "plain_bf16": None, "screened_ratio_rule_12": None,
            "screened_fp8_refined": None, "plain_fp8": None}
+    err_detail = {}
     ref64, dt64 = None, None
     if m > 0:
         t0 = time.perf_counter()
@@ -298,11 +299,23 @@ def main():
             return float(np.sum(w_np[:k] * e[:k, 0]) / np.sum(w_np[:k]))
 
         ref64 = energy_of(e64)
+        wm = w_np[:m] / np.sum(w_np[:m])
         for name, e in (("screened_bf16_refined", e_scr), ("plain_bf16", e_pl), ("screened_ratio_rule_12", e_ra),
                         ("screened_fp8_refined", e_f8), ("plain_fp8", e_f8p)):
-            err[name] = energy_of(e) - ref64 if e is not None else None
+            if e is None:
+                continue
+            err[name] = energy_of(e) - ref64
+            # the energy error is a weighted mean of per-sample errors: their
+            # RMS and the mean's scatter (independent errors) say how much of
+            # it is chance
+            dl = e[:m, 0] - e64[:m, 0]
+            err_detail[name] = {"eloc_rms_ha": float(np.sqrt(np.mean(dl * dl))),
+                                "eloc_max_ha": float(np.max(np.abs(dl))),
+                                "energy_scatter_ha": float(np.sqrt(np.sum(wm * wm * dl * dl)))}
         log(f"energy error vs FP64 over {m} samples: " +
             ", ".join(f"{k} {v:.2e} Ha" for k, v in err.items() if v is not None))
+        log("per-sample E_loc error (RMS / scatter of the weighted mean): " +
+            ", ".join(f"{k} {v['eloc_rms_ha']:.2e} / {v['energy_scatter_ha']:.2e} Ha" for k, v in err_detail.items()))
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
@@ -414,6 +427,7 @@ def main():
         "plain_fp64": {"samples_per_s": m / dt64, "samples": m, "energy_first_samples": ref64} if m > 0 else None,
         "fp8": (dict(fp8, energy_err_vs_fp64_ha={"screened_fp8_refined": err["screened_fp8_refined"],
                                                   "plain_fp8": err["plain_fp8"]}) if fp8 else None),
+        "error_per_sample": err_detail or None,
         "error_reference": f"plain FP64 GPU path on the first {m} samples (itself checked against the FP64 oracle "
                            "to 1e-10 per sample in the tests)",
         "screen": {"pairs": n_pairs, "labels": "BF16 network log|psi(x')|", "data_s": t_data,
