@@ -142,14 +142,24 @@ __global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, in
     gemm64_tile<EPI, TB>(A, lda, W, ldw, bias, M, N, Kd, C, ldc, blockIdx.x * 64);
 }
 
-// Products whose inner dimension is the model width 64 (output projection,
-// FFN input), with that width fixed at compile time: two k slices, no
-// run-time bounds on k.
-template <int EPI>
-__global__ void __launch_bounds__(256) k64_gemm_k64(const double *__restrict__ A, const double *__restrict__ W,
-                                                    int ldw, const double *__restrict__ bias, int64_t M, int N,
-                                                    double *__restrict__ C, int ldc) {
-    gemm64_tile<EPI, false>(A, 64, W, ldw, bias, M, N, 64, C, ldc, blockIdx.x * 64);
+// Products whose inner dimension is fixed at compile time: the model width
+// 64 (output projection, FFN input) and the FFN width 256 (FFN output) of
+// the networks measured here; no run-time bounds on k.
+template <int EPI, int KD>
+__global__ void __launch_bounds__(256) k64_gemm_kd(const double *__restrict__ A, int lda, const double *__restrict__ W,
+                                                   int ldw, const double *__restrict__ bias, int64_t M, int N,
+                                                   double *__restrict__ C, int ldc) {
+    gemm64_tile<EPI, false>(A, lda, W, ldw, bias, M, N, KD, C, ldc, blockIdx.x * 64);
+}
+
+// FFN output product h += f W2 + b2 over R rows (inner dimension F).
+static void ffn_out(const double *f, int ldf, const double *W2, const double *b2, int64_t R, int F, double *h,
+                    hipStream_t st) {
+    const dim3 grid(1, (unsigned)((R + 63) / 64));
+    if (F == 256)
+        hipLaunchKernelGGL((k64_gemm_kd<1, 256>), grid, dim3(256), 0, st, f, ldf, W2, 64, b2, R, 64, h, 64);
+    else
+        hipLaunchKernelGGL(k64_gemm<1>, grid, dim3(256), 0, st, f, ldf, W2, 64, b2, R, 64, F, h, 64);
 }
 
 // Q, K and V of 64-wide rows in one launch: column block x = 0, 1, 2 of the
@@ -657,14 +667,13 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
                 hipLaunchKernelGGL(k64_cache_kv, dim3(blocks_for(R * 64)), dim3(256), 0, st, kk, v, B, K, l, M.L,
                                    kvc + b0 * M.L * 2 * K * 64);
             hipLaunchKernelGGL(k64_attention, dim3((unsigned)B), dim3(256), 0, st, q, kk, v, B, K, scale, a);
-            hipLaunchKernelGGL(k64_gemm_k64<1>, dim3(1, gy), dim3(256), 0, st, a, Lw + LO.wo, d, Lw + LO.bo, R, d, h,
+            hipLaunchKernelGGL((k64_gemm_kd<1, 64>), dim3(1, gy), dim3(256), 0, st, a, 64, Lw + LO.wo, d, Lw + LO.bo, R, d, h,
                                d);
             hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,
                                Lw + LO.ln2_b, R, a);
-            hipLaunchKernelGGL(k64_gemm_k64<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, Lw + LO.w1,
+            hipLaunchKernelGGL((k64_gemm_kd<2, 64>), dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, 64, Lw + LO.w1,
                                F, Lw + LO.b1, R, F, f, (int)fcols);
-            hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, f, (int)fcols, Lw + LO.w2, d, Lw + LO.b2,
-                               R, d, F, h, d);
+            ffn_out(f, (int)fcols, Lw + LO.w2, Lw + LO.b2, R, F, h, st);
         }
         hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, W + M.off.lnf_g,
                            W + M.off.lnf_b, R, a);
@@ -753,14 +762,13 @@ nnqs_status enqueue_f64_list(const nnqs_model *cm, const uint64_t *xkeys, int64_
                                LO.wk - LO.wq, R, qb, (int64_t)(kk - qb));
             hipLaunchKernelGGL(k64x_attention, dim3((unsigned)B), dim3(256), 0, st, qb, kk, v, kvc, lq, sq, oq, off0,
                                C, B, K, M.L, l, scale, a);
-            hipLaunchKernelGGL(k64_gemm_k64<1>, dim3(1, gy), dim3(256), 0, st, a, Lw + LO.wo, d, Lw + LO.bo, R, d, h,
+            hipLaunchKernelGGL((k64_gemm_kd<1, 64>), dim3(1, gy), dim3(256), 0, st, a, 64, Lw + LO.wo, d, Lw + LO.bo, R, d, h,
                                d);
             hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,
                                Lw + LO.ln2_b, R, a);
-            hipLaunchKernelGGL(k64_gemm_k64<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, Lw + LO.w1,
+            hipLaunchKernelGGL((k64_gemm_kd<2, 64>), dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, 64, Lw + LO.w1,
                                F, Lw + LO.b1, R, F, f, F);
-            hipLaunchKernelGGL(k64_gemm<1>, dim3(1, gy), dim3(256), 0, st, f, F, Lw + LO.w2, d, Lw + LO.b2, R, d, F,
-                               h, d);
+            ffn_out(f, F, Lw + LO.w2, Lw + LO.b2, R, F, h, st);
         }
         hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, W + M.off.lnf_g,
                            W + M.off.lnf_b, R, a);
