@@ -415,8 +415,12 @@ typedef struct {
  * only rows from 16 b on, attending to the sample's cached rows before (by
  * causality of the attention and of the autoregressive product of Eq. 8 the
  * rows up to s0 equal the sample's; results are identical to the whole
- * forward of x').  `stats` (host, may be NULL) receives the counters; with
- * refinement (or a screen in FP64) or stats the call synchronises `stream`.
+ * forward of x').  The FP64 refinement runs each refined x' from row s0
+ * itself, reading the sample's FP64 keys and values below it.  `stats`
+ * (host, may be NULL) receives the counters; with refinement (or a screen in
+ * FP64) or stats the call synchronises `stream` (the refined and selected
+ * counts size the following launches), so such a call cannot be captured
+ * into a graph.
  * Uses library-owned scratch sized at first use (one call at a time per
  * model).
  * Errors: EINVAL, ECONSERVE (VALIDATE), ENOMEM, EUNSUPPORTED, EHIP. */
