@@ -57,6 +57,28 @@ __global__ void __launch_bounds__(256) k64_layernorm(const double *__restrict__ 
     out[row * 64 + lane] = (v - mean) * r * g[lane] + b[lane];
 }
 
+// The same row statistics alone, st[row] = (mean, 1/sqrt(var + eps)), for
+// products that normalise their A rows while staging them (gemm64_tile with
+// NORM), which saves writing and re-reading the normalised rows.
+__global__ void __launch_bounds__(256) k64_ln_stats(const double *__restrict__ in, int64_t rows,
+                                                    double *__restrict__ st) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= rows) return;
+    const double v = in[row * 64 + lane];
+    double s = v;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    const double mean = s / 64.0;
+    double q = (v - mean) * (v - mean);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) q += __shfl_xor(q, off, 64);
+    if (lane == 0) {
+        st[2 * row] = mean;
+        st[2 * row + 1] = 1.0 / sqrt(q / 64.0 + 1e-5);
+    }
+}
+
 // C[r][j] = epi(bias[j] + sum_k A[r][k] B[k][j]) for r < M, j < N, with
 // B[k][j] = W[k][j], or W[j][k] with TB (products with a transposed weight in
 // the backward); EPI 0 stores, 1 adds to C (residual), 2 stores GELU.  Block: 64 x 64 tile of C,
@@ -66,16 +88,35 @@ __global__ void __launch_bounds__(256) k64_layernorm(const double *__restrict__ 
 // k in slices of 32 through LDS, the next slice's global loads in flight
 // during the current slice's products.  FP64 throughout: only the summation order differs from a plain dot
 // product.
-template <int EPI, bool TB>
+// With NORM (Kd = 64) the A rows are LayerNorm inputs: each staged element
+// becomes (a - mean) rstd g[k] + b[k] with the row's statistics from lnst
+// (k64_ln_stats) and the scale and shift lng, lnb.  With STATS (EPI 1, N = 64,
+// one column block) the wave holds all 64 columns of its 16 updated rows and
+// also writes their LayerNorm statistics (mean, rstd) to stout, as
+// k64_ln_stats would.
+template <int EPI, bool TB, bool NORM = false, bool STATS = false>
 __device__ __forceinline__ void gemm64_tile(const double *__restrict__ A, int lda, const double *__restrict__ W,
                                             int ldw, const double *__restrict__ bias, int64_t M, int N, int Kd,
-                                            double *__restrict__ C, int ldc, int c0) {
+                                            double *__restrict__ C, int ldc, int c0,
+                                            const double *__restrict__ lnst = nullptr,
+                                            const double *__restrict__ lng = nullptr,
+                                            const double *__restrict__ lnb = nullptr,
+                                            double *__restrict__ stout = nullptr) {
     constexpr int KS = 32;  // k per slice
     __shared__ double As[64][KS + 1];
     __shared__ double Ws[KS][64 + 1];
+    __shared__ double Ln[NORM ? 4 * 64 : 1];  // mean and rstd of the tile's rows, then g and b
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lr = l & 15, lk = l >> 4;
     const int64_t r0 = (int64_t)blockIdx.y * 64;
+    if constexpr (NORM) {  // read after the first barrier of the slice loop
+        const int t = threadIdx.x & 63, part = threadIdx.x >> 6;
+        const int64_t r = r0 + t;
+        if (part == 0) Ln[t] = r < M ? lnst[2 * r] : 0.0;
+        else if (part == 1) Ln[64 + t] = r < M ? lnst[2 * r + 1] : 0.0;
+        else if (part == 2) Ln[128 + t] = lng[t];
+        else Ln[192 + t] = lnb[t];
+    }
     // slice loads: thread t takes A[r0 + (t >> 5) + 8 e][k0 + (t & 31)] and
     // W[k0 + (t >> 6) + 4 e][c0 + (t & 63)], e = 0..7 (coalesced rows); with
     // TB, W[c0 + (t >> 5) + 8 e][k0 + (t & 31)] into the slice's column
@@ -103,7 +144,12 @@ __device__ __forceinline__ void gemm64_tile(const double *__restrict__ A, int ld
         __syncthreads();  // the previous slice is consumed
 #pragma unroll
         for (int e = 0; e < 8; e++) {
-            As[ar + 8 * e][at] = pa[e];
+            if constexpr (NORM) {
+                const int rr = ar + 8 * e, kk = k0 + at;
+                As[rr][at] = (pa[e] - Ln[rr]) * Ln[64 + rr] * Ln[128 + kk] + Ln[192 + kk];
+            } else {
+                As[ar + 8 * e][at] = pa[e];
+            }
             if (TB) Ws[at][ar + 8 * e] = pw[e];
             else Ws[wr + 4 * e][wc] = pw[e];
         }
@@ -116,6 +162,45 @@ __device__ __forceinline__ void gemm64_tile(const double *__restrict__ A, int ld
             for (int cb = 0; cb < 4; cb++)
                 acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ws[k4 + lk][cb * 16 + lr], acc[cb], 0, 0, 0);
         }
+    }
+    if constexpr (STATS) {
+        static_assert(EPI == 1, "statistics of the updated residual rows");
+        double nv[4][4];
+#pragma unroll
+        for (int cb = 0; cb < 4; cb++) {
+            const int c = cb * 16 + lr;
+            const double bc = bias ? bias[c] : 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int64_t r = r0 + 16 * w + lk + 4 * i;
+                nv[cb][i] = 0.0;
+                if (r < M) {
+                    double *dst = C + r * ldc + c;
+                    nv[cb][i] = *dst + (bc + acc[cb][i]);
+                    *dst = nv[cb][i];
+                }
+            }
+        }
+        // row lk + 4 i of the wave: its 64 columns are cb * 16 + lr over the
+        // 16 lanes lr of lane group lk
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            double sm = (nv[0][i] + nv[1][i]) + (nv[2][i] + nv[3][i]);
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) sm += __shfl_xor(sm, off, 16);
+            const double mean = sm / 64.0;
+            double q = 0.0;
+#pragma unroll
+            for (int cb = 0; cb < 4; cb++) q += (nv[cb][i] - mean) * (nv[cb][i] - mean);
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) q += __shfl_xor(q, off, 16);
+            const int64_t r = r0 + 16 * w + lk + 4 * i;
+            if (lr == 0 && r < M) {
+                stout[2 * r] = mean;
+                stout[2 * r + 1] = 1.0 / sqrt(q / 64.0 + 1e-5);
+            }
+        }
+        return;
     }
 #pragma unroll
     for (int cb = 0; cb < 4; cb++) {
@@ -142,34 +227,51 @@ __global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, in
     gemm64_tile<EPI, TB>(A, lda, W, ldw, bias, M, N, Kd, C, ldc, blockIdx.x * 64);
 }
 
-// Products whose inner dimension is fixed at compile time: the model width
-// 64 (output projection, FFN input) and the FFN width 256 (FFN output) of
-// the networks measured here; no run-time bounds on k.
-template <int EPI, int KD>
-__global__ void __launch_bounds__(256) k64_gemm_kd(const double *__restrict__ A, int lda, const double *__restrict__ W,
-                                                   int ldw, const double *__restrict__ bias, int64_t M, int N,
-                                                   double *__restrict__ C, int ldc) {
-    gemm64_tile<EPI, false>(A, lda, W, ldw, bias, M, N, KD, C, ldc, blockIdx.x * 64);
+// Residual products h += A W + b of 64-wide rows whose inner dimension is
+// fixed at compile time: the model width 64 (output projection) and the FFN
+// width 256 (FFN output) of the networks measured here; no run-time bounds
+// on k; the next LayerNorm's statistics of the updated rows go to stout.
+template <int KD>
+__global__ void __launch_bounds__(256) k64_gemm_res(const double *__restrict__ A, int lda, const double *__restrict__ W,
+                                                    const double *__restrict__ bias, int64_t M,
+                                                    double *__restrict__ h, double *__restrict__ stout) {
+    gemm64_tile<1, false, false, true>(A, lda, W, 64, bias, M, 64, KD, h, 64, 0, nullptr, nullptr, nullptr, stout);
 }
 
-// FFN output product h += f W2 + b2 over R rows (inner dimension F).
+// FFN output product h += f W2 + b2 over R rows (inner dimension F), and the
+// LayerNorm statistics of the updated rows into lst.
 static void ffn_out(const double *f, int ldf, const double *W2, const double *b2, int64_t R, int F, double *h,
-                    hipStream_t st) {
+                    double *lst, hipStream_t st) {
     const dim3 grid(1, (unsigned)((R + 63) / 64));
-    if (F == 256)
-        hipLaunchKernelGGL((k64_gemm_kd<1, 256>), grid, dim3(256), 0, st, f, ldf, W2, 64, b2, R, 64, h, 64);
-    else
+    if (F == 256) {
+        hipLaunchKernelGGL(k64_gemm_res<256>, grid, dim3(256), 0, st, f, ldf, W2, b2, R, h, lst);
+    } else {
         hipLaunchKernelGGL(k64_gemm<1>, grid, dim3(256), 0, st, f, ldf, W2, 64, b2, R, 64, F, h, 64);
+        hipLaunchKernelGGL(k64_ln_stats, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, st, h, R, lst);
+    }
 }
 
-// Q, K and V of 64-wide rows in one launch: column block x = 0, 1, 2 of the
+// FFN input product of LayerNorm(h) (statistics lnst, scale and shift lng,
+// lnb) without the normalised rows in memory.
+template <int EPI>
+__global__ void __launch_bounds__(256) k64_gemm_ln(const double *__restrict__ h, const double *__restrict__ W, int ldw,
+                                                   const double *__restrict__ bias, int64_t M, int N,
+                                                   double *__restrict__ C, int ldc, const double *__restrict__ lnst,
+                                                   const double *__restrict__ lng, const double *__restrict__ lnb) {
+    gemm64_tile<EPI, false, true>(h, 64, W, ldw, bias, M, N, 64, C, ldc, blockIdx.x * 64, lnst, lng, lnb);
+}
+
+// Q, K and V of LayerNorm(h) in one launch: column block x = 0, 1, 2 of the
 // grid takes the weight and bias at W + x ws, bias + x ws (the layer block
 // keeps W_q, b_q, W_k, b_k, W_v, b_v at equal strides) and writes C + x cs.
-__global__ void __launch_bounds__(256) k64_gemm_qkv(const double *__restrict__ A, const double *__restrict__ W,
+__global__ void __launch_bounds__(256) k64_gemm_qkv(const double *__restrict__ h, const double *__restrict__ W,
                                                     const double *__restrict__ bias, int64_t ws, int64_t M,
-                                                    double *__restrict__ C, int64_t cs) {
+                                                    double *__restrict__ C, int64_t cs,
+                                                    const double *__restrict__ lnst, const double *__restrict__ lng,
+                                                    const double *__restrict__ lnb) {
     const int x = blockIdx.x;
-    gemm64_tile<0, false>(A, 64, W + x * ws, 64, bias + x * ws, M, 64, 64, C + x * cs, 64, 0);
+    gemm64_tile<0, false, true>(h, 64, W + x * ws, 64, bias + x * ws, M, 64, 64, C + x * cs, 64, 0, lnst, lng,
+                                lnb);
 }
 
 // Causal attention on FP64 MFMA: one wave per (configuration, head), the four
@@ -633,8 +735,9 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
     const int K = M.K, d = M.d, F = M.F, P = M.P;
     const int64_t Bmax = n < kF64Batch ? n : kF64Batch;
     const int64_t rows_max = Bmax * K;
-    // h, a, q, k, v [rows][64]; f [rows][F] (also z1, z2 [B][P]); lp [rows]; tok [rows]
-    const size_t need = (size_t)rows_max * (5 * d + (F > 2 * P / K + 1 ? F : 2 * P / K + 1) + 1) * 8 + rows_max + 256;
+    // h, a, q, k, v [rows][64]; f [rows][F] (also z1, z2 [B][P]); lp [rows]; LayerNorm statistics [rows][2];
+    // tok [rows]
+    const size_t need = (size_t)rows_max * (5 * d + (F > 2 * P / K + 1 ? F : 2 * P / K + 1) + 3) * 8 + rows_max + 256;
     if (m->f64cap < need) {
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
         hipFree(m->d_f64s);
@@ -647,8 +750,8 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
     double *h = reinterpret_cast<double *>(m->d_f64s);
     double *a = h + rows_max * d, *q = a + rows_max * d, *kk = q + rows_max * d, *v = kk + rows_max * d;
     double *f = v + rows_max * d;
-    double *lp = f + rows_max * fcols;
-    int8_t *tok = reinterpret_cast<int8_t *>(lp + rows_max);
+    double *lp = f + rows_max * fcols, *lst = lp + rows_max;
+    int8_t *tok = reinterpret_cast<int8_t *>(lst + 2 * rows_max);
     const LayerOffsets LO = layer_offsets(d, F);
     const double *W = m->d_w64;
     const double scale = 1.0 / sqrt((double)(d / M.H));
@@ -659,21 +762,19 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *cm, const uint64_t *keys, int64
         hipLaunchKernelGGL(k64_embed, dim3(blocks_for(R * d)), dim3(256), 0, st, M, keys + 2 * b0, B, tok, h);
         for (int l = 0; l < M.L; l++) {
             const double *Lw = W + M.off.layer0 + (int64_t)l * M.off.layer_stride;
-            hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln1_g,
-                               Lw + LO.ln1_b, R, a);
-            hipLaunchKernelGGL(k64_gemm_qkv, dim3(3, gy), dim3(256), 0, st, a, Lw + LO.wq, Lw + LO.bq,
-                               LO.wk - LO.wq, R, q, (int64_t)(kk - q));
+            if (l == 0)  // later layers: the statistics come with the previous FFN output
+                hipLaunchKernelGGL(k64_ln_stats, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, R, lst);
+            hipLaunchKernelGGL(k64_gemm_qkv, dim3(3, gy), dim3(256), 0, st, h, Lw + LO.wq, Lw + LO.bq,
+                               LO.wk - LO.wq, R, q, (int64_t)(kk - q), lst, Lw + LO.ln1_g, Lw + LO.ln1_b);
             if (kvc)
                 hipLaunchKernelGGL(k64_cache_kv, dim3(blocks_for(R * 64)), dim3(256), 0, st, kk, v, B, K, l, M.L,
                                    kvc + b0 * M.L * 2 * K * 64);
             hipLaunchKernelGGL(k64_attention, dim3((unsigned)B), dim3(256), 0, st, q, kk, v, B, K, scale, a);
-            hipLaunchKernelGGL((k64_gemm_kd<1, 64>), dim3(1, gy), dim3(256), 0, st, a, 64, Lw + LO.wo, d, Lw + LO.bo, R, d, h,
-                               d);
-            hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,
-                               Lw + LO.ln2_b, R, a);
-            hipLaunchKernelGGL((k64_gemm_kd<2, 64>), dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, 64, Lw + LO.w1,
-                               F, Lw + LO.b1, R, F, f, (int)fcols);
-            ffn_out(f, (int)fcols, Lw + LO.w2, Lw + LO.b2, R, F, h, st);
+            hipLaunchKernelGGL(k64_gemm_res<64>, dim3(1, gy), dim3(256), 0, st, a, 64, Lw + LO.wo, Lw + LO.bo, R, h,
+                               lst);
+            hipLaunchKernelGGL(k64_gemm_ln<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, h, Lw + LO.w1, F,
+                               Lw + LO.b1, R, F, f, (int)fcols, lst, Lw + LO.ln2_g, Lw + LO.ln2_b);
+            ffn_out(f, (int)fcols, Lw + LO.w2, Lw + LO.b2, R, F, h, lst, st);
         }
         hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, W + M.off.lnf_g,
                            W + M.off.lnf_b, R, a);
@@ -727,8 +828,9 @@ nnqs_status enqueue_f64_list(const nnqs_model *cm, const uint64_t *xkeys, int64_
     NNQS_HIP_CHECK(hipMemcpyAsync(off, h_off.data(), (size_t)(n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
     const int64_t Bmax = n < kF64Batch ? n : kF64Batch;
     const int64_t Rmax = Bmax * K;
-    // h, a, q, k, v [rows][64]; f [rows][F]; z1, z2 [B][P]; lp [rows]; ckeys [B][2]; row maps [rows][2]
-    const size_t need = ((size_t)Rmax * (5 * d + F + 1) + (size_t)Bmax * (2 * P + 2)) * 8 + (size_t)Rmax * 8 + 256;
+    // h, a, q, k, v [rows][64]; f [rows][F]; z1, z2 [B][P]; lp [rows]; LayerNorm statistics [rows][2];
+    // ckeys [B][2]; row maps [rows][2]
+    const size_t need = ((size_t)Rmax * (5 * d + F + 3) + (size_t)Bmax * (2 * P + 2)) * 8 + (size_t)Rmax * 8 + 256;
     if (m->f64cap < need) {
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
         hipFree(m->d_f64s);
@@ -740,7 +842,8 @@ nnqs_status enqueue_f64_list(const nnqs_model *cm, const uint64_t *xkeys, int64_
     double *h = reinterpret_cast<double *>(m->d_f64s);
     double *a = h + Rmax * d, *qb = a + Rmax * d, *kk = qb + Rmax * d, *v = kk + Rmax * d;
     double *f = v + Rmax * d, *z1 = f + Rmax * F, *z2 = z1 + Bmax * P, *lp = z2 + Bmax * P;
-    uint64_t *ckeys = reinterpret_cast<uint64_t *>(lp + Rmax);
+    double *lst = lp + Rmax;  // LayerNorm statistics [rows][2]
+    uint64_t *ckeys = reinterpret_cast<uint64_t *>(lst + 2 * Rmax);
     int32_t *row_cfg = reinterpret_cast<int32_t *>(ckeys + 2 * Bmax), *row_pos = row_cfg + Rmax;
     const LayerOffsets LO = layer_offsets(d, F);
     const double *W = m->d_w64;
@@ -756,19 +859,17 @@ nnqs_status enqueue_f64_list(const nnqs_model *cm, const uint64_t *xkeys, int64_
         hipLaunchKernelGGL(k64x_embed, dim3(blocks_for(R * d)), dim3(256), 0, st, M, ckeys, row_cfg, row_pos, R, h);
         for (int l = 0; l < M.L; l++) {
             const double *Lw = W + M.off.layer0 + (int64_t)l * M.off.layer_stride;
-            hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln1_g,
-                               Lw + LO.ln1_b, R, a);
-            hipLaunchKernelGGL(k64_gemm_qkv, dim3(3, gy), dim3(256), 0, st, a, Lw + LO.wq, Lw + LO.bq,
-                               LO.wk - LO.wq, R, qb, (int64_t)(kk - qb));
+            if (l == 0)  // later layers: the statistics come with the previous FFN output
+                hipLaunchKernelGGL(k64_ln_stats, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, R, lst);
+            hipLaunchKernelGGL(k64_gemm_qkv, dim3(3, gy), dim3(256), 0, st, h, Lw + LO.wq, Lw + LO.bq,
+                               LO.wk - LO.wq, R, qb, (int64_t)(kk - qb), lst, Lw + LO.ln1_g, Lw + LO.ln1_b);
             hipLaunchKernelGGL(k64x_attention, dim3((unsigned)B), dim3(256), 0, st, qb, kk, v, kvc, lq, sq, oq, off0,
                                C, B, K, M.L, l, scale, a);
-            hipLaunchKernelGGL((k64_gemm_kd<1, 64>), dim3(1, gy), dim3(256), 0, st, a, 64, Lw + LO.wo, d, Lw + LO.bo, R, d, h,
-                               d);
-            hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, Lw + LO.ln2_g,
-                               Lw + LO.ln2_b, R, a);
-            hipLaunchKernelGGL((k64_gemm_kd<2, 64>), dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, a, 64, Lw + LO.w1,
-                               F, Lw + LO.b1, R, F, f, F);
-            ffn_out(f, F, Lw + LO.w2, Lw + LO.b2, R, F, h, st);
+            hipLaunchKernelGGL(k64_gemm_res<64>, dim3(1, gy), dim3(256), 0, st, a, 64, Lw + LO.wo, Lw + LO.bo, R, h,
+                               lst);
+            hipLaunchKernelGGL(k64_gemm_ln<2>, dim3((unsigned)((F + 63) / 64), gy), dim3(256), 0, st, h, Lw + LO.w1, F,
+                               Lw + LO.b1, R, F, f, F, lst, Lw + LO.ln2_g, Lw + LO.ln2_b);
+            ffn_out(f, F, Lw + LO.w2, Lw + LO.b2, R, F, h, lst, st);
         }
         hipLaunchKernelGGL(k64_layernorm, dim3(blocks_for(R, 4)), dim3(256), 0, st, h, W + M.off.lnf_g,
                            W + M.off.lnf_b, R, a);
