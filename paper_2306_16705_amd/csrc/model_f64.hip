@@ -8,6 +8,7 @@
 // The arithmetic is the FP64 definition of the network; only the summation
 // order differs from a one-configuration-at-a-time evaluation.
 #include <cmath>
+#include <climits>
 #include <vector>
 
 #include "f64_kernels.hpp"
@@ -807,7 +808,10 @@ nnqs_status enqueue_f64_list(const nnqs_model *cm, const uint64_t *xkeys, int64_
     nnqs_model *m = const_cast<nnqs_model *>(cm);
     const ModelView M = model_view(m);
     const int K = M.K, d = M.d, F = M.F, P = M.P;
-    // per-connection starts and row counts, then their offsets (host scan)
+    // per-connection starts and row counts, then their offsets (host scan);
+    // offsets are 32-bit (a chunk holds at most 2^24 connections of <= 64 rows)
+    if (n * K > (int64_t)INT32_MAX)
+        return fail(NNQS_EINVAL, "%lld refined connections exceed 32-bit row offsets", (long long)n);
     const size_t rag_need = (size_t)(3 * n + 1) * sizeof(int32_t);
     if (m->ragcap < rag_need) {
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
