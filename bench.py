@@ -64,7 +64,10 @@ REFINE_NATS = 7.0
 # for a plain device copy of known size.  Valid only for the kernel sources
 # they were taken with (hash below); otherwise the bench reports no traffic.
 TF_COUNTERS = {"sources_sha256_16": "ebcfe029a2e781b1", "fetch_kib": 40986.9, "write_kib": 14060.1,
-               "fetch_scale": 262144.0 / 131093.4, "write_scale": 1.0}
+               "fetch_scale": 262144.0 / 131093.4, "write_scale": 1.0,
+               # SQ_INSTS_VALU and SQ_VALU_MFMA_BUSY_CYCLES of one step's eight
+               # launches per algorithmic FLOP of that step (1.1608e14)
+               "valu_per_flop": 1.118e11 / 1.1608e14, "mfma_busy_cycles_per_flop": 1.504e11 / 1.1608e14}
 TF_SOURCES = ("paper_2306_16705_amd/csrc/model_bf16.hip",)
 
 
@@ -74,6 +77,18 @@ def sources_hash(files):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def tf_counters(flops_step, list_s_per_step):
+    """VALU issue and MFMA busy fractions of the list kernel from the counter
+    ratios above and the live kernel time (1,024 SIMDs at 2.4 GHz)."""
+    c = TF_COUNTERS
+    if c["sources_sha256_16"] != sources_hash(TF_SOURCES) or not list_s_per_step:
+        return None
+    return {"valu_issue_frac": c["valu_per_flop"] * flops_step / list_s_per_step / VALU_ISSUE_PEAK,
+            "mfma_busy_frac": c["mfma_busy_cycles_per_flop"] * flops_step / list_s_per_step / (1024 * 2.4e9),
+            "sources_sha256_16": c["sources_sha256_16"],
+            "from": "profiles/k_transformer_bf16_list_n120.md"}
 
 
 def tf_traffic_bytes():
@@ -407,7 +422,8 @@ def main():
                      "evaluated_by_prefix_class": cls,
                      "other_kernels_ms_per_step": {"k_transformer_bf16": smp_ms / args.steps,
                                                    "k_screen_infer": scr_ms / args.steps,
-                                                   "k_phase_bf16": ph_ms / args.steps}},
+                                                   "k_phase_bf16": ph_ms / args.steps},
+                     "counters": tf_counters(flops_step, list_ms * 1e-3 / args.steps)},
         "cpu_baseline": cpu,
         "screened_bf16_refined": {"samples_per_s": samples_s, "energy": float(en_scr[0]),
                                   "evaluated_fraction": st_scr["evaluated"] / st_scr["connections"],
