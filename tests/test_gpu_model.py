@@ -55,6 +55,27 @@ def test_logpsi_fp64_matches_oracle(nn, kw):
     assert np.max(np.abs(ph - oph)) < 1e-12
 
 
+@pytest.mark.parametrize("F", [128, 320])
+def test_logpsi_fp64_other_ffn_widths_match_oracle(nn, F):
+    """The layer-batched FP64 forward at FFN widths other than 256 (its FFN
+    output product then takes the run-time inner dimension and a separate
+    LayerNorm statistics pass); larger weights (std 0.2) so that LayerNorm and
+    GELU act far from their linear ranges."""
+    K, nu, nd = 12, 4, 3
+    shape = synth.TransformerShape(K=K, d_model=64, n_layers=2, n_heads=4, d_ff=F, phase_hidden=96)
+    w = synth.transformer_weights(shape, nu, nd, np.random.default_rng([synth.SEED_ROOT, 903, F]), std=0.2)
+    w = {k: np.asarray(v, dtype=np.float64) for k, v in w.items()}
+    keys, _ = synth.geometric_samples(K, nu, nd, 300, np.random.default_rng(7))
+    _print_case("logpsi_fp64_ffn", K=K, F=F)
+    M = nn.Model(shape, nu, nd, w)
+    la, ph = nn.model_logpsi(M, dev(keys), nn.NNQS_FP64)
+    torch.cuda.synchronize()
+    ola, oph = oracle.net_logpsi(w, shape, nu, nd, keys, nthreads=0)
+    la, ph = la.cpu().numpy(), ph.cpu().numpy()
+    assert np.max(np.abs(la - ola) / np.maximum(1.0, np.abs(ola))) < 1e-12
+    assert np.max(np.abs(ph - oph)) < 1e-12
+
+
 @pytest.mark.parametrize("kw,take", [(dict(K=5, n_up=2, n_dn=2), None), (dict(K=6, n_up=2, n_dn=3), None),
                                      (dict(K=16, n_up=4, n_dn=4, n_unique=64), 4)])
 def test_eloc_model_fp64_matches_oracle(nn, kw, take):
