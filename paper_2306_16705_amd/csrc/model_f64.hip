@@ -87,8 +87,8 @@ __global__ void __launch_bounds__(256) k64_ln_stats(const double *__restrict__ i
 // A[l & 15][l >> 4] and B[l >> 4][l & 15]; accumulator register i of lane l
 // holds row (l >> 4) + 4 i, column l & 15, unlike the BF16 16x16 variants);
 // k in slices of 32 through LDS, the next slice's global loads in flight
-// during the current slice's products.  FP64 throughout: only the summation order differs from a plain dot
-// product.
+// during the current slice's products.  FP64 throughout: only the summation
+// order differs from a plain dot product.
 // With NORM (Kd = 64) the A rows are LayerNorm inputs: each staged element
 // becomes (a - mean) rstd g[k] + b[k] with the row's statistics from lnst
 // (k64_ln_stats) and the scale and shift lng, lnb.  With STATS (EPI 1, N = 64,
