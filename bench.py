@@ -131,7 +131,7 @@ def main():
     ap.add_argument("--screen-steps", type=int, default=8000, help="Adam steps of the screen training")
     ap.add_argument("--skip-nats", type=float, default=SKIP_NATS)
     ap.add_argument("--refine-nats", type=float, default=REFINE_NATS)
-    ap.add_argument("--cpu-connections", type=int, default=4096,
+    ap.add_argument("--cpu-connections", type=int, default=16384,
                     help="connections of one sample the FP64 oracle network evaluates (CPU baseline; 0 = skip)")
     ap.add_argument("--sa", type=int, default=1, help="also time the sample-aware N=48 path (0 = skip)")
     ap.add_argument("--batch-systems", type=int, default=32, help="systems of the batched launch (0 = skip)")
