@@ -66,7 +66,7 @@ REFINE_NATS = 7.0
 TF_COUNTERS = {"sources_sha256_16": "ebcfe029a2e781b1", "fetch_kib": 40986.9, "write_kib": 14060.1,
                "fetch_scale": 262144.0 / 131093.4, "write_scale": 1.0,
                # SQ_INSTS_VALU and SQ_VALU_MFMA_BUSY_CYCLES of one step's eight
-               # launches per algorithmic FLOP of that step (1.1608e14)
+               # launches per FLOP of the class blocks that step ran (1.1608e14)
                "valu_per_flop": 1.118e11 / 1.1608e14, "mfma_busy_cycles_per_flop": 1.504e11 / 1.1608e14}
 TF_SOURCES = ("paper_2306_16705_amd/csrc/model_bf16.hip",)
 
@@ -79,14 +79,15 @@ def sources_hash(files):
     return h.hexdigest()[:16]
 
 
-def tf_counters(flops_step, list_s_per_step):
+def tf_counters(block_flops_step, list_s_per_step):
     """VALU issue and MFMA busy fractions of the list kernel from the counter
-    ratios above and the live kernel time (1,024 SIMDs at 2.4 GHz)."""
+    ratios above (per class-block FLOP) and the live kernel time (1,024 SIMDs
+    at 2.4 GHz)."""
     c = TF_COUNTERS
     if c["sources_sha256_16"] != sources_hash(TF_SOURCES) or not list_s_per_step:
         return None
-    return {"valu_issue_frac": c["valu_per_flop"] * flops_step / list_s_per_step / VALU_ISSUE_PEAK,
-            "mfma_busy_frac": c["mfma_busy_cycles_per_flop"] * flops_step / list_s_per_step / (1024 * 2.4e9),
+    return {"valu_issue_frac": c["valu_per_flop"] * block_flops_step / list_s_per_step / VALU_ISSUE_PEAK,
+            "mfma_busy_frac": c["mfma_busy_cycles_per_flop"] * block_flops_step / list_s_per_step / (1024 * 2.4e9),
             "sources_sha256_16": c["sources_sha256_16"],
             "from": "profiles/k_transformer_bf16_list_n120.md"}
 
@@ -98,13 +99,24 @@ def tf_traffic_bytes():
     return (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"]) * 1024.0
 
 
+# FLOP of one sequence row of the transformer: four layers of QKV (64 x 192),
+# output (64 x 64) and FFN (64 x 256 x 64) products, and the 64 x 4 head; and
+# of one (row, attended key) pair: Q K^T and P V over 4 heads of 16, 4 layers.
+TF_ROW_FLOP = 4 * 2 * (64 * 192 + 64 * 64 + 2 * 64 * 256) + 2 * 64 * 4
+TF_KEY_FLOP = 4 * 4 * 2 * 16 * 2
+
+
+def tf_required_flops(rows: int, keys: int) -> float:
+    """Algorithmic FLOP of the prefix-reusing forward: only the rows from each
+    connection's first changed position s0 on (`rows` = sum of K - s0), each
+    row s attending to s + 1 keys (`keys` = sum of s + 1 over those rows)."""
+    return float(TF_ROW_FLOP * rows + TF_KEY_FLOP * keys)
+
+
 def tf_class_flops(K: int, b: int) -> float:
-    """Algorithmic FLOP of the prefix-reusing forward for one connection of
-    class b: rows s = 16 b .. K-1, each through four layers of QKV (64 x 192),
-    output (64 x 64) and FFN (64 x 256 x 64) products, causal attention over
-    s + 1 keys (Q K^T and P V, 4 heads of 16), and the 64 x 4 head."""
-    per_row = 4 * 2 * (64 * 192 + 64 * 64 + 2 * 64 * 256) + 2 * 64 * 4
-    return float(sum(per_row + 4 * 4 * 2 * 16 * 2 * (s + 1) for s in range(16 * b, K)))
+    """FLOP the list kernel executes for one connection of prefix class b (its
+    rows s = 16 b .. K-1 in whole 16-row blocks, padding rows past K aside)."""
+    return float(sum(TF_ROW_FLOP + TF_KEY_FLOP * (s + 1) for s in range(16 * b, K)))
 
 
 def log(msg):
@@ -232,7 +244,10 @@ def main():
     en_scr = energy.cpu().numpy().copy()
     samples_s = S_n / (ms_step * 1e-3)
     cls = st_scr["evaluated_class"]
-    flops_step = sum(cls[b] * tf_class_flops(K, b) for b in range(4))
+    # algorithmic work: the rows each connection needs; the class blocks the
+    # kernel runs (from 16 floor(s0 / 16)) are reported beside it
+    flops_step = tf_required_flops(st_scr["evaluated_rows"], st_scr["evaluated_keys"])
+    flops_blocks = sum(cls[b] * tf_class_flops(K, b) for b in range(4))
     achieved = flops_step * args.steps / (list_ms * 1e-3) / 1e12 if list_ms > 0 else None
     log(f"screened: {ms_step:.1f} ms/step, {samples_s:.4g} samples/s; evaluated {st_scr['evaluated']} "
         f"(classes {cls}), refined {st_scr['refined']}; list kernel {list_ms / max(1, list_launches):.3f} ms x "
@@ -419,11 +434,15 @@ def main():
                      "kernel_ms_per_launch": list_ms / max(1, list_launches),
                      "launches_per_step": list_launches / args.steps,
                      "algorithmic_flop_per_step": flops_step,
+                     "algorithmic_unit": "rows s0 .. K-1 of every evaluated connection (s0: first changed "
+                                         "position), 393,728 FLOP per row + 1,024 per attended key",
+                     "executed_block_flop_per_step": flops_blocks,
+                     "evaluated_rows": st_scr["evaluated_rows"], "evaluated_keys": st_scr["evaluated_keys"],
                      "evaluated_by_prefix_class": cls,
                      "other_kernels_ms_per_step": {"k_transformer_bf16": smp_ms / args.steps,
                                                    "k_screen_infer": scr_ms / args.steps,
                                                    "k_phase_bf16": ph_ms / args.steps},
-                     "counters": tf_counters(flops_step, list_ms * 1e-3 / args.steps)},
+                     "counters": tf_counters(flops_blocks, list_ms * 1e-3 / args.steps)},
         "cpu_baseline": cpu,
         "screened_bf16_refined": {"samples_per_s": samples_s, "energy": float(en_scr[0]),
                                   "evaluated_fraction": st_scr["evaluated"] / st_scr["connections"],

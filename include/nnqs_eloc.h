@@ -376,6 +376,12 @@ typedef struct {
      * from 48 on); the forward evaluates their rows from 16 b on (see
      * nnqs_eloc_model).  Zero for FP64. */
     int64_t evaluated_class[4];
+    /* BF16 only: the rows the evaluated x' need at the least, sum over them
+     * of K - s0 (the positions from the first changed one on), and sum over
+     * those rows s of s + 1 (the keys row s attends to): the work a
+     * prefix-reusing forward cannot avoid.  Zero for FP64. */
+    int64_t evaluated_rows;
+    int64_t evaluated_keys;
 } nnqs_stats;
 
 /* Screen rules: a connection x' goes to the network when

@@ -125,7 +125,8 @@ class ModelDesc(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("connections", _i64), ("evaluated", _i64), ("refined", _i64), ("evaluated_class", _i64 * 4)]
+    _fields_ = [("connections", _i64), ("evaluated", _i64), ("refined", _i64), ("evaluated_class", _i64 * 4),
+                ("evaluated_rows", _i64), ("evaluated_keys", _i64)]
 
 
 class ElocOpts(ctypes.Structure):

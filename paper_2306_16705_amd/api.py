@@ -407,7 +407,8 @@ def eloc_model(system: System, model: Model, keys, counts=None, precision: int =
                                      ctypes.byref(st) if with_stats else None, NNQS_VALIDATE if validate else 0,
                                      _stream(stream)))
     stats = ({"connections": st.connections, "evaluated": st.evaluated, "refined": st.refined,
-              "evaluated_class": list(st.evaluated_class)} if with_stats else None)
+              "evaluated_class": list(st.evaluated_class), "evaluated_rows": st.evaluated_rows,
+              "evaluated_keys": st.evaluated_keys} if with_stats else None)
     return eloc, (energy if with_energy else None), stats
 
 

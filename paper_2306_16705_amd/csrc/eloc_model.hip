@@ -278,6 +278,37 @@ __global__ void __launch_bounds__(64) k_cls_write(ClsArgs a, const int32_t *__re
     }
 }
 
+// The rows and attended keys the kept connections need at the least (rows
+// s0 .. K-1 from the first changed position; the diagonal: its last row),
+// summed into req[0], req[1] (integers: the totals do not depend on order).
+__global__ void __launch_bounds__(256) k_req_work(ClsArgs a, unsigned long long *__restrict__ req) {
+    __shared__ unsigned long long sh[2][256];
+    unsigned long long rows = 0, keys = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.total; e += (int64_t)gridDim.x * blockDim.x) {
+        if (!cls_keep(a, e)) continue;
+        const uint64_t *x = a.keys + 2 * (e / a.R.C), *xp = a.xkeys + 2 * e;
+        const uint64_t d0 = x[0] ^ xp[0], d1 = x[1] ^ xp[1];
+        const int p = d1 ? 127 - __clzll(d1) : (d0 ? 63 - __clzll(d0) : 0);
+        const int s0 = (d0 | d1) ? a.K - 1 - (p >> 1) : a.K - 1;
+        rows += (unsigned long long)(a.K - s0);
+        keys += (unsigned long long)(a.K * (a.K + 1) / 2 - s0 * (s0 + 1) / 2);
+    }
+    sh[0][threadIdx.x] = rows;
+    sh[1][threadIdx.x] = keys;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(req, sh[0][0]);
+        atomicAdd(req + 1, sh[1][0]);
+    }
+}
+
 __global__ void k_zero_i64(int64_t *p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
@@ -556,7 +587,7 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
     }
     int64_t evaluated = 0, refined = 0;
     int64_t *d_evalcnt = model->d_hdr + 8;
-    if (bf16) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, d_evalcnt, 5);
+    if (bf16) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, d_evalcnt, 7);
     for (int64_t s0 = 0; s0 < n; s0 += chunk) {
         const int64_t m = n - s0 < chunk ? n - s0 : chunk;
         const int64_t total = m * C;
@@ -593,6 +624,9 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
             hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, model->d_blockcnt, nb, model->d_hdr, d_evalcnt);
             hipLaunchKernelGGL(k_cls_write, dim3(nb), dim3(64), 0, st, ca, model->d_blockcnt, model->d_sel,
                                screen != nullptr, model->d_xla, model->d_xph);
+            if (stats)
+                hipLaunchKernelGGL(k_req_work, dim3(1024), dim3(256), 0, st, ca,
+                                   reinterpret_cast<unsigned long long *>(d_evalcnt + 5));
             NNQS_HIP_CHECK(hipGetLastError());
             s1 = enqueue_bf16_list(model, model->d_xkeys, C, model->d_sel, model->d_hdr, total, model->d_kv,
                                    model->d_pre, model->d_xla, model->d_xph, st, fp8);
@@ -657,11 +691,13 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (s1 != NNQS_OK) return s1;
     }
     if (stats) {
-        int64_t ev[5] = {0, 0, 0, 0, 0};
+        int64_t ev[7] = {0, 0, 0, 0, 0, 0, 0};
         if (bf16) NNQS_HIP_CHECK(hipMemcpyAsync(ev, d_evalcnt, sizeof(ev), hipMemcpyDeviceToHost, st));
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
         if (bf16) evaluated = ev[0];
         for (int k = 0; k < 4; k++) stats->evaluated_class[k] = ev[1 + k];
+        stats->evaluated_rows = ev[5];
+        stats->evaluated_keys = ev[6];
         stats->connections = n * C;
         stats->evaluated = evaluated;
         stats->refined = refined;

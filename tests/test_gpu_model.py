@@ -227,6 +227,21 @@ def test_bf16_prefix_reuse_equals_whole_forward(nn, kw, take, prec):
     absum = np.abs(terms).sum(axis=1)
     g = eloc_complex(e)
     assert st["evaluated"] == take * C
+    # the work a prefix-reusing forward needs: rows s0 .. K-1 of every x'
+    # (s0 = K-1 for x' = x), each row s attending to s + 1 keys
+    K = d["K"]
+    xk = keys.cpu().numpy().view(np.uint64)
+    xp = con["xprime"].cpu().numpy().view(np.uint64)
+    d0, d1 = xk[:, None, 0] ^ xp[..., 0], xk[:, None, 1] ^ xp[..., 1]
+
+    def bitlen(v):  # bit length of uint64 values, exactly (32-bit halves in float64)
+        hi, lo = (v >> np.uint64(32)).astype(np.float64), (v & np.uint64(0xFFFFFFFF)).astype(np.float64)
+        return np.where(hi > 0, 32 + np.frexp(hi)[1], np.frexp(lo)[1])
+
+    top = np.where(d1 != 0, 64 + bitlen(d1) - 1, bitlen(d0) - 1)  # highest differing bit, -1 for x' = x
+    s0 = np.where(top >= 0, K - 1 - (top // 2), K - 1).astype(np.int64)
+    assert st["evaluated_rows"] == int(np.sum(K - s0))
+    assert st["evaluated_keys"] == int(np.sum(K * (K + 1) // 2 - s0 * (s0 + 1) // 2))
     err = np.abs(g - ref) / absum
     print(f"prefix vs whole-forward {prec} K={d['K']}: max |dE|/A = {err.max():.3e}")
     assert err.max() <= 1e-12
