@@ -199,6 +199,12 @@ def test_trained_screen_cuts_evaluations_within_1e4_ha(nn):
         torch.cuda.synchronize()
         de = abs(en1[0].item() - en0[0].item())
         frac = st1["evaluated"] / st1["connections"]
+        # required rows: at least one per evaluated x', at most its class
+        # blocks (rows from 16 b); each row attends to 1 .. K keys
+        K = d["K"]
+        blocks = sum(st1["evaluated_class"][b] * (K - 16 * b) for b in range(4))
+        assert st1["evaluated"] <= st1["evaluated_rows"] <= blocks
+        assert st1["evaluated_rows"] <= st1["evaluated_keys"] <= K * st1["evaluated_rows"]
         per = np.max(np.abs(eloc_complex(e1) - eloc_complex(e0)))
         res[(rule, thr)] = (frac, de)
         print(f"rule {'ratio' if rule == nn.NNQS_SKIP_RATIO else 'contribution'} {thr}: evaluated "
