@@ -1,0 +1,80 @@
+"""Edge cases of the GPU entry points: empty inputs are refused without
+touching the device state, and the degenerate sectors of the method (one
+spin without electrons, one spin filling every orbital, so that no
+excitation of that spin exists) evaluate to the oracle's local energies."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import assert_eloc_close, dev, eloc_complex
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_16705_amd as nn
+    return nn
+
+
+def _einval(nn, fn):
+    with pytest.raises(nn.NNQSError) as ei:
+        fn()
+    assert ei.value.code == -1, str(ei.value)  # NNQS_EINVAL
+
+
+def test_empty_inputs_are_refused_and_the_library_stays_usable(nn):
+    d = synth.config_inputs(2, K=12, n_up=4, n_dn=3, n_unique=20, model=True)
+    print(f"[case] empty inputs K={d['K']}", flush=True)
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    k0 = torch.empty((0, 2), dtype=torch.int64, device="cuda")
+    c0 = torch.empty((0,), dtype=torch.int32, device="cuda")
+    e0 = torch.empty((0, 2), dtype=torch.float64, device="cuda")
+    _einval(nn, lambda: nn.eloc_model(S, M, k0, c0, nn.NNQS_FP64))
+    _einval(nn, lambda: nn.eloc_model(S, M, k0, c0, nn.NNQS_BF16, refine_nats=7.0))
+    _einval(nn, lambda: nn.model_logpsi(M, k0, nn.NNQS_FP64))
+    _einval(nn, lambda: nn.model_logpsi(M, k0, nn.NNQS_BF16))
+    _einval(nn, lambda: nn.connections(S, k0))
+    _einval(nn, lambda: nn.energy_noalloc(c0, e0))
+    _einval(nn, lambda: nn.vmc_gradient(M, k0, c0, e0))
+    torch.cuda.synchronize()
+    # the next real call is unaffected
+    keys, counts = d["keys"][:6], d["counts"][:6]
+    e, en, _ = nn.eloc_model(S, M, dev(keys), dev(counts, torch.int32), nn.NNQS_FP64)
+    ora, absum = oracle.eloc_model(d["K"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"], d["weights"],
+                                   d["model_shape"], keys, with_absum=True)
+    assert_eloc_close(eloc_complex(e), ora, absum, label="after empty calls")
+
+
+@pytest.mark.parametrize("kw", [dict(K=5, n_up=0, n_dn=2),   # no up electrons
+                                dict(K=4, n_up=4, n_dn=1),   # up spin fills every orbital
+                                dict(K=6, n_up=3, n_dn=0)])  # no down electrons
+def test_degenerate_sectors_match_the_oracle(nn, kw):
+    """Every determinant of a sector in which one spin has no excitation:
+    FP64 full E_loc against the oracle, and BF16 with every term refined
+    against the FP64 path; the connection count is the closed form."""
+    d = synth.config_inputs(1, model=True, **kw)
+    print(f"[case] degenerate sector {kw}", flush=True)
+    K, nu, nd = d["K"], d["n_up"], d["n_dn"]
+    S = nn.System(d["N"], nu, nd, d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], nu, nd, d["weights"])
+    vu, vd = K - nu, K - nd
+    C = 1 + nu * vu + nd * vd + (nu * (nu - 1) // 2) * (vu * (vu - 1) // 2) \
+        + (nd * (nd - 1) // 2) * (vd * (vd - 1) // 2) + nu * vu * nd * vd
+    assert S.connection_count == C
+    keys, counts = d["keys"], d["counts"]
+    e64, en64, _ = nn.eloc_model(S, M, dev(keys), dev(counts, torch.int32), nn.NNQS_FP64)
+    e16, en16, st = nn.eloc_model(S, M, dev(keys), dev(counts, torch.int32), nn.NNQS_BF16, refine_nats=60.0,
+                                  with_stats=True)
+    torch.cuda.synchronize()
+    ora, absum = oracle.eloc_model(K, nu, nd, d["h"], d["g"], d["e_core"], d["weights"], d["model_shape"], keys,
+                                   with_absum=True)
+    assert_eloc_close(eloc_complex(e64), ora, absum, label=str(kw))
+    a, b = eloc_complex(e64), eloc_complex(e16)
+    assert st["refined"] > 0
+    assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.abs(a).max())
