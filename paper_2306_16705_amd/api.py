@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import ctypes
+import hashlib
 
 import numpy as np
 import torch
@@ -631,14 +632,32 @@ class Batch:
         L.check(self._lib.nnqs_batch_get_tune(self.handle, ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in Tune._fields_}
 
-    def autotune(self, reps: int = 2, stream=None):
+    def tune_key(self) -> str:
+        """Autotuner cache key of the whole batch: the device, the item count
+        and a digest of every item's own workload key."""
+        keys = [tune_key(it["system"], it["keys"].shape[0]) for it in self._keep]
+        digest = hashlib.sha256("|".join(keys).encode()).hexdigest()[:16]
+        return f"{keys[0].split(':')[0]}:batch{len(keys)}:{digest}"
+
+    def autotune(self, reps: int = 2, cache_path: str | None = None, stream=None):
         """Times the candidate schedules and keeps the fastest; returns
-        ``(tune dict, best step ms)``."""
+        ``(tune dict, best step ms)``.  With ``cache_path`` a schedule stored
+        there for this batch's key is used without timing, and a newly timed
+        one is stored (``nnqs_tune_cache_*``)."""
+        key = self.tune_key() if cache_path is not None else None
+        if key is not None:
+            hit = tune_cache_lookup(cache_path, key)
+            if hit is not None:
+                self.set_tune(**hit[0])
+                return hit
         t = Tune()
         ms = ctypes.c_double()
         L.check(self._lib.nnqs_batch_autotune(self.handle, int(reps), ctypes.byref(t), ctypes.byref(ms),
                                               _stream(stream)))
-        return {f: getattr(t, f) for f, _ in Tune._fields_}, ms.value
+        tune = {f: getattr(t, f) for f, _ in Tune._fields_}
+        if key is not None:
+            tune_cache_store(cache_path, key, tune, ms.value)
+        return tune, ms.value
 
     def close(self):
         if getattr(self, "handle", None):

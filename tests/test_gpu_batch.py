@@ -117,6 +117,33 @@ def test_batch_autotune_keeps_results(nn):
         assert np.all(np.abs(g - r) <= 1e-12 * np.maximum(1.0, np.abs(r)))
 
 
+def test_batch_autotune_cache_round_trip(nn, tmp_path):
+    """A batch schedule timed once is stored under the batch's key (device,
+    item count, digest of the items' workload keys) and used again by an
+    equal batch without timing; results are unchanged."""
+    _print_case("batch_autotune_cache")
+    path = str(tmp_path / "tune.txt")
+    items = _items(nn, SYSTEMS[1:3])
+    B = nn.Batch(items)
+    key = B.tune_key()
+    assert ":batch2:" in key and key.startswith("gfx")
+    tune, ms = B.autotune(reps=1, cache_path=path)
+    assert nn.tune_cache_lookup(path, key) == (tune, pytest.approx(ms))
+    B.run()
+    torch.cuda.synchronize()
+    ref = [it["eloc"].clone() for it in items]
+    items2 = _items(nn, SYSTEMS[1:3])
+    B2 = nn.Batch(items2)
+    assert B2.tune_key() == key
+    tune2, ms2 = B2.autotune(reps=1, cache_path=path)
+    assert tune2 == tune and ms2 == pytest.approx(ms) and B2.get_tune() == tune
+    B2.run()
+    torch.cuda.synchronize()
+    for it, r in zip(items2, ref):
+        assert torch.equal(it["eloc"], r)
+    assert nn.Batch(_items(nn, SYSTEMS[2:4])).tune_key() != key
+
+
 def test_batch_with_models_feeds_the_table_from_the_network(nn):
     _print_case("batch_models")
     specs = [dict(K=6, n_up=2, n_dn=3, n_unique=150), dict(K=12, n_up=3, n_dn=3, n_unique=700),
