@@ -345,6 +345,16 @@ nnqs_status nnqs_screen_destroy(nnqs_screen *screen);
 /* Copies the current FP64 weights to the host.  Synchronises `stream`. */
 nnqs_status nnqs_screen_get_weights(const nnqs_screen *screen, double *host_out, void *stream);
 
+/* Adam state of the screen (checkpoint and resume of its training): the
+ * first and second moments (host m_out, v_out, weight-count doubles each)
+ * and the step count *t_out; nnqs_screen_set_state loads them back (host m,
+ * v; t >= 0), so that the next nnqs_screen_adam_step continues exactly where
+ * the saved run left off.  Both synchronise `stream`.  Callers: those that
+ * save a partly trained screen.  Errors: EINVAL, EHIP. */
+nnqs_status nnqs_screen_get_state(const nnqs_screen *screen, double *m_out, double *v_out, int64_t *t_out,
+                                  void *stream);
+nnqs_status nnqs_screen_set_state(nnqs_screen *screen, const double *m, const double *v, int64_t t, void *stream);
+
 /* Predictions for n connections (device xkeys [n][2], exc [n][4]) into device
  * pred [n].  Key bits at or above N and excitation codes >= N (255 included)
  * contribute no input.  precision: NNQS_FP64, NNQS_FP32, NNQS_BF16 or NNQS_FP8 (the

@@ -69,6 +69,8 @@ SIGNATURES = {
     "nnqs_screen_create": (_i32, [ctypes.POINTER(_c_void_p), _i32, _i32, _c_void_p]),
     "nnqs_screen_destroy": (_i32, [_c_void_p]),
     "nnqs_screen_get_weights": (_i32, [_c_void_p, _c_void_p, _c_void_p]),
+    "nnqs_screen_get_state": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "nnqs_screen_set_state": (_i32, [_c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p]),
     "nnqs_screen_forward": (_i32, [_c_void_p, _c_void_p, _c_void_p, _i64, _i32, _c_void_p, _c_void_p]),
     "nnqs_screen_gradient": (_i32, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _i64, _i32, _c_void_p, _c_void_p,
                                     _c_void_p]),

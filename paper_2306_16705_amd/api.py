@@ -446,20 +446,43 @@ class Screen:
         L.check(self._lib.nnqs_screen_get_weights(self.handle, out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return out
 
+    def state(self, stream=None):
+        """Adam state ``(m, v, t)``: host copies of both moments and the step count."""
+        m, v = np.empty(self.count, np.float64), np.empty(self.count, np.float64)
+        t = ctypes.c_int64()
+        L.check(self._lib.nnqs_screen_get_state(self.handle, m.ctypes.data_as(ctypes.c_void_p),
+                                                v.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t), _stream(stream)))
+        return m, v, t.value
+
+    def set_state(self, m, v, t: int, stream=None) -> None:
+        m = np.ascontiguousarray(m, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        if m.size != self.count or v.size != self.count:
+            raise ValueError(f"Adam moments need {self.count} values each")
+        L.check(self._lib.nnqs_screen_set_state(self.handle, m.ctypes.data_as(ctypes.c_void_p),
+                                                v.ctypes.data_as(ctypes.c_void_p), int(t), _stream(stream)))
+
     def save(self, path: str, stream=None) -> None:
-        """Writes the FP64 master weights and the shape to ``path`` (a
-        safetensors file: no code runs when it is read back)."""
+        """Writes the FP64 master weights, the Adam state and the shape to
+        ``path`` (a safetensors file: no code runs when it is read back), so
+        that training can resume where it stopped."""
         from safetensors.numpy import save_file
-        save_file({"weights": self.weights(stream),
+        m, v, t = self.state(stream)
+        save_file({"weights": self.weights(stream), "adam_m": m, "adam_v": v,
+                   "adam_t": np.array([t], dtype=np.int64),
                    "shape": np.array([self.n_spin_orb, self.hidden], dtype=np.int64)}, path)
 
     @classmethod
     def load(cls, path: str) -> "Screen":
-        """A screen with the weights and shape stored by :meth:`save`."""
+        """A screen with the weights, shape and (when stored) Adam state
+        written by :meth:`save`."""
         from safetensors.numpy import load_file
         d = load_file(path)
         n_spin_orb, hidden = (int(v) for v in d["shape"])
-        return cls(n_spin_orb, hidden, d["weights"])
+        scr = cls(n_spin_orb, hidden, d["weights"])
+        if "adam_m" in d:
+            scr.set_state(d["adam_m"], d["adam_v"], int(d["adam_t"][0]))
+        return scr
 
     def forward(self, xkeys, exc, precision: int = NNQS_FP64, out=None, stream=None):
         n = xkeys.shape[0]

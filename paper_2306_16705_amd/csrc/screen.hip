@@ -799,6 +799,30 @@ nnqs_status nnqs_screen_get_weights(const nnqs_screen *s, double *host_out, void
     return NNQS_OK;
 }
 
+nnqs_status nnqs_screen_get_state(const nnqs_screen *s, double *m_out, double *v_out, int64_t *t_out,
+                                  void *stream) {
+    clear_error();
+    if (!s || !m_out || !v_out || !t_out) return fail(NNQS_EINVAL, "null pointer argument");
+    hipStream_t st = as_stream(stream);
+    NNQS_HIP_CHECK(hipMemcpyAsync(m_out, s->m, s->count * 8, hipMemcpyDeviceToHost, st));
+    NNQS_HIP_CHECK(hipMemcpyAsync(v_out, s->v, s->count * 8, hipMemcpyDeviceToHost, st));
+    NNQS_HIP_CHECK(hipStreamSynchronize(st));
+    *t_out = s->t;
+    return NNQS_OK;
+}
+
+nnqs_status nnqs_screen_set_state(nnqs_screen *s, const double *m, const double *v, int64_t t, void *stream) {
+    clear_error();
+    if (!s || !m || !v) return fail(NNQS_EINVAL, "null pointer argument");
+    if (t < 0) return fail(NNQS_EINVAL, "negative Adam step count");
+    hipStream_t st = as_stream(stream);
+    NNQS_HIP_CHECK(hipMemcpyAsync(s->m, m, s->count * 8, hipMemcpyHostToDevice, st));
+    NNQS_HIP_CHECK(hipMemcpyAsync(s->v, v, s->count * 8, hipMemcpyHostToDevice, st));
+    NNQS_HIP_CHECK(hipStreamSynchronize(st));
+    s->t = t;
+    return NNQS_OK;
+}
+
 nnqs_status nnqs_screen_forward(nnqs_screen *s, const uint64_t *keys, const uint8_t *exc, int64_t n,
                                 int32_t precision, double *pred, void *stream) {
     clear_error();

@@ -290,3 +290,33 @@ def test_screen_save_load_round_trip(nn, tmp_path):
     s2 = nn.Screen.load(path)
     assert (s2.n_spin_orb, s2.hidden) == (N, H)
     assert np.array_equal(s2.weights(), s1.weights())
+
+
+def test_screen_training_resumes_from_a_checkpoint(nn, tmp_path):
+    """Weights and Adam state (both moments, the step count) saved after some
+    steps and loaded into a new screen: the next steps of the two screens
+    agree bit for bit, and a screen loaded without the state (fresh moments)
+    does not."""
+    N, H = 48, 32
+    rng = np.random.default_rng(13)
+    cnt = int(oracle.screen_size(N, H))
+    s1 = nn.Screen(N, H, rng.normal(0.0, 0.1, size=cnt))
+    grads = [torch.tensor(rng.normal(0.0, 1.0, size=cnt), device="cuda") for _ in range(6)]
+    for g in grads[:3]:
+        s1.adam_step(g, lr=1e-3)
+    m, v, t = s1.state()
+    assert t == 3 and np.all(v > 0.0)
+    path = str(tmp_path / "screen_ckpt.safetensors")
+    s1.save(path)
+    s2 = nn.Screen.load(path)
+    m2, v2, t2 = s2.state()
+    assert t2 == 3 and np.array_equal(m2, m) and np.array_equal(v2, v)
+    s3 = nn.Screen(N, H, s1.weights())  # weights only: moments restart at zero
+    for g in grads[3:]:
+        s1.adam_step(g, lr=1e-3)
+        s2.adam_step(g, lr=1e-3)
+        s3.adam_step(g, lr=1e-3)
+    assert np.array_equal(s2.weights(), s1.weights())
+    assert not np.array_equal(s3.weights(), s1.weights())
+    with pytest.raises(nn.NNQSError):
+        s2.set_state(m, v, -1)
