@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import ctypes
 import hashlib
+import os
 
 import numpy as np
 import torch
@@ -121,9 +122,10 @@ class Table:
     def autotune(self, keys, logabs, phase, reps: int = 2, eloc=None, cache_path: str | None = None, stream=None):
         """Times the candidate schedules of ``nnqs_eloc_table`` on these
         samples, keeps the fastest (the table is left built from them) and
-        returns ``(tune dict, best ms)``.  With ``cache_path`` a schedule
-        stored there for this workload's key is used without timing, and a
-        newly timed one is stored (``nnqs_tune_cache_*``)."""
+        returns ``(tune dict, best ms)``.  With ``cache_path`` (default: the
+        ``NNQS_TUNE_CACHE`` environment variable) a schedule stored there for
+        this workload's key is used without timing, and a newly timed one is
+        stored (``nnqs_tune_cache_*``)."""
         n = keys.shape[0]
         _need(keys, "keys", _KEY_DTYPES, (n, 2))
         _need(logabs, "logabs", (torch.float64,), (n,))
@@ -131,6 +133,8 @@ class Table:
         t = Tune()
         ms = ctypes.c_double()
         key = None
+        if cache_path is None:
+            cache_path = os.environ.get("NNQS_TUNE_CACHE") or None
         if cache_path is not None:
             key = tune_key(self.system, n)
             found = ctypes.c_int32(0)
@@ -664,9 +668,12 @@ class Batch:
 
     def autotune(self, reps: int = 2, cache_path: str | None = None, stream=None):
         """Times the candidate schedules and keeps the fastest; returns
-        ``(tune dict, best step ms)``.  With ``cache_path`` a schedule stored
-        there for this batch's key is used without timing, and a newly timed
-        one is stored (``nnqs_tune_cache_*``)."""
+        ``(tune dict, best step ms)``.  With ``cache_path`` (default: the
+        ``NNQS_TUNE_CACHE`` environment variable) a schedule stored there for
+        this batch's key is used without timing, and a newly timed one is
+        stored (``nnqs_tune_cache_*``)."""
+        if cache_path is None:
+            cache_path = os.environ.get("NNQS_TUNE_CACHE") or None
         key = self.tune_key() if cache_path is not None else None
         if key is not None:
             hit = tune_cache_lookup(cache_path, key)

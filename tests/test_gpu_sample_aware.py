@@ -2,6 +2,8 @@
 sets and signs bit-exact, table build bit-exact, E_loc within 1e-10 per
 sample, the weighted energy, determinism, tuning invariance and the error
 model of the C ABI."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -232,6 +234,13 @@ def test_autotune_cache_round_trip(nn, tmp_path):
     e2, _ = nn.eloc_table(S, T2, *args)
     torch.cuda.synchronize()
     assert torch.equal(e1, e2)
+    # the cache path may also come from the environment
+    os.environ["NNQS_TUNE_CACHE"] = path
+    try:
+        T3 = nn.Table(S, capacity=2048)
+        assert T3.autotune(args[0], args[2], args[3], reps=1) == (tune2, pytest.approx(ms))
+    finally:
+        del os.environ["NNQS_TUNE_CACHE"]
 
 
 # ---------------------------------------------------------- error model
