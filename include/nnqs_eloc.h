@@ -157,7 +157,9 @@ nnqs_status nnqs_connections(const nnqs_system *sys, const uint64_t *keys, int64
  * samples themselves.  Outputs (device): eloc [n][2] complex E_loc(x);
  * energy [4] = { sum c Re E_loc / sum c, sum c Im E_loc / sum c, sum c,
  * sum c (Re E_loc - E)^2 / sum c } (Eq. 6 over unique samples); energy may
- * be NULL.  Matrix elements, ratios and sums are FP64; per-sample sums are
+ * be NULL.  A count of zero removes its sample from the sums; with every
+ * count zero the energy's ratios are NaN.  Matrix elements, ratios and sums
+ * are FP64; per-sample sums are
  * compensated (Neumaier) and the reduction order is fixed, so repeated
  * calls give bit-identical results.  Calls sharing one table must be ordered
  * on one stream (the energy reduction uses the table's scratch).

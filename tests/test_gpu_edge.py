@@ -78,3 +78,24 @@ def test_degenerate_sectors_match_the_oracle(nn, kw):
     a, b = eloc_complex(e64), eloc_complex(e16)
     assert st["refined"] > 0
     assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.abs(a).max())
+
+
+def test_zero_counts_contribute_nothing(nn):
+    """Counts are occurrence weights (Eq. 6): samples of weight zero drop
+    out of the weighted energy and variance, which then equal those of the
+    remaining samples."""
+    rng = np.random.default_rng(5)
+    n = 5000
+    eloc = rng.normal(-20.0, 3.0, size=(n, 2))
+    counts = rng.integers(1, 50, size=n).astype(np.uint32)
+    zero = rng.random(n) < 0.3
+    counts[zero] = 0
+    print(f"[case] zero counts n={n} zeros={int(zero.sum())}", flush=True)
+    full = nn.energy_noalloc(dev(counts, torch.int32), dev(eloc)).cpu().numpy()
+    keep = ~zero
+    sub = nn.energy_noalloc(dev(counts[keep], torch.int32), dev(eloc[keep])).cpu().numpy()
+    ref = oracle.energy(counts[keep], eloc[keep, 0] + 1j * eloc[keep, 1])
+    assert full[2] == sub[2] == counts.sum()
+    for k in (0, 1, 3):
+        assert abs(full[k] - sub[k]) <= 1e-13 * max(1.0, abs(sub[k]))
+        assert abs(full[k] - ref[k]) <= 1e-12 * max(1.0, abs(ref[k]))
