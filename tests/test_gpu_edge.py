@@ -99,3 +99,26 @@ def test_zero_counts_contribute_nothing(nn):
     for k in (0, 1, 3):
         assert abs(full[k] - sub[k]) <= 1e-13 * max(1.0, abs(sub[k]))
         assert abs(full[k] - ref[k]) <= 1e-12 * max(1.0, abs(ref[k]))
+
+
+def test_mismatched_handles_are_refused_before_any_launch(nn):
+    """A table built for another system, or a model whose orbitals or
+    electron numbers differ from the system's, is refused with EINVAL and
+    the outputs keep their contents; the system too large for the 128-bit
+    keys (N > 128) is refused at creation."""
+    d = synth.config_inputs(2, K=12, n_up=4, n_dn=3, n_unique=40, model=True)
+    e = synth.config_inputs(2, K=12, n_up=3, n_dn=3, n_unique=40, model=True, sys=1)
+    print("[case] mismatched handles", flush=True)
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    S2 = nn.System(e["N"], e["n_up"], e["n_dn"], e["h"], e["g"], e["e_core"])
+    T2 = nn.Table(S2, capacity=40)
+    T2.build(dev(e["keys"]), dev(e["logabs"]), dev(e["phase"]))
+    M2 = nn.Model(e["model_shape"], e["n_up"], e["n_dn"], e["weights"])
+    n = d["keys"].shape[0]
+    sentinel = torch.full((n, 2), 3.0, dtype=torch.float64, device="cuda")
+    args = (dev(d["keys"]), dev(d["counts"], torch.int32), dev(d["logabs"]), dev(d["phase"]))
+    _einval(nn, lambda: nn.eloc_table(S, T2, *args, eloc=sentinel))
+    _einval(nn, lambda: nn.eloc_model(S, M2, args[0], args[1], nn.NNQS_FP64, eloc=sentinel))
+    torch.cuda.synchronize()
+    assert bool((sentinel == 3.0).all())
+    _einval(nn, lambda: nn.System(130, 4, 4, np.zeros((65, 65)), np.zeros((65,) * 4)))
