@@ -438,7 +438,8 @@ typedef struct {
  * (host, may be NULL) receives the counters; with refinement (or a screen in
  * FP64) or stats the call synchronises `stream` (the refined and selected
  * counts size the following launches), so such a call cannot be captured
- * into a graph.
+ * into a graph; without them, once its scratch has grown (a first call of
+ * the same size), the call makes no host synchronisation and can be.
  * Uses library-owned scratch sized at first use (one call at a time per
  * model).
  * Errors: EINVAL, ECONSERVE (VALIDATE), ENOMEM, EUNSUPPORTED, EHIP. */

@@ -320,3 +320,39 @@ def test_screen_training_resumes_from_a_checkpoint(nn, tmp_path):
     assert not np.array_equal(s3.weights(), s1.weights())
     with pytest.raises(nn.NNQSError):
         s2.set_state(m, v, -1)
+
+
+def test_screened_bf16_path_replays_from_a_hip_graph(nn):
+    """Without FP64 refinement, validation or statistics the screened BF16
+    full path makes no host synchronisation once its scratch is grown, so it
+    can be captured into a graph: every replay, with eager work between the
+    replays, reproduces the eager local energies and energy bit for bit."""
+    from paper_2306_16705_amd import screen_train
+    d = synth.config_inputs(2, K=16, n_up=4, n_dn=4, n_unique=24, model=True)
+    _print_case("screened_graph", K=d["K"])
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    scr = nn.Screen(d["N"], 256, screen_train.init_weights(d["N"], 256, seed=2))
+    keys, cnt = dev(d["keys"]), dev(d["counts"], torch.int32)
+    n = keys.shape[0]
+    eloc = torch.empty((n, 2), dtype=torch.float64, device="cuda")
+    energy = torch.empty(4, dtype=torch.float64, device="cuda")
+    kw = dict(eloc=eloc, energy=energy, screen=scr, skip_nats=14.0, skip_rule=nn.NNQS_SKIP_CONTRIBUTION)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for _ in range(2):  # grows every scratch buffer before the capture
+            nn.eloc_model(S, M, keys, cnt, nn.NNQS_BF16, stream=s, **kw)
+    s.synchronize()
+    ref, ref_en = eloc.clone(), energy.clone()
+    assert torch.isfinite(ref).all()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        nn.eloc_model(S, M, keys, cnt, nn.NNQS_BF16, stream=s, **kw)
+    for rep in range(3):
+        eloc.fill_(float("nan"))  # eager work between replays
+        energy.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(eloc, ref), rep
+        assert torch.equal(energy, ref_en), rep
