@@ -143,6 +143,8 @@ def main():
     ap.add_argument("--screen-steps", type=int, default=8000, help="Adam steps of the screen training")
     ap.add_argument("--skip-nats", type=float, default=SKIP_NATS)
     ap.add_argument("--refine-nats", type=float, default=REFINE_NATS)
+    ap.add_argument("--dedup", type=int, default=0,
+                    help="screened path: evaluate every distinct x' of the step once (1) or per connection (0)")
     ap.add_argument("--cpu-connections", type=int, default=16384,
                     help="connections of one sample the FP64 oracle network evaluates (CPU baseline; 0 = skip)")
     ap.add_argument("--sa", type=int, default=1, help="also time the sample-aware N=48 path (0 = skip)")
@@ -213,6 +215,7 @@ def main():
         f"{losses[0]:.3g} -> {float(np.mean(losses[-50:])):.3g}, held-out RMSE {rmse:.3f} nats "
         f"-> {'screened' if scr_used is not None else 'plain fallback'}")
     screened_kw = dict(screen=scr_used, skip_nats=args.skip_nats, skip_rule=nn.NNQS_SKIP_CONTRIBUTION,
+                       dedup=bool(args.dedup),
                        refine_nats=args.refine_nats)
     eloc = torch.empty((S_n, 2), dtype=torch.float64, device=dev)
     energy = torch.empty(4, dtype=torch.float64, device=dev)

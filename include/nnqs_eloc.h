@@ -394,6 +394,9 @@ typedef struct {
      * prefix-reusing forward cannot avoid.  Zero for FP64. */
     int64_t evaluated_rows;
     int64_t evaluated_keys;
+    /* BF16 only: the distinct x' the forward evaluated (equal to `evaluated`
+     * without dedup; with it, evaluated_class / rows / keys count these). */
+    int64_t evaluated_distinct;
 } nnqs_stats;
 
 /* Screen rules: a connection x' goes to the network when
@@ -403,7 +406,7 @@ typedef struct {
  * exp(-skip_nats) Ha when the prediction is right). */
 enum { NNQS_SKIP_RATIO = 0, NNQS_SKIP_CONTRIBUTION = 1 };
 
-/* Options of nnqs_eloc_model (NULL = {12, NNQS_SKIP_RATIO, 0, NNQS_BF16}).
+/* Options of nnqs_eloc_model (NULL = {12, NNQS_SKIP_RATIO, 0, NNQS_BF16, 0}).
  * screen_precision selects the screen's inference: NNQS_BF16 or NNQS_FP8
  * (hidden layer on FP8 MFMA).
  * refine_nats > 0 turns on the precision ladder for a lower-precision
@@ -417,6 +420,14 @@ typedef struct {
     int32_t skip_rule;
     double refine_nats;
     int32_t screen_precision;
+    /* BF16 / FP8 only: nonzero evaluates every distinct x' of a chunk once,
+     * however many samples connect to it (the kept connections are sorted by
+     * key; each run of equal keys is evaluated from the sample whose first
+     * changed position is the latest, the fewest rows, and the result copied
+     * to the others; with refinement a run is refined when any of its terms
+     * qualifies).  Chunks then hold up to 2^27 connections, so that many
+     * samples share one chunk.  Synchronises `stream` once per chunk. */
+    int32_t dedup;
 } nnqs_eloc_opts;
 
 /* Full local energies (Eq. 4 over every connected x', psi from the model,

@@ -128,11 +128,12 @@ class ModelDesc(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("connections", _i64), ("evaluated", _i64), ("refined", _i64), ("evaluated_class", _i64 * 4),
-                ("evaluated_rows", _i64), ("evaluated_keys", _i64)]
+                ("evaluated_rows", _i64), ("evaluated_keys", _i64), ("evaluated_distinct", _i64)]
 
 
 class ElocOpts(ctypes.Structure):
-    _fields_ = [("skip_nats", _f64), ("skip_rule", _i32), ("refine_nats", _f64), ("screen_precision", _i32)]
+    _fields_ = [("skip_nats", _f64), ("skip_rule", _i32), ("refine_nats", _f64), ("screen_precision", _i32),
+                ("dedup", _i32)]
 
 
 NNQS_SKIP_RATIO = 0

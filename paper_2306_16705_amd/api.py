@@ -388,13 +388,14 @@ def model_logpsi(model: Model, keys, precision: int = NNQS_FP64, logabs=None, ph
 def eloc_model(system: System, model: Model, keys, counts=None, precision: int = NNQS_FP64, eloc=None,
                energy=None, with_energy: bool = True, with_stats: bool = False, validate: bool = False,
                screen=None, skip_nats: float = 12.0, skip_rule: int = L.NNQS_SKIP_RATIO, refine_nats: float = 0.0,
-               screen_precision: int = NNQS_BF16, stream=None):
+               screen_precision: int = NNQS_BF16, dedup: bool = False, stream=None):
     """Full local energies with every x' from the network (``nnqs_eloc_model``).
 
     With a learned ``screen`` only connections kept by ``skip_rule`` at
     ``skip_nats`` go to the network; ``refine_nats > 0`` re-evaluates in FP64
     every connection whose first-pass contribution is at least
-    ``exp(-refine_nats)`` Ha.  Returns ``(eloc [n, 2], energy [4] or None,
+    ``exp(-refine_nats)`` Ha; ``dedup`` evaluates every distinct x' of a
+    chunk once (BF16 / FP8).  Returns ``(eloc [n, 2], energy [4] or None,
     stats dict or None)``."""
     n = keys.shape[0]
     _need(keys, "keys", _KEY_DTYPES, (n, 2))
@@ -405,7 +406,7 @@ def eloc_model(system: System, model: Model, keys, counts=None, precision: int =
     if eloc is None:
         eloc = torch.empty((n, 2), dtype=torch.float64, device=keys.device)
     st = Stats()
-    opts = L.ElocOpts(float(skip_nats), int(skip_rule), float(refine_nats), int(screen_precision))
+    opts = L.ElocOpts(float(skip_nats), int(skip_rule), float(refine_nats), int(screen_precision), int(bool(dedup)))
     L.check(L.load().nnqs_eloc_model(system.handle, model.handle, screen.handle if screen is not None else None,
                                      ctypes.byref(opts), int(precision), _ptr(keys), _ptr(counts), n,
                                      _ptr(eloc), _ptr(energy) if with_energy else None,
@@ -413,7 +414,8 @@ def eloc_model(system: System, model: Model, keys, counts=None, precision: int =
                                      _stream(stream)))
     stats = ({"connections": st.connections, "evaluated": st.evaluated, "refined": st.refined,
               "evaluated_class": list(st.evaluated_class), "evaluated_rows": st.evaluated_rows,
-              "evaluated_keys": st.evaluated_keys} if with_stats else None)
+              "evaluated_keys": st.evaluated_keys, "evaluated_distinct": st.evaluated_distinct}
+             if with_stats else None)
     return eloc, (energy if with_energy else None), stats
 
 

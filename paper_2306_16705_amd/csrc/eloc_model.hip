@@ -20,6 +20,7 @@ namespace nnqs {
 
 constexpr int kConnPerBlock = 4096;            // connections handled by one block
 constexpr int64_t kMaxChunkConnections = 1 << 24;
+constexpr int64_t kMaxChunkConnectionsDedup = 1 << 27;  // many samples per chunk, so that x' are shared
 constexpr int64_t kMaxChunkSamplesBf16 = 4096;  // samples whose key / value cache is kept at once
 
 __global__ void __launch_bounds__(256) k_enum_keys(SysView S, const uint64_t *__restrict__ keys, int64_t m,
@@ -171,13 +172,105 @@ __device__ __forceinline__ int conn_class(int K, const uint64_t *x, const uint64
 struct ClsArgs {
     SelRule R;                  // keep rule, used when `rule`
     bool rule;
+    const uint8_t *mask;        // optional: keep only connections with mask[e] != 0
     const uint64_t *keys;       // chunk samples [m][2]
     const uint64_t *xkeys;      // chunk connections [m*C][2]
     int64_t total;
     int K;
 };
 
-__device__ __forceinline__ bool cls_keep(const ClsArgs &a, int64_t e) { return !a.rule || sel_keep(a.R, e); }
+__device__ __forceinline__ bool cls_keep(const ClsArgs &a, int64_t e) {
+    return (!a.rule || sel_keep(a.R, e)) && (!a.mask || a.mask[e]);
+}
+
+// ------------------------------------------------ distinct x' (dedup)
+// First changed sequence position of x' against its sample x (the sample
+// itself: K - 1, its last row).
+__device__ __forceinline__ int conn_s0(int K, const uint64_t *x, uint64_t lo, uint64_t hi) {
+    const uint64_t d0 = x[0] ^ lo, d1 = x[1] ^ hi;
+    if (!d0 && !d1) return K - 1;
+    const int p = d1 ? 127 - __clzll(d1) : 63 - __clzll(d0);
+    return K - 1 - (p >> 1);
+}
+
+// Keys of the n kept connections (list sel) for the sort, padded to P with
+// all-ones keys behind every real one.
+__global__ void k_dd_gather(const uint64_t *__restrict__ xkeys, const int32_t *__restrict__ sel, int64_t n,
+                            int64_t P, uint64_t *__restrict__ sk, uint32_t *__restrict__ si,
+                            unsigned long long *__restrict__ best) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    if (i < n) {
+        const int64_t e = sel[i];
+        sk[2 * i] = xkeys[2 * e];
+        sk[2 * i + 1] = xkeys[2 * e + 1];
+        si[i] = (uint32_t)i;
+        best[i] = 0ull;
+    } else {
+        sk[2 * i] = ~0ull;
+        sk[2 * i + 1] = ~0ull;
+        si[i] = 0xFFFFFFFFu;
+    }
+}
+
+// Sorted position p < n: the head of its run of equal keys, and at the head
+// the largest score (s0 << 32) | (2^32 - 1 - e) of the run's members: the
+// latest first change, then the smallest connection index (max is
+// independent of the order of the atomic updates).
+__global__ void k_dd_score(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ si, int64_t n,
+                           const int32_t *__restrict__ sel, const uint64_t *__restrict__ keys, int64_t C, int K,
+                           int32_t *__restrict__ head, unsigned long long *__restrict__ best) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint64_t lo = sk[2 * p], hi = sk[2 * p + 1];
+    int64_t h = p;
+    while (h > 0 && sk[2 * (h - 1)] == lo && sk[2 * (h - 1) + 1] == hi) --h;
+    head[p] = (int32_t)h;
+    const int64_t e = sel[si[p]];
+    const int s0 = conn_s0(K, keys + 2 * (e / C), lo, hi);
+    atomicMax(best + h, ((unsigned long long)s0 << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)e));
+}
+
+// Representative of every kept connection (rep[i] for list position i), and
+// the mask of the representatives over the chunk.
+__global__ void k_dd_mark(const uint32_t *__restrict__ si, const int32_t *__restrict__ sel, int64_t n,
+                          const int32_t *__restrict__ head, const unsigned long long *__restrict__ best,
+                          int32_t *__restrict__ rep, uint8_t *__restrict__ repmask) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t i = si[p];
+    const int32_t e = sel[i];
+    const int32_t r = (int32_t)(0xFFFFFFFFu - (uint32_t)(best[head[p]] & 0xFFFFFFFFull));
+    rep[i] = r;
+    if (e == r) repmask[e] = 1;
+}
+
+// Copies each representative's log|psi| and phase to the other members of
+// its run (representatives are only read here).
+__global__ void k_dd_scatter(const int32_t *__restrict__ sel, const int32_t *__restrict__ rep, int64_t n,
+                             double *__restrict__ xla, double *__restrict__ xph) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t e = sel[i], r = rep[i];
+    if (e != r) {
+        xla[e] = xla[r];
+        xph[e] = xph[r];
+    }
+}
+
+// Marks the representative of every kept connection that the refinement
+// rule selects (all writers store 1).
+__global__ void k_dd_refmark(const int32_t *__restrict__ sel, const int32_t *__restrict__ rep, int64_t n, SelRule R,
+                             uint8_t *__restrict__ refmask) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (sel_keep(R, sel[i])) refmask[rep[i]] = 1;
+}
+
+__global__ void k_dd_zero_u32(uint32_t *__restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
 
 // Kept connections per class in each block of kSelBlock connections.
 __global__ void __launch_bounds__(256) k_cls_count(ClsArgs a, int32_t *__restrict__ cnt) {
@@ -426,6 +519,20 @@ void eloc_model_free(nnqs_model *m) {
     hipFree(m->d_kv64);
     hipFree(m->d_pre64);
     hipFree(m->d_rag);
+    hipFree(m->d_ddk);
+    hipFree(m->d_ddi);
+    hipFree(m->d_ddhead);
+    hipFree(m->d_ddrep);
+    hipFree(m->d_sel2);
+    hipFree(m->d_ddbest);
+    hipFree(m->d_repmask);
+    hipFree(m->d_refmask);
+    m->d_ddk = nullptr;
+    m->d_ddi = nullptr;
+    m->d_ddhead = m->d_ddrep = m->d_sel2 = nullptr;
+    m->d_ddbest = nullptr;
+    m->d_repmask = m->d_refmask = nullptr;
+    m->ddcap = m->maskcap = 0;
     m->d_kv64 = m->d_pre64 = nullptr;
     m->d_rag = nullptr;
     m->kv64cap = 0;
@@ -488,7 +595,7 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
     if (precision != NNQS_FP64 && precision != NNQS_BF16 && precision != NNQS_FP8)
         return fail(NNQS_EUNSUPPORTED, "unknown precision");
     if (precision != NNQS_FP64 && !model->bf16_ok) return fail(NNQS_EUNSUPPORTED, "model shape has no BF16 / FP8 path");
-    nnqs_eloc_opts o{12.0, NNQS_SKIP_RATIO, 0.0, NNQS_BF16};
+    nnqs_eloc_opts o{12.0, NNQS_SKIP_RATIO, 0.0, NNQS_BF16, 0};
     if (opts) o = *opts;
     if (o.screen_precision != NNQS_BF16 && o.screen_precision != NNQS_FP8)
         return fail(NNQS_EINVAL, "screen precision must be NNQS_BF16 or NNQS_FP8");
@@ -511,7 +618,8 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
     const int64_t C = sys->view.C;
     const bool bf16 = precision == NNQS_BF16 || precision == NNQS_FP8;  // prefix-reusing MFMA paths
     const bool fp8 = precision == NNQS_FP8;
-    int64_t chunk = kMaxChunkConnections / C;
+    const bool dedup = bf16 && o.dedup != 0;  // each distinct x' of a chunk evaluated once
+    int64_t chunk = (dedup ? kMaxChunkConnectionsDedup : kMaxChunkConnections) / C;
     if (chunk < 1) chunk = 1;
     if (bf16 && chunk > kMaxChunkSamplesBf16) chunk = kMaxChunkSamplesBf16;  // bounds the key / value cache
     if (chunk > n) chunk = n;
@@ -534,7 +642,7 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cla), cc * 8);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_cph), cc * 8);
         if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_nsel), 8);
-        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_hdr), 24 * 8);
+        if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_hdr), 32 * 8);
         if (s1 != NNQS_OK) {
             eloc_model_free(model);
             return s1;
@@ -586,8 +694,13 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (s1 != NNQS_OK) return s1;
     }
     int64_t evaluated = 0, refined = 0;
-    int64_t *d_evalcnt = model->d_hdr + 8;
-    if (bf16) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, d_evalcnt, 7);
+    int64_t *d_evalcnt = model->d_hdr + 8;   // [8, 15): forward's lists (total, classes), required rows / keys
+    int64_t *d_keptcnt = model->d_hdr + 24;  // [24, 29): kept connections before dedup (total, classes)
+    if (bf16) {
+        hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, d_evalcnt, 7);
+        hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, d_keptcnt, 5);
+    }
+    int64_t n_kept = 0;  // dedup: kept connections of the current chunk
     for (int64_t s0 = 0; s0 < n; s0 += chunk) {
         const int64_t m = n - s0 < chunk ? n - s0 : chunk;
         const int64_t total = m * C;
@@ -621,16 +734,75 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
             ca.K = sys->view.K;
             const int nb = (int)((total + kSelBlock - 1) / kSelBlock);
             hipLaunchKernelGGL(k_cls_count, dim3(nb), dim3(256), 0, st, ca, model->d_blockcnt);
-            hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, model->d_blockcnt, nb, model->d_hdr, d_evalcnt);
+            hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, model->d_blockcnt, nb, model->d_hdr,
+                               dedup ? d_keptcnt : d_evalcnt);
             hipLaunchKernelGGL(k_cls_write, dim3(nb), dim3(64), 0, st, ca, model->d_blockcnt, model->d_sel,
                                screen != nullptr, model->d_xla, model->d_xph);
-            if (stats)
+            NNQS_HIP_CHECK(hipGetLastError());
+            const int32_t *flist = model->d_sel;  // the list the forward runs
+            if (dedup) {
+                // the kept connections sorted by key; each run of equal x' is
+                // evaluated once, from its representative's sample
+                int64_t kh[4];
+                NNQS_HIP_CHECK(hipMemcpyAsync(kh, model->d_hdr, sizeof(kh), hipMemcpyDeviceToHost, st));
+                NNQS_HIP_CHECK(hipStreamSynchronize(st));
+                n_kept = kh[0] + kh[1] + kh[2] + kh[3];
+                int64_t P = 2;
+                while (P < n_kept) P <<= 1;
+                if (model->ddcap < P || model->maskcap < total) {
+                    const size_t pc = (size_t)std::max<int64_t>(P, model->ddcap);
+                    const size_t mc = (size_t)std::max<int64_t>(total, model->maskcap);
+                    s1 = grow(reinterpret_cast<void **>(&model->d_ddk), pc * 16);
+                    if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_ddi), pc * 4);
+                    if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_ddhead), pc * 4);
+                    if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_ddrep), pc * 4);
+                    if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_sel2), pc * 4);
+                    if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_ddbest), pc * 8);
+                    if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_repmask), (mc + 3) / 4 * 4);
+                    if (s1 == NNQS_OK) s1 = grow(reinterpret_cast<void **>(&model->d_refmask), (mc + 3) / 4 * 4);
+                    if (s1 != NNQS_OK) {
+                        eloc_model_free(model);
+                        return s1;
+                    }
+                    model->ddcap = (int64_t)pc;
+                    model->maskcap = (int64_t)mc;
+                }
+                const int64_t mw = (total + 3) / 4;
+                hipLaunchKernelGGL(k_dd_zero_u32, dim3((unsigned)((mw + 255) / 256)), dim3(256), 0, st,
+                                   reinterpret_cast<uint32_t *>(model->d_repmask), mw);
+                hipLaunchKernelGGL(k_dd_gather, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, model->d_xkeys,
+                                   model->d_sel, n_kept, P, model->d_ddk, model->d_ddi, model->d_ddbest);
+                bitonic_sort128(model->d_ddk, model->d_ddi, P, st);
+                const unsigned gk = (unsigned)((n_kept + 255) / 256);
+                hipLaunchKernelGGL(k_dd_score, dim3(gk), dim3(256), 0, st, model->d_ddk, model->d_ddi, n_kept,
+                                   model->d_sel, keys + 2 * s0, C, sys->view.K, model->d_ddhead, model->d_ddbest);
+                hipLaunchKernelGGL(k_dd_mark, dim3(gk), dim3(256), 0, st, model->d_ddi, model->d_sel, n_kept,
+                                   model->d_ddhead, model->d_ddbest, model->d_ddrep, model->d_repmask);
+                ClsArgs cr = ca;
+                cr.mask = model->d_repmask;
+                hipLaunchKernelGGL(k_cls_count, dim3(nb), dim3(256), 0, st, cr, model->d_blockcnt);
+                hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, model->d_blockcnt, nb, model->d_hdr,
+                                   d_evalcnt);
+                hipLaunchKernelGGL(k_cls_write, dim3(nb), dim3(64), 0, st, cr, model->d_blockcnt, model->d_sel2,
+                                   false, (double *)nullptr, (double *)nullptr);
+                if (stats)
+                    hipLaunchKernelGGL(k_req_work, dim3(1024), dim3(256), 0, st, cr,
+                                       reinterpret_cast<unsigned long long *>(d_evalcnt + 5));
+                NNQS_HIP_CHECK(hipGetLastError());
+                flist = model->d_sel2;
+            } else if (stats) {
                 hipLaunchKernelGGL(k_req_work, dim3(1024), dim3(256), 0, st, ca,
                                    reinterpret_cast<unsigned long long *>(d_evalcnt + 5));
-            NNQS_HIP_CHECK(hipGetLastError());
-            s1 = enqueue_bf16_list(model, model->d_xkeys, C, model->d_sel, model->d_hdr, total, model->d_kv,
+                NNQS_HIP_CHECK(hipGetLastError());
+            }
+            s1 = enqueue_bf16_list(model, model->d_xkeys, C, flist, model->d_hdr, total, model->d_kv,
                                    model->d_pre, model->d_xla, model->d_xph, st, fp8);
             if (s1 != NNQS_OK) return s1;
+            if (dedup) {
+                hipLaunchKernelGGL(k_dd_scatter, dim3((unsigned)((n_kept + 255) / 256)), dim3(256), 0, st,
+                                   model->d_sel, model->d_ddrep, n_kept, model->d_xla, model->d_xph);
+                NNQS_HIP_CHECK(hipGetLastError());
+            }
         } else if (!screen) {
             s1 = enqueue_logpsi(model, model->d_xkeys, total, precision, model->d_xla, model->d_xph, st);
             if (s1 != NNQS_OK) return s1;
@@ -656,12 +828,23 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
             ra.xkeys = model->d_xkeys;
             ra.total = total;
             ra.K = sys->view.K;
+            int32_t *rlist = model->d_sel;
+            if (dedup) {  // refine a run's representative when any member qualifies
+                const int64_t mw = (total + 3) / 4;
+                hipLaunchKernelGGL(k_dd_zero_u32, dim3((unsigned)((mw + 255) / 256)), dim3(256), 0, st,
+                                   reinterpret_cast<uint32_t *>(model->d_refmask), mw);
+                hipLaunchKernelGGL(k_dd_refmark, dim3((unsigned)((n_kept + 255) / 256)), dim3(256), 0, st,
+                                   model->d_sel, model->d_ddrep, n_kept, ra.R, model->d_refmask);
+                ra.rule = false;
+                ra.mask = model->d_refmask;
+                rlist = model->d_sel2;  // the first list stays for the copies below
+            }
             const int nb = (int)((total + kSelBlock - 1) / kSelBlock);
             int64_t *d_rhdr = model->d_hdr + 16;
             hipLaunchKernelGGL(k_cls_count, dim3(nb), dim3(256), 0, st, ra, model->d_blockcnt);
             hipLaunchKernelGGL(k_cls_scan, dim3(1), dim3(256), 0, st, model->d_blockcnt, nb, d_rhdr,
                                (int64_t *)nullptr);
-            hipLaunchKernelGGL(k_cls_write, dim3(nb), dim3(64), 0, st, ra, model->d_blockcnt, model->d_sel, false,
+            hipLaunchKernelGGL(k_cls_write, dim3(nb), dim3(64), 0, st, ra, model->d_blockcnt, rlist, false,
                                (double *)nullptr, (double *)nullptr);
             NNQS_HIP_CHECK(hipGetLastError());
             int64_t rh[8];
@@ -669,9 +852,14 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
             NNQS_HIP_CHECK(hipStreamSynchronize(st));
             const int64_t nref = rh[0] + rh[1] + rh[2] + rh[3];
             refined += nref;
-            s1 = enqueue_f64_list(model, model->d_xkeys, C, model->d_sel, nref, keys + 2 * s0, model->d_kv64,
+            s1 = enqueue_f64_list(model, model->d_xkeys, C, rlist, nref, keys + 2 * s0, model->d_kv64,
                                   model->d_pre64, model->d_xla, model->d_xph, st);
             if (s1 != NNQS_OK) return s1;
+            if (dedup) {
+                hipLaunchKernelGGL(k_dd_scatter, dim3((unsigned)((n_kept + 255) / 256)), dim3(256), 0, st,
+                                   model->d_sel, model->d_ddrep, n_kept, model->d_xla, model->d_xph);
+                NNQS_HIP_CHECK(hipGetLastError());
+            }
         } else if (refine) {  // FP64 for every connection whose first-pass contribution is not negligible
             SelRule R{nullptr, model->d_xla, model->d_loghx, model->d_sla + s0, C, o.refine_nats};
             int64_t k = 0;
@@ -691,13 +879,15 @@ extern "C" nnqs_status nnqs_eloc_model(const nnqs_system *sys, nnqs_model *model
         if (s1 != NNQS_OK) return s1;
     }
     if (stats) {
-        int64_t ev[7] = {0, 0, 0, 0, 0, 0, 0};
+        int64_t ev[7] = {0, 0, 0, 0, 0, 0, 0}, kept = 0;
         if (bf16) NNQS_HIP_CHECK(hipMemcpyAsync(ev, d_evalcnt, sizeof(ev), hipMemcpyDeviceToHost, st));
+        if (dedup) NNQS_HIP_CHECK(hipMemcpyAsync(&kept, d_keptcnt, sizeof(kept), hipMemcpyDeviceToHost, st));
         NNQS_HIP_CHECK(hipStreamSynchronize(st));
-        if (bf16) evaluated = ev[0];
+        if (bf16) evaluated = dedup ? kept : ev[0];
         for (int k = 0; k < 4; k++) stats->evaluated_class[k] = ev[1 + k];
         stats->evaluated_rows = ev[5];
         stats->evaluated_keys = ev[6];
+        stats->evaluated_distinct = bf16 ? ev[0] : evaluated;
         stats->connections = n * C;
         stats->evaluated = evaluated;
         stats->refined = refined;

@@ -92,6 +92,15 @@ struct nnqs_model {
     int64_t kv64cap = 0;
     void *d_rag = nullptr;  // starts, row counts and row offsets of the refined connections
     size_t ragcap = 0;
+    // evaluation of distinct x' (dedup): sort keys / payloads, run heads,
+    // best representative per run, representative of every kept connection,
+    // the second list, and per-connection masks (representatives, refined runs)
+    uint64_t *d_ddk = nullptr;
+    uint32_t *d_ddi = nullptr;
+    int32_t *d_ddhead = nullptr, *d_ddrep = nullptr, *d_sel2 = nullptr;
+    unsigned long long *d_ddbest = nullptr;
+    uint8_t *d_repmask = nullptr, *d_refmask = nullptr;
+    int64_t ddcap = 0, maskcap = 0;
 };
 
 namespace nnqs {
@@ -140,6 +149,11 @@ nnqs_status enqueue_logpsi_f64(const nnqs_model *m, const uint64_t *keys, int64_
 // [L][2][K][64] + [K + 1] doubles); each x' from its first changed position
 // on; see model_f64.hip.
 int64_t f64_cache_doubles(const nnqs_model *m);
+
+// Ascending bitonic sort of P (a power of two >= 2) 128-bit keys sk[2 i],
+// sk[2 i + 1] (word 1 major) with 32-bit payloads si[i] as the final
+// tie-break, in place (nnqs_core.hip).
+void bitonic_sort128(uint64_t *sk, uint32_t *si, int64_t P, hipStream_t st);
 nnqs_status enqueue_f64_list(const nnqs_model *m, const uint64_t *xkeys, int64_t C, const int32_t *list, int64_t n,
                              const uint64_t *keys, const double *kvc, const double *pre, double *xla, double *xph,
                              hipStream_t st);

@@ -677,6 +677,37 @@ nnqs_status nnqs_table_get_tune(const nnqs_table *t, nnqs_tune *tune) {
     return NNQS_OK;
 }
 
+}  // extern "C"
+
+namespace nnqs {
+
+// Ascending bitonic sort of P (a power of two >= 2) entries: 128-bit keys
+// sk[2 i], sk[2 i + 1] (word 1 major) with 32-bit payloads si[i] as the
+// final tie-break, in place on `st`.
+void bitonic_sort128(uint64_t *sk, uint32_t *si, int64_t P, hipStream_t st) {
+    const int tile = P < 2048 ? (int)P : 2048;
+    const int thr = 256;
+    const size_t lds = (size_t)tile * 20;
+    const int lthreads = tile / 2 < 1024 ? tile / 2 : 1024;
+    hipLaunchKernelGGL(k_bitonic_local, dim3((unsigned)(P / tile)), dim3(lthreads), lds, st, sk, si, tile,
+                       (int64_t)2, (int64_t)tile, (int64_t)1);
+    for (int64_t k = (int64_t)tile * 2; k <= P; k <<= 1) {
+        int64_t j = k >> 1;
+        for (; j >= 2 * (int64_t)tile; j >>= 2)  // stages j and j/2 together
+            hipLaunchKernelGGL(k_bitonic_global2, dim3((unsigned)((P / 4 + thr - 1) / thr)), dim3(thr), 0, st, sk,
+                               si, P, k, j);
+        if (j >= tile)
+            hipLaunchKernelGGL(k_bitonic_global, dim3((unsigned)((P / 2 + thr - 1) / thr)), dim3(thr), 0, st, sk,
+                               si, P, k, j);
+        hipLaunchKernelGGL(k_bitonic_local, dim3((unsigned)(P / tile)), dim3(lthreads), lds, st, sk, si, tile, k, k,
+                           (int64_t)(tile / 2));
+    }
+}
+
+}  // namespace nnqs
+
+extern "C" {
+
 nnqs_status nnqs_table_build(nnqs_table *t, const uint64_t *keys, const double *logabs, const double *phase,
                              int64_t n, uint32_t flags, void *stream) {
     clear_error();
@@ -687,25 +718,10 @@ nnqs_status nnqs_table_build(nnqs_table *t, const uint64_t *keys, const double *
     hipStream_t st = as_stream(stream);
     int64_t P = 2;
     while (P < n) P <<= 1;
-    const int tile = P < 2048 ? (int)P : 2048;
     const int thr = 256;
     hipLaunchKernelGGL(k_sort_init, dim3((unsigned)((P + thr - 1) / thr)), dim3(thr), 0, st, keys, n, P, t->sort_keys,
                        t->sort_idx);
-    const size_t lds = (size_t)tile * 20;
-    const int lthreads = tile / 2 < 1024 ? tile / 2 : 1024;
-    hipLaunchKernelGGL(k_bitonic_local, dim3((unsigned)(P / tile)), dim3(lthreads), lds, st, t->sort_keys, t->sort_idx,
-                       tile, (int64_t)2, (int64_t)tile, (int64_t)1);
-    for (int64_t k = (int64_t)tile * 2; k <= P; k <<= 1) {
-        int64_t j = k >> 1;
-        for (; j >= 2 * (int64_t)tile; j >>= 2)  // stages j and j/2 together
-            hipLaunchKernelGGL(k_bitonic_global2, dim3((unsigned)((P / 4 + thr - 1) / thr)), dim3(thr), 0, st,
-                               t->sort_keys, t->sort_idx, P, k, j);
-        if (j >= tile)
-            hipLaunchKernelGGL(k_bitonic_global, dim3((unsigned)((P / 2 + thr - 1) / thr)), dim3(thr), 0, st,
-                               t->sort_keys, t->sort_idx, P, k, j);
-        hipLaunchKernelGGL(k_bitonic_local, dim3((unsigned)(P / tile)), dim3(lthreads), lds, st, t->sort_keys,
-                           t->sort_idx, tile, k, k, (int64_t)(tile / 2));
-    }
+    bitonic_sort128(t->sort_keys, t->sort_idx, P, st);
     const int fl = t->tune.filter_log2_bits;
     const int64_t fwords = int64_t(1) << (fl - 5);
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((fwords + thr - 1) / thr)), dim3(thr), 0, st, t->filter, fwords,

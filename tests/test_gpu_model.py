@@ -292,3 +292,60 @@ def test_logpsi_fp8_error_vs_oracle(nn, kw):
     print(f"FP8 vs FP64 oracle K={d['K']}: max |dlogabs| {d8.max():.3e} (mean {d8.mean():.3e}); "
           f"BF16 max {d16.max():.3e} (mean {d16.mean():.3e}); n={len(keys)}")
     assert np.all(d8 <= 0.5 + 0.02 * np.abs(ola))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_dedup_evaluates_each_distinct_xprime_once(nn, prec):
+    """With dedup every distinct x' of the chunk goes through the forward
+    once (from the sample whose first change is latest) and its amplitude is
+    copied to every connection that reaches it: E_loc equals the per-
+    connection evaluation up to FP64 summation order, and the forward's
+    distinct count is the number of distinct keys among the connections."""
+    d = synth.config_inputs(2, K=16, n_up=4, n_dn=4, n_unique=40, model=True)
+    P = nn.NNQS_BF16 if prec == "bf16" else nn.NNQS_FP8
+    _print_case("dedup", K=d["K"], prec=prec)
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    keys, cnt = dev(d["keys"]), dev(d["counts"], torch.int32)
+    e0, en0, st0 = nn.eloc_model(S, M, keys, cnt, P, with_stats=True)
+    e1, en1, st1 = nn.eloc_model(S, M, keys, cnt, P, with_stats=True, dedup=True)
+    con = nn.connections(S, keys)
+    torch.cuda.synchronize()
+    xp = con["xprime"].cpu().numpy().reshape(-1, 2)
+    distinct = np.unique(xp.view([("a", np.int64), ("b", np.int64)])).shape[0]
+    print(f"dedup {prec}: {st1['evaluated']} connections, {st1['evaluated_distinct']} distinct "
+          f"(rows {st0['evaluated_rows']} -> {st1['evaluated_rows']})")
+    assert st1["evaluated"] == st0["evaluated"] == keys.shape[0] * S.connection_count
+    assert st1["evaluated_distinct"] == distinct < st1["evaluated"]
+    assert sum(st1["evaluated_class"]) == distinct
+    assert st1["evaluated_rows"] < st0["evaluated_rows"]
+    # scale of each E_loc: sum of |terms| from the whole-sequence amplitudes
+    C = S.connection_count
+    xla, _ = nn.model_logpsi(M, con["xprime"].reshape(-1, 2), P)
+    sla, _ = nn.model_logpsi(M, keys, P)
+    torch.cuda.synchronize()
+    absum = (np.abs(con["hxx"].cpu().numpy())
+             * np.exp(xla.cpu().numpy().reshape(-1, C) - sla.cpu().numpy()[:, None])).sum(axis=1)
+    a, b = eloc_complex(e0), eloc_complex(e1)
+    err = np.abs(a - b) / absum
+    print(f"dedup vs per-connection {prec}: max |dE|/A = {err.max():.3e}")
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("cfg,kw", [(2, dict(K=40, n_up=3, n_dn=3, n_unique=6, model=True)),
+                                    (3, dict(n_unique=2))])
+def test_dedup_with_every_term_refined_equals_fp64(nn, cfg, kw):
+    """Dedup and the FP64 refinement together: with every term refined the
+    result is the FP64 path's (each distinct x' refined once, from its
+    representative's FP64 cache, and copied)."""
+    d = synth.config_inputs(cfg, **kw)
+    _print_case("dedup_refine_all", K=d["K"])
+    S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
+    M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
+    keys, cnt = dev(d["keys"]), dev(d["counts"], torch.int32)
+    e64, _, _ = nn.eloc_model(S, M, keys, cnt, nn.NNQS_FP64)
+    e, _, st = nn.eloc_model(S, M, keys, cnt, nn.NNQS_BF16, refine_nats=60.0, with_stats=True, dedup=True)
+    torch.cuda.synchronize()
+    a, b = eloc_complex(e64), eloc_complex(e)
+    assert 0 < st["refined"] <= st["evaluated_distinct"] <= st["evaluated"]
+    assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.abs(a).max())
