@@ -58,16 +58,17 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 VALU instructions/s: 4 SIMDs per
 SKIP_NATS = 15.0
 REFINE_NATS = 7.0
 
-# HBM traffic of one k_transformer_bf16_list launch of this workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over the
-# dispatches of the profiled command) scaled by what the same counters read
-# for a plain device copy of known size.  Valid only for the kernel sources
-# they were taken with (hash below); otherwise the bench reports no traffic.
-TF_COUNTERS = {"sources_sha256_16": "ebcfe029a2e781b1", "fetch_kib": 40986.9, "write_kib": 14060.1,
+# HBM traffic of one k_transformer_bf16_list launch of this workload (with
+# distinct-x' evaluation: one launch per step), from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, averaged over the dispatches of the profiled
+# command) scaled by what the same counters read for a plain device copy of
+# known size.  Valid only for the kernel sources they were taken with (hash
+# below) and that launch shape; otherwise the bench reports no traffic.
+TF_COUNTERS = {"sources_sha256_16": "ebcfe029a2e781b1", "fetch_kib": 230771.5, "write_kib": 75713.0,
                "fetch_scale": 262144.0 / 131093.4, "write_scale": 1.0,
-               # SQ_INSTS_VALU and SQ_VALU_MFMA_BUSY_CYCLES of one step's eight
-               # launches per FLOP of the class blocks that step ran (1.1608e14)
-               "valu_per_flop": 1.118e11 / 1.1608e14, "mfma_busy_cycles_per_flop": 1.504e11 / 1.1608e14}
+               # SQ_INSTS_VALU and SQ_VALU_MFMA_BUSY_CYCLES of one step's launch
+               # per FLOP of the class blocks that step ran (7.2503e13)
+               "valu_per_flop": 6.984e10 / 7.2503e13, "mfma_busy_cycles_per_flop": 9.393e10 / 7.2503e13}
 TF_SOURCES = ("paper_2306_16705_amd/csrc/model_bf16.hip",)
 
 
@@ -143,7 +144,7 @@ def main():
     ap.add_argument("--screen-steps", type=int, default=8000, help="Adam steps of the screen training")
     ap.add_argument("--skip-nats", type=float, default=SKIP_NATS)
     ap.add_argument("--refine-nats", type=float, default=REFINE_NATS)
-    ap.add_argument("--dedup", type=int, default=0,
+    ap.add_argument("--dedup", type=int, default=1,
                     help="screened path: evaluate every distinct x' of the step once (1) or per connection (0)")
     ap.add_argument("--cpu-connections", type=int, default=16384,
                     help="connections of one sample the FP64 oracle network evaluates (CPU baseline; 0 = skip)")
@@ -271,6 +272,20 @@ def main():
     en_pl = energy.cpu().numpy().copy() if times else None
     if times:
         log(f"plain BF16: {S_n / dt_pl:.4g} samples/s (median of {args.plain_reps}), classes {cls_pl}")
+    # the plain path with distinct-x' evaluation too (no screen): what dedup
+    # alone gives, so that the screen's own share of the speed-up is visible
+    pld = None
+    if args.plain_reps and args.dedup:
+        run(nn.NNQS_BF16, dedup=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, st_pld = run(nn.NNQS_BF16, dedup=True, with_stats=True)
+        torch.cuda.synchronize()
+        dt_pld = time.perf_counter() - t0
+        pld = {"samples_per_s": S_n / dt_pld, "connections_per_s": S_n * C / dt_pld,
+               "evaluated_distinct": st_pld["evaluated_distinct"], "reps": 1,
+               "note": "no screen, every distinct x' evaluated once (timed with its statistics)"}
+        log(f"plain BF16 with dedup: {S_n / dt_pld:.4g} samples/s, {st_pld['evaluated_distinct']} distinct x'")
 
     # ---- the workload's own rule: ratio rule at 12 nats, no refinement
     ratio_kw = dict(screen=scr_used, skip_nats=12.0, skip_rule=nn.NNQS_SKIP_RATIO, refine_nats=0.0)
@@ -424,15 +439,18 @@ def main():
         "config": {"workload": f"learned screen + BF16 transformer full E_loc: N=120 (K=60), 20 up + 20 down, "
                                f"{C} connections per sample, first {S_n} samples of the seeded N=120 generator per "
                                f"step; contribution rule at {args.skip_nats} nats, FP64 refinement above "
-                               f"exp(-{args.refine_nats}) Ha; FP64 ratios and sums",
+                               f"exp(-{args.refine_nats}) Ha; "
+                               + ("each distinct x' of the step evaluated once; " if args.dedup else "")
+                               + "FP64 ratios and sums",
                    "samples_per_step": S_n, "connections_per_sample": C},
         "connections_per_s": S_n * C / (ms_step * 1e-3),
         "speedup_vs_plain_bf16": samples_s / (S_n / dt_pl) if dt_pl else None,
+        "speedup_vs_plain_bf16_dedup": samples_s / pld["samples_per_s"] if pld else None,
         "energy_err_vs_fp64_ha": err["screened_bf16_refined"],
         "meets_1e-4_ha": abs(err["screened_bf16_refined"]) <= 1e-4 if m > 0 else None,
         "roofline": {"bound": "mfma", "kernel": "k_transformer_bf16_list", "achieved": achieved,
                      "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / BF16_PEAK_TFLOPS if achieved else None, "traffic": tf_traffic_bytes(),
+                     "frac": achieved / BF16_PEAK_TFLOPS if achieved else None, "traffic": tf_traffic_bytes() if args.dedup else None,
                      "traffic_unit": "bytes per launch", "sources_sha256_16": sources_hash(TF_SOURCES),
                      "kernel_ms_per_launch": list_ms / max(1, list_launches),
                      "launches_per_step": list_launches / args.steps,
@@ -451,7 +469,9 @@ def main():
                                   "evaluated_fraction": st_scr["evaluated"] / st_scr["connections"],
                                   "refined_fraction": st_scr["refined"] / st_scr["connections"],
                                   "skip_rule": "contribution", "skip_nats": args.skip_nats,
-                                  "refine_nats": args.refine_nats},
+                                  "refine_nats": args.refine_nats, "dedup": bool(args.dedup),
+                                  "evaluated_distinct": st_scr["evaluated_distinct"]},
+        "plain_bf16_dedup": pld,
         "plain_bf16": ({"samples_per_s": S_n / dt_pl, "connections_per_s": S_n * C / dt_pl,
                         "energy": float(en_pl[0]), "energy_err_vs_fp64_ha": err["plain_bf16"],
                         "evaluated_by_prefix_class": cls_pl, "reps": args.plain_reps} if dt_pl else None),
