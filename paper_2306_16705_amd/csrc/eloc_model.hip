@@ -216,15 +216,31 @@ __global__ void k_dd_gather(const uint64_t *__restrict__ xkeys, const int32_t *_
 // Sorted position p < n: the head of its run of equal keys, and at the head
 // the largest score (s0 << 32) | (2^32 - 1 - e) of the run's members: the
 // latest first change, then the smallest connection index (max is
-// independent of the order of the atomic updates).
+// independent of the order of the atomic updates).  The positions j <= p
+// whose key equals p's are exactly those from the head on, so the head is
+// found by doubling steps back from p and then bisecting: O(log L) loads
+// for a run of length L (an x' shared by many samples makes L large).
 __global__ void k_dd_score(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ si, int64_t n,
                            const int32_t *__restrict__ sel, const uint64_t *__restrict__ keys, int64_t C, int K,
                            int32_t *__restrict__ head, unsigned long long *__restrict__ best) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const uint64_t lo = sk[2 * p], hi = sk[2 * p + 1];
-    int64_t h = p;
-    while (h > 0 && sk[2 * (h - 1)] == lo && sk[2 * (h - 1) + 1] == hi) --h;
+    auto same = [&](int64_t j) { return sk[2 * j] == lo && sk[2 * j + 1] == hi; };
+    int64_t in = p, out = -1;  // same(in) holds; out < in is outside the run, or -1
+    for (int64_t step = 1; p - step >= 0; step <<= 1) {
+        if (!same(p - step)) {
+            out = p - step;
+            break;
+        }
+        in = p - step;
+    }
+    while (in - out > 1) {
+        const int64_t mid = out + (in - out) / 2;
+        if (same(mid)) in = mid;
+        else out = mid;
+    }
+    const int64_t h = in;
     head[p] = (int32_t)h;
     const int64_t e = sel[si[p]];
     const int s0 = conn_s0(K, keys + 2 * (e / C), lo, hi);

@@ -294,16 +294,22 @@ def test_logpsi_fp8_error_vs_oracle(nn, kw):
     assert np.all(d8 <= 0.5 + 0.02 * np.abs(ola))
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
-def test_dedup_evaluates_each_distinct_xprime_once(nn, prec):
+@pytest.mark.parametrize("prec,case", [("bf16", "sampled"), ("fp8", "sampled"), ("bf16", "sector")])
+def test_dedup_evaluates_each_distinct_xprime_once(nn, prec, case):
     """With dedup every distinct x' of the chunk goes through the forward
     once (from the sample whose first change is latest) and its amplitude is
     copied to every connection that reaches it: E_loc equals the per-
     connection evaluation up to FP64 summation order, and the forward's
-    distinct count is the number of distinct keys among the connections."""
-    d = synth.config_inputs(2, K=16, n_up=4, n_dn=4, n_unique=40, model=True)
+    distinct count is the number of distinct keys among the connections.
+    The whole-sector case takes every determinant as a sample, so each x'
+    is reached from every sample it connects to (runs of up to C equal
+    keys in the sorted list)."""
+    if case == "sector":
+        d = synth.config_inputs(1, K=7, n_up=3, n_dn=2, model=True)
+    else:
+        d = synth.config_inputs(2, K=16, n_up=4, n_dn=4, n_unique=40, model=True)
     P = nn.NNQS_BF16 if prec == "bf16" else nn.NNQS_FP8
-    _print_case("dedup", K=d["K"], prec=prec)
+    _print_case("dedup", K=d["K"], prec=prec, case=case, n=d["keys"].shape[0])
     S = nn.System(d["N"], d["n_up"], d["n_dn"], d["h"], d["g"], d["e_core"])
     M = nn.Model(d["model_shape"], d["n_up"], d["n_dn"], d["weights"])
     keys, cnt = dev(d["keys"]), dev(d["counts"], torch.int32)
