@@ -551,7 +551,7 @@ __global__ void k64x_embed(ModelView M, const uint64_t *__restrict__ ckeys, cons
 // holding s0 on, queries below s0 read as zero and are not written; keys and
 // values below s0 come from the cache of the connection's sample (list[i] / C
 // in the chunk), the rest from this pass (row off[i] - off0 + s - s0).
-__global__ void __launch_bounds__(256) k64x_attention(const double *__restrict__ q, const double *__restrict__ k,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k64x_attention(const double *__restrict__ q, const double *__restrict__ k,
                                                       const double *__restrict__ v, const double *__restrict__ kvc,
                                                       const int32_t *__restrict__ list,
                                                       const int32_t *__restrict__ s0v,
@@ -571,26 +571,28 @@ __global__ void __launch_bounds__(256) k64x_attention(const double *__restrict__
     const double *kc = kvc + ((smp * L + l) * 2) * per + hh * 16, *vc = kc + per;
     const int64_t rb = (int64_t)(off[i] - off0) * 64 + hh * 16;  // row s0 of this connection, head hh
     const double *qh = q + rb, *kh = k + rb, *vh = v + rb;
-    auto ldk = [&](int s, int c) { return s >= K ? 0.0 : s < s0 ? kc[(int64_t)s * 64 + c] : kh[(int64_t)(s - s0) * 64 + c]; };
     auto ldv = [&](int s, int c) { return s >= K ? 0.0 : s < s0 ? vc[(int64_t)s * 64 + c] : vh[(int64_t)(s - s0) * 64 + c]; };
-    double kf[4][4], vf[16];
+    // The score product's contraction index is the head column 4 lk + k4, so
+    // a lane's four operands of one key (or query) row are contiguous: one
+    // 32-byte load, and the four lanes of a row read its 128 bytes.  The
+    // values are read where the P V product takes them (16 lanes of a row,
+    // 128 bytes), not held: 114 registers, four waves per SIMD.
+    f64x4 kf[4];
 #pragma unroll
-    for (int kb = 0; kb < 4; kb++)
-#pragma unroll
-        for (int k4 = 0; k4 < 4; k4++) kf[kb][k4] = ldk(kb * 16 + lr, 4 * k4 + lk);
-#pragma unroll
-    for (int kk = 0; kk < 16; kk++) vf[kk] = ldv(4 * kk + lk, lr);
+    for (int kb = 0; kb < 4; kb++) {
+        const int s = kb * 16 + lr;
+        kf[kb] = s >= K ? f64x4{0.0, 0.0, 0.0, 0.0}
+                        : *reinterpret_cast<const f64x4 *>((s < s0 ? kc + (int64_t)s * 64 : kh + (int64_t)(s - s0) * 64) +
+                                                           4 * lk);
+    }
     double(*P)[64 + 1] = Ps[w];
     const int qb0 = s0 >> 4;
 #pragma unroll
     for (int qb = 0; qb < 4; qb++) {
         if (qb < qb0 || 16 * qb >= K) continue;  // wave-uniform
-        double qf[4];
-#pragma unroll
-        for (int k4 = 0; k4 < 4; k4++) {
-            const int s = qb * 16 + lr;
-            qf[k4] = (s >= s0 && s < K) ? qh[(int64_t)(s - s0) * 64 + 4 * k4 + lk] : 0.0;
-        }
+        const int sq = qb * 16 + lr;
+        const f64x4 qf = (sq >= s0 && sq < K) ? *reinterpret_cast<const f64x4 *>(qh + (int64_t)(sq - s0) * 64 + 4 * lk)
+                                              : f64x4{0.0, 0.0, 0.0, 0.0};
         f64x4 st[4];
 #pragma unroll
         for (int kb = 0; kb < 4; kb++) {
@@ -631,7 +633,7 @@ __global__ void __launch_bounds__(256) k64x_attention(const double *__restrict__
         f64x4 ot = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < 4 * (qb + 1); kk++)
-            ot = __builtin_amdgcn_mfma_f64_16x16x4f64(P[lr][4 * kk + lk], vf[kk], ot, 0, 0, 0);
+            ot = __builtin_amdgcn_mfma_f64_16x16x4f64(P[lr][4 * kk + lk], ldv(4 * kk + lk, lr), ot, 0, 0, 0);
 #pragma unroll
         for (int ii = 0; ii < 4; ii++) {
             const int s = qb * 16 + lk + 4 * ii;

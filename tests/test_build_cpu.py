@@ -1,7 +1,8 @@
 """Build-level guards that need no GPU: every sample-aware kernel instance
 (single-system, exact pass, batched, Pauli) keeps all values in registers.
 The library also refuses such a build at run time (hipFuncGetAttributes);
-this test catches a spilling build before it reaches a GPU."""
+this test catches a spilling build before it reaches a GPU.  The FP64
+list attention is held to four waves per SIMD without spills."""
 import os
 import re
 import subprocess
@@ -13,7 +14,7 @@ from paper_2306_16705_amd import build as hip_build
 KERNELS = re.compile(r"k_eloc_sa|k_eloc_pauli")
 
 
-def _resource_usage(src):
+def _resource_usage(src, field="ScratchSize"):
     cmd = [hip_build.hipcc(), f"--offload-arch={hip_build.ARCH}", "-O3", "-std=c++17", "-fPIC", "-c",
            "--cuda-device-only", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument", f"-I{hip_build.INCLUDE}", f"-I{hip_build.CSRC}",
@@ -26,7 +27,7 @@ def _resource_usage(src):
         if m:
             name = m.group(1)
             continue
-        m = re.search(r"remark:\s+ScratchSize \[bytes/lane\]: (\d+)", line)
+        m = re.search(r"remark:\s+" + re.escape(field) + r" \[[^]]*\]: (\d+)", line)
         if m and name:
             usage[name] = int(m.group(1))
     return usage
@@ -43,3 +44,12 @@ def test_sample_aware_kernels_do_not_spill(src):
         names = " ".join(hot)
         for part in ("k_eloc_sa_exact", "k_eloc_sa_batch", "k_eloc_saI"):
             assert part in names, part
+
+
+def test_fp64_list_attention_runs_four_waves_per_simd_without_spills():
+    scratch = _resource_usage("model_f64.hip")
+    occ = _resource_usage("model_f64.hip", "Occupancy")
+    name = [k for k in scratch if "k64x_attention" in k]
+    assert len(name) == 1, name
+    assert scratch[name[0]] == 0
+    assert occ[name[0]] >= 4
