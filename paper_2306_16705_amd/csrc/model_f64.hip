@@ -221,10 +221,12 @@ __device__ __forceinline__ void gemm64_tile(const double *__restrict__ A, int ld
     }
 }
 
+// The products run four waves per SIMD (four 33.5 KB blocks per CU): the
+// register budget that sets holds the tile without spills.
 template <int EPI, bool TB>
-__global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, int lda, const double *__restrict__ W,
-                                                int ldw, const double *__restrict__ bias, int64_t M, int N, int Kd,
-                                                double *__restrict__ C, int ldc) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k64_gemm(const double *__restrict__ A, int lda, const double *__restrict__ W, int ldw, const double *__restrict__ bias,
+         int64_t M, int N, int Kd, double *__restrict__ C, int ldc) {
     gemm64_tile<EPI, TB>(A, lda, W, ldw, bias, M, N, Kd, C, ldc, blockIdx.x * 64);
 }
 
@@ -233,9 +235,9 @@ __global__ void __launch_bounds__(256) k64_gemm(const double *__restrict__ A, in
 // width 256 (FFN output) of the networks measured here; no run-time bounds
 // on k; the next LayerNorm's statistics of the updated rows go to stout.
 template <int KD>
-__global__ void __launch_bounds__(256) k64_gemm_res(const double *__restrict__ A, int lda, const double *__restrict__ W,
-                                                    const double *__restrict__ bias, int64_t M,
-                                                    double *__restrict__ h, double *__restrict__ stout) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k64_gemm_res(const double *__restrict__ A, int lda, const double *__restrict__ W, const double *__restrict__ bias,
+             int64_t M, double *__restrict__ h, double *__restrict__ stout) {
     gemm64_tile<1, false, false, true>(A, lda, W, 64, bias, M, 64, KD, h, 64, 0, nullptr, nullptr, nullptr, stout);
 }
 

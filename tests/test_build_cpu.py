@@ -2,7 +2,8 @@
 (single-system, exact pass, batched, Pauli) keeps all values in registers.
 The library also refuses such a build at run time (hipFuncGetAttributes);
 this test catches a spilling build before it reaches a GPU.  The FP64
-list attention is held to four waves per SIMD without spills."""
+list attention and products are held to four waves per SIMD without
+spills."""
 import os
 import re
 import subprocess
@@ -46,10 +47,15 @@ def test_sample_aware_kernels_do_not_spill(src):
             assert part in names, part
 
 
-def test_fp64_list_attention_runs_four_waves_per_simd_without_spills():
+def test_fp64_list_kernels_run_four_waves_per_simd_without_spills():
+    """The list attention and every FP64 product instance (plain, residual,
+    LayerNorm-staged, QKV)."""
     scratch = _resource_usage("model_f64.hip")
     occ = _resource_usage("model_f64.hip", "Occupancy")
-    name = [k for k in scratch if "k64x_attention" in k]
-    assert len(name) == 1, name
-    assert scratch[name[0]] == 0
-    assert occ[name[0]] >= 4
+    names = [k for k in scratch if re.search(r"k64x_attention|k64_gemm", k)]
+    assert any("k64x_attention" in k for k in names), names
+    assert sum("k64_gemm_res" in k for k in names) >= 2, names
+    assert sum("k64_gemmI" in k for k in names) >= 5, names
+    for k in names:
+        assert scratch[k] == 0, k
+        assert occ[k] >= 4, (k, occ[k])
