@@ -285,9 +285,9 @@ __global__ void __launch_bounds__(256) k64_gemm_qkv(const double *__restrict__ h
 // row over the 16 lanes that hold it (the largest score, then one
 // exponential per key), P through LDS into the A-operand layout, O = P V.
 // Rows at or beyond K read as zero and are never written.
-__global__ void __launch_bounds__(256) k64_attention(const double *__restrict__ q, const double *__restrict__ k,
-                                                     const double *__restrict__ v, int64_t B, int K, double scale,
-                                                     double *__restrict__ o) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k64_attention(const double *__restrict__ q, const double *__restrict__ k, const double *__restrict__ v, int64_t B, int K,
+              double scale, double *__restrict__ o) {
     __shared__ double Ps[4][16][64 + 1];
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lr = l & 15, lk = l >> 4;
@@ -297,20 +297,20 @@ __global__ void __launch_bounds__(256) k64_attention(const double *__restrict__ 
     const int hh = (int)(g & 3);
     const double *qh = q + b * K * 64 + hh * 16, *kh = k + b * K * 64 + hh * 16, *vh = v + b * K * 64 + hh * 16;
     auto ld = [&](const double *base, int s, int c) { return s < K ? base[(int64_t)s * 64 + c] : 0.0; };
-    // B operands: K^T tiles kf[kb][k4] = K[16 kb + lr][4 k4 + lk]; V tiles vf[kk] = V[4 kk + lk][lr]
-    double kf[4][4], vf[16];
+    // Four adjacent head columns of row s (lane lk's share of the score
+    // product's contraction, column 4 lk + k4): one 32-byte load.
+    auto ld4 = [&](const double *base, int s) {
+        return s < K ? *reinterpret_cast<const f64x4 *>(base + (int64_t)s * 64 + 4 * lk) : f64x4{0.0, 0.0, 0.0, 0.0};
+    };
+    // B operands: K^T tiles kf[kb][k4] = K[16 kb + lr][4 lk + k4]; the V tiles
+    // V[4 kk + lk][lr] are read where the P V product takes them
+    f64x4 kf[4];
 #pragma unroll
-    for (int kb = 0; kb < 4; kb++)
-#pragma unroll
-        for (int k4 = 0; k4 < 4; k4++) kf[kb][k4] = ld(kh, kb * 16 + lr, 4 * k4 + lk);
-#pragma unroll
-    for (int kk = 0; kk < 16; kk++) vf[kk] = ld(vh, 4 * kk + lk, lr);
+    for (int kb = 0; kb < 4; kb++) kf[kb] = ld4(kh, kb * 16 + lr);
     double(*P)[64 + 1] = Ps[w];
 #pragma unroll
     for (int qb = 0; qb < 4; qb++) {
-        double qf[4];
-#pragma unroll
-        for (int k4 = 0; k4 < 4; k4++) qf[k4] = ld(qh, qb * 16 + lr, 4 * k4 + lk);
+        const f64x4 qf = ld4(qh, qb * 16 + lr);
         f64x4 st[4];
 #pragma unroll
         for (int kb = 0; kb < 4; kb++) {
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(256) k64_attention(const double *__restrict__ 
         f64x4 ot = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < 4 * (qb + 1); kk++)
-            ot = __builtin_amdgcn_mfma_f64_16x16x4f64(P[lr][4 * kk + lk], vf[kk], ot, 0, 0, 0);
+            ot = __builtin_amdgcn_mfma_f64_16x16x4f64(P[lr][4 * kk + lk], ld(vh, 4 * kk + lk, lr), ot, 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             const int s = qb * 16 + lk + 4 * i;
@@ -553,13 +553,11 @@ __global__ void k64x_embed(ModelView M, const uint64_t *__restrict__ ckeys, cons
 // holding s0 on, queries below s0 read as zero and are not written; keys and
 // values below s0 come from the cache of the connection's sample (list[i] / C
 // in the chunk), the rest from this pass (row off[i] - off0 + s - s0).
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k64x_attention(const double *__restrict__ q, const double *__restrict__ k,
-                                                      const double *__restrict__ v, const double *__restrict__ kvc,
-                                                      const int32_t *__restrict__ list,
-                                                      const int32_t *__restrict__ s0v,
-                                                      const int32_t *__restrict__ off, int32_t off0, int64_t C,
-                                                      int64_t B, int K, int L, int l, double scale,
-                                                      double *__restrict__ o) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k64x_attention(const double *__restrict__ q, const double *__restrict__ k, const double *__restrict__ v,
+               const double *__restrict__ kvc, const int32_t *__restrict__ list, const int32_t *__restrict__ s0v,
+               const int32_t *__restrict__ off, int32_t off0, int64_t C, int64_t B, int K, int L, int l, double scale,
+               double *__restrict__ o) {
     __shared__ double Ps[4][16][64 + 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;

@@ -2,8 +2,7 @@
 (single-system, exact pass, batched, Pauli) keeps all values in registers.
 The library also refuses such a build at run time (hipFuncGetAttributes);
 this test catches a spilling build before it reaches a GPU.  The FP64
-list attention and products are held to four waves per SIMD without
-spills."""
+attentions and products are held to four waves per SIMD without spills."""
 import os
 import re
 import subprocess
@@ -48,12 +47,13 @@ def test_sample_aware_kernels_do_not_spill(src):
 
 
 def test_fp64_list_kernels_run_four_waves_per_simd_without_spills():
-    """The list attention and every FP64 product instance (plain, residual,
-    LayerNorm-staged, QKV)."""
+    """Both attentions (whole sequence, list) and every FP64 product
+    instance (plain, residual, LayerNorm-staged, QKV)."""
     scratch = _resource_usage("model_f64.hip")
     occ = _resource_usage("model_f64.hip", "Occupancy")
-    names = [k for k in scratch if re.search(r"k64x_attention|k64_gemm", k)]
+    names = [k for k in scratch if re.search(r"k64x?_attention|k64_gemm", k)]
     assert any("k64x_attention" in k for k in names), names
+    assert any("k64_attention" in k for k in names), names
     assert sum("k64_gemm_res" in k for k in names) >= 2, names
     assert sum("k64_gemmI" in k for k in names) >= 5, names
     for k in names:
